@@ -1,0 +1,905 @@
+/*
+ * mmref.c -- CPU reference ("oracle") for the finite-difference micromagnetic
+ * hot path of Bruckner et al., "magnum.np -- A PyTorch based GPU enhanced
+ * Finite Difference Micromagnetic Simulation Framework" (arXiv:2302.08843).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so and is
+ * loaded by the tests, by the smoke check and by the CPU-baseline leg of the
+ * benchmark.  The product library never links, loads or calls it, and the two
+ * share no source: every formula here is written out again from the paper and
+ * from the works it cites.
+ *
+ * Plain, slow, obviously correct: FP64 everywhere except the near-field Newell
+ * tensor, which is evaluated in x87 long double and rounded to double because
+ * Newell's f and g cancel catastrophically at a distance of a few cells.
+ * OpenMP only splits independent rows / cells across threads; it reorders no
+ * arithmetic inside a row or a cell.
+ *
+ * Parity status of each part (what pins it) is listed with each function.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Constants                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Vacuum permeability.  The paper does not print it; the classical exact
+ * value 4*pi*1e-7 is used. */
+#define OR_MU0 (4.0e-7 * 3.14159265358979323846)
+/* Reduced gyromagnetic ratio as printed with the LLG equation (Sec. 3). */
+#define OR_GAMMA 2.21e5
+#define OR_PI_L 3.141592653589793238462643383279502884L
+
+enum { OR_DEMAG = 1, OR_EXCH = 2, OR_ANIS = 4, OR_ZEEMAN = 8 };
+
+/* ------------------------------------------------------------------------- */
+/* Newell, Williams & Dunlop (1993) cell-averaged demagnetisation tensor,     */
+/* cited in Sec. 4.4 for the near field.  Pinned by: self term 1/3 of a cube, */
+/* trace identities, Aharoni's prism factors, the dipole limit, the uniform-  */
+/* cube field, and the box demag factors (tests/test_oracle_tensor.py).       */
+/* ------------------------------------------------------------------------- */
+
+/* Newell's f: even in each argument. */
+static long double newell_f(long double x, long double y, long double z)
+{
+    x = fabsl(x);
+    y = fabsl(y);
+    z = fabsl(z);
+    long double x2 = x * x, y2 = y * y, z2 = z * z;
+    long double R = sqrtl(x2 + y2 + z2);
+    if (R == 0.0L)
+        return 0.0L;
+    long double s = (2.0L * x2 - y2 - z2) * R / 6.0L;
+    /* A term whose logarithm / arctangent argument is singular has a vanishing
+     * prefactor there; dropping it is the exact limit. */
+    if (x2 + z2 > 0.0L)
+        s += 0.5L * y * (z2 - x2) * asinhl(y / sqrtl(x2 + z2));
+    if (x2 + y2 > 0.0L)
+        s += 0.5L * z * (y2 - x2) * asinhl(z / sqrtl(x2 + y2));
+    if (x > 0.0L)
+        s -= x * y * z * atanl(y * z / (x * R));
+    return s;
+}
+
+/* Newell's g: odd in x and in y, even in z. */
+static long double newell_g(long double x, long double y, long double z)
+{
+    long double sg = 1.0L;
+    if (x < 0.0L) { x = -x; sg = -sg; }
+    if (y < 0.0L) { y = -y; sg = -sg; }
+    z = fabsl(z);
+    long double x2 = x * x, y2 = y * y, z2 = z * z;
+    long double R = sqrtl(x2 + y2 + z2);
+    if (R == 0.0L)
+        return 0.0L;
+    long double s = -x * y * R / 3.0L;
+    if (x2 + y2 > 0.0L)
+        s += x * y * z * asinhl(z / sqrtl(x2 + y2));
+    if (y2 + z2 > 0.0L)
+        s += y / 6.0L * (3.0L * z2 - y2) * asinhl(x / sqrtl(y2 + z2));
+    if (x2 + z2 > 0.0L)
+        s += x / 6.0L * (3.0L * z2 - x2) * asinhl(y / sqrtl(x2 + z2));
+    if (z > 0.0L)
+        s -= z * z2 / 6.0L * atanl(x * y / (z * R));
+    if (y > 0.0L)
+        s -= z * y2 / 2.0L * atanl(x * z / (y * R));
+    if (x > 0.0L)
+        s -= z * x2 / 2.0L * atanl(y * z / (x * R));
+    return sg * s;
+}
+
+/* Second-difference stencil over the 27 neighbours of (X,Y,Z) with cell size
+ * (a,b,c): weight 2 for a zero shift and -1 for a +-1 shift, per axis.
+ * which: 0 -> f, 1 -> g. */
+static long double newell_stencil(int which, long double X, long double Y, long double Z,
+                                  long double a, long double b, long double c)
+{
+    long double acc = 0.0L;
+    for (int e1 = -1; e1 <= 1; e1++)
+        for (int e2 = -1; e2 <= 1; e2++)
+            for (int e3 = -1; e3 <= 1; e3++) {
+                long double w = (e1 == 0 ? 2.0L : -1.0L) * (e2 == 0 ? 2.0L : -1.0L) *
+                                (e3 == 0 ? 2.0L : -1.0L);
+                long double u = X + e1 * a, v = Y + e2 * b, q = Z + e3 * c;
+                acc += w * (which == 0 ? newell_f(u, v, q) : newell_g(u, v, q));
+            }
+    return acc / (4.0L * OR_PI_L * a * b * c);
+}
+
+/* Newell tensor N (positive self term) between cells offset by (I,J,K) cells.
+ * out = {Nxx, Nyy, Nzz, Nxy, Nxz, Nyz}. */
+void or_newell(const double d[3], long oi, long oj, long ok, double out[6])
+{
+    long double dx = d[0], dy = d[1], dz = d[2];
+    long double X = oi * dx, Y = oj * dy, Z = ok * dz;
+    out[0] = (double)newell_stencil(0, X, Y, Z, dx, dy, dz);
+    out[1] = (double)newell_stencil(0, Y, X, Z, dy, dx, dz);
+    out[2] = (double)newell_stencil(0, Z, Y, X, dz, dy, dx);
+    out[3] = (double)newell_stencil(1, X, Y, Z, dx, dy, dz);
+    out[4] = (double)newell_stencil(1, X, Z, Y, dx, dz, dy);
+    out[5] = (double)newell_stencil(1, Y, Z, X, dy, dz, dx);
+}
+
+/* Point-dipole kernel of Eq. (dipole): the field of the moment V*Ms*m at the
+ * cell-centre distance r.  out in the same component order, positive sign
+ * (it multiplies M to give h). */
+void or_dipole(const double d[3], long oi, long oj, long ok, double out[6])
+{
+    double r[3] = {oi * d[0], oj * d[1], ok * d[2]};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double r5 = r2 * r2 * sqrt(r2);
+    double pre = d[0] * d[1] * d[2] / (4.0 * M_PI) / r5;
+    out[0] = pre * (3.0 * r[0] * r[0] - r2);
+    out[1] = pre * (3.0 * r[1] * r[1] - r2);
+    out[2] = pre * (3.0 * r[2] * r[2] - r2);
+    out[3] = pre * 3.0 * r[0] * r[1];
+    out[4] = pre * 3.0 * r[0] * r[2];
+    out[5] = pre * 3.0 * r[1] * r[2];
+}
+
+/* Demag kernel K with h_i = sum_j K_{i-j} Ms_j m_j (Sec. 4.4, discrete
+ * convolution).  Near field (Chebyshev index distance <= p): K = -N_Newell.
+ * Far field: the dipole kernel.  p < 0 means Newell everywhere. */
+void or_tensor_entry(const double d[3], long oi, long oj, long ok, int p, double out[6])
+{
+    long cheb = labs(oi);
+    if (labs(oj) > cheb) cheb = labs(oj);
+    if (labs(ok) > cheb) cheb = labs(ok);
+    if (p < 0 || cheb <= p) {
+        or_newell(d, oi, oj, ok, out);
+        for (int c = 0; c < 6; c++)
+            out[c] = -out[c];
+    } else {
+        or_dipole(d, oi, oj, ok, out);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* FFT: iterative radix-2 Cooley-Tukey with bit reversal, twiddles from long  */
+/* double sin/cos.  sign = -1 forward, +1 inverse (unnormalised).  Pinned by  */
+/* the naive DFT below at every power-of-two length up to 1024.              */
+/* ------------------------------------------------------------------------- */
+
+static void fft_pow2(long n, double complex *x, const double complex *tw /* n/2 roots */)
+{
+    for (long i = 1, j = 0; i < n; i++) {
+        long bit = n >> 1;
+        for (; j & bit; bit >>= 1)
+            j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double complex t = x[i];
+            x[i] = x[j];
+            x[j] = t;
+        }
+    }
+    for (long len = 2; len <= n; len <<= 1) {
+        long half = len >> 1, step = n / len;
+        for (long s = 0; s < n; s += len)
+            for (long k = 0; k < half; k++) {
+                double complex w = tw[k * step];
+                double complex u = x[s + k], v = x[s + k + half] * w;
+                x[s + k] = u + v;
+                x[s + k + half] = u - v;
+            }
+    }
+}
+
+static double complex *make_twiddles(long n, int sign)
+{
+    double complex *tw = malloc(sizeof(double complex) * (n > 1 ? n / 2 : 1));
+    for (long k = 0; k < n / 2; k++) {
+        long double ang = sign * 2.0L * OR_PI_L * (long double)k / (long double)n;
+        tw[k] = (double)cosl(ang) + I * (double)sinl(ang);
+    }
+    return tw;
+}
+
+void or_fft1d(long n, double complex *x, int sign)
+{
+    if (n <= 1)
+        return;
+    double complex *tw = make_twiddles(n, sign);
+    fft_pow2(n, x, tw);
+    free(tw);
+}
+
+/* Naive O(n^2) DFT with long-double accumulation (the definition). */
+void or_dft1d(long n, const double complex *x, double complex *X, int sign)
+{
+    for (long k = 0; k < n; k++) {
+        long double re = 0.0L, im = 0.0L;
+        for (long j = 0; j < n; j++) {
+            long double ang = sign * 2.0L * OR_PI_L * (long double)((j * k) % n) / (long double)n;
+            long double c = cosl(ang), s = sinl(ang);
+            long double xr = creal(x[j]), xi = cimag(x[j]);
+            re += xr * c - xi * s;
+            im += xr * s + xi * c;
+        }
+        X[k] = (double)re + I * (double)im;
+    }
+}
+
+/* 3-D transform of a complex array a[k][j][i] of extent P (x fastest), done
+ * as 1-D transforms along x, then y, then z. */
+static void fft3d(const long P[3], double complex *a, int sign)
+{
+    for (int ax = 0; ax < 3; ax++) {
+        long n = P[ax];
+        if (n <= 1)
+            continue;
+        long stride = ax == 0 ? 1 : (ax == 1 ? P[0] : P[0] * P[1]);
+        long nlines = P[0] * P[1] * P[2] / n;
+        double complex *tw = make_twiddles(n, sign);
+#pragma omp parallel
+        {
+            double complex *buf = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+            for (long l = 0; l < nlines; l++) {
+                long base;
+                if (ax == 0)
+                    base = l * P[0];
+                else if (ax == 1)
+                    base = (l / P[0]) * P[0] * P[1] + (l % P[0]);
+                else
+                    base = l;
+                for (long e = 0; e < n; e++)
+                    buf[e] = a[base + e * stride];
+                fft_pow2(n, buf, tw);
+                for (long e = 0; e < n; e++)
+                    a[base + e * stride] = buf[e];
+            }
+            free(buf);
+        }
+        free(tw);
+    }
+}
+
+/* Padded extent for the zero-padded (aperiodic) convolution: 1 for a single
+ * layer, else the next power of two >= 2n-1. */
+long or_padded(long n)
+{
+    if (n <= 1)
+        return 1;
+    long p = 1;
+    while (p < 2 * n - 1)
+        p <<= 1;
+    return p;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Problem context                                                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct or_ctx {
+    long n[3];
+    double d[3];
+    long N;
+    int p;
+    double *Ms;      /* per cell, A/m; 0 marks a vacuum cell               */
+    double *A;       /* per cell exchange constant, J/m                    */
+    double Ku;       /* first-order uniaxial anisotropy constant, J/m^3    */
+    double eu[3];    /* easy axis (unit)                                   */
+    double alpha;
+    double Hext[3];  /* uniform external field, A/m                        */
+    /* sinusoidal drive: H += mask_i * amp * sin(2 pi f t) */
+    double drive_amp[3];
+    double drive_freq;
+    unsigned char *drive_mask;
+    int demag_direct;          /* 1: O(N^2) direct sum, 0: FFT            */
+    /* FFT path */
+    long P[3];
+    long PN;
+    double complex *Khat;      /* 6 x PN spectra of the padded kernel     */
+    /* direct path: kernel per offset, (2nx-1)(2ny-1)(2nz-1) x 6            */
+    double *Koff;
+    int terms;                 /* field-term mask used by heff            */
+} or_ctx;
+
+static long cidx(const or_ctx *c, long i, long j, long k) { return i + c->n[0] * (j + c->n[1] * k); }
+
+static void build_kernel(or_ctx *c)
+{
+    long nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    long ox = 2 * nx - 1, oy = 2 * ny - 1, oz = 2 * nz - 1;
+    long noff = ox * oy * oz;
+    double *Koff = malloc(sizeof(double) * 6 * noff);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < noff; q++) {
+        long oi = q % ox - (nx - 1);
+        long oj = (q / ox) % oy - (ny - 1);
+        long ok = q / (ox * oy) - (nz - 1);
+        double e[6];
+        or_tensor_entry(c->d, oi, oj, ok, c->p, e);
+        for (int s = 0; s < 6; s++)
+            Koff[s * noff + q] = e[s];
+    }
+    if (c->demag_direct) {
+        c->Koff = Koff;
+        return;
+    }
+    /* Place K(I,J,K) at (I mod Px, J mod Py, K mod Pz); all other entries are
+     * zero.  Then transform each of the six components. */
+    for (int a = 0; a < 3; a++)
+        c->P[a] = or_padded(c->n[a]);
+    c->PN = c->P[0] * c->P[1] * c->P[2];
+    c->Khat = calloc(6 * c->PN, sizeof(double complex));
+    for (long q = 0; q < noff; q++) {
+        long oi = q % ox - (nx - 1);
+        long oj = (q / ox) % oy - (ny - 1);
+        long ok = q / (ox * oy) - (nz - 1);
+        long pi = ((oi % c->P[0]) + c->P[0]) % c->P[0];
+        long pj = ((oj % c->P[1]) + c->P[1]) % c->P[1];
+        long pk = ((ok % c->P[2]) + c->P[2]) % c->P[2];
+        long pidx = pi + c->P[0] * (pj + c->P[1] * pk);
+        for (int s = 0; s < 6; s++)
+            c->Khat[s * c->PN + pidx] = Koff[s * noff + q];
+    }
+    free(Koff);
+    for (int s = 0; s < 6; s++)
+        fft3d(c->P, c->Khat + s * c->PN, -1);
+}
+
+or_ctx *or_create(const long n[3], const double d[3], int p, const double *Ms, const double *A,
+                  double Ku, const double eu[3], double alpha, int demag_direct)
+{
+    or_ctx *c = calloc(1, sizeof(or_ctx));
+    for (int a = 0; a < 3; a++) {
+        c->n[a] = n[a];
+        c->d[a] = d[a];
+        c->eu[a] = eu[a];
+    }
+    c->N = n[0] * n[1] * n[2];
+    c->p = p;
+    c->Ms = malloc(sizeof(double) * c->N);
+    c->A = malloc(sizeof(double) * c->N);
+    memcpy(c->Ms, Ms, sizeof(double) * c->N);
+    memcpy(c->A, A, sizeof(double) * c->N);
+    c->Ku = Ku;
+    c->alpha = alpha;
+    c->demag_direct = demag_direct;
+    c->drive_mask = calloc(c->N, 1);
+    c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN;
+    build_kernel(c);
+    return c;
+}
+
+void or_destroy(or_ctx *c)
+{
+    if (!c)
+        return;
+    free(c->Ms);
+    free(c->A);
+    free(c->drive_mask);
+    free(c->Khat);
+    free(c->Koff);
+    free(c);
+}
+
+void or_set_field(or_ctx *c, const double H[3], unsigned terms)
+{
+    for (int a = 0; a < 3; a++)
+        c->Hext[a] = H[a];
+    c->terms = (int)terms;
+}
+
+void or_set_drive(or_ctx *c, const double amp[3], double freq, const unsigned char *mask)
+{
+    for (int a = 0; a < 3; a++)
+        c->drive_amp[a] = amp[a];
+    c->drive_freq = freq;
+    memcpy(c->drive_mask, mask, c->N);
+}
+
+/* Replace the per-cell saturation magnetisation (the kernel is unchanged). */
+void or_set_Ms(or_ctx *c, const double *Ms) { memcpy(c->Ms, Ms, sizeof(double) * c->N); }
+
+/* ------------------------------------------------------------------------- */
+/* Field terms (Sec. 4).  m and h are [3][N] arrays, x fastest.               */
+/* ------------------------------------------------------------------------- */
+
+/* Demagnetisation field, h_i = sum_j K_{i-j} Ms_j m_j (Sec. 4.4). */
+void or_demag(const or_ctx *c, const double *m, double *h)
+{
+    long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    if (c->demag_direct) {
+        long ox = 2 * nx - 1, oy = 2 * ny - 1, oz = 2 * nz - 1, noff = ox * oy * oz;
+        const double *K = c->Koff;
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < N; t++) {
+            long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+            double hx = 0, hy = 0, hz = 0;
+            for (long s = 0; s < N; s++) {
+                long si = s % nx, sj = (s / nx) % ny, sk = s / (nx * ny);
+                long q = (i - si + nx - 1) + ox * ((j - sj + ny - 1) + oy * (k - sk + nz - 1));
+                double Mx = c->Ms[s] * m[s], My = c->Ms[s] * m[N + s], Mz = c->Ms[s] * m[2 * N + s];
+                double kxx = K[q], kyy = K[noff + q], kzz = K[2 * noff + q];
+                double kxy = K[3 * noff + q], kxz = K[4 * noff + q], kyz = K[5 * noff + q];
+                hx += kxx * Mx + kxy * My + kxz * Mz;
+                hy += kxy * Mx + kyy * My + kyz * Mz;
+                hz += kxz * Mx + kyz * My + kzz * Mz;
+            }
+            h[t] = hx;
+            h[N + t] = hy;
+            h[2 * N + t] = hz;
+        }
+        (void)oz;
+        return;
+    }
+    long PN = c->PN;
+    double complex *Mh = calloc(3 * PN, sizeof(double complex));
+    for (long k = 0; k < nz; k++)
+        for (long j = 0; j < ny; j++)
+            for (long i = 0; i < nx; i++) {
+                long t = cidx(c, i, j, k);
+                long pidx = i + c->P[0] * (j + c->P[1] * k);
+                for (int a = 0; a < 3; a++)
+                    Mh[a * PN + pidx] = c->Ms[t] * m[a * N + t];
+            }
+    for (int a = 0; a < 3; a++)
+        fft3d(c->P, Mh + a * PN, -1);
+    /* full symmetric 3x3 product per frequency: index of K_ab in the six */
+    static const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < PN; q++) {
+        double complex M0 = Mh[q], M1 = Mh[PN + q], M2 = Mh[2 * PN + q];
+        double complex H[3];
+        for (int a = 0; a < 3; a++)
+            H[a] = c->Khat[comp[a][0] * PN + q] * M0 + c->Khat[comp[a][1] * PN + q] * M1 +
+                   c->Khat[comp[a][2] * PN + q] * M2;
+        for (int a = 0; a < 3; a++)
+            Mh[a * PN + q] = H[a];
+    }
+    for (int a = 0; a < 3; a++)
+        fft3d(c->P, Mh + a * PN, +1);
+    double scale = 1.0 / (double)PN;
+    for (long k = 0; k < nz; k++)
+        for (long j = 0; j < ny; j++)
+            for (long i = 0; i < nx; i++) {
+                long t = cidx(c, i, j, k);
+                long pidx = i + c->P[0] * (j + c->P[1] * k);
+                for (int a = 0; a < 3; a++)
+                    h[a * N + t] = creal(Mh[a * PN + pidx]) * scale;
+            }
+    free(Mh);
+}
+
+/* Exchange field with the harmonic mean of A between neighbours (Sec. 4.2,
+ * the discrete form for spatially varying A).  A is taken as zero outside the
+ * grid, which gives dm/dn = 0.  A harmonic mean with A_i + A_j = 0 is 0.
+ * Cells with Ms = 0 get h = 0. */
+void or_exchange(const or_ctx *c, const double *m, double *h)
+{
+    long N = c->N;
+    long nx = c->n[0], ny = c->n[1], nz = c->n[2];
+#pragma omp parallel for schedule(static)
+    for (long t = 0; t < N; t++) {
+        long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+        double acc[3] = {0, 0, 0};
+        if (c->Ms[t] != 0.0) {
+            long nb[6][3] = {{i + 1, j, k}, {i - 1, j, k}, {i, j + 1, k},
+                             {i, j - 1, k}, {i, j, k + 1}, {i, j, k - 1}};
+            for (int q = 0; q < 6; q++) {
+                long a = nb[q][0], b = nb[q][1], e = nb[q][2];
+                if (a < 0 || a >= nx || b < 0 || b >= ny || e < 0 || e >= nz)
+                    continue; /* A = 0 outside: the harmonic mean vanishes */
+                long s = cidx(c, a, b, e);
+                double Ai = c->A[t], As = c->A[s];
+                double hm = (Ai + As) != 0.0 ? Ai * As / (Ai + As) : 0.0;
+                double dk = c->d[q / 2];
+                double w = 2.0 / (dk * dk) * hm;
+                for (int comp = 0; comp < 3; comp++)
+                    acc[comp] += w * (m[comp * N + s] - m[comp * N + t]);
+            }
+            for (int comp = 0; comp < 3; comp++)
+                acc[comp] *= 2.0 / (OR_MU0 * c->Ms[t]);
+        }
+        for (int comp = 0; comp < 3; comp++)
+            h[comp * N + t] = acc[comp];
+    }
+}
+
+/* First-order uniaxial anisotropy field, h = 2 Ku/(mu0 Ms) e (e.m)
+ * (Sec. 4.1); zero where Ms = 0 (the listing's nan_to_num). */
+void or_anisotropy(const or_ctx *c, const double *m, double *h)
+{
+    long N = c->N;
+    for (long t = 0; t < N; t++) {
+        double em = c->eu[0] * m[t] + c->eu[1] * m[N + t] + c->eu[2] * m[2 * N + t];
+        double pre = c->Ms[t] != 0.0 ? 2.0 * c->Ku / (OR_MU0 * c->Ms[t]) : 0.0;
+        for (int a = 0; a < 3; a++)
+            h[a * N + t] = pre * c->eu[a] * em;
+    }
+}
+
+/* Zeeman field at time t: uniform Hext plus the masked sinusoidal drive. */
+void or_zeeman(const or_ctx *c, double t, double *h)
+{
+    long N = c->N;
+    double s = c->drive_freq != 0.0 ? sin(2.0 * M_PI * c->drive_freq * t) : 0.0;
+    for (long q = 0; q < N; q++)
+        for (int a = 0; a < 3; a++)
+            h[a * N + q] = c->Ms[q] != 0.0 ? c->Hext[a] + (c->drive_mask[q] ? c->drive_amp[a] * s : 0.0) : 0.0;
+}
+
+/* Effective field: sum of the terms selected by mask (bit 0 demag, 1 exchange,
+ * 2 anisotropy, 3 Zeeman).  Vacuum cells get h = 0. */
+void or_heff(const or_ctx *c, const double *m, double t, unsigned mask, double *h)
+{
+    long N = c->N;
+    double *tmp = malloc(sizeof(double) * 3 * N);
+    memset(h, 0, sizeof(double) * 3 * N);
+    if (mask & OR_DEMAG) {
+        or_demag(c, m, tmp);
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += c->Ms[q % N] != 0.0 ? tmp[q] : 0.0;
+    }
+    if (mask & OR_EXCH) {
+        or_exchange(c, m, tmp);
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += tmp[q];
+    }
+    if (mask & OR_ANIS) {
+        or_anisotropy(c, m, tmp);
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += tmp[q];
+    }
+    if (mask & OR_ZEEMAN) {
+        or_zeeman(c, t, tmp);
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += tmp[q];
+    }
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------------- */
+/* LLG right-hand side (Sec. 3, Eq. llg):                                     */
+/*   dm/dt = -gamma/(1+alpha^2) [ m x h + alpha m x (m x h) ]                 */
+/* precess = 0 drops the m x h term (relaxation).  Vacuum cells: dm = 0.      */
+/* ------------------------------------------------------------------------- */
+
+void or_llg_rhs(const or_ctx *c, const double *m, const double *h, double alpha, int precess,
+                double *dm)
+{
+    long N = c->N;
+    double g = OR_GAMMA / (1.0 + alpha * alpha);
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0) {
+            dm[q] = dm[N + q] = dm[2 * N + q] = 0.0;
+            continue;
+        }
+        double mx = m[q], my = m[N + q], mz = m[2 * N + q];
+        double hx = h[q], hy = h[N + q], hz = h[2 * N + q];
+        double px = my * hz - mz * hy, py = mz * hx - mx * hz, pz = mx * hy - my * hx; /* m x h */
+        double dx = my * pz - mz * py, dy = mz * px - mx * pz, dz = mx * py - my * px;  /* m x (m x h) */
+        double pf = precess ? 1.0 : 0.0;
+        dm[q] = -g * (pf * px + alpha * dx);
+        dm[N + q] = -g * (pf * py + alpha * dy);
+        dm[2 * N + q] = -g * (pf * pz + alpha * dz);
+    }
+}
+
+static void rhs_at(const or_ctx *c, const double *m, double t, double alpha, int precess,
+                   double *h, double *dm)
+{
+    or_heff(c, m, t, (unsigned)c->terms, h);
+    or_llg_rhs(c, m, h, alpha, precess, dm);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Energies (Sec. 4, Eqs. linear_energy / linear_energy_discrete).            */
+/* E_t = -1/2 mu0 V sum Ms m.h_t for the linear terms (demag, exchange,       */
+/* anisotropy); Zeeman E = -mu0 V sum Ms m.H.  E[4] is the total.             */
+/* Accumulated in long double.                                               */
+/* ------------------------------------------------------------------------- */
+
+void or_energy(const or_ctx *c, const double *m, double t, double E[5])
+{
+    long N = c->N;
+    double V = c->d[0] * c->d[1] * c->d[2];
+    double *h = malloc(sizeof(double) * 3 * N);
+    unsigned masks[4] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN};
+    double tot = 0;
+    for (int e = 0; e < 4; e++) {
+        long double acc = 0.0L;
+        if (c->terms & (int)masks[e]) {
+            or_heff(c, m, t, masks[e], h);
+            for (long q = 0; q < N; q++)
+                acc += (long double)c->Ms[q] *
+                       ((long double)m[q] * h[q] + (long double)m[N + q] * h[N + q] +
+                        (long double)m[2 * N + q] * h[2 * N + q]);
+        }
+        double pre = (e == 3 ? -1.0 : -0.5) * OR_MU0 * V;
+        E[e] = (double)(pre * acc);
+        tot += E[e];
+    }
+    E[4] = tot;
+    free(h);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dormand-Prince 5(4) with first-same-as-last (Dormand & Prince, 1980).      */
+/* The paper's default is Fehlberg's RK45 (Sec. 3); this hot path uses the    */
+/* Dormand-Prince pair.  Controller reading: Hairer RMS norm over magnetic    */
+/* components with sc = atol + rtol*max(|y|,|y1|); accept iff err <= 1;       */
+/* dt *= min(facmax, max(0.2, 0.9 err^-1/5)), facmax = 10 (1 after a reject). */
+/* ------------------------------------------------------------------------- */
+
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+/* 5th-order weights (= last row of A) and the embedded 4th-order weights. */
+static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
+                               -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+static const double DP_BS[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
+                                -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
+
+enum { OR_OK = 0, OR_EDTMIN = -5, OR_ENOTCONV = -6, OR_ENONFINITE = -4 };
+
+typedef struct {
+    long accepted, rejected, rhs_evals;
+    double t, dt, err_last;
+} or_stats;
+
+static double err_norm(const or_ctx *c, const double *y, const double *y1, const double *e,
+                       double rtol, double atol)
+{
+    long N = c->N;
+    long double acc = 0.0L;
+    long cnt = 0;
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0)
+            continue;
+        for (int a = 0; a < 3; a++) {
+            double ya = fabs(y[a * N + q]), yb = fabs(y1[a * N + q]);
+            double sc = atol + rtol * (ya > yb ? ya : yb);
+            long double r = e[a * N + q] / sc;
+            acc += r * r;
+            cnt++;
+        }
+    }
+    if (cnt == 0)
+        return 0.0;
+    return sqrt((double)(acc / cnt));
+}
+
+static void renormalise(const or_ctx *c, double *m)
+{
+    long N = c->N;
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0) {
+            m[q] = m[N + q] = m[2 * N + q] = 0.0;
+            continue;
+        }
+        double nrm = sqrt(m[q] * m[q] + m[N + q] * m[N + q] + m[2 * N + q] * m[2 * N + q]);
+        for (int a = 0; a < 3; a++)
+            m[a * N + q] /= nrm;
+    }
+}
+
+/* Hairer-Norsett-Wanner starting step size (Solving ODEs I, Sec. II.4). */
+static double initial_dt(const or_ctx *c, const double *y, const double *f0, double t, double alpha,
+                         int precess, double rtol, double atol, long *evals)
+{
+    long N = c->N, n3 = 3 * N;
+    double *y1 = malloc(sizeof(double) * n3), *f1 = malloc(sizeof(double) * n3);
+    double *h = malloc(sizeof(double) * n3);
+    long double s0 = 0, s1 = 0;
+    long cnt = 0;
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0)
+            continue;
+        for (int a = 0; a < 3; a++) {
+            double sc = atol + rtol * fabs(y[a * N + q]);
+            s0 += (long double)(y[a * N + q] / sc) * (y[a * N + q] / sc);
+            s1 += (long double)(f0[a * N + q] / sc) * (f0[a * N + q] / sc);
+            cnt++;
+        }
+    }
+    double d0 = cnt ? sqrt((double)(s0 / cnt)) : 0.0, d1 = cnt ? sqrt((double)(s1 / cnt)) : 0.0;
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    for (long q = 0; q < n3; q++)
+        y1[q] = y[q] + h0 * f0[q];
+    rhs_at(c, y1, t + h0, alpha, precess, h, f1);
+    (*evals)++;
+    long double s2 = 0;
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0)
+            continue;
+        for (int a = 0; a < 3; a++) {
+            double sc = atol + rtol * fabs(y[a * N + q]);
+            double r = (f1[a * N + q] - f0[a * N + q]) / sc;
+            s2 += (long double)r * r;
+        }
+    }
+    double d2 = (cnt ? sqrt((double)(s2 / cnt)) : 0.0) / h0;
+    double mx = d1 > d2 ? d1 : d2;
+    double h1 = mx <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / mx, 1.0 / 5.0);
+    free(y1);
+    free(f1);
+    free(h);
+    return fmin(100.0 * h0, h1);
+}
+
+/* Integrate the LLG from *t until t_end or until max_steps steps have been
+ * accepted.  m is updated in place.  renorm != 0 renormalises m after each
+ * accepted step (then FSAL cannot be used and k1 is re-evaluated).
+ * fixed != 0 disables error control (every step accepted, dt constant): used
+ * by the order test only.  *dt <= 0 asks for the automatic initial step. */
+int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double atol, double t_end,
+            long max_steps, int renorm, int precess, double alpha, int fixed, or_stats *st,
+            double torque_tol)
+{
+    long N = c->N, n3 = 3 * N;
+    double *k[7];
+    for (int s = 0; s < 7; s++)
+        k[s] = malloc(sizeof(double) * n3);
+    double *y = malloc(sizeof(double) * n3), *ys = malloc(sizeof(double) * n3);
+    double *h = malloc(sizeof(double) * n3), *e = malloc(sizeof(double) * n3);
+    memset(st, 0, sizeof(*st));
+    int status = OR_OK;
+
+    memcpy(y, m, sizeof(double) * n3);
+    rhs_at(c, y, *t, alpha, precess, h, k[0]);
+    st->rhs_evals++;
+    if (*dt <= 0.0) {
+        *dt = initial_dt(c, y, k[0], *t, alpha, precess, rtol, atol, &st->rhs_evals);
+    }
+    int last_rejected = 0;
+    /* relaxation mode: stop when the torque criterion holds (checked on the
+     * current state before every step) */
+    while (st->accepted < max_steps && *t < t_end) {
+        if (torque_tol > 0.0) {
+            double mxt = 0.0;
+            for (long q = 0; q < N; q++) {
+                if (c->Ms[q] == 0.0)
+                    continue;
+                double mx_ = y[q], my_ = y[N + q], mz_ = y[2 * N + q];
+                double hx = h[q], hy = h[N + q], hz = h[2 * N + q];
+                double px = my_ * hz - mz_ * hy, py = mz_ * hx - mx_ * hz, pz = mx_ * hy - my_ * hx;
+                double tq = sqrt(px * px + py * py + pz * pz) / c->Ms[q];
+                if (tq > mxt)
+                    mxt = tq;
+            }
+            if (mxt < torque_tol)
+                break;
+        }
+        double hstep = *dt;
+        if (*t + hstep > t_end)
+            hstep = t_end - *t;
+        for (int s = 1; s < 7; s++) {
+            for (long q = 0; q < n3; q++) {
+                double acc = 0.0;
+                for (int j = 0; j < s; j++)
+                    acc += DP_A[s][j] * k[j][q];
+                ys[q] = y[q] + hstep * acc;
+            }
+            rhs_at(c, ys, *t + DP_C[s] * hstep, alpha, precess, h, k[s]);
+            st->rhs_evals++;
+        }
+        /* ys now holds the 5th-order solution (stage 7 input = b-weighted sum) */
+        for (long q = 0; q < n3; q++) {
+            double acc = 0.0;
+            for (int j = 0; j < 7; j++)
+                acc += (DP_B[j] - DP_BS[j]) * k[j][q];
+            e[q] = hstep * acc;
+        }
+        double err = fixed ? 0.0 : err_norm(c, y, ys, e, rtol, atol);
+        st->err_last = err;
+        if (!isfinite(err)) {
+            status = OR_ENONFINITE;
+            break;
+        }
+        if (err <= 1.0) {
+            *t += hstep;
+            memcpy(y, ys, sizeof(double) * n3);
+            st->accepted++;
+            if (renorm) {
+                renormalise(c, y);
+                rhs_at(c, y, *t, alpha, precess, h, k[0]);
+                st->rhs_evals++;
+            } else {
+                double *tmp = k[0];
+                k[0] = k[6];
+                k[6] = tmp; /* first same as last; h holds the field at y */
+            }
+            if (!fixed) {
+                double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+                if (last_rejected && fac > 1.0)
+                    fac = 1.0;
+                /* a step clipped to t_end keeps the unclipped proposal */
+                if (!(hstep < *dt))
+                    *dt = fac * hstep;
+            }
+            last_rejected = 0;
+        } else {
+            st->rejected++;
+            double fac = fmax(0.2, 0.9 * pow(err, -0.2));
+            *dt = fac * hstep;
+            last_rejected = 1;
+            /* field h was overwritten by the stages; restore the one at y */
+            or_heff(c, y, *t, (unsigned)c->terms, h);
+        }
+        if (*dt < 1e-20) {
+            status = OR_EDTMIN;
+            break;
+        }
+    }
+    if (torque_tol > 0.0 && status == OR_OK && st->accepted >= max_steps) {
+        /* converged only if the criterion holds on the final state */
+        double mxt = 0.0;
+        for (long q = 0; q < N; q++) {
+            if (c->Ms[q] == 0.0)
+                continue;
+            double px = y[N + q] * h[2 * N + q] - y[2 * N + q] * h[N + q];
+            double py = y[2 * N + q] * h[q] - y[q] * h[2 * N + q];
+            double pz = y[q] * h[N + q] - y[N + q] * h[q];
+            double tq = sqrt(px * px + py * py + pz * pz) / c->Ms[q];
+            if (tq > mxt)
+                mxt = tq;
+        }
+        if (!(mxt < torque_tol))
+            status = OR_ENOTCONV;
+    }
+    memcpy(m, y, sizeof(double) * n3);
+    st->t = *t;
+    st->dt = *dt;
+    for (int s = 0; s < 7; s++)
+        free(k[s]);
+    free(y);
+    free(ys);
+    free(h);
+    free(e);
+    return status;
+}
+
+/* Relaxation (Sec. 3): high damping (alpha = 1) without the precession term,
+ * renormalised Dormand-Prince steps, until max_i |m_i x h_i| / Ms_i < tol. */
+int or_relax(or_ctx *c, double *m, double tol, long max_steps, double rtol, or_stats *st)
+{
+    double t = 0.0, dt = -1.0;
+    return or_dp45(c, m, &t, &dt, rtol, rtol, INFINITY, max_steps, 1, 0, 1.0, 0, st, tol);
+}
+
+/* Maximum torque max_i |m_i x h_i| / Ms_i over magnetic cells. */
+double or_max_torque(const or_ctx *c, const double *m, double t)
+{
+    long N = c->N;
+    double *h = malloc(sizeof(double) * 3 * N);
+    or_heff(c, m, t, (unsigned)c->terms, h);
+    double mxt = 0.0;
+    for (long q = 0; q < N; q++) {
+        if (c->Ms[q] == 0.0)
+            continue;
+        double px = m[N + q] * h[2 * N + q] - m[2 * N + q] * h[N + q];
+        double py = m[2 * N + q] * h[q] - m[q] * h[2 * N + q];
+        double pz = m[q] * h[N + q] - m[N + q] * h[q];
+        double tq = sqrt(px * px + py * py + pz * pz) / c->Ms[q];
+        if (tq > mxt)
+            mxt = tq;
+    }
+    free(h);
+    return mxt;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
