@@ -800,8 +800,20 @@ int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double ato
         double err = fixed ? 0.0 : err_norm(c, y, ys, e, rtol, atol);
         st->err_last = err;
         if (!isfinite(err)) {
-            status = OR_ENONFINITE;
-            break;
+            /* A trial step that overflows is rejected like any too-large step
+             * (minimum factor 0.2); only a non-finite current state is an
+             * error. */
+            int bad = 0;
+            for (long q = 0; q < n3; q++)
+                if (!isfinite(y[q])) {
+                    bad = 1;
+                    break;
+                }
+            if (bad) {
+                status = OR_ENONFINITE;
+                break;
+            }
+            err = INFINITY;
         }
         if (err <= 1.0) {
             *t += hstep;

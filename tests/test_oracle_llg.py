@@ -167,3 +167,17 @@ def test_relax_step_cap_reports_not_converged(orc):
     m0 = W.random_unit_sphere(n, 2)
     m, st, status = o.relax(m0, tol=1e-9, max_steps=3)
     assert status == orc.ENOTCONV and st["accepted"] == 3
+
+
+def test_overflowing_trial_step_is_rejected_not_fatal(orc):
+    # a first step far beyond stability overflows the stages; the controller
+    # rejects it (factor 0.2) and carries on; a NaN in the state is fatal
+    n = (8, 8, 2)
+    o = orc.Oracle(n, (2e-9,) * 3, Ms=8e5, A=1.3e-11, alpha=0.5)
+    m0 = W.random_unit_sphere(n, 1)
+    m, t, dt, st, status = o.dp45(m0, dt=1e-6, rtol=1e-6, max_steps=20)
+    assert status == 0 and st["accepted"] == 20 and st["rejected"] >= 5
+    assert np.all(np.isfinite(m)) and np.abs(np.sqrt((m ** 2).sum(0)) - 1).max() < 1e-3
+    bad = m0.copy()
+    bad[1, 0, 0, 0] = np.nan
+    assert o.dp45(bad, dt=1e-13, max_steps=3)[4] == orc.ENONFINITE
