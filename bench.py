@@ -1,0 +1,206 @@
+"""Benchmark of the micromagnetic hot path on one MI355X.
+
+Workload (default): the 512 x 512 x 64 grid of 4 nm cells (16.7 M cells,
+padded FFT 1024 x 1024 x 128), Ms 1e6 A/m, A 1.5e-11 J/m, alpha 0.02, Ku 0,
+H 0 (demag + exchange), seeded Voronoi vortex domains.  One step is one
+accepted adaptive Dormand-Prince step in FP32 (six effective-field + LLG
+right-hand-side evaluations through the FFT passes, the stage combinations,
+the error norm in FP64 and the host controller).  `value` is effective-field
+evaluations x cells per second over the timed steps.  Inputs are resident in
+HBM before timing starts.
+
+The JSON line also carries: the same steps in FP64, effective-field-only
+throughput (FP32 and FP64), the roofline of the dominant kernel (the z pass
+with the spectral product) from HIP-event timing of every launch inside the
+timed region, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Heff evals×cells/s at 16.7M cells FP32 vs FP64; p50/p99 batched solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(grid, prec):
+    """Algorithmic HBM bytes per launch of each pass (model)."""
+    nx, ny, nz = grid
+    P = [1 if n == 1 else 1 << (2 * n - 2).bit_length() for n in grid]
+    Px, Py, Pz = P
+    hx = Px // 2 + 1 if Px > 1 else 1
+    w = 4 if prec == "fp32" else 8
+    N = nx * ny * nz
+    S1 = 3 * hx * ny * nz * 2 * w
+    S2 = 3 * hx * Py * nz * 2 * w
+    K = 6 * hx * (Py // 2 + 1) * (Pz // 2 + 1) * w
+    m = 3 * N * w
+    return {"x_fwd": m + S1, "y_fwd": S1 + S2, "mid": 2 * S2 + K, "y_inv": S2 + S1,
+            "x_inv_local": S1 + m + m}
+
+
+def run_steps(mm, plan, m, cfg, steps, warmup, rtol, profile=False):
+    import torch
+
+    H = cfg["H"]
+    t, dt = 0.0, -1.0
+    if warmup:
+        _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=warmup)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+    t0 = time.perf_counter()
+    _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = plan.profile_read() if profile else None
+    if profile:
+        plan.profile(False)
+    return wall, st, prof
+
+
+def heff_only(mm, plan, m, cfg, iters):
+    import torch
+
+    out = plan.empty()
+    for _ in range(3):
+        plan.heff(m, cfg["H"], cfg["terms"], out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        plan.heff(m, cfg["H"], cfg["terms"], out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / iters
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The CPU oracle (plain FP64 C, OpenMP over FFT lines) on a bounded sample:
+    the same material and start state on a 256 x 256 x 32 grid."""
+    import oracle
+    from paper_2302_08843_amd import workloads as W
+
+    n = (256, 256, 32)
+    c = W.config_large(n=n)
+    o = oracle.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    o.set_field(c["H"], terms=c["terms"])
+    o.heff(c["m0"])  # first touch
+    evals, t0 = 0, time.perf_counter()
+    while True:
+        o.heff(c["m0"])
+        evals += 1
+        el = time.perf_counter() - t0
+        if el > seconds_budget / 2 or evals >= 8:
+            break
+    N = int(np.prod(n))
+    return {"value": N * evals / el, "unit": "cell-evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle effective field (FFT demag + exchange), %d evaluations of the "
+                      "same material and vortex start on a 256x256x32 grid (padded 512x512x64); "
+                      "cells x evaluations per second" % evals}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--grid", type=str, default="512,512,64")
+    ap.add_argument("--heff-iters", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2302_08843_amd import mm
+    from paper_2302_08843_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    grid = tuple(int(v) for v in args.grid.split(","))
+    cfg = W.config_large(n=grid)
+    N = int(np.prod(grid))
+    res = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        print("[bench] %s plan %s" % (prec, grid), file=sys.stderr, flush=True)
+        plan = mm.Plan(grid, cfg["d"], Ms=cfg["Ms"], A=cfg["A"], Ku=cfg["Ku"], alpha=cfg["alpha"],
+                       prec=prec)
+        m = plan._t(cfg["m0"])
+        wall, st, prof = run_steps(mm, plan, m, cfg, args.steps, args.warmup, args.rtol,
+                                   profile=(prec == "fp32"))
+        print("[bench] %s %d steps in %.3f s (%d evals)" % (prec, st["accepted"], wall,
+                                                            st["rhs_evals"]),
+              file=sys.stderr, flush=True)
+        th = heff_only(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters)
+        res[prec] = dict(wall=wall, stats=st, prof=prof, heff_s=th, device_bytes=plan.device_bytes())
+        del plan, m
+        torch.cuda.empty_cache()
+
+    r32 = res["fp32"]
+    evals = r32["stats"]["rhs_evals"]
+    value = evals * N / r32["wall"]
+    prof = r32["prof"]
+    pb = pass_bytes(grid, "fp32")
+    mid_ms, mid_n = prof["mid"]
+    mid_avg_s = mid_ms / 1e3 / mid_n
+    achieved = pb["mid"] / mid_avg_s / 1e9
+    passes = {}
+    for k in ("x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local"):
+        ms, n = prof[k]
+        if n:
+            passes[k] = {"avg_us": 1e3 * ms / n, "launches": n, "model_bytes": pb[k],
+                         "GBs": pb[k] / (ms / 1e3 / n) / 1e9}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["wall"] / max(1, r32["stats"]["accepted"]),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large_512x512x64 adaptive Dormand-Prince steps, FP32 bulk, "
+                               "demag + exchange, vortex-domain start",
+                   "grid": list(grid), "cells": N, "cell_m": list(cfg["d"]), "rtol": args.rtol,
+                   "rhs_evals": evals, "rejected": r32["stats"]["rejected"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_mid<float,128,2> (z forward + spectral product + z inverse)",
+                     "bytes_per_launch": pb["mid"], "avg_us": mid_avg_s * 1e6},
+        "passes_fp32": passes,
+        "heff_only": {"fp32_cell_evals_per_s": N / r32["heff_s"], "fp32_ms": 1e3 * r32["heff_s"]},
+        "serving": None,
+    }
+    if "fp64" in res:
+        r64 = res["fp64"]
+        out["fp64"] = {"value": r64["stats"]["rhs_evals"] * N / r64["wall"],
+                       "ms_per_step": 1e3 * r64["wall"] / max(1, r64["stats"]["accepted"]),
+                       "rhs_evals": r64["stats"]["rhs_evals"]}
+        out["heff_only"]["fp64_cell_evals_per_s"] = N / r64["heff_s"]
+        out["heff_only"]["fp64_ms"] = 1e3 * r64["heff_s"]
+        out["fp32_over_fp64"] = value / out["fp64"]["value"]
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

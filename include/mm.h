@@ -1,0 +1,208 @@
+/*
+ * mm.h -- C ABI of an MI355X-native finite-difference micromagnetic hot path.
+ *
+ * The method is the one of Bruckner, Koraltan, Abert & Suess, "magnum.np -- A
+ * PyTorch based GPU enhanced Finite Difference Micromagnetic Simulation
+ * Framework for High Level Development and Inverse Design" (arXiv:2302.08843):
+ *   - a regular grid of nx*ny*nz cells of size dx*dy*dz (Sec. 2);
+ *   - the effective field h = h_demag + h_exchange + h_anisotropy + h_zeeman
+ *     (Sec. 4): demag as the zero-padded FFT convolution of M = Ms m with the
+ *     cell-averaged Newell tensor in the near field and the point dipole
+ *     beyond (Sec. 4.4, Eqs. convolution and dipole), the 6-neighbour
+ *     exchange stencil with dm/dn = 0 (Sec. 4.2), first-order uniaxial
+ *     anisotropy (Sec. 4.1) and a uniform external field;
+ *   - the LLG equation (Sec. 3, Eq. llg) integrated by an adaptive
+ *     Dormand-Prince 5(4) Runge-Kutta pair;
+ *   - relaxation with high damping and no precession term (Sec. 3);
+ *   - the linear-term energies (Sec. 4, Eqs. linear_energy(_discrete)).
+ *
+ * Units are SI: lengths in m, Ms and h in A/m, A in J/m, Ku in J/m^3, t in s.
+ * gamma = 2.21e5 m/(A s) as printed with Eq. llg; mu0 = 4 pi 1e-7.
+ *
+ * Data layout.  A vector field (m, h, dm/dt) is one caller-owned DEVICE buffer
+ * of 3*N values of the plan's precision (float for MM_FP32, double for
+ * MM_FP64), component-major with x fastest:
+ *     v[c*N + i + nx*(j + ny*k)],  c = 0,1,2 (x,y,z),  N = nx*ny*nz.
+ * Scalar per-cell fields (Ms) use the same cell order with one component.
+ *
+ * Ownership.  The plan owns every internal buffer (spectral tensor, FFT
+ * spectra, Runge-Kutta stages) and frees them in mm_plan_destroy.  Caller
+ * buffers are only read or written during the call (stream-ordered): they
+ * must stay valid until the plan's stream has consumed the work.
+ *
+ * Ordering.  All device work of a plan runs on the plan's stream (mm_opts
+ * .stream, a hipStream_t; NULL = the null stream).  mm_heff and mm_llg_rhs
+ * enqueue work and return without synchronising.  mm_llg_step, mm_relax,
+ * mm_energy and mm_max_torque return host values and synchronise the stream.
+ *
+ * Errors.  Every call returns an mm_status; no exception crosses the ABI.
+ * mm_last_error() returns a thread-local message for the last failure.  On an
+ * error the caller's output buffers are left unchanged, except that
+ * mm_llg_step and mm_relax leave the last accepted state in m.
+ *
+ * Threads.  A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_plan mm_plan;
+
+typedef enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,     /* invalid argument (sizes, cell, material, pointer) */
+    MM_ENOMEM = -2,     /* device allocation failed                          */
+    MM_EHIP = -3,       /* a HIP runtime call or kernel launch failed        */
+    MM_ENONFINITE = -4, /* the magnetisation became NaN or infinite          */
+    MM_EDTMIN = -5,     /* the adaptive step fell below dt_min               */
+    MM_ENOTCONV = -6,   /* mm_relax hit max_steps before the torque criterion */
+    MM_EBUSY = -7       /* resource temporarily unavailable                  */
+} mm_status;
+
+typedef enum { MM_FP32 = 0, MM_FP64 = 1 } mm_prec;
+
+/* Field-term mask (Sec. 4). */
+enum { MM_DEMAG = 1, MM_EXCH = 2, MM_ANIS = 4, MM_ZEEMAN = 8, MM_ALL = 15 };
+
+typedef struct {
+    int prec;            /* MM_FP32 (bulk arithmetic in float; tensor set up and
+                            reductions in double) or MM_FP64                  */
+    double ku_axis[3];   /* uniaxial easy axis; normalised by the library     */
+    int demag_p;         /* Newell near-field radius in cells (Chebyshev index
+                            distance, Sec. 4.4 default 20); < 0: Newell at
+                            every distance                                    */
+    void *stream;        /* hipStream_t for all device work; NULL = null stream */
+} mm_opts;
+
+/* Fill *o with defaults: MM_FP64, axis (0,0,1), demag_p 20, stream NULL. */
+void mm_opts_default(mm_opts *o);
+
+/* Create a plan for grid[3] = (nx, ny, nz) cells of size cell[3] = (dx, dy,
+ * dz) with saturation magnetisation Ms, exchange constant A, uniaxial
+ * anisotropy constant Ku and damping alpha (Sec. 2 mesh and material; Sec. 3
+ * alpha).  Builds the demag kernel on the device (Newell tensor in
+ * double-double arithmetic for the near field, dipole beyond, Sec. 4.4),
+ * transforms it once and keeps its real spectrum resident.  Every grid
+ * extent must be in [1, 512] (padded FFT length <= 1024).  Returns
+ * MM_EINVAL for invalid sizes, a non-positive cell, Ms < 0, A < 0 or
+ * alpha < 0; MM_ENOMEM if device memory runs out.  opt may be NULL
+ * (defaults).  Synchronises the stream before returning. */
+mm_status mm_plan_create(mm_plan **out, const int grid[3], const double cell[3], double Ms,
+                         double A, double Ku, double alpha, const mm_opts *opt);
+
+/* Release every device buffer of the plan (synchronises its stream first).
+ * NULL is ignored. */
+void mm_plan_destroy(mm_plan *p);
+
+/* Device bytes held by the plan. */
+size_t mm_plan_device_bytes(const mm_plan *p);
+
+/* Padded FFT extents (Px, Py, Pz): 1 for a single layer, else the next power
+ * of two >= 2n-1 (the zero padding of Sec. 4.4). */
+void mm_plan_padded(const mm_plan *p, int P[3]);
+
+/* Set a per-cell saturation magnetisation: Ms_cell is a device buffer of N
+ * values in the plan's precision, copied into the plan (stream-ordered).
+ * Ms = 0 marks a vacuum cell: its field, torque and dm/dt are zero and it is
+ * left out of norms and energies; its exchange constant is taken as zero, so
+ * neighbours see dm/dn = 0 there.  NULL restores the uniform Ms of
+ * mm_plan_create. */
+mm_status mm_set_ms(mm_plan *p, const void *Ms_cell);
+
+/* Time-dependent Zeeman drive added to the external field on masked cells:
+ * H(t) += mask_i * amp * sin(2 pi freq t).  mask is a device buffer of N
+ * bytes (0/1) copied into the plan; NULL removes the drive. */
+mm_status mm_set_drive(mm_plan *p, const double amp[3], double freq, const unsigned char *mask);
+
+/* Effective field h_out = sum of the terms selected by `terms` (MM_* mask)
+ * at the state m and time t (t only matters for a drive).  h_ext is the
+ * uniform external field in A/m (NULL = 0).  m and h_out are device buffers
+ * of 3N values; they must not alias.  Asynchronous. */
+mm_status mm_heff(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
+                  void *h_out);
+
+/* LLG right-hand side dm/dt = -gamma/(1+alpha^2) [m x h + alpha m x (m x h)]
+ * (Sec. 3, Eq. llg) with h the effective field of `terms` at (m, t).
+ * Asynchronous. */
+mm_status mm_llg_rhs(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
+                     void *dmdt_out);
+
+typedef struct {
+    double rtol, atol;  /* error tolerances of the step controller           */
+    double t_end;       /* integrate until t reaches t_end ...               */
+    long max_steps;     /* ... or until max_steps steps have been accepted   */
+    double dt_min;      /* a step below dt_min gives MM_EDTMIN (0 -> 1e-20)  */
+    int renorm;         /* renormalise |m| = 1 after each accepted step      */
+} mm_step_opts;
+
+typedef struct {
+    long accepted, rejected, rhs_evals;
+    double t, dt, err_last;
+} mm_step_stats;
+
+/* Adaptive Dormand-Prince 5(4) integration of the LLG equation (Sec. 3) with
+ * first-same-as-last, propagating the 5th-order solution.  The error norm is
+ * the RMS over magnetic components of e/(atol + rtol max(|y|,|y_new|)),
+ * computed in double on the device; a step is accepted iff the norm <= 1 and
+ * dt is rescaled by min(10, max(0.2, 0.9 err^-1/5)) (no growth right after a
+ * rejection).  A trial step whose error norm is not finite (overflow) is
+ * rejected with the factor 0.2; MM_ENONFINITE is returned only when the
+ * current state itself holds a NaN or infinity.  *dt <= 0 selects the Hairer-Norsett-Wanner starting step.  m is
+ * updated in place; *t and *dt are advanced.  st may be NULL.  Synchronises
+ * once per step (8 bytes to the host). */
+mm_status mm_llg_step(mm_plan *p, void *m, const double h_ext[3], unsigned terms, double *t,
+                      double *dt, const mm_step_opts *o, mm_step_stats *st);
+
+/* Relaxation (Sec. 3): integrate dm/dt = -gamma/2 m x (m x h) (alpha = 1, no
+ * precession term) with renormalised Dormand-Prince steps at tolerance rtol
+ * until max_i |m_i x h_i| / Ms_i < tol.  Returns MM_ENOTCONV with the last
+ * accepted state in m if max_steps steps do not reach the criterion. */
+mm_status mm_relax(mm_plan *p, void *m, const double h_ext[3], unsigned terms, double tol,
+                   long max_steps, double rtol, mm_step_stats *st);
+
+/* Energies (Sec. 4, Eq. linear_energy_discrete) in J, accumulated in double:
+ * E[0] demag, E[1] exchange, E[2] anisotropy, each -1/2 mu0 V sum Ms m.h_t;
+ * E[3] Zeeman, -mu0 V sum Ms m.H; E[4] total of the terms in `terms`.
+ * Synchronises. */
+mm_status mm_energy(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
+                    double E[5]);
+
+/* max_i |m_i x h_i| / Ms_i over magnetic cells.  Synchronises. */
+mm_status mm_max_torque(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,
+                        double t, double *out);
+
+/* Per-pass timing with HIP events recorded on the plan's stream around every
+ * launch of the field pipeline (diagnostics for roofline measurements).
+ * Passes: x forward transform, y forward transform, last-axis transform with
+ * the spectral product (the hottest pass), y inverse transform, x inverse
+ * transform with the local terms, and the Runge-Kutta vector kernels.
+ * mm_profile(p, 1) clears the totals and starts recording; mm_profile(p, 0)
+ * stops.  mm_profile_read synchronises and returns the summed milliseconds
+ * and launch counts per pass (arrays of MM_NPASS). */
+enum { MM_PASS_X_FWD = 0, MM_PASS_Y_FWD = 1, MM_PASS_MID = 2, MM_PASS_Y_INV = 3,
+       MM_PASS_X_INV_LOCAL = 4, MM_PASS_RK = 5, MM_NPASS = 6 };
+mm_status mm_profile(mm_plan *p, int enable);
+mm_status mm_profile_read(mm_plan *p, double ms[], long count[]);
+
+/* Diagnostics for bit-level tests.  mm_debug_kernel writes the real-space
+ * demag kernel K (h = sum K M) of component s (0..5 = xx,yy,zz,xy,xz,yz) as
+ * placed in the zero-padded grid, Px*Py*Pz doubles with x fastest, into the
+ * device buffer out.  mm_debug_spectrum writes the resident folded spectrum
+ * of component s, (Pz/2+1)*(Py/2+1)*(Px/2+1) doubles with kx fastest,
+ * including the 1/(Px Py Pz) normalisation of the inverse transform. */
+mm_status mm_debug_kernel(mm_plan *p, int s, void *out);
+mm_status mm_debug_spectrum(mm_plan *p, int s, void *out);
+
+/* Thread-local message describing the last failure of this thread. */
+const char *mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

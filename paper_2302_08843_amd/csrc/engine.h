@@ -1,0 +1,127 @@
+// engine.h -- internal plan state and the device-side pipeline of the
+// micromagnetic hot path (not part of the public ABI, see include/mm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+
+namespace mmx {
+
+// Physical constants: mu0 = 4 pi 1e-7 (the paper does not print it) and the
+// reduced gyromagnetic ratio printed with the LLG equation (Sec. 3).
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double kGamma = 2.21e5;
+
+// Largest padded FFT length per axis handled by the kernels.
+constexpr int kMaxFFT = 1024;
+
+constexpr int kRedSlots = 8192;
+
+// Event-based per-pass timing (mm_profile).
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        int pass;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    double ms[MM_NPASS] = {};
+    long cnt[MM_NPASS] = {};
+};
+
+struct Plan {
+    // geometry
+    int n[3];      // nx, ny, nz
+    double d[3];   // dx, dy, dz
+    int P[3];      // padded extents
+    int Hx;        // Px/2 + 1 (1 when Px == 1): x bins kept by the real transform
+    int Hxp;       // row stride of every spectral array (Hx rounded up to 16)
+    long N;        // cells
+    long S1n;      // complex values in S1 = 3 * nz * ny * Hxp
+    long S2n;      // complex values in S2 = 3 * nz * Py * Hxp
+    long Kn;       // reals per spectral-tensor component (Pz/2+1)(Py/2+1) Hxp
+    int Lmax;      // twiddle table length = max(P)
+    // material
+    int prec;      // MM_FP32 / MM_FP64
+    double Ms, A, Ku, alpha;
+    double eu[3];
+    int demag_p;
+    bool percell;  // per-cell Ms present
+    long n_magnetic;  // magnetic cells (Ms > 0)
+    // drive
+    bool drive;
+    double drive_amp[3], drive_freq;
+    hipStream_t stream;
+    // device buffers (element type = plan precision unless noted)
+    void *Khat = nullptr;     // [6][Pz/2+1][Py/2+1][Hxp] real, scaled by 1/(Px Py Pz)
+    void *S1 = nullptr;       // [3][nz][ny][Hxp] complex
+    void *S2 = nullptr;       // [3][nz][Py][Hxp] complex (aliases S1 when Py == 1)
+    void *tw = nullptr;       // Lmax complex roots exp(-2 pi i n / Lmax)
+    void *Ms_cell = nullptr;  // N reals, or null
+    unsigned char *mask = nullptr;  // N bytes drive mask, or null
+    // Runge-Kutta work space (allocated on first use)
+    void *rk = nullptr;       // 10 vectors of 3N
+    double *red = nullptr;    // reduction partials (kRedSlots doubles)
+    double *red_out = nullptr;  // reduction results (8 doubles)
+    double *host_out = nullptr; // pinned host mirror of red_out
+    size_t bytes = 0;
+    Profiler prof;
+};
+
+// Record an event pair around one launch when profiling is on.
+hipError_t prof_begin(Plan &p, int pass, hipEvent_t *a);
+hipError_t prof_end(Plan &p, int pass, hipEvent_t a);
+hipError_t prof_flush(Plan &p);
+
+// Thread-local error message (mm_last_error).
+void set_error(const std::string &msg);
+
+// Device pipeline, instantiated for float and double in kernels.hip.
+template <typename T>
+hipError_t build_tensor(Plan &p);
+template <typename T>
+hipError_t init_twiddles(Plan &p);
+
+// Field / right-hand side evaluation at state m (3N) and time t.
+//   h_out    : effective field (may be null)
+//   dm_out   : LLG right-hand side (may be null), with alpha_eff and precess
+//   torque   : if non-null, per-block maxima of |m x h|/Ms into p.red and the
+//              final maximum into *torque (device double)
+template <typename T>
+hipError_t eval_field(Plan &p, const T *m, const double hext[3], unsigned terms, double t,
+                      T *h_out, T *dm_out, double alpha_eff, bool precess, double *torque);
+
+// y_out = y + h * sum_j a[j] k[j]  (nk <= 7)
+template <typename T>
+hipError_t rk_combine(Plan &p, T *y_out, const T *y, double h, const double *a, T *const *k,
+                      int nk);
+// RMS error norm of e = h sum_j e[j] k[j] scaled by atol + rtol max(|y|,|y1|)
+// over magnetic components into out_dev[0]; the number of non-finite entries
+// of y into out_dev[5].
+template <typename T>
+hipError_t rk_error_norm(Plan &p, const T *y, const T *y1, double h, const double *e,
+                         T *const *k, int nk, double rtol, double atol, double *out_dev);
+// Renormalise |m| = 1 on magnetic cells, zero m on vacuum cells.
+template <typename T>
+hipError_t renormalise(Plan &p, T *m);
+// sum over cells of Ms * (a . b) in double -> *out_dev
+template <typename T>
+hipError_t dot_ms(Plan &p, const T *a, const T *b, double *out_dev);
+// Hairer-Norsett-Wanner starting-step norms: sums of (y/sc)^2, (f/sc)^2 and
+// ((f1 - f0)/sc)^2 with sc = atol + rtol |y|, into out_dev[0..2]
+template <typename T>
+hipError_t start_norms(Plan &p, const T *y, const T *f0, const T *f1, double rtol, double atol,
+                       double *out_dev);
+// Count magnetic cells (Ms > 0) into *out_dev.
+template <typename T>
+hipError_t count_magnetic(Plan &p, double *out_dev);
+// Debug: real-space kernel (component s) placed in the padded grid, doubles.
+hipError_t debug_kernel(Plan &p, int s, double *out);
+template <typename T>
+hipError_t debug_spectrum(Plan &p, int s, double *out);
+
+}  // namespace mmx

@@ -1,0 +1,1199 @@
+// kernels.hip -- device pipeline of the micromagnetic hot path on gfx950.
+//
+// Effective field (Sec. 4) at a state m, one pass per arrow:
+//
+//   m --F1--> S1 --F2--> S2 --F3--> S2 --I2--> S1 --I1--> h (+ dm/dt)
+//
+//   F1  x real-to-complex FFT of M = Ms m with the zero padding implied
+//       (only nx of Px inputs are loaded), per x-row.
+//   F2  y forward FFT (ny of Py inputs nonzero), batched over adjacent kx
+//       columns so every global access is a contiguous run of columns.
+//   F3  z forward FFT, product with the real symmetric 3x3 spectral kernel
+//       (Sec. 4.4: h = N * M becomes a pointwise product after the
+//       transform), z inverse FFT, keep k < nz -- one kernel, in registers.
+//   I2  y inverse FFT, keep j < ny.
+//   I1  x complex-to-real FFT, keep i < nx, then in the same kernel the local
+//       terms: exchange stencil with dm/dn = 0 (Sec. 4.2), uniaxial
+//       anisotropy (Sec. 4.1), Zeeman, and optionally the LLG right-hand side
+//       (Sec. 3, Eq. llg) and the torque maximum used by relaxation.
+//
+// With a single layer (Pz = 1) F2/F3/I2 collapse into one kernel (y forward,
+// product, y inverse).  The 1/(Px Py Pz) of the inverse transform is folded
+// into the resident spectral kernel.  No MFMA: FFTs and stencils are not dense
+// contractions; everything here is VALU + LDS, bounded by HBM traffic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "engine.h"
+#include "fft.h"
+#include "newell.h"
+
+namespace mmx {
+
+// Registers per thread in each kind of pass (complex values).
+template <typename T>
+struct Regs;
+template <>
+struct Regs<float> {
+    static constexpr int x = 32;    // F1 row transforms
+    static constexpr int s = 32;    // strided y passes
+    static constexpr int mid = 16;  // F3: three components resident
+    static constexpr int x1 = 16;   // I1: three components per row
+};
+template <>
+struct Regs<double> {
+    static constexpr int x = 16;
+    static constexpr int s = 16;
+    static constexpr int mid = 8;
+    static constexpr int x1 = 8;
+};
+
+constexpr int kBlock = 256;
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Twiddle table: tw[n] = exp(-2 pi i n / Lmax), rounded from double.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_twiddles(cx<T>* tw, int Lmax)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= Lmax) return;
+    double s, c;
+    sincospi(-2.0 * (double)n / (double)Lmax, &s, &c);
+    tw[n] = {(T)c, (T)s};
+}
+
+// ---------------------------------------------------------------------------
+// F1: x real-to-complex transform of rows of length 2M (M >= 2).
+// Row r of component c reads in[c*in_comp + r*in_row + i] for i < n_in (zero
+// beyond) times Ms, and writes X[k], k = 0..M, to out[c*out_comp + r*out_row].
+// A real transform of length 2M is a complex transform of length M of
+// z[n] = x[2n] + i x[2n+1] followed by the split
+//   X[k] = (Z[k] + conj Z[M-k])/2 - i w^k (Z[k] - conj Z[M-k])/2,
+//   w = exp(-2 pi i/(2M)).
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+struct XR2C {
+    using S = FFTShape<M, Regs<T>::x>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr int kRows = cmax(1, kBlock / kT);
+};
+
+template <typename T, int M, bool PERCELL>
+__global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, long in_row,
+                                                  long in_comp, int n_in,
+                                                  const T* __restrict__ Ms_cell, T Ms,
+                                                  cx<T>* __restrict__ out, long out_row,
+                                                  long out_comp, int nrows, int ncomp,
+                                                  const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = XR2C<T, M>;
+    constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows;
+    __shared__ cx<T> lds[kRows * M];
+    const int t = threadIdx.x % kT, rl = threadIdx.x / kT;
+    const long row = (long)blockIdx.x * kRows + rl;
+    const bool valid = row < (long)nrows * ncomp;
+    const long c = valid ? row / nrows : 0, r = valid ? row % nrows : 0;
+    const T* src = in + c * in_comp + r * in_row;
+    const T* msrc = PERCELL ? Ms_cell + r * in_row : nullptr;
+    cx<T> v[kE];
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+        const int n = t + q * kT;  // first-stage input index
+        const int i0 = 2 * n, i1 = 2 * n + 1;
+        T a = 0, b = 0;
+        if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
+        if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+        v[q] = {a, b};
+    }
+    cx<T>* L = lds + rl * M;
+    WgFFT<T, M, Regs<T>::x, -1>::run(v, t, L, 1, tw, Lmax / M);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q) L[G::S::out_index(t, q)] = v[q];
+    __syncthreads();
+    if (!valid) return;
+    cx<T>* dst = out + c * out_comp + r * out_row;
+    const int tws = Lmax / (2 * M);
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+        const int k = t + q * kT;
+        const cx<T> A = L[k], B = cconj(L[(M - k) & (M - 1)]);
+        const cx<T> S = {(T)0.5 * (A.x + B.x), (T)0.5 * (A.y + B.y)};
+        const cx<T> D = {(T)0.5 * (A.x - B.x), (T)0.5 * (A.y - B.y)};
+        const cx<T> wD = cmul(tw[k * tws], D);
+        dst[k] = {S.x + wD.y, S.y - wD.x};  // S - i wD
+    }
+    if (t == 0) {
+        const cx<T> Z0 = L[0];
+        dst[M] = {Z0.x - Z0.y, (T)0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// F2 / I2 (and the kernel set-up): batched strided complex transforms.
+// A block owns B adjacent columns (contiguous in memory) of one pencil group;
+// element e of column col sits at base + e*es + col.  Loads e < n_in (zeros
+// beyond), stores e < n_out.
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+struct Strided {
+    using S = FFTShape<L, Regs<T>::s>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr int kB = cmin(64, cmax(1, kBlock / kT));
+};
+
+template <typename T, int L, int DIR>
+__global__ __launch_bounds__(kBlock) void k_strided(const cx<T>* in, cx<T>* out, int n_in,
+                                                    int n_out, long es_in, long es_out, int ncols,
+                                                    long g1_in, long g1_out, long g2_in,
+                                                    long g2_out, const cx<T>* __restrict__ tw,
+                                                    int Lmax)
+{
+    using G = Strided<T, L>;
+    constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
+    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * L : 1];
+    const int b = threadIdx.x % kB, t = threadIdx.x / kB;
+    const int col = blockIdx.x * kB + b;
+    const bool cv = col < ncols;
+    const cx<T>* src = in + blockIdx.z * g1_in + blockIdx.y * g2_in + col;
+    cx<T>* dst = out + blockIdx.z * g1_out + blockIdx.y * g2_out + col;
+    cx<T> v[kE];
+#pragma unroll
+    for (int r = 0; r < kE; ++r) {
+        const int e = t + r * kT;
+        v[r] = (cv && e < n_in) ? src[(long)e * es_in] : cx<T>{0, 0};
+    }
+    WgFFT<T, L, Regs<T>::s, DIR>::run(v, t, lds + b, kB, tw, Lmax / L);
+    if (!cv) return;
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+        const int e = G::S::out_index(t, i);
+        if (e < n_out) dst[(long)e * es_out] = v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// F3 (and the single-layer y pass): forward transform of all three
+// components along the last padded axis, product with the folded real
+// spectral kernel, inverse transform, store the first n_valid elements.
+// AXIS = 2: pencils along z, group g = ky.  AXIS = 1: pencils along y (Pz=1).
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+struct Mid {
+    using S = FFTShape<L, Regs<T>::mid>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr int kB = cmin(64, cmax(1, kBlock / kT));
+};
+
+template <typename T, int L, int AXIS>
+__global__ __launch_bounds__(kBlock) void k_mid(cx<T>* S, const T* __restrict__ Khat, int n_valid,
+                                                long es, long cs, long gstride, int ncols, int Py,
+                                                int Pz, long Kn, int Hxp,
+                                                const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = Mid<T, L>;
+    constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
+    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * L : 1];
+    const int b = threadIdx.x % kB, t = threadIdx.x / kB;
+    const int col = blockIdx.x * kB + b;
+    const bool cv = col < ncols;
+    const int g = blockIdx.y;
+    cx<T>* base = S + (long)g * gstride + col;
+    cx<T> v[3][kE];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < kE; ++r) {
+            const int e = t + r * kT;
+            v[c][r] = (cv && e < n_valid) ? base[c * cs + (long)e * es] : cx<T>{0, 0};
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) WgFFT<T, L, Regs<T>::mid, -1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+
+    if (cv) {
+        const int hy = Py / 2, hz = Pz / 2;
+        const long plane = (long)(hy + 1) * Hxp;
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            const int kk = G::S::out_index(t, i);
+            int ky, kz;
+            if constexpr (AXIS == 2) {
+                kz = kk;
+                ky = g;
+            } else {
+                ky = kk;
+                kz = 0;
+            }
+            const bool fy = ky > hy, fz = kz > hz;
+            const int kyf = fy ? Py - ky : ky, kzf = fz ? Pz - kz : kz;
+            const T sy = fy ? (T)-1 : (T)1, sz = fz ? (T)-1 : (T)1;
+            const T* K = Khat + kzf * plane + (long)kyf * Hxp + col;
+            const T kxx = K[0], kyy = K[Kn], kzz = K[2 * Kn];
+            const T kxy = sy * K[3 * Kn], kxz = sz * K[4 * Kn], kyz = sy * sz * K[5 * Kn];
+            const cx<T> mx = v[0][i], my = v[1][i], mz = v[2][i];
+            v[0][i] = {kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y};
+            v[1][i] = {kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y};
+            v[2][i] = {kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y};
+        }
+    }
+    // The forward outputs of thread t are exactly the inverse inputs
+    // t + m*kT; only their register order differs.
+    constexpr int Rl = G::S::kLast;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<T> w[kE];
+#pragma unroll
+        for (int i = 0; i < kE; ++i) w[i / Rl + (i % Rl) * (kE / Rl)] = v[c][i];
+#pragma unroll
+        for (int i = 0; i < kE; ++i) v[c][i] = w[i];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) WgFFT<T, L, Regs<T>::mid, 1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+    if (!cv) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            const int e = G::S::out_index(t, i);
+            if (e < n_valid) base[c * cs + (long)e * es] = v[c][i];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// I1: x complex-to-real transform + local field terms + LLG right-hand side.
+// ---------------------------------------------------------------------------
+struct LocalParams {
+    int nx, ny, nz;
+    long N;
+    long s1_comp;     // nz*ny*Hxp
+    int Hxp;
+    int with_demag, with_exch, with_anis, with_zee;
+    double Ms;        // uniform Ms (ignored with per-cell Ms)
+    double exch;      // 2 A / mu0 (divided by Ms_i per cell)
+    double idx2, idy2, idz2;  // 1/dx^2 ...
+    double anis;      // 2 Ku / mu0 (divided by Ms_i per cell)
+    double eu[3];
+    double H[3];      // uniform external field
+    double Hd[3];     // drive field at time t on masked cells
+    double gp;        // gamma / (1 + alpha^2)
+    double alpha;
+    int precess;
+};
+
+template <typename T, int M>
+struct XC2R {
+    static constexpr int Mf = M > 0 ? M : 1;
+    using S = FFTShape<Mf, Regs<T>::x1>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr int kRows = cmax(1, kBlock / (3 * kT));
+};
+
+__device__ inline void atomic_max_nonneg(double* addr, double v)
+{
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename T, int M, bool PERCELL>
+__global__ __launch_bounds__(kBlock) void k_x_c2r_local(
+    const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
+    T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
+    LocalParams P, double* torque, const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = XC2R<T, M>;
+    constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows, Mf = G::Mf;
+    __shared__ cx<T> lds[kRows * 3 * Mf];
+    const int k = blockIdx.y;
+    const int j0 = blockIdx.x * kRows;
+    const int nx = P.nx, ny = P.ny;
+
+    if constexpr (M >= 2) {
+        if (P.with_demag) {
+            const int t = threadIdx.x % kT;
+            const int c = (threadIdx.x / kT) % 3;
+            const int rl = threadIdx.x / (3 * kT);
+            const int j = j0 + rl;
+            const bool valid = rl < kRows && j < ny;
+            const cx<T>* X = S1 + c * P.s1_comp + ((long)k * ny + (valid ? j : 0)) * P.Hxp;
+            const int tws = Lmax / (2 * M);
+            cx<T> v[kE];
+#pragma unroll
+            for (int r = 0; r < kE; ++r) {
+                const int n = t + r * kT;
+                cx<T> z = {0, 0};
+                if (valid) {
+                    const cx<T> a = X[n], bb = X[M - n];
+                    // 2 Z[n] = (a + conj b) + i w^-n (a - conj b)
+                    const cx<T> D = {a.x - bb.x, a.y + bb.y};
+                    const cx<T> wD = cmulc(D, tw[n * tws]);
+                    z = {a.x + bb.x - wD.y, a.y - bb.y + wD.x};
+                }
+                v[r] = z;
+            }
+            cx<T>* L = lds + (rl * 3 + c) * Mf;
+            WgFFT<T, M, Regs<T>::x1, 1>::run(v, t, L, 1, tw, Lmax / M);
+            __syncthreads();
+            T* hd = reinterpret_cast<T*>(L);
+#pragma unroll
+            for (int i = 0; i < kE; ++i) {
+                const int e = G::S::out_index(t, i);
+                hd[2 * e] = v[i].x;
+                hd[2 * e + 1] = v[i].y;
+            }
+            __syncthreads();
+        }
+    }
+
+    const long N = P.N;
+    const T exch = (T)P.exch, anis = (T)P.anis;
+    const T ix2 = (T)P.idx2, iy2 = (T)P.idy2, iz2 = (T)P.idz2;
+    const T eux = (T)P.eu[0], euy = (T)P.eu[1], euz = (T)P.eu[2];
+    double tmax = 0.0;
+    for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
+        const int rl = idx / nx, i = idx - rl * nx;
+        const int j = j0 + rl;
+        if (j >= ny) continue;
+        const long cell = i + (long)nx * (j + (long)ny * k);
+        const T ms = PERCELL ? Ms_cell[cell] : (T)P.Ms;
+        T hx = 0, hy = 0, hz = 0;
+        const T mx = m[cell], my = m[N + cell], mz = m[2 * N + cell];
+        if (ms != (T)0) {
+            if (P.with_demag) {
+                if constexpr (M >= 2) {
+                    const T* hd = reinterpret_cast<const T*>(lds + rl * 3 * Mf);
+                    hx = hd[i];
+                    hy = hd[2 * Mf + i];
+                    hz = hd[4 * Mf + i];
+                } else {
+                    const cx<T>* X = S1 + ((long)k * ny + j) * P.Hxp;
+                    hx = X[0].x;
+                    hy = X[P.s1_comp].x;
+                    hz = X[2 * P.s1_comp].x;
+                }
+            }
+            const T inv_ms = (T)1 / ms;
+            if (P.with_exch) {
+                T ax = 0, ay = 0, az = 0;
+                auto nb = [&](long q, T w) {
+                    if (PERCELL && Ms_cell[q] == (T)0) return;
+                    ax += w * (m[q] - mx);
+                    ay += w * (m[N + q] - my);
+                    az += w * (m[2 * N + q] - mz);
+                };
+                if (i > 0) nb(cell - 1, ix2);
+                if (i + 1 < nx) nb(cell + 1, ix2);
+                if (j > 0) nb(cell - nx, iy2);
+                if (j + 1 < ny) nb(cell + nx, iy2);
+                if (k > 0) nb(cell - (long)nx * ny, iz2);
+                if (k + 1 < P.nz) nb(cell + (long)nx * ny, iz2);
+                const T ce = exch * inv_ms;
+                hx += ce * ax;
+                hy += ce * ay;
+                hz += ce * az;
+            }
+            if (P.with_anis) {
+                const T ca = anis * inv_ms * (eux * mx + euy * my + euz * mz);
+                hx += ca * eux;
+                hy += ca * euy;
+                hz += ca * euz;
+            }
+            if (P.with_zee) {
+                hx += (T)P.H[0];
+                hy += (T)P.H[1];
+                hz += (T)P.H[2];
+                if (mask && mask[cell]) {
+                    hx += (T)P.Hd[0];
+                    hy += (T)P.Hd[1];
+                    hz += (T)P.Hd[2];
+                }
+            }
+        }
+        if (h_out) {
+            h_out[cell] = hx;
+            h_out[N + cell] = hy;
+            h_out[2 * N + cell] = hz;
+        }
+        // m x h and m x (m x h)
+        const T px = my * hz - mz * hy, py = mz * hx - mx * hz, pz = mx * hy - my * hx;
+        if (dm_out) {
+            const T qx = my * pz - mz * py, qy = mz * px - mx * pz, qz = mx * py - my * px;
+            const T gp = (T)P.gp, al = (T)P.alpha, pf = P.precess ? (T)1 : (T)0;
+            const bool mag = ms != (T)0;
+            dm_out[cell] = mag ? -gp * (pf * px + al * qx) : (T)0;
+            dm_out[N + cell] = mag ? -gp * (pf * py + al * qy) : (T)0;
+            dm_out[2 * N + cell] = mag ? -gp * (pf * pz + al * qz) : (T)0;
+        }
+        if (torque && ms != (T)0) {
+            const double tq = sqrt((double)px * px + (double)py * py + (double)pz * pz) / (double)ms;
+            tmax = tmax > tq ? tmax : tq;
+        }
+    }
+    if (torque) {
+        // wavefront max, then one atomic per wavefront
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_down(tmax, off, 64);
+            tmax = tmax > o ? tmax : o;
+        }
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(torque, tmax);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch helpers (power-of-two lengths 1..1024).
+// ---------------------------------------------------------------------------
+#define MMX_CASES(MACRO) \
+    MACRO(1) MACRO(2) MACRO(4) MACRO(8) MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) \
+    MACRO(512) MACRO(1024)
+
+template <typename T, int L, int DIR>
+static hipError_t launch_strided_L(const Plan& p, const cx<T>* in, cx<T>* out, int n_in, int n_out,
+                                   long es_in, long es_out, int ncols, int G1, long g1_in,
+                                   long g1_out, int G2, long g2_in, long g2_out)
+{
+    using G = Strided<T, L>;
+    dim3 grid((ncols + G::kB - 1) / G::kB, G2, G1);
+    k_strided<T, L, DIR><<<grid, G::kB * G::kT, 0, p.stream>>>(
+        in, out, n_in, n_out, es_in, es_out, ncols, g1_in, g1_out, g2_in, g2_out,
+        (const cx<T>*)p.tw, p.Lmax);
+    return hipGetLastError();
+}
+
+template <typename T, int DIR>
+static hipError_t launch_strided(const Plan& p, int L, const cx<T>* in, cx<T>* out, int n_in,
+                                 int n_out, long es_in, long es_out, int ncols, int G1,
+                                 long g1_in, long g1_out, int G2, long g2_in, long g2_out)
+{
+    switch (L) {
+#define MMX_S(LL)                                                                               \
+    case LL:                                                                                    \
+        return launch_strided_L<T, LL, DIR>(p, in, out, n_in, n_out, es_in, es_out, ncols, G1, \
+                                            g1_in, g1_out, G2, g2_in, g2_out);
+        MMX_CASES(MMX_S)
+#undef MMX_S
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int M, bool PC>
+static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long in_comp, int n_in,
+                                 const T* Ms_cell, T Ms, cx<T>* out, long out_row, long out_comp,
+                                 int nrows, int ncomp);
+
+template <typename T, bool PC>
+static hipError_t launch_x_r2c(const Plan& p, int M, const T* in, long in_row, long in_comp,
+                               int n_in, const T* Ms_cell, T Ms, cx<T>* out, long out_row,
+                               long out_comp, int nrows, int ncomp)
+{
+    switch (M) {
+#define MMX_X(LL)                                                                                 \
+    case LL:                                                                                      \
+        return launch_x_r2c_M<T, LL, PC>(p, in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, \
+                                         out_comp, nrows, ncomp);
+        MMX_X(0) MMX_CASES(MMX_X)
+#undef MMX_X
+    }
+    return hipErrorInvalidValue;
+}
+
+// Px == 1: the x transform of a single cell is the cell value itself.
+template <typename T, bool PERCELL>
+__global__ void k_x_copy(const T* __restrict__ in, long in_row, long in_comp, int n_in,
+                         const T* __restrict__ Ms_cell, T Ms, cx<T>* __restrict__ out, long out_row,
+                         long out_comp, int nrows, int ncomp)
+{
+    const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= (long)nrows * ncomp) return;
+    const long c = row / nrows, r = row % nrows;
+    T a = n_in > 0 ? in[c * in_comp + r * in_row] * (PERCELL ? Ms_cell[r * in_row] : Ms) : (T)0;
+    out[c * out_comp + r * out_row] = {a, (T)0};
+}
+
+template <typename T, int M, bool PC>
+static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long in_comp, int n_in,
+                                 const T* Ms_cell, T Ms, cx<T>* out, long out_row, long out_comp,
+                                 int nrows, int ncomp)
+{
+    const long rows = (long)nrows * ncomp;
+    if constexpr (M == 0 || M == 1) {
+        k_x_copy<T, PC><<<(rows + 255) / 256, 256, 0, p.stream>>>(in, in_row, in_comp, n_in, Ms_cell,
+                                                                   Ms, out, out_row, out_comp,
+                                                                   nrows, ncomp);
+    } else {
+        using G = XR2C<T, M>;
+        k_x_r2c<T, M, PC><<<(rows + G::kRows - 1) / G::kRows, G::kRows * G::kT, 0, p.stream>>>(
+            in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
+            (const cx<T>*)p.tw, p.Lmax);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int L, int AXIS>
+static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, long cs,
+                               long gstride, int G)
+{
+    using Gm = Mid<T, L>;
+    dim3 grid((p.Hx + Gm::kB - 1) / Gm::kB, G);
+    k_mid<T, L, AXIS><<<grid, Gm::kB * Gm::kT, 0, p.stream>>>(
+        S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, p.P[1], p.P[2], p.Kn, p.Hxp,
+        (const cx<T>*)p.tw, p.Lmax);
+    return hipGetLastError();
+}
+
+template <typename T, int AXIS>
+static hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long es, long cs,
+                             long gstride, int G)
+{
+    switch (L) {
+#define MMX_M(LL) \
+    case LL: return launch_mid_L<T, LL, AXIS>(p, S, n_valid, es, cs, gstride, G);
+        MMX_CASES(MMX_M)
+#undef MMX_M
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int M, bool PC>
+static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
+                                 double* torque)
+{
+    using G = XC2R<T, M>;
+    dim3 grid((p.n[1] + G::kRows - 1) / G::kRows, p.n[2]);
+    k_x_c2r_local<T, M, PC><<<grid, G::kRows * 3 * G::kT, 0, p.stream>>>(
+        (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque,
+        (const cx<T>*)p.tw, p.Lmax);
+    return hipGetLastError();
+}
+
+template <typename T, bool PC>
+static hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
+                               const LocalParams& P, double* torque)
+{
+    switch (M) {
+#define MMX_L(LL) \
+    case LL: return launch_local_M<T, LL, PC>(p, m, h, dm, P, torque);
+        MMX_L(0) MMX_CASES(MMX_L)
+#undef MMX_L
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Small vector kernels and deterministic reductions.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 512;
+
+__device__ inline double block_sum(double v)
+{
+    __shared__ double wsum[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int w = threadIdx.x / 64, l = threadIdx.x & 63;
+    if (l == 0) wsum[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) s += wsum[i];
+    }
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// out[slot] = sum over partials[0..n) in a fixed order (one block).
+__global__ void k_final_sum(const double* __restrict__ partials, int n, double* out, int slot,
+                            double scale, int do_sqrt)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) {
+        v *= scale;
+        out[slot] = do_sqrt ? sqrt(v) : v;
+    }
+}
+
+__global__ void k_fill(double* p, int n, double v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+struct Coef7 {
+    double c[7];
+};
+
+template <typename T>
+__global__ void k_rk_combine(T* __restrict__ y_out, const T* __restrict__ y, Coef7 cf,
+                             const T* k0, const T* k1, const T* k2, const T* k3, const T* k4,
+                             const T* k5, const T* k6, int nk, long n3)
+{
+    const T* ks[7] = {k0, k1, k2, k3, k4, k5, k6};
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n3;
+         q += (long)gridDim.x * blockDim.x) {
+        T acc = y[q];
+        for (int j = 0; j < nk; ++j)
+            if (cf.c[j] != 0.0) acc += (T)cf.c[j] * ks[j][q];
+        y_out[q] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
+                                                     const T* __restrict__ y1, Coef7 cf,
+                                                     const T* k0, const T* k1, const T* k2,
+                                                     const T* k3, const T* k4, const T* k5,
+                                                     const T* k6, int nk, long N,
+                                                     const T* __restrict__ Ms_cell, double rtol,
+                                                     double atol, double* partials)
+{
+    const T* ks[7] = {k0, k1, k2, k3, k4, k5, k6};
+    double acc = 0.0, bad = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * N;
+         q += (long)gridDim.x * blockDim.x) {
+        if (!isfinite((double)y[q])) bad += 1.0;
+        if (Ms_cell && Ms_cell[q % N] == (T)0) continue;
+        double e = 0.0;
+        for (int j = 0; j < nk; ++j)
+            if (cf.c[j] != 0.0) e += cf.c[j] * (double)ks[j][q];
+        const double a = fabs((double)y[q]), b = fabs((double)y1[q]);
+        const double sc = atol + rtol * (a > b ? a : b);
+        const double r = e / sc;
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    bad = block_sum(bad);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc;
+        partials[kRedBlocks + blockIdx.x] = bad;
+    }
+}
+
+template <typename T>
+__global__ void k_renorm(T* __restrict__ m, const T* __restrict__ Ms_cell, long N)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        if (Ms_cell && Ms_cell[q] == (T)0) {
+            m[q] = m[N + q] = m[2 * N + q] = (T)0;
+            continue;
+        }
+        const T x = m[q], y = m[N + q], z = m[2 * N + q];
+        const T inv = (T)1 / sqrt(x * x + y * y + z * z);
+        m[q] = x * inv;
+        m[N + q] = y * inv;
+        m[2 * N + q] = z * inv;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot_ms(const T* __restrict__ a, const T* __restrict__ b,
+                                                   const T* __restrict__ Ms_cell, double Ms,
+                                                   long N, double* partials)
+{
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        const double ms = Ms_cell ? (double)Ms_cell[q] : Ms;
+        acc += ms * ((double)a[q] * b[q] + (double)a[N + q] * b[N + q] +
+                     (double)a[2 * N + q] * b[2 * N + q]);
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start_norms(const T* __restrict__ y,
+                                                        const T* __restrict__ f0,
+                                                        const T* __restrict__ f1,
+                                                        const T* __restrict__ Ms_cell, long N,
+                                                        double rtol, double atol,
+                                                        double* partials)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * N;
+         q += (long)gridDim.x * blockDim.x) {
+        if (Ms_cell && Ms_cell[q % N] == (T)0) continue;
+        const double sc = atol + rtol * fabs((double)y[q]);
+        const double a = (double)y[q] / sc, b = (double)f0[q] / sc;
+        s0 += a * a;
+        s1 += b * b;
+        if (f1) {
+            const double c = ((double)f1[q] - (double)f0[q]) / sc;
+            s2 += c * c;
+        }
+    }
+    s0 = block_sum(s0);
+    s1 = block_sum(s1);
+    s2 = block_sum(s2);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = s0;
+        partials[kRedBlocks + blockIdx.x] = s1;
+        partials[2 * kRedBlocks + blockIdx.x] = s2;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_count_mag(const T* __restrict__ Ms_cell, long N,
+                                                      double* partials)
+{
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x)
+        acc += Ms_cell[q] != (T)0 ? 1.0 : 0.0;
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Demag kernel set-up (once per plan).
+// ---------------------------------------------------------------------------
+// Near field: -N_Newell for offsets 0 <= I < nI etc., all six components,
+// in double-double (rounded to double at the end).
+__global__ void k_near(double* __restrict__ near, int nI, int nJ, int nK, double dx, double dy,
+                       double dz)
+{
+    const long total = 6L * nI * nJ * nK;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int s = (int)(q / ((long)nI * nJ * nK));
+    const long o = q % ((long)nI * nJ * nK);
+    const int I = (int)(o % nI), J = (int)((o / nI) % nJ), K = (int)(o / ((long)nI * nJ));
+    near[q] = kernel_near(s, I, J, K, dx, dy, dz);
+}
+
+// Place component s into the zero-padded real grid: entry (pi, pj, pk) holds
+// K(I, J, K) with I = pi (pi < nx) or pi - Px (pi > Px - nx), else zero.
+__global__ void k_place(double* __restrict__ R, int s, int nx, int ny, int nz, int Px, int Py,
+                        int Pz, const double* __restrict__ near, int nI, int nJ, int nK, int p,
+                        double dx, double dy, double dz)
+{
+    const long total = (long)Px * Py * Pz;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int pi = (int)(q % Px), pj = (int)((q / Px) % Py), pk = (int)(q / ((long)Px * Py));
+    auto off = [](int pp, int n, int P, int& o) {
+        if (pp < n) { o = pp; return true; }
+        if (pp > P - n) { o = pp - P; return true; }
+        return false;
+    };
+    int I, J, K;
+    double v = 0.0;
+    if (off(pi, nx, Px, I) && off(pj, ny, Py, J) && off(pk, nz, Pz, K)) {
+        const int aI = I < 0 ? -I : I, aJ = J < 0 ? -J : J, aK = K < 0 ? -K : K;
+        int cheb = aI > aJ ? aI : aJ;
+        cheb = cheb > aK ? cheb : aK;
+        if (p < 0 || cheb <= p) {
+            double sg = 1.0;
+            if (s == 3) sg = ((I < 0) != (J < 0)) ? -1.0 : 1.0;
+            if (s == 4) sg = ((I < 0) != (K < 0)) ? -1.0 : 1.0;
+            if (s == 5) sg = ((J < 0) != (K < 0)) ? -1.0 : 1.0;
+            v = sg * near[(((long)s * nK + aK) * nJ + aJ) * nI + aI];
+        } else {
+            v = kernel_dipole(s, I, J, K, dx, dy, dz);
+        }
+    }
+    R[q] = v;
+}
+
+// Keep the real part of the transformed component (it is real by parity) for
+// 0 <= ky <= Py/2, 0 <= kz <= Pz/2, scaled by 1/(Px Py Pz).
+template <typename T>
+__global__ void k_fold(T* __restrict__ Khat, const cx<double>* __restrict__ C, int Hx, int Hxp,
+                       int Py, int Pz, double scale)
+{
+    const int hy = Py / 2 + 1, hz = Pz / 2 + 1;
+    const long total = (long)hz * hy * Hxp;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int kx = (int)(q % Hxp), ky = (int)((q / Hxp) % hy), kz = (int)(q / ((long)Hxp * hy));
+    Khat[q] = kx < Hx ? (T)(C[((long)kz * Py + ky) * Hxp + kx].x * scale) : (T)0;
+}
+
+#define MMX_TRY_PROF(x)                   \
+    do {                                  \
+        hipError_t e__ = (x);             \
+        if (e__ != hipSuccess) return e__; \
+    } while (0)
+
+#define MMX_TRY(x)                        \
+    do {                                  \
+        hipError_t e__ = (x);             \
+        if (e__ != hipSuccess) return e__; \
+    } while (0)
+
+static long blocks_for(long n, int bs) { return (n + bs - 1) / bs; }
+
+// ---------------------------------------------------------------------------
+// Per-pass event timing (mm_profile).
+// ---------------------------------------------------------------------------
+static hipError_t take_event(Plan& p, hipEvent_t* e)
+{
+    if (!p.prof.pool.empty()) {
+        *e = p.prof.pool.back();
+        p.prof.pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+hipError_t prof_flush(Plan& p)
+{
+    if (p.prof.pending.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return e;
+    for (auto& r : p.prof.pending) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return e;
+        p.prof.ms[r.pass] += ms;
+        p.prof.cnt[r.pass] += 1;
+        p.prof.pool.push_back(r.a);
+        p.prof.pool.push_back(r.b);
+    }
+    p.prof.pending.clear();
+    return hipSuccess;
+}
+
+hipError_t prof_begin(Plan& p, int pass, hipEvent_t* a)
+{
+    (void)pass;
+    if (!p.prof.on) return hipSuccess;
+    hipError_t e = take_event(p, a);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(*a, p.stream);
+}
+
+hipError_t prof_end(Plan& p, int pass, hipEvent_t a)
+{
+    if (!p.prof.on) return hipSuccess;
+    hipEvent_t b;
+    hipError_t e = take_event(p, &b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, p.stream);
+    if (e != hipSuccess) return e;
+    p.prof.pending.push_back({pass, a, b});
+    if (p.prof.pending.size() >= 4096) return prof_flush(p);
+    return hipSuccess;
+}
+
+// Launch `body` between a pair of profiling events for `pass`.
+template <typename F>
+static hipError_t timed(Plan& p, int pass, F&& body)
+{
+    hipEvent_t a = nullptr;
+    MMX_TRY_PROF(prof_begin(p, pass, &a));
+    MMX_TRY_PROF(body());
+    return prof_end(p, pass, a);
+}
+
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch()
+    {
+        for (void* q : ptrs) (void)hipFree(q);
+    }
+    template <typename U>
+    hipError_t get(U** out, size_t bytes)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+        if (e != hipSuccess) return e;
+        ptrs.push_back(q);
+        *out = static_cast<U*>(q);
+        return hipSuccess;
+    }
+};
+
+template <typename T>
+hipError_t init_twiddles(Plan& p)
+{
+    k_twiddles<T><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>((cx<T>*)p.tw, p.Lmax);
+    return hipGetLastError();
+}
+
+static hipError_t near_table(Plan& p, Scratch& sc, double** near, int& nI, int& nJ, int& nK)
+{
+    const int lim = p.demag_p < 0 ? (1 << 30) : p.demag_p;
+    nI = std::min(p.n[0] - 1, lim) + 1;
+    nJ = std::min(p.n[1] - 1, lim) + 1;
+    nK = std::min(p.n[2] - 1, lim) + 1;
+    const long total = 6L * nI * nJ * nK;
+    MMX_TRY(sc.get(near, sizeof(double) * total));
+    k_near<<<blocks_for(total, 64), 64, 0, p.stream>>>(*near, nI, nJ, nK, p.d[0], p.d[1], p.d[2]);
+    return hipGetLastError();
+}
+
+hipError_t debug_kernel(Plan& p, int s, double* out)
+{
+    Scratch sc;
+    double* near;
+    int nI, nJ, nK;
+    MMX_TRY(near_table(p, sc, &near, nI, nJ, nK));
+    const long PN = (long)p.P[0] * p.P[1] * p.P[2];
+    k_place<<<blocks_for(PN, 256), 256, 0, p.stream>>>(out, s, p.n[0], p.n[1], p.n[2], p.P[0],
+                                                      p.P[1], p.P[2], near, nI, nJ, nK,
+                                                      p.demag_p, p.d[0], p.d[1], p.d[2]);
+    MMX_TRY(hipGetLastError());
+    return hipStreamSynchronize(p.stream);
+}
+
+template <typename T>
+hipError_t build_tensor(Plan& p)
+{
+    Scratch sc;
+    double* near;
+    int nI, nJ, nK;
+    MMX_TRY(near_table(p, sc, &near, nI, nJ, nK));
+    const int Px = p.P[0], Py = p.P[1], Pz = p.P[2];
+    const long PN = (long)Px * Py * Pz;
+    double* R;
+    cx<double>* C;
+    cx<double>* tw64;
+    MMX_TRY(sc.get(&R, sizeof(double) * PN));
+    MMX_TRY(sc.get(&C, sizeof(cx<double>) * (long)Pz * Py * p.Hxp));
+    MMX_TRY(sc.get(&tw64, sizeof(cx<double>) * p.Lmax));
+    k_twiddles<double><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>(tw64, p.Lmax);
+    MMX_TRY(hipGetLastError());
+    // the FFT launchers read the twiddles from the plan: point them at the
+    // double table while the kernel is transformed
+    Plan q = p;
+    q.tw = tw64;
+    for (int s = 0; s < 6; ++s) {
+        k_place<<<blocks_for(PN, 256), 256, 0, p.stream>>>(R, s, p.n[0], p.n[1], p.n[2], Px, Py, Pz,
+                                                          near, nI, nJ, nK, p.demag_p, p.d[0],
+                                                          p.d[1], p.d[2]);
+        MMX_TRY(hipGetLastError());
+        // x: real rows of length Px -> Hx bins
+        MMX_TRY((launch_x_r2c<double, false>(q, Px / 2, R, Px, 0, Px, nullptr, 1.0, C, p.Hxp, 0,
+                                             Py * Pz, 1)));
+        // y: in place, pencils along ky (stride Hxp), groups kz
+        if (Py > 1)
+            MMX_TRY((launch_strided<double, -1>(q, Py, C, C, Py, Py, p.Hxp, p.Hxp, p.Hx, 1, 0, 0,
+                                                Pz, (long)Py * p.Hxp, (long)Py * p.Hxp)));
+        // z: in place, pencils along kz (stride Py Hxp), groups ky
+        if (Pz > 1)
+            MMX_TRY((launch_strided<double, -1>(q, Pz, C, C, Pz, Pz, (long)Py * p.Hxp,
+                                                (long)Py * p.Hxp, p.Hx, 1, 0, 0, Py, p.Hxp,
+                                                p.Hxp)));
+        k_fold<T><<<blocks_for(p.Kn, 256), 256, 0, p.stream>>>(
+            (T*)p.Khat + s * p.Kn, C, p.Hx, p.Hxp, Py, Pz, 1.0 / (double)PN);
+        MMX_TRY(hipGetLastError());
+    }
+    return hipStreamSynchronize(p.stream);
+}
+
+template <typename T>
+__global__ void k_to_double(const T* in, double* out, long n, int Hx, int Hxp)
+{
+    // drop the row padding: (rows x Hxp) -> (rows x Hx)
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const long row = q / Hx, kx = q % Hx;
+    out[q] = (double)in[row * Hxp + kx];
+}
+
+template <typename T>
+hipError_t debug_spectrum(Plan& p, int s, double* out)
+{
+    const long rows = p.Kn / p.Hxp;
+    const long n = rows * p.Hx;
+    k_to_double<T><<<blocks_for(n, 256), 256, 0, p.stream>>>((const T*)p.Khat + s * p.Kn, out, n,
+                                                            p.Hx, p.Hxp);
+    MMX_TRY(hipGetLastError());
+    return hipStreamSynchronize(p.stream);
+}
+
+// ---------------------------------------------------------------------------
+// Field evaluation.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
+                      T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
+{
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int Px = p.P[0], Py = p.P[1], Pz = p.P[2];
+    const int M = Px / 2;
+    const long s1c = (long)nz * ny * p.Hxp;
+    cx<T>* S1 = (cx<T>*)p.S1;
+    cx<T>* S2 = (cx<T>*)p.S2;
+    const bool pc = p.percell;
+    if (terms & MM_DEMAG) {
+        MMX_TRY(timed(p, MM_PASS_X_FWD, [&] {
+            return pc ? launch_x_r2c<T, true>(p, M, m, nx, p.N, nx, (const T*)p.Ms_cell, (T)p.Ms,
+                                              S1, p.Hxp, s1c, ny * nz, 3)
+                      : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, (T)p.Ms, S1, p.Hxp,
+                                               s1c, ny * nz, 3);
+        }));
+        if (Pz > 1) {
+            const long s2c = (long)nz * Py * p.Hxp;
+            if (Py > 1)
+                MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
+                    return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c,
+                                                 s2c, nz, (long)ny * p.Hxp, (long)Py * p.Hxp);
+                }));
+            MMX_TRY(timed(p, MM_PASS_MID, [&] {
+                return launch_mid<T, 2>(p, Pz, S2, nz, (long)Py * p.Hxp, s2c, p.Hxp, Py);
+            }));
+            if (Py > 1)
+                MMX_TRY(timed(p, MM_PASS_Y_INV, [&] {
+                    return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c,
+                                                s1c, nz, (long)Py * p.Hxp, (long)ny * p.Hxp);
+                }));
+        } else {
+            MMX_TRY(timed(p, MM_PASS_MID, [&] {
+                return launch_mid<T, 1>(p, Py, S1, ny, p.Hxp, s1c, 0, 1);
+            }));
+        }
+    }
+    LocalParams P;
+    P.nx = nx;
+    P.ny = ny;
+    P.nz = nz;
+    P.N = p.N;
+    P.s1_comp = s1c;
+    P.Hxp = p.Hxp;
+    P.with_demag = (terms & MM_DEMAG) ? 1 : 0;
+    P.with_exch = (terms & MM_EXCH) && p.A != 0.0 ? 1 : 0;
+    P.with_anis = (terms & MM_ANIS) && p.Ku != 0.0 ? 1 : 0;
+    P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
+    P.Ms = p.Ms;
+    P.exch = 2.0 * p.A / kMu0;
+    P.idx2 = 1.0 / (p.d[0] * p.d[0]);
+    P.idy2 = 1.0 / (p.d[1] * p.d[1]);
+    P.idz2 = 1.0 / (p.d[2] * p.d[2]);
+    P.anis = 2.0 * p.Ku / kMu0;
+    for (int a = 0; a < 3; ++a) {
+        P.eu[a] = p.eu[a];
+        P.H[a] = hext ? hext[a] : 0.0;
+        P.Hd[a] = 0.0;
+    }
+    if (p.drive && p.mask) {
+        const double s = sin(2.0 * M_PI * p.drive_freq * t);
+        for (int a = 0; a < 3; ++a) P.Hd[a] = p.drive_amp[a] * s;
+    }
+    P.gp = kGamma / (1.0 + alpha_eff * alpha_eff);
+    P.alpha = alpha_eff;
+    P.precess = precess ? 1 : 0;
+    if (torque) {
+        k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
+        MMX_TRY(hipGetLastError());
+    }
+    return timed(p, MM_PASS_X_INV_LOCAL, [&] {
+        return pc ? launch_local<T, true>(p, M, m, h_out, dm_out, P, torque)
+                  : launch_local<T, false>(p, M, m, h_out, dm_out, P, torque);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Runge-Kutta helpers.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, T* const* k, int nk)
+{
+    Coef7 cf{};
+    const T* ks[7] = {};
+    for (int j = 0; j < nk; ++j) {
+        cf.c[j] = h * a[j];
+        ks[j] = k[j];
+    }
+    const long n3 = 3 * p.N;
+    const int blocks = (int)std::min<long>(blocks_for(n3, 256), 4096);
+    return timed(p, MM_PASS_RK, [&] {
+        k_rk_combine<T><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks[0], ks[1], ks[2], ks[3],
+                                                      ks[4], ks[5], ks[6], nk, n3);
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const double* e, T* const* k,
+                         int nk, double rtol, double atol, double* out_dev)
+{
+    Coef7 cf{};
+    const T* ks[7] = {};
+    for (int j = 0; j < nk; ++j) {
+        cf.c[j] = h * e[j];
+        ks[j] = k[j];
+    }
+    MMX_TRY(timed(p, MM_PASS_RK, [&] {
+        k_err_norm<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
+            y, y1, cf, ks[0], ks[1], ks[2], ks[3], ks[4], ks[5], ks[6], nk, p.N,
+            p.percell ? (const T*)p.Ms_cell : nullptr, rtol, atol, p.red);
+        return hipGetLastError();
+    }));
+    const double cnt = 3.0 * (double)p.n_magnetic;
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0,
+                                            cnt > 0 ? 1.0 / cnt : 0.0, 1);
+    MMX_TRY(hipGetLastError());
+    // out_dev[5]: number of non-finite entries of the current state y
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + kRedBlocks, kRedBlocks, out_dev, 5, 1.0, 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t renormalise(Plan& p, T* m)
+{
+    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    k_renorm<T><<<blocks, 256, 0, p.stream>>>(m, p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dot_ms(Plan& p, const T* a, const T* b, double* out_dev)
+{
+    k_dot_ms<T><<<kRedBlocks, kBlock, 0, p.stream>>>(a, b, p.percell ? (const T*)p.Ms_cell : nullptr,
+                                                     p.Ms, p.N, p.red);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t start_norms(Plan& p, const T* y, const T* f0, const T* f1, double rtol, double atol,
+                       double* out_dev)
+{
+    k_start_norms<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
+        y, f0, f1, p.percell ? (const T*)p.Ms_cell : nullptr, p.N, rtol, atol, p.red);
+    MMX_TRY(hipGetLastError());
+    for (int i = 0; i < 3; ++i) {
+        k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + i * kRedBlocks, kRedBlocks, out_dev, i, 1.0,
+                                                0);
+        MMX_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t count_magnetic(Plan& p, double* out_dev)
+{
+    k_count_mag<T><<<kRedBlocks, kBlock, 0, p.stream>>>((const T*)p.Ms_cell, p.N, p.red);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
+    return hipGetLastError();
+}
+
+#define MMX_INST(T)                                                                              \
+    template hipError_t build_tensor<T>(Plan&);                                                  \
+    template hipError_t init_twiddles<T>(Plan&);                                                 \
+    template hipError_t eval_field<T>(Plan&, const T*, const double*, unsigned, double, T*, T*, \
+                                      double, bool, double*);                                    \
+    template hipError_t rk_combine<T>(Plan&, T*, const T*, double, const double*, T* const*,     \
+                                      int);                                                      \
+    template hipError_t rk_error_norm<T>(Plan&, const T*, const T*, double, const double*,       \
+                                         T* const*, int, double, double, double*);               \
+    template hipError_t renormalise<T>(Plan&, T*);                                               \
+    template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*);                           \
+    template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \
+                                       double*);                                                 \
+    template hipError_t count_magnetic<T>(Plan&, double*);                                       \
+    template hipError_t debug_spectrum<T>(Plan&, int, double*);
+
+MMX_INST(float)
+MMX_INST(double)
+
+}  // namespace mmx

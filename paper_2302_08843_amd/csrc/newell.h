@@ -1,0 +1,148 @@
+// newell.h -- the demag kernel of Sec. 4.4 in double-double arithmetic.
+//
+// Near field: the cell-averaged tensor of Newell, Williams & Dunlop (1993),
+// built from the auxiliary functions f (for the diagonal) and g (for the off
+// diagonal) through a 27-point second-difference stencil with weights
+// 2 (zero shift) / -1 (+-1 shift) per axis, divided by 4 pi dx dy dz.  The
+// stencil cancels ~R^6-fold at distance R cells, so f and g are evaluated in
+// double-double and only the final entry is rounded to double.
+// Far field: the point dipole of Eq. (dipole) with moment V Ms m.
+// The demag kernel K (h = K M) is -N in the near field.
+#pragma once
+#include "dd.h"
+
+#pragma clang fp contract(off)
+
+namespace mmx {
+
+// Newell f, even in every argument; x, y, z >= 0.
+__host__ __device__ inline dd newell_f(dd x, dd y, dd z)
+{
+    dd x2 = dd_mul(x, x), y2 = dd_mul(y, y), z2 = dd_mul(z, z);
+    dd R2 = dd_add(dd_add(x2, y2), z2);
+    if (R2.hi == 0.0) return dd_from(0.0);
+    dd R = dd_sqrt(R2);
+    // (2x^2 - y^2 - z^2) R / 6
+    dd s = dd_div_d(dd_mul(dd_sub(dd_sub(dd_mul_d(x2, 2.0), y2), z2), R), 6.0);
+    dd xz2 = dd_add(x2, z2);
+    if (xz2.hi > 0.0) {  // y/2 (z^2 - x^2) asinh(y / sqrt(x^2 + z^2))
+        dd a = dd_asinh_pos(dd_div(y, dd_sqrt(xz2)));
+        s = dd_add(s, dd_mul(dd_mul_d(dd_mul(y, dd_sub(z2, x2)), 0.5), a));
+    }
+    dd xy2 = dd_add(x2, y2);
+    if (xy2.hi > 0.0) {  // z/2 (y^2 - x^2) asinh(z / sqrt(x^2 + y^2))
+        dd a = dd_asinh_pos(dd_div(z, dd_sqrt(xy2)));
+        s = dd_add(s, dd_mul(dd_mul_d(dd_mul(z, dd_sub(y2, x2)), 0.5), a));
+    }
+    if (x.hi > 0.0) {  // - x y z atan(y z / (x R))
+        dd xyz = dd_mul(dd_mul(x, y), z);
+        dd a = dd_atan(dd_div(dd_mul(y, z), dd_mul(x, R)));
+        s = dd_sub(s, dd_mul(xyz, a));
+    }
+    return s;
+}
+
+// Newell g for x, y, z >= 0 (the caller applies the odd parity in x and y).
+__host__ __device__ inline dd newell_g(dd x, dd y, dd z)
+{
+    dd x2 = dd_mul(x, x), y2 = dd_mul(y, y), z2 = dd_mul(z, z);
+    dd R2 = dd_add(dd_add(x2, y2), z2);
+    if (R2.hi == 0.0) return dd_from(0.0);
+    dd R = dd_sqrt(R2);
+    dd s = dd_neg(dd_div_d(dd_mul(dd_mul(x, y), R), 3.0));  // - x y R / 3
+    dd xy2 = dd_add(x2, y2);
+    if (xy2.hi > 0.0)  // x y z asinh(z / sqrt(x^2 + y^2))
+        s = dd_add(s, dd_mul(dd_mul(dd_mul(x, y), z), dd_asinh_pos(dd_div(z, dd_sqrt(xy2)))));
+    dd yz2 = dd_add(y2, z2);
+    if (yz2.hi > 0.0) {  // y/6 (3 z^2 - y^2) asinh(x / sqrt(y^2 + z^2))
+        dd c = dd_div_d(dd_mul(y, dd_sub(dd_mul_d(z2, 3.0), y2)), 6.0);
+        s = dd_add(s, dd_mul(c, dd_asinh_pos(dd_div(x, dd_sqrt(yz2)))));
+    }
+    dd xz2 = dd_add(x2, z2);
+    if (xz2.hi > 0.0) {  // x/6 (3 z^2 - x^2) asinh(y / sqrt(x^2 + z^2))
+        dd c = dd_div_d(dd_mul(x, dd_sub(dd_mul_d(z2, 3.0), x2)), 6.0);
+        s = dd_add(s, dd_mul(c, dd_asinh_pos(dd_div(y, dd_sqrt(xz2)))));
+    }
+    if (z.hi > 0.0) {  // - z^3/6 atan(x y / (z R))
+        dd c = dd_div_d(dd_mul(z, z2), 6.0);
+        s = dd_sub(s, dd_mul(c, dd_atan(dd_div(dd_mul(x, y), dd_mul(z, R)))));
+    }
+    if (y.hi > 0.0) {  // - z y^2/2 atan(x z / (y R))
+        dd c = dd_mul_d(dd_mul(z, y2), 0.5);
+        s = dd_sub(s, dd_mul(c, dd_atan(dd_div(dd_mul(x, z), dd_mul(y, R)))));
+    }
+    if (x.hi > 0.0) {  // - z x^2/2 atan(y z / (x R))
+        dd c = dd_mul_d(dd_mul(z, x2), 0.5);
+        s = dd_sub(s, dd_mul(c, dd_atan(dd_div(dd_mul(y, z), dd_mul(x, R)))));
+    }
+    return s;
+}
+
+// Stencil sum for one tensor component.  (I, J, K) is the cell offset along
+// the component's own axis order, (a, b, c) the matching cell sizes; which = 0
+// uses f, 1 uses g.  Returns N (positive self term).
+__host__ __device__ inline double newell_component(int which, int I, int J, int K, double a,
+                                                   double b, double c)
+{
+    dd acc = dd_from(0.0);
+    for (int e1 = -1; e1 <= 1; ++e1)
+        for (int e2 = -1; e2 <= 1; ++e2)
+            for (int e3 = -1; e3 <= 1; ++e3) {
+                const double w = (e1 == 0 ? 2.0 : -1.0) * (e2 == 0 ? 2.0 : -1.0) *
+                                 (e3 == 0 ? 2.0 : -1.0);
+                int u = I + e1, v = J + e2, q = K + e3;
+                double sg = 1.0;
+                if (which == 1) {  // g is odd in its first two arguments
+                    if (u < 0) { u = -u; sg = -sg; }
+                    if (v < 0) { v = -v; sg = -sg; }
+                } else {
+                    u = u < 0 ? -u : u;
+                    v = v < 0 ? -v : v;
+                }
+                q = q < 0 ? -q : q;
+                // the coordinates (integer) * (cell size) are exact in double-double
+                dd X = two_prod((double)u, a), Y = two_prod((double)v, b), Z = two_prod((double)q, c);
+                dd val = which == 0 ? newell_f(X, Y, Z) : newell_g(X, Y, Z);
+                acc = dd_add(acc, dd_mul_d(val, w * sg));
+            }
+    dd den = dd_mul_d(dd_mul_d(dd_mul_d(dd_mul_d(dd_pi(), 4.0), a), b), c);
+    dd r = dd_div(acc, den);
+    return r.hi + r.lo;
+}
+
+// Demag kernel entry K_s (h = K M) for offset (I, J, K) >= 0 in cells, near
+// field: -N.  s = 0..5 -> xx, yy, zz, xy, xz, yz.
+__host__ __device__ inline double kernel_near(int s, int I, int J, int K, double dx, double dy,
+                                              double dz)
+{
+    switch (s) {
+    case 0: return -newell_component(0, I, J, K, dx, dy, dz);
+    case 1: return -newell_component(0, J, I, K, dy, dx, dz);
+    case 2: return -newell_component(0, K, J, I, dz, dy, dx);
+    case 3: return -newell_component(1, I, J, K, dx, dy, dz);
+    case 4: return -newell_component(1, I, K, J, dx, dz, dy);
+    default: return -newell_component(1, J, K, I, dy, dz, dx);
+    }
+}
+
+// Far field: point dipole (Eq. dipole), h = V/(4 pi) (3 r (M.r) - r^2 M) / r^5.
+__host__ __device__ inline double kernel_dipole(int s, int I, int J, int K, double dx, double dy,
+                                                double dz)
+{
+    const double rx = I * dx, ry = J * dy, rz = K * dz;
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double pre = dx * dy * dz / (4.0 * M_PI) / (r2 * r2 * sqrt(r2));
+    switch (s) {
+    case 0: return pre * (3.0 * rx * rx - r2);
+    case 1: return pre * (3.0 * ry * ry - r2);
+    case 2: return pre * (3.0 * rz * rz - r2);
+    case 3: return pre * 3.0 * rx * ry;
+    case 4: return pre * 3.0 * rx * rz;
+    default: return pre * 3.0 * ry * rz;
+    }
+}
+
+}  // namespace mmx
+
+// restore the compiler default for the code that follows
+#pragma clang fp contract(fast)

@@ -1,0 +1,357 @@
+"""Thin ctypes binding of the C ABI in include/mm.h.
+
+Every function here only marshals arguments: device buffers come from torch
+tensors (``tensor.data_ptr()``), the stream from torch's current stream, and
+all arithmetic runs in libmmx.so.  If the library is missing this module
+raises -- there is no fallback.
+
+Vector fields are torch tensors of shape (3, nz, ny, nx) (component-major, x
+fastest), dtype float32 for MM_FP32 plans and float64 for MM_FP64 plans, on
+the plan's device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmmx.so")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ENONFINITE, MM_EDTMIN, MM_ENOTCONV, MM_EBUSY = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MM_FP32, MM_FP64 = 0, 1
+MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_ALL = 1, 2, 4, 8, 15
+
+STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4: "MM_ENONFINITE",
+                -5: "MM_EDTMIN", -6: "MM_ENOTCONV", -7: "MM_EBUSY"}
+
+# Every entry point declared in include/mm.h.
+EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
+           "mm_plan_padded", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
+           "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
+           "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error"]
+
+PASS_NAMES = ["x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local", "rk"]
+MM_NPASS = len(PASS_NAMES)
+
+
+class mm_opts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("ku_axis", C.c_double * 3), ("demag_p", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class mm_step_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("t_end", C.c_double),
+                ("max_steps", C.c_long), ("dt_min", C.c_double), ("renorm", C.c_int)]
+
+
+class mm_step_stats(C.Structure):
+    _fields_ = [("accepted", C.c_long), ("rejected", C.c_long), ("rhs_evals", C.c_long),
+                ("t", C.c_double), ("dt", C.c_double), ("err_last", C.c_double)]
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libmmx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmmx.so is not built: run `python -m paper_2302_08843_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.mm_opts_default.argtypes = [C.POINTER(mm_opts)]
+        L.mm_opts_default.restype = None
+        L.mm_plan_create.argtypes = [C.POINTER(vp), ip, dp, C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.POINTER(mm_opts)]
+        L.mm_plan_destroy.argtypes = [vp]
+        L.mm_plan_destroy.restype = None
+        L.mm_plan_device_bytes.argtypes = [vp]
+        L.mm_plan_device_bytes.restype = C.c_size_t
+        L.mm_plan_padded.argtypes = [vp, ip]
+        L.mm_plan_padded.restype = None
+        L.mm_set_ms.argtypes = [vp, vp]
+        L.mm_set_drive.argtypes = [vp, dp, C.c_double, vp]
+        L.mm_heff.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
+        L.mm_llg_rhs.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
+        L.mm_llg_step.argtypes = [vp, vp, dp, C.c_uint, dp, dp, C.POINTER(mm_step_opts),
+                                  C.POINTER(mm_step_stats)]
+        L.mm_relax.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_long, C.c_double,
+                               C.POINTER(mm_step_stats)]
+        L.mm_energy.argtypes = [vp, vp, dp, C.c_uint, C.c_double, dp]
+        L.mm_max_torque.argtypes = [vp, vp, dp, C.c_uint, C.c_double, dp]
+        L.mm_profile.argtypes = [vp, C.c_int]
+        L.mm_profile_read.argtypes = [vp, dp, C.POINTER(C.c_long)]
+        L.mm_debug_kernel.argtypes = [vp, C.c_int, vp]
+        L.mm_debug_spectrum.argtypes = [vp, C.c_int, vp]
+        L.mm_last_error.restype = C.c_char_p
+        for name in ("mm_plan_create", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs",
+                     "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
+                     "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != MM_OK:
+        raise MMError(status, lib().mm_last_error().decode())
+    return status
+
+
+def _vec3(v):
+    if v is None:
+        return None
+    a = (C.c_double * 3)(*[float(x) for x in np.asarray(v, dtype=np.float64).reshape(3)])
+    return a
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Functions with the C names (argument marshalling only)
+# ---------------------------------------------------------------------------
+
+def mm_opts_default():
+    o = mm_opts()
+    lib().mm_opts_default(C.byref(o))
+    return o
+
+
+def mm_plan_create(grid, cell, Ms, A, Ku, alpha, opts=None):
+    h = C.c_void_p()
+    g = (C.c_int * 3)(*[int(v) for v in grid])
+    d = (C.c_double * 3)(*[float(v) for v in cell])
+    _check(lib().mm_plan_create(C.byref(h), g, d, float(Ms), float(A), float(Ku), float(alpha),
+                                C.byref(opts) if opts is not None else None))
+    return h
+
+
+def mm_plan_destroy(plan):
+    lib().mm_plan_destroy(plan)
+
+
+def mm_heff(plan, m, h_ext, terms, t, h_out):
+    _check(lib().mm_heff(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(h_out)))
+
+
+def mm_llg_rhs(plan, m, h_ext, terms, t, dmdt_out):
+    _check(lib().mm_llg_rhs(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(dmdt_out)))
+
+
+def mm_set_ms(plan, Ms_cell):
+    _check(lib().mm_set_ms(plan, None if Ms_cell is None else _ptr(Ms_cell)))
+
+
+def mm_set_drive(plan, amp, freq, mask):
+    _check(lib().mm_set_drive(plan, _vec3(amp), float(freq), None if mask is None else _ptr(mask)))
+
+
+def mm_llg_step(plan, m, h_ext, terms, t, dt, opts):
+    tt, dd = C.c_double(t), C.c_double(dt)
+    st = mm_step_stats()
+    status = lib().mm_llg_step(plan, _ptr(m), _vec3(h_ext), int(terms), C.byref(tt), C.byref(dd),
+                               C.byref(opts), C.byref(st))
+    return status, tt.value, dd.value, st
+
+
+def mm_relax(plan, m, h_ext, terms, tol, max_steps, rtol):
+    st = mm_step_stats()
+    status = lib().mm_relax(plan, _ptr(m), _vec3(h_ext), int(terms), float(tol), int(max_steps),
+                            float(rtol), C.byref(st))
+    return status, st
+
+
+def mm_energy(plan, m, h_ext, terms, t):
+    E = (C.c_double * 5)()
+    _check(lib().mm_energy(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), E))
+    return np.array(list(E))
+
+
+def mm_max_torque(plan, m, h_ext, terms, t):
+    out = C.c_double()
+    _check(lib().mm_max_torque(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), C.byref(out)))
+    return out.value
+
+
+def mm_profile(plan, enable):
+    _check(lib().mm_profile(plan, int(bool(enable))))
+
+
+def mm_profile_read(plan):
+    ms = (C.c_double * MM_NPASS)()
+    cnt = (C.c_long * MM_NPASS)()
+    _check(lib().mm_profile_read(plan, ms, cnt))
+    return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(MM_NPASS)}
+
+
+def mm_debug_kernel(plan, s, out):
+    _check(lib().mm_debug_kernel(plan, int(s), _ptr(out)))
+
+
+def mm_debug_spectrum(plan, s, out):
+    _check(lib().mm_debug_spectrum(plan, int(s), _ptr(out)))
+
+
+def mm_plan_padded(plan):
+    P = (C.c_int * 3)()
+    lib().mm_plan_padded(plan, P)
+    return tuple(P)
+
+
+def mm_plan_device_bytes(plan):
+    return int(lib().mm_plan_device_bytes(plan))
+
+
+# ---------------------------------------------------------------------------
+# Convenience object (same calls, holds the handle and the tensor dtype)
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """A plan on the current CUDA (HIP) device; see mm_plan_create."""
+
+    def __init__(self, grid, cell, Ms, A=0.0, Ku=0.0, alpha=0.5, prec="fp64", ku_axis=(0, 0, 1),
+                 demag_p=20, stream=None):
+        import torch
+
+        self.grid = tuple(int(v) for v in grid)
+        self.cell = tuple(float(v) for v in cell)
+        self.prec = MM_FP32 if prec in ("fp32", MM_FP32, "f32") else MM_FP64
+        self.dtype = torch.float32 if self.prec == MM_FP32 else torch.float64
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        o = mm_opts_default()
+        o.prec = self.prec
+        for a in range(3):
+            o.ku_axis[a] = float(ku_axis[a])
+        o.demag_p = int(demag_p)
+        o.stream = _stream_handle(stream)
+        self._stream = stream
+        self.handle = mm_plan_create(self.grid, self.cell, Ms, A, Ku, alpha, o)
+        nx, ny, nz = self.grid
+        self.shape = (3, nz, ny, nx)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            mm_plan_destroy(h)
+            self.handle = None
+
+    def _t(self, a):
+        import torch
+
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=self.dtype).contiguous()
+
+    def empty(self):
+        import torch
+
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def heff(self, m, h_ext=None, terms=MM_ALL, t=0.0, out=None):
+        m = self._t(m)
+        out = self.empty() if out is None else out
+        mm_heff(self.handle, m, h_ext, terms, t, out)
+        return out
+
+    def llg_rhs(self, m, h_ext=None, terms=MM_ALL, t=0.0, out=None):
+        m = self._t(m)
+        out = self.empty() if out is None else out
+        mm_llg_rhs(self.handle, m, h_ext, terms, t, out)
+        return out
+
+    def set_ms(self, Ms_cell):
+        import torch
+
+        if Ms_cell is None:
+            mm_set_ms(self.handle, None)
+            return
+        nx, ny, nz = self.grid
+        mm_set_ms(self.handle, self._t(Ms_cell).reshape(nz, ny, nx).contiguous())
+        torch.cuda.current_stream().synchronize()
+
+    def set_drive(self, amp, freq, mask):
+        import torch
+
+        if mask is None:
+            mm_set_drive(self.handle, None, 0.0, None)
+            return
+        mk = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to(self.device).contiguous()
+        mm_set_drive(self.handle, amp, freq, mk)
+        torch.cuda.current_stream().synchronize()
+
+    def llg_step(self, m, h_ext=None, terms=MM_ALL, t=0.0, dt=-1.0, rtol=1e-6, atol=None,
+                 t_end=float("inf"), max_steps=1 << 40, renorm=False, dt_min=0.0, check=True):
+        """Advance m (a plan-dtype device tensor, updated in place)."""
+        o = mm_step_opts(rtol=rtol, atol=rtol if atol is None else atol, t_end=t_end,
+                         max_steps=max_steps, dt_min=dt_min, renorm=int(bool(renorm)))
+        status, t, dt, st = mm_llg_step(self.handle, m, h_ext, terms, t, dt, o)
+        if check:
+            _check(status)
+        return status, t, dt, _stats(st)
+
+    def relax(self, m, h_ext=None, terms=MM_ALL, tol=1e-5, max_steps=50000, rtol=1e-4):
+        status, st = mm_relax(self.handle, m, h_ext, terms, tol, max_steps, rtol)
+        return status, _stats(st)
+
+    def energy(self, m, h_ext=None, terms=MM_ALL, t=0.0):
+        return mm_energy(self.handle, self._t(m), h_ext, terms, t)
+
+    def max_torque(self, m, h_ext=None, terms=MM_ALL, t=0.0):
+        return mm_max_torque(self.handle, self._t(m), h_ext, terms, t)
+
+    def padded(self):
+        return mm_plan_padded(self.handle)
+
+    def profile(self, enable=True):
+        mm_profile(self.handle, enable)
+
+    def profile_read(self):
+        """{pass name: (total ms, launches)} since profiling was enabled."""
+        return mm_profile_read(self.handle)
+
+    def device_bytes(self):
+        return mm_plan_device_bytes(self.handle)
+
+    def debug_kernel(self, s):
+        import torch
+
+        Px, Py, Pz = self.padded()
+        out = torch.empty((Pz, Py, Px), dtype=torch.float64, device=self.device)
+        mm_debug_kernel(self.handle, s, out)
+        return out
+
+    def debug_spectrum(self, s):
+        import torch
+
+        Px, Py, Pz = self.padded()
+        hx = Px // 2 + 1 if Px > 1 else 1
+        out = torch.empty((Pz // 2 + 1, Py // 2 + 1, hx), dtype=torch.float64, device=self.device)
+        mm_debug_spectrum(self.handle, s, out)
+        return out
+
+
+def _stats(st):
+    return dict(accepted=st.accepted, rejected=st.rejected, rhs_evals=st.rhs_evals, t=st.t,
+                dt=st.dt, err_last=st.err_last)

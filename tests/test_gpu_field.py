@@ -1,0 +1,153 @@
+"""GPU parity of the demag kernel set-up and of the effective field (Sec. 4):
+the HIP library, called through the C ABI, against the CPU oracle on the same
+seeded inputs.  Bars: kernel placement bit-exact; kernel entries within the
+oracle's own long-double accuracy; fields within 1e-12 (FP64) / 2e-5 (FP32)
+relative L2."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, banner, rel_l2, to_np
+from paper_2302_08843_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MU0 = 4e-7 * np.pi
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2302_08843_amd import mm as _mm
+
+    _mm.lib()
+    return _mm
+
+
+KERNEL_GRIDS = [((5, 3, 2), (2e-9, 3e-9, 2.5e-9), 20), ((30, 4, 3), (1e-9, 1e-9, 1e-9), 20),
+                ((9, 7, 5), (2e-9, 2e-9, 1e-9), 2), ((6, 1, 1), (1e-9, 2e-9, 3e-9), -1),
+                ((1, 1, 1), (3e-9, 3e-9, 3e-9), 20), ((1, 6, 4), (5e-9, 5e-9, 5e-9), 3)]
+
+
+@pytest.mark.parametrize("grid,cell,p", KERNEL_GRIDS)
+def test_kernel_placement_and_entries(torch_cuda, mm, orc, grid, cell, p):
+    banner("kernel %s p=%d" % (grid, p))
+    plan = mm.Plan(grid, cell, Ms=1.0, prec="fp64", demag_p=p)
+    Px, Py, Pz = plan.padded()
+    assert (Px, Py, Pz) == tuple(orc.padded(n) for n in grid)
+    nx, ny, nz = grid
+    for s in range(6):
+        K = to_np(plan.debug_kernel(s))
+        ref = np.zeros((Pz, Py, Px))
+        inside = np.zeros((Pz, Py, Px), bool)
+        for I in range(-(nx - 1), nx):
+            for J in range(-(ny - 1), ny):
+                for Kk in range(-(nz - 1), nz):
+                    ref[Kk % Pz, J % Py, I % Px] = orc.tensor_entry(cell, I, J, Kk, p)[s]
+                    inside[Kk % Pz, J % Py, I % Px] = True
+        # placement: every entry outside the offset window is exactly zero
+        assert np.all(K[~inside] == 0.0)
+        # entries: double-double on the GPU vs long double in the oracle
+        assert np.abs(K - ref).max() <= 2e-15, (s, np.abs(K - ref).max())
+
+
+def _random_problem(grid, seed, percell=False, vacuum=False):
+    g = W.rng(seed)
+    nx, ny, nz = grid
+    m = W.random_unit_sphere(grid, seed)
+    if percell:
+        Ms = g.uniform(4e5, 1.2e6, (nz, ny, nx))
+        if vacuum:
+            Ms[g.uniform(size=Ms.shape) < 0.2] = 0.0
+    else:
+        Ms = 8e5
+    return m, Ms
+
+
+FIELD_GRIDS = [(5, 3, 2), (8, 8, 4), (7, 1, 1), (1, 1, 5), (6, 5, 1), (1, 9, 3), (16, 12, 3),
+               (32, 32, 4), (48, 20, 10), (101, 51, 1), (200, 3, 1), (33, 17, 9)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid", FIELD_GRIDS)
+def test_heff_all_terms_matches_oracle(torch_cuda, mm, orc, prec, grid):
+    banner("heff %s %s" % (prec, grid))
+    torch = torch_cuda
+    d = (2e-9, 2.5e-9, 3e-9)
+    m, Ms = _random_problem(grid, 3)
+    A, Ku, eu = 1.3e-11, 4e4, (0.3, 0.4, np.sqrt(0.75))
+    H = np.array([1.5e4, -2e4, 5e3])
+    plan = mm.Plan(grid, d, Ms=Ms, A=A, Ku=Ku, alpha=0.3, prec=prec, ku_axis=eu)
+    o = orc.Oracle(grid, d, Ms=Ms, A=A, Ku=Ku, eu=np.array(eu) / np.linalg.norm(eu), alpha=0.3)
+    o.set_field(H)
+    mt = plan._t(m)
+    for terms in (mm.MM_DEMAG, mm.MM_EXCH, mm.MM_ANIS, mm.MM_ZEEMAN, mm.MM_ALL):
+        h = to_np(plan.heff(mt, H, terms))
+        torch.cuda.synchronize()
+        ref = o.heff(m, 0.0, terms)
+        err = rel_l2(h, ref)
+        assert err <= TOL[prec], (terms, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_heff_percell_ms_with_vacuum(torch_cuda, mm, orc, prec):
+    grid = (20, 14, 5)
+    banner("heff percell %s %s" % (prec, grid))
+    d = (3e-9, 3e-9, 3e-9)
+    m, Ms = _random_problem(grid, 5, percell=True, vacuum=True)
+    A = 1.5e-11
+    H = np.array([0.0, 1e4, 2e4])
+    plan = mm.Plan(grid, d, Ms=1.0, A=A, Ku=2e4, alpha=0.1, prec=prec)
+    plan.set_ms(Ms)
+    # the oracle's per-cell exchange constant is zero in vacuum cells
+    o = orc.Oracle(grid, d, Ms=Ms, A=np.where(Ms > 0, A, 0.0), Ku=2e4, alpha=0.1)
+    o.set_field(H)
+    mt = plan._t(m)
+    for terms in (mm.MM_DEMAG, mm.MM_EXCH, mm.MM_ALL):
+        h = to_np(plan.heff(mt, H, terms))
+        ref = o.heff(m, 0.0, terms)
+        assert rel_l2(h, ref) <= TOL[prec], terms
+        assert np.abs(h[:, Ms == 0]).max() == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_llg_rhs_and_drive(torch_cuda, mm, orc, prec):
+    grid = (24, 10, 1)
+    banner("rhs+drive %s" % prec)
+    d = (5e-9, 5e-9, 5e-9)
+    m, _ = _random_problem(grid, 8)
+    plan = mm.Plan(grid, d, Ms=8e5, A=1.3e-11, alpha=0.05, prec=prec)
+    o = orc.Oracle(grid, d, Ms=8e5, A=1.3e-11, alpha=0.05)
+    mask = np.zeros((1, 10, 24), np.uint8)
+    mask[:, :, 4:8] = 1
+    amp = np.array([0.0, W.mT(20.0), 0.0])
+    plan.set_drive(amp, 20e9, mask)
+    o.set_drive(amp, 20e9, mask)
+    o.set_field((0, 0, 0))
+    t = 13e-12
+    dm = to_np(plan.llg_rhs(plan._t(m), None, mm.MM_ALL, t))
+    ref = o.llg_rhs(m, o.heff(m, t))
+    assert rel_l2(dm, ref) <= TOL[prec]
+
+
+def test_trace_invariant_full_large_grid(torch_cuda, mm):
+    # sum_a h_a[m = e_a] = -Ms at every cell, any grid, any p: checks the whole
+    # FFT pipeline at the 512 x 512 x 64 size (padded 1024 x 1024 x 128)
+    torch = torch_cuda
+    grid = (512, 512, 64)
+    banner("trace invariant fp32 %s" % (grid,))
+    plan = mm.Plan(grid, (4e-9,) * 3, Ms=1e6, prec="fp32")
+    tot = torch.zeros((64, 512, 512), dtype=torch.float64, device="cuda")
+    for a in range(3):
+        m = torch.zeros(plan.shape, dtype=torch.float32, device="cuda")
+        m[a] = 1.0
+        h = plan.heff(m, None, mm.MM_DEMAG)
+        tot += h[a].double()
+    err = (tot + 1e6).abs().max().item() / 1e6
+    assert err < 2e-5, err

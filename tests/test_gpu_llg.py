@@ -1,0 +1,136 @@
+"""GPU parity of the LLG integration (Sec. 3): adaptive Dormand-Prince steps,
+energies, torque, relaxation and the failure paths, through the C ABI against
+the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, banner, rel_l2, to_np
+from paper_2302_08843_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2302_08843_amd import mm as _mm
+
+    _mm.lib()
+    return _mm
+
+
+@pytest.fixture(scope="module")
+def small_llg_oracle(orc):
+    c = W.config_small_llg()
+    o = orc.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    o.set_field(c["H"], terms=c["terms"])
+    m, t, dt, st, status = o.dp45(c["m0"], rtol=c["rtol"], max_steps=c["steps"])
+    assert status == 0
+    return c, o, m, t, st
+
+
+def test_small_llg_fp64_200_steps(torch_cuda, mm, small_llg_oracle):
+    c, o, m_ref, t_ref, st_ref = small_llg_oracle
+    banner("llg 32x32x4 fp64 200 steps")
+    plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec="fp64")
+    m = plan._t(c["m0"])
+    status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=c["rtol"], max_steps=c["steps"])
+    assert st["accepted"] == 200
+    assert st["accepted"] == st_ref["accepted"] and st["rejected"] == st_ref["rejected"]
+    assert st["rhs_evals"] == st_ref["rhs_evals"]
+    # the embedded error estimate is a small difference of stage values, so
+    # field differences of ~1e-14 move the accepted step sizes by ~1e-9
+    assert abs(t - t_ref) <= 1e-4 * t_ref
+    # compare at equal physical time
+    m_o, t_o, _, _, status_o = o.dp45(c["m0"], rtol=c["rtol"], t_end=t)
+    assert status_o == 0
+    mm_ = to_np(m)
+    assert np.abs(mm_ - m_o).max() <= 1e-8, np.abs(mm_ - m_o).max()
+    assert np.abs(mm_ - m_ref).max() <= 1e-4
+    E = plan.energy(m, c["H"], c["terms"])
+    Er = o.energy(m_o)
+    assert np.allclose(E, Er, rtol=1e-7, atol=1e-30)
+
+
+def test_small_llg_fp32_equal_time(torch_cuda, mm, orc, small_llg_oracle):
+    c, o, m_ref, t_ref, st_ref = small_llg_oracle
+    banner("llg 32x32x4 fp32 200 steps")
+    plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec="fp32")
+    m = plan._t(c["m0"])
+    status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=c["rtol"], max_steps=c["steps"])
+    assert st["accepted"] == 200
+    # compare at equal physical time: run the oracle to the GPU's final t
+    m_o, t_o, _, _, status_o = o.dp45(c["m0"], rtol=c["rtol"], t_end=t)
+    assert status_o == 0 and abs(t_o - t) <= 1e-12 * t
+    assert np.abs(to_np(m) - m_o).max() <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_energy_matches_oracle(torch_cuda, mm, orc, prec):
+    grid = (24, 18, 3)
+    banner("energy %s" % prec)
+    d = (2e-9, 2e-9, 3e-9)
+    m = W.random_unit_sphere(grid, 4)
+    H = np.array([3e4, 0.0, -1e4])
+    plan = mm.Plan(grid, d, Ms=9e5, A=1.1e-11, Ku=3e4, alpha=0.2, prec=prec)
+    o = orc.Oracle(grid, d, Ms=9e5, A=1.1e-11, Ku=3e4, alpha=0.2)
+    o.set_field(H)
+    E = plan.energy(m, H, mm.MM_ALL)
+    Er = o.energy(m)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    for e in range(5):
+        assert abs(E[e] - Er[e]) <= tol * np.abs(Er).max(), (e, E, Er)
+    tq = plan.max_torque(m, H, mm.MM_ALL)
+    assert abs(tq - o.max_torque(m)) <= (1e-12 if prec == "fp64" else 1e-5) * o.max_torque(m)
+
+
+def test_relax_matches_oracle(torch_cuda, mm, orc):
+    grid = (16, 16, 2)
+    banner("relax fp64")
+    d = (3e-9, 3e-9, 3e-9)
+    m0 = W.smooth_random(grid, 4.0, 6)
+    H = np.array([0.0, 0.0, 2e4])
+    plan = mm.Plan(grid, d, Ms=8e5, A=1.3e-11, Ku=5e4, alpha=0.5, prec="fp64")
+    o = orc.Oracle(grid, d, Ms=8e5, A=1.3e-11, Ku=5e4, alpha=0.5)
+    o.set_field(H)
+    # an explicit integrator stalls at a torque of ~100 rtol: tol 1e-3 at rtol 1e-5
+    m_ref, st_ref, status_ref = o.relax(m0, tol=1e-3, max_steps=20000, rtol=1e-5)
+    m = plan._t(m0)
+    status, st = plan.relax(m, H, mm.MM_ALL, tol=1e-3, max_steps=20000, rtol=1e-5)
+    assert status_ref == 0 and status == 0
+    assert abs(st["accepted"] - st_ref["accepted"]) <= 0.01 * st_ref["accepted"]
+    assert plan.max_torque(m, H) < 1e-3
+    # same relaxed state: energies agree to the torque tolerance
+    E = plan.energy(m, H)
+    Er = o.energy(m_ref)
+    assert abs(E[4] - Er[4]) <= 1e-6 * abs(Er[4])
+
+
+def test_failure_paths(torch_cuda, mm):
+    torch = torch_cuda
+    grid = (8, 8, 2)
+    banner("failure paths")
+    plan = mm.Plan(grid, (2e-9,) * 3, Ms=8e5, A=1.3e-11, alpha=0.5, prec="fp64")
+    m0 = plan._t(W.random_unit_sphere(grid, 1))
+    # NaN in the state: the error norm is non-finite
+    m = m0.clone()
+    m[0, 0, 0, 3] = float("nan")
+    status, t, dt, st = plan.llg_step(m, None, mm.MM_ALL, dt=1e-13, max_steps=5, check=False)
+    assert status == mm.MM_ENONFINITE
+    # dt_min above the first step
+    m = m0.clone()
+    status, t, dt, st = plan.llg_step(m, None, mm.MM_ALL, dt=1e-14, max_steps=5, dt_min=1e-12,
+                                      check=False)
+    assert status == mm.MM_EDTMIN
+    # relaxation capped before convergence
+    m = m0.clone()
+    status, st = plan.relax(m, None, mm.MM_ALL, tol=1e-9, max_steps=2)
+    assert status == mm.MM_ENOTCONV and st["accepted"] == 2
+    torch.cuda.synchronize()
