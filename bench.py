@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--heff-iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -130,6 +132,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        # torch.mul(a, 1, out=b): reads 1 GiB, writes 1 GiB; HBM counters of
+        # this kernel calibrate FETCH_SIZE / WRITE_SIZE
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 3 x (1 GiB read + 1 GiB write)", file=sys.stderr,
+              flush=True)
+        del a, b
     grid = tuple(int(v) for v in args.grid.split(","))
     cfg = W.config_large(n=grid)
     N = int(np.prod(grid))
