@@ -27,15 +27,17 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile every source to an object and link libmmx.so; always rebuilds."""
+def build(verbose: bool = False, jobs: int = 2, out: str = LIB, defines=()) -> str:
+    """Compile every source to an object and link the library (libmmx.so by
+    default); always rebuilds.  `defines` are extra -D flags (tuning knobs)."""
     tmp = tempfile.mkdtemp(prefix="mmx_build_")
     try:
         objs = []
         procs = []
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC, *FLAGS, *["-D" + d for d in defines], "-c", os.path.join(CSRC, src),
+                   "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((subprocess.Popen(cmd), src))
@@ -47,15 +49,15 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         for p, s in procs:
             if p.wait() != 0:
                 raise RuntimeError("hipcc failed on " + s)
-        out_tmp = LIB + ".tmp"
+        out_tmp = out + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out_tmp, *objs]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, out)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

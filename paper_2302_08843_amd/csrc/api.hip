@@ -337,7 +337,10 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
     }
     p->N = (long)grid[0] * grid[1] * grid[2];
     p->Hx = p->P[0] > 1 ? p->P[0] / 2 + 1 : 1;
-    p->Hxp = (p->Hx + 15) / 16 * 16;
+    // spectral rows start on 128-byte boundaries for the real kernel array
+    // (32 floats or 16 doubles) and therefore for the complex spectra too
+    const int row_align = o.prec == MM_FP32 ? 32 : 16;
+    p->Hxp = (p->Hx + row_align - 1) / row_align * row_align;
     p->S1n = 3L * grid[2] * grid[1] * p->Hxp;
     p->S2n = 3L * grid[2] * p->P[1] * p->Hxp;
     p->Kn = (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
@@ -352,6 +355,13 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
     p->n_magnetic = Ms > 0.0 ? p->N : 0;
     p->drive = false;
     p->stream = (hipStream_t)o.stream;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            p->ncu = ncu;
+    }
     const size_t es = elem_size(*p);
     mm_status s;
 #define MM_ALLOC(ptr, bytes, what)                              \

@@ -39,7 +39,7 @@ struct Plan {
     double d[3];   // dx, dy, dz
     int P[3];      // padded extents
     int Hx;        // Px/2 + 1 (1 when Px == 1): x bins kept by the real transform
-    int Hxp;       // row stride of every spectral array (Hx rounded up to 16)
+    int Hxp;       // row stride of every spectral array (Hx rounded up to 128 bytes of reals)
     long N;        // cells
     long S1n;      // complex values in S1 = 3 * nz * ny * Hxp
     long S2n;      // complex values in S2 = 3 * nz * Py * Hxp
@@ -56,6 +56,7 @@ struct Plan {
     bool drive;
     double drive_amp[3], drive_freq;
     hipStream_t stream;
+    int ncu = 256;  // compute units of the device (persistent launches)
     // device buffers (element type = plan precision unless noted)
     void *Khat = nullptr;     // [6][Pz/2+1][Py/2+1][Hxp] real, scaled by 1/(Px Py Pz)
     void *S1 = nullptr;       // [3][nz][ny][Hxp] complex

@@ -95,8 +95,9 @@ constexpr int bitrev(int v, int bits)
 
 // In-register DFT of length R <= 64 on a[0..R), natural order in and out.
 // Radix-2 decimation in frequency followed by a compile-time bit-reversal
-// permutation (register renaming only).
-template <int R, int DIR, typename T>
+// permutation (register renaming only).  HALF_IN: a[R/2..R) are known to be
+// zero (zero padding), so the first butterfly level only rotates.
+template <int R, int DIR, bool HALF_IN = false, typename T>
 __device__ __forceinline__ void dft(cx<T>* a)
 {
     if constexpr (R == 1) {
@@ -109,9 +110,13 @@ __device__ __forceinline__ void dft(cx<T>* a)
             for (int s = 0; s < R; s += len) {
 #pragma unroll
                 for (int k = 0; k < half; ++k) {
-                    cx<T> u = a[s + k], w = a[s + k + half];
-                    a[s + k] = cadd(u, w);
-                    a[s + k + half] = rot64<DIR>(csub(u, w), k * (64 / len));
+                    if (HALF_IN && len == R) {
+                        a[s + k + half] = rot64<DIR>(a[s + k], k * (64 / len));
+                    } else {
+                        cx<T> u = a[s + k], w = a[s + k + half];
+                        a[s + k] = cadd(u, w);
+                        a[s + k + half] = rot64<DIR>(csub(u, w), k * (64 / len));
+                    }
                 }
             }
         }
@@ -152,6 +157,12 @@ struct FFTShape {
     static constexpr int kT = L / kE;                 // threads per transform
     static constexpr int kStages = stage_count(L, kE);
     static constexpr int kLast = kStages > 0 ? stage_radix(L, kE, kStages - 1) : 1;
+    // LDS slots per transform: one pad slot after every kE elements.  The
+    // first stage writes element j*kE + r from thread j; without the pad all
+    // threads of a lane group would hit the same LDS bank.
+    static constexpr int kPadLog = ilog2(kE);
+    static constexpr int kLds = L + (L >> kPadLog);
+    __device__ static constexpr int lds_slot(int e) { return e + (e >> kPadLog); }
     // natural output index held in v[i] after run()
     __device__ static constexpr int out_index(int t, int i)
     {
@@ -162,10 +173,11 @@ struct FFTShape {
 };
 
 // One Stockham transform per group of kT threads.  `lds` points to this
-// transform's scratch of L complex values, element e at lds[e * lstride].
+// transform's scratch of S::kLds complex slots, slot s at lds[s * lstride].
 // All threads of the workgroup must call run() (it contains barriers), also
-// those whose transform is masked out.
-template <typename T, int L, int E, int DIR>
+// those whose transform is masked out.  HALF_IN: the inputs x[L/2..L) are zero
+// (the caller leaves v[kE/2..kE) zero; the first stage skips them).
+template <typename T, int L, int E, int DIR, bool HALF_IN = false>
 struct WgFFT {
     using S = FFTShape<L, E>;
     static constexpr int kE = S::kE;
@@ -185,7 +197,7 @@ struct WgFFT {
             for (int q = 0; q < NB; ++q) {
                 const int j = t + q * kT;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[q * R + r] = lds[(j + r * (L / R)) * lstride];
+                for (int r = 0; r < R; ++r) v[q * R + r] = lds[S::lds_slot(j + r * (L / R)) * lstride];
             }
         }
 #pragma unroll
@@ -200,7 +212,7 @@ struct WgFFT {
                     v[q * R + r] = DIR < 0 ? cmul(v[q * R + r], w) : cmulc(v[q * R + r], w);
                 }
             }
-            dft<R, DIR>(&v[q * R]);
+            dft<R, DIR, HALF_IN && s == 0>(&v[q * R]);
         }
         if constexpr (s + 1 < S::kStages) {
             __syncthreads();  // previous readers of lds are done
@@ -209,7 +221,7 @@ struct WgFFT {
                 const int j = t + q * kT;
                 const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[(base + r * Ns) * lstride] = v[q * R + r];
+                for (int r = 0; r < R; ++r) lds[S::lds_slot(base + r * Ns) * lstride] = v[q * R + r];
             }
             stage<s + 1>(v, t, lds, lstride, tw, twstride);
         }

@@ -33,28 +33,84 @@
 
 namespace mmx {
 
-// Registers per thread in each kind of pass (complex values).
+// Registers per thread in each kind of pass (complex values).  The defaults
+// can be overridden at build time for tuning sweeps.
+#ifndef MMX_RX_F32
+#define MMX_RX_F32 16
+#endif
+#ifndef MMX_RS_F32
+#define MMX_RS_F32 32
+#endif
+#ifndef MMX_RM_F32
+#define MMX_RM_F32 16
+#endif
+#ifndef MMX_RX1_F32
+#define MMX_RX1_F32 8
+#endif
+#ifndef MMX_RX_F64
+#define MMX_RX_F64 16
+#endif
+#ifndef MMX_RS_F64
+#define MMX_RS_F64 16
+#endif
+#ifndef MMX_RM_F64
+#define MMX_RM_F64 8
+#endif
+#ifndef MMX_RX1_F64
+#define MMX_RX1_F64 8
+#endif
+// threads per block targeted by the strided and last-axis passes
+#ifndef MMX_SBLOCK
+#define MMX_SBLOCK 512
+#endif
+#ifndef MMX_MBLOCK
+#define MMX_MBLOCK 256
+#endif
+#ifndef MMX_XBLOCK
+#define MMX_XBLOCK 128
+#endif
+#ifndef MMX_X1BLOCK
+#define MMX_X1BLOCK 512
+#endif
+#ifndef MMX_X1BLOCK_F64
+#define MMX_X1BLOCK_F64 256
+#endif
 template <typename T>
 struct Regs;
 template <>
 struct Regs<float> {
-    static constexpr int x = 32;    // F1 row transforms
-    static constexpr int s = 32;    // strided y passes
-    static constexpr int mid = 16;  // F3: three components resident
-    static constexpr int x1 = 16;   // I1: three components per row
+    static constexpr int x = MMX_RX_F32;    // F1 row transforms
+    static constexpr int s = MMX_RS_F32;    // strided y passes
+    static constexpr int mid = MMX_RM_F32;  // F3: three components resident
+    static constexpr int x1 = MMX_RX1_F32;  // I1: three components per row
 };
 template <>
 struct Regs<double> {
-    static constexpr int x = 16;
-    static constexpr int s = 16;
-    static constexpr int mid = 8;
-    static constexpr int x1 = 8;
+    static constexpr int x = MMX_RX_F64;
+    static constexpr int s = MMX_RS_F64;
+    static constexpr int mid = MMX_RM_F64;
+    static constexpr int x1 = MMX_RX1_F64;
 };
 
 constexpr int kBlock = 256;
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// The dispatcher hands linear workgroup b to XCD (b mod 8), and every XCD has
+// its own L2.  Launches below use 1-D grids padded to a multiple of 8 and the
+// logical block (b mod 8) * (G/8) + b/8, so each XCD walks one contiguous
+// range of logical blocks: neighbouring column tiles that share 128-byte lines
+// (and neighbouring rows of the exchange stencil) are then served by the same
+// L2 at about the same time.
+constexpr int kXCD = 8;
+__host__ __device__ inline long xcd_grid(long blocks) { return (blocks + kXCD - 1) / kXCD * kXCD; }
+__device__ inline long xcd_logical()
+{
+    const long G = gridDim.x, b = blockIdx.x;
+    return (b % kXCD) * (G / kXCD) + b / kXCD;
+}
+
 
 // ---------------------------------------------------------------------------
 // Twiddle table: tw[n] = exp(-2 pi i n / Lmax), rounded from double.
@@ -82,20 +138,19 @@ template <typename T, int M>
 struct XR2C {
     using S = FFTShape<M, Regs<T>::x>;
     static constexpr int kE = S::kE, kT = S::kT;
-    static constexpr int kRows = cmax(1, kBlock / kT);
+    static constexpr int kRows = cmax(1, MMX_XBLOCK / kT);
 };
 
-template <typename T, int M, bool PERCELL>
-__global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, long in_row,
-                                                  long in_comp, int n_in,
-                                                  const T* __restrict__ Ms_cell, T Ms,
-                                                  cx<T>* __restrict__ out, long out_row,
-                                                  long out_comp, int nrows, int ncomp,
-                                                  const cx<T>* __restrict__ tw, int Lmax)
+template <typename T, int M, bool PERCELL, bool HALF>
+__global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) void k_x_r2c(
+    const T* __restrict__ in, long in_row, long in_comp, int n_in, const T* __restrict__ Ms_cell,
+    T Ms, cx<T>* __restrict__ out, long out_row, long out_comp, int nrows, int ncomp,
+    const cx<T>* __restrict__ tw, int Lmax)
 {
     using G = XR2C<T, M>;
     constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows;
-    __shared__ cx<T> lds[kRows * M];
+    constexpr int kL = G::S::kLds;  // LDS slots per row
+    __shared__ cx<T> lds[kRows * kL];
     const int t = threadIdx.x % kT, rl = threadIdx.x / kT;
     const long row = (long)blockIdx.x * kRows + rl;
     const bool valid = row < (long)nrows * ncomp;
@@ -108,12 +163,15 @@ __global__ __launch_bounds__(kBlock) void k_x_r2c(const T* __restrict__ in, long
         const int n = t + q * kT;  // first-stage input index
         const int i0 = 2 * n, i1 = 2 * n + 1;
         T a = 0, b = 0;
-        if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
-        if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+        // HALF: n_in <= M, so inputs q >= kE/2 (n >= M/2) are zero padding
+        if (!(HALF && q >= kE / 2)) {
+            if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
+            if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+        }
         v[q] = {a, b};
     }
-    cx<T>* L = lds + rl * M;
-    WgFFT<T, M, Regs<T>::x, -1>::run(v, t, L, 1, tw, Lmax / M);
+    cx<T>* L = lds + rl * kL;
+    WgFFT<T, M, Regs<T>::x, -1, HALF>::run(v, t, L, 1, tw, Lmax / M);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kE; ++q) L[G::S::out_index(t, q)] = v[q];
@@ -146,34 +204,43 @@ template <typename T, int L>
 struct Strided {
     using S = FFTShape<L, Regs<T>::s>;
     static constexpr int kE = S::kE, kT = S::kT;
-    static constexpr int kB = cmin(64, cmax(1, kBlock / kT));
+    static constexpr int kB = cmin(64, cmax(1, MMX_SBLOCK / kT));
 };
 
-template <typename T, int L, int DIR>
-__global__ __launch_bounds__(kBlock) void k_strided(const cx<T>* in, cx<T>* out, int n_in,
-                                                    int n_out, long es_in, long es_out, int ncols,
-                                                    long g1_in, long g1_out, long g2_in,
-                                                    long g2_out, const cx<T>* __restrict__ tw,
-                                                    int Lmax)
+// HALF (forward): n_in <= L/2, the upper half of the inputs is zero padding.
+// HALF (inverse): n_out <= L/2, outputs e >= L/2 are never stored.
+template <typename T, int L, int DIR, bool HALF>
+__global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_strided(
+    const cx<T>* in, cx<T>* out, int n_in, int n_out, long es_in, long es_out, int ncols,
+    int ntile, int G2, long nblocks, long g1_in, long g1_out, long g2_in, long g2_out,
+    const cx<T>* __restrict__ tw, int Lmax)
 {
     using G = Strided<T, L>;
     constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
-    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * L : 1];
+    constexpr bool HIN = HALF && DIR < 0, HOUT = HALF && DIR > 0;
+    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * G::S::kLds : 1];
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;
+    const int tile = (int)(lb % ntile);
+    const long rest = lb / ntile;
+    const long g2 = rest % G2, g1 = rest / G2;
     const int b = threadIdx.x % kB, t = threadIdx.x / kB;
-    const int col = blockIdx.x * kB + b;
+    const int col = tile * kB + b;
     const bool cv = col < ncols;
-    const cx<T>* src = in + blockIdx.z * g1_in + blockIdx.y * g2_in + col;
-    cx<T>* dst = out + blockIdx.z * g1_out + blockIdx.y * g2_out + col;
+    const cx<T>* src = in + g1 * g1_in + g2 * g2_in + col;
+    cx<T>* dst = out + g1 * g1_out + g2 * g2_out + col;
     cx<T> v[kE];
 #pragma unroll
     for (int r = 0; r < kE; ++r) {
         const int e = t + r * kT;
-        v[r] = (cv && e < n_in) ? src[(long)e * es_in] : cx<T>{0, 0};
+        v[r] = (!(HIN && r >= kE / 2) && cv && e < n_in) ? src[(long)e * es_in] : cx<T>{0, 0};
     }
-    WgFFT<T, L, Regs<T>::s, DIR>::run(v, t, lds + b, kB, tw, Lmax / L);
+    WgFFT<T, L, Regs<T>::s, DIR, HIN>::run(v, t, lds + b, kB, tw, Lmax / L);
     if (!cv) return;
+    constexpr int Rl = G::S::kLast;
 #pragma unroll
     for (int i = 0; i < kE; ++i) {
+        if (HOUT && (i % Rl) >= Rl / 2) continue;  // e >= L/2
         const int e = G::S::out_index(t, i);
         if (e < n_out) dst[(long)e * es_out] = v[i];
     }
@@ -185,43 +252,48 @@ __global__ __launch_bounds__(kBlock) void k_strided(const cx<T>* in, cx<T>* out,
 // spectral kernel, inverse transform, store the first n_valid elements.
 // AXIS = 2: pencils along z, group g = ky.  AXIS = 1: pencils along y (Pz=1).
 // ---------------------------------------------------------------------------
+#ifndef MMX_MID_CHUNK
+#define MMX_MID_CHUNK 0
+#endif
 template <typename T, int L>
 struct Mid {
     using S = FFTShape<L, Regs<T>::mid>;
     static constexpr int kE = S::kE, kT = S::kT;
-    static constexpr int kB = cmin(64, cmax(1, kBlock / kT));
+    static constexpr int kB = cmin(64, cmax(1, MMX_MBLOCK / kT));
 };
 
-template <typename T, int L, int AXIS>
-__global__ __launch_bounds__(kBlock) void k_mid(cx<T>* S, const T* __restrict__ Khat, int n_valid,
-                                                long es, long cs, long gstride, int ncols, int Py,
-                                                int Pz, long Kn, int Hxp,
-                                                const cx<T>* __restrict__ tw, int Lmax)
+// One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
+// components, forward transform, product with the spectral kernel, inverse
+// transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
+template <typename T, int L, int AXIS, bool HALF>
+__device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Khat, int n_valid,
+                                          long es, long cs, bool cv, int col, int g, int t, int b,
+                                          cx<T>* lds, int Py, int Pz, long Kn, int Hxp,
+                                          const cx<T>* __restrict__ tw, int Lmax)
 {
     using G = Mid<T, L>;
     constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
-    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * L : 1];
-    const int b = threadIdx.x % kB, t = threadIdx.x / kB;
-    const int col = blockIdx.x * kB + b;
-    const bool cv = col < ncols;
-    const int g = blockIdx.y;
-    cx<T>* base = S + (long)g * gstride + col;
     cx<T> v[3][kE];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < kE; ++r) {
             const int e = t + r * kT;
-            v[c][r] = (cv && e < n_valid) ? base[c * cs + (long)e * es] : cx<T>{0, 0};
+            v[c][r] = (!(HALF && r >= kE / 2) && cv && e < n_valid) ? base[c * cs + (long)e * es]
+                                                                  : cx<T>{0, 0};
         }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) WgFFT<T, L, Regs<T>::mid, -1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+    for (int c = 0; c < 3; ++c)
+        WgFFT<T, L, Regs<T>::mid, -1, HALF>::run(v[c], t, lds + b, kB, tw, Lmax / L);
 
     if (cv) {
         const int hy = Py / 2, hz = Pz / 2;
         const long plane = (long)(hy + 1) * Hxp;
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
+            // Keep the scheduler from hoisting every kernel load of the
+            // pencil at once (that alone would hold 6 kE registers).
+            if (MMX_MID_CHUNK > 0 && i > 0 && i % MMX_MID_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
             const int kk = G::S::out_index(t, i);
             int ky, kz;
             if constexpr (AXIS == 2) {
@@ -255,15 +327,47 @@ __global__ __launch_bounds__(kBlock) void k_mid(cx<T>* S, const T* __restrict__ 
         for (int i = 0; i < kE; ++i) v[c][i] = w[i];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) WgFFT<T, L, Regs<T>::mid, 1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+    for (int c = 0; c < 3; ++c)
+        WgFFT<T, L, Regs<T>::mid, 1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
     if (!cv) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
+            if (HALF && (i % Rl) >= Rl / 2) continue;  // e >= L/2
             const int e = G::S::out_index(t, i);
             if (e < n_valid) base[c * cs + (long)e * es] = v[c][i];
         }
+}
+
+// AXIS = 2: pencils along z; a block owns the column tile at ky = g and, for
+// 0 < g < Py/2, also ky = Py - g, which uses the same (folded) rows of the
+// spectral kernel -- the second read comes from L2, so HBM sees the kernel
+// once.  AXIS = 1: pencils along y (single layer), one group.
+template <typename T, int L, int AXIS, bool HALF>
+__global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(cx<T>* S, const T* __restrict__ Khat, int n_valid,
+                                                long es, long cs, long gstride, int ncols,
+                                                int ntile, long nblocks, int Py, int Pz, long Kn,
+                                                int Hxp, const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = Mid<T, L>;
+    constexpr int kT = G::kT, kB = G::kB;
+    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * G::S::kLds : 1];
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;
+    const int tile = (int)(lb % ntile);
+    const int g = (int)(lb / ntile);
+    const int b = threadIdx.x % kB, t = threadIdx.x / kB;
+    const int col = tile * kB + b;
+    const bool cv = col < ncols;
+    (void)kT;
+    mid_group<T, L, AXIS, HALF>(S + (long)g * gstride + col, Khat, n_valid, es, cs, cv, col, g, t,
+                                b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    if (AXIS == 2 && g > 0 && 2 * g < Py) {
+        const int g2 = Py - g;
+        mid_group<T, L, AXIS, HALF>(S + (long)g2 * gstride + col, Khat, n_valid, es, cs, cv, col,
+                                    g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -292,7 +396,9 @@ struct XC2R {
     static constexpr int Mf = M > 0 ? M : 1;
     using S = FFTShape<Mf, Regs<T>::x1>;
     static constexpr int kE = S::kE, kT = S::kT;
-    static constexpr int kRows = cmax(1, kBlock / (3 * kT));
+    static constexpr int kL = S::kLds;  // LDS slots per (row, component) >= Mf
+    static constexpr int kRows =
+        cmax(1, (sizeof(T) == 4 ? MMX_X1BLOCK : MMX_X1BLOCK_F64) / (3 * kT));
 };
 
 __device__ inline void atomic_max_nonneg(double* addr, double v)
@@ -302,16 +408,18 @@ __device__ inline void atomic_max_nonneg(double* addr, double v)
 }
 
 template <typename T, int M, bool PERCELL>
-__global__ __launch_bounds__(kBlock) void k_x_c2r_local(
+__global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
-    LocalParams P, double* torque, const cx<T>* __restrict__ tw, int Lmax)
+    LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax)
 {
     using G = XC2R<T, M>;
-    constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows, Mf = G::Mf;
-    __shared__ cx<T> lds[kRows * 3 * Mf];
-    const int k = blockIdx.y;
-    const int j0 = blockIdx.x * kRows;
+    constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows, Mf = G::Mf, kL = G::kL;
+    __shared__ cx<T> lds[kRows * 3 * kL];
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;
+    const int k = (int)(lb / njt);
+    const int j0 = (int)(lb % njt) * kRows;
     const int nx = P.nx, ny = P.ny;
 
     if constexpr (M >= 2) {
@@ -337,12 +445,15 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r_local(
                 }
                 v[r] = z;
             }
-            cx<T>* L = lds + (rl * 3 + c) * Mf;
+            cx<T>* L = lds + (rl * 3 + c) * kL;
             WgFFT<T, M, Regs<T>::x1, 1>::run(v, t, L, 1, tw, Lmax / M);
             __syncthreads();
             T* hd = reinterpret_cast<T*>(L);
+            constexpr int Rl = G::S::kLast;
 #pragma unroll
             for (int i = 0; i < kE; ++i) {
+                // outputs n >= M/2 are cells x >= M >= nx: never used
+                if ((i % Rl) >= Rl / 2) continue;
                 const int e = G::S::out_index(t, i);
                 hd[2 * e] = v[i].x;
                 hd[2 * e + 1] = v[i].y;
@@ -367,10 +478,10 @@ __global__ __launch_bounds__(kBlock) void k_x_c2r_local(
         if (ms != (T)0) {
             if (P.with_demag) {
                 if constexpr (M >= 2) {
-                    const T* hd = reinterpret_cast<const T*>(lds + rl * 3 * Mf);
+                    const T* hd = reinterpret_cast<const T*>(lds + rl * 3 * kL);
                     hx = hd[i];
-                    hy = hd[2 * Mf + i];
-                    hz = hd[4 * Mf + i];
+                    hy = hd[2 * kL + i];
+                    hz = hd[4 * kL + i];
                 } else {
                     const cx<T>* X = S1 + ((long)k * ny + j) * P.Hxp;
                     hx = X[0].x;
@@ -458,10 +569,18 @@ static hipError_t launch_strided_L(const Plan& p, const cx<T>* in, cx<T>* out, i
                                    long g1_out, int G2, long g2_in, long g2_out)
 {
     using G = Strided<T, L>;
-    dim3 grid((ncols + G::kB - 1) / G::kB, G2, G1);
-    k_strided<T, L, DIR><<<grid, G::kB * G::kT, 0, p.stream>>>(
-        in, out, n_in, n_out, es_in, es_out, ncols, g1_in, g1_out, g2_in, g2_out,
-        (const cx<T>*)p.tw, p.Lmax);
+    const int ntile = (ncols + G::kB - 1) / G::kB;
+    const long nblocks = (long)ntile * G2 * G1;
+    const long grid = xcd_grid(nblocks);
+    const bool half = DIR < 0 ? 2 * n_in <= L : 2 * n_out <= L;
+    if (half && L > 1)
+        k_strided<T, L, DIR, true><<<grid, G::kB * G::kT, 0, p.stream>>>(
+            in, out, n_in, n_out, es_in, es_out, ncols, ntile, G2, nblocks, g1_in, g1_out, g2_in,
+            g2_out, (const cx<T>*)p.tw, p.Lmax);
+    else
+        k_strided<T, L, DIR, false><<<grid, G::kB * G::kT, 0, p.stream>>>(
+            in, out, n_in, n_out, es_in, es_out, ncols, ntile, G2, nblocks, g1_in, g1_out, g2_in,
+            g2_out, (const cx<T>*)p.tw, p.Lmax);
     return hipGetLastError();
 }
 
@@ -527,9 +646,15 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
                                                                    nrows, ncomp);
     } else {
         using G = XR2C<T, M>;
-        k_x_r2c<T, M, PC><<<(rows + G::kRows - 1) / G::kRows, G::kRows * G::kT, 0, p.stream>>>(
-            in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
-            (const cx<T>*)p.tw, p.Lmax);
+        const long grid = (rows + G::kRows - 1) / G::kRows;
+        if (n_in <= M)
+            k_x_r2c<T, M, PC, true><<<grid, G::kRows * G::kT, 0, p.stream>>>(
+                in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
+                (const cx<T>*)p.tw, p.Lmax);
+        else
+            k_x_r2c<T, M, PC, false><<<grid, G::kRows * G::kT, 0, p.stream>>>(
+                in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
+                (const cx<T>*)p.tw, p.Lmax);
     }
     return hipGetLastError();
 }
@@ -539,10 +664,18 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
                                long gstride, int G)
 {
     using Gm = Mid<T, L>;
-    dim3 grid((p.Hx + Gm::kB - 1) / Gm::kB, G);
-    k_mid<T, L, AXIS><<<grid, Gm::kB * Gm::kT, 0, p.stream>>>(
-        S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, p.P[1], p.P[2], p.Kn, p.Hxp,
-        (const cx<T>*)p.tw, p.Lmax);
+    const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
+    // AXIS = 2 pairs ky with Py - ky: groups 0 .. Py/2
+    const int groups = (AXIS == 2 && G > 1) ? G / 2 + 1 : G;
+    const long nblocks = (long)ntile * groups;
+    if (2 * n_valid <= L && L > 1)
+        k_mid<T, L, AXIS, true><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(
+            S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nblocks, p.P[1], p.P[2],
+            p.Kn, p.Hxp, (const cx<T>*)p.tw, p.Lmax);
+    else
+        k_mid<T, L, AXIS, false><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(
+            S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nblocks, p.P[1], p.P[2],
+            p.Kn, p.Hxp, (const cx<T>*)p.tw, p.Lmax);
     return hipGetLastError();
 }
 
@@ -564,9 +697,10 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
                                  double* torque)
 {
     using G = XC2R<T, M>;
-    dim3 grid((p.n[1] + G::kRows - 1) / G::kRows, p.n[2]);
-    k_x_c2r_local<T, M, PC><<<grid, G::kRows * 3 * G::kT, 0, p.stream>>>(
-        (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque,
+    const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
+    const long nblocks = (long)njt * p.n[2];
+    k_x_c2r_local<T, M, PC><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
+        (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
         (const cx<T>*)p.tw, p.Lmax);
     return hipGetLastError();
 }
@@ -628,42 +762,120 @@ struct Coef7 {
 };
 
 template <typename T>
-__global__ void k_rk_combine(T* __restrict__ y_out, const T* __restrict__ y, Coef7 cf,
-                             const T* k0, const T* k1, const T* k2, const T* k3, const T* k4,
-                             const T* k5, const T* k6, int nk, long n3)
+struct Ptr7 {
+    const T* p[7];
+};
+
+// 16-byte vectors for the Runge-Kutta vector kernels.
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct V16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+
+template <typename T>
+__device__ inline void vload(const T* p, T (&o)[V16<T>::n])
 {
-    const T* ks[7] = {k0, k1, k2, k3, k4, k5, k6};
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n3;
+    typename V16<T>::type v = *reinterpret_cast<const typename V16<T>::type*>(p);
+    if constexpr (V16<T>::n == 4) {
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    } else {
+        o[0] = v.x; o[1] = v.y;
+    }
+}
+template <typename T>
+__device__ inline void vstore(T* p, const T (&o)[V16<T>::n])
+{
+    typename V16<T>::type v;
+    if constexpr (V16<T>::n == 4) {
+        v.x = o[0]; v.y = o[1]; v.z = o[2]; v.w = o[3];
+    } else {
+        v.x = o[0]; v.y = o[1];
+    }
+    *reinterpret_cast<typename V16<T>::type*>(p) = v;
+}
+
+// y_out = y + sum_{j < NK} c_j k_j.  VEC: every pointer is 16-byte aligned and
+// n3 is a multiple of the vector width.
+template <typename T, int NK, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_rk_combine(T* __restrict__ y_out,
+                                                       const T* __restrict__ y, Coef7 cf,
+                                                       Ptr7<T> ks, long n3)
+{
+    constexpr int W = VEC ? V16<T>::n : 1;
+    T cj[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) cj[j] = (T)cf.c[j];
+    const long nv = n3 / W;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
          q += (long)gridDim.x * blockDim.x) {
-        T acc = y[q];
-        for (int j = 0; j < nk; ++j)
-            if (cf.c[j] != 0.0) acc += (T)cf.c[j] * ks[j][q];
-        y_out[q] = acc;
+        T acc[W];
+        if constexpr (VEC) vload(y + q * W, acc); else acc[0] = y[q];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+            if (cf.c[j] == 0.0) continue;
+            T kv[W];
+            if constexpr (VEC) vload(ks.p[j] + q * W, kv); else kv[0] = ks.p[j][q];
+#pragma unroll
+            for (int w = 0; w < W; ++w) acc[w] += cj[j] * kv[w];
+        }
+        if constexpr (VEC) vstore(y_out + q * W, acc); else y_out[q] = acc[0];
     }
 }
 
-template <typename T>
+// Sum over magnetic components of (e/sc)^2 with e = sum_j c_j k_j (in double)
+// and sc = atol + rtol max(|y|, |y1|); also counts non-finite entries of y.
+template <typename T, bool VEC, bool PERCELL>
 __global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
-                                                     const T* __restrict__ y1, Coef7 cf,
-                                                     const T* k0, const T* k1, const T* k2,
-                                                     const T* k3, const T* k4, const T* k5,
-                                                     const T* k6, int nk, long N,
-                                                     const T* __restrict__ Ms_cell, double rtol,
-                                                     double atol, double* partials)
+                                                     const T* __restrict__ y1, Coef7 cf, Ptr7<T> ks,
+                                                     long N, const T* __restrict__ Ms_cell,
+                                                     double rtol, double atol, double* partials)
 {
-    const T* ks[7] = {k0, k1, k2, k3, k4, k5, k6};
+    constexpr int W = VEC ? V16<T>::n : 1;
     double acc = 0.0, bad = 0.0;
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * N;
+    const long nv = 3 * N / W;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
          q += (long)gridDim.x * blockDim.x) {
-        if (!isfinite((double)y[q])) bad += 1.0;
-        if (Ms_cell && Ms_cell[q % N] == (T)0) continue;
-        double e = 0.0;
-        for (int j = 0; j < nk; ++j)
-            if (cf.c[j] != 0.0) e += cf.c[j] * (double)ks[j][q];
-        const double a = fabs((double)y[q]), b = fabs((double)y1[q]);
-        const double sc = atol + rtol * (a > b ? a : b);
-        const double r = e / sc;
-        acc += r * r;
+        T a[W], b[W], ms[W];
+        if constexpr (VEC) {
+            vload(y + q * W, a);
+            vload(y1 + q * W, b);
+        } else {
+            a[0] = y[q];
+            b[0] = y1[q];
+        }
+        if constexpr (PERCELL) {
+            // W divides N, so a vector never straddles two components
+            const long cell = (q * W) % N;
+            if constexpr (VEC) vload(Ms_cell + cell, ms); else ms[0] = Ms_cell[cell];
+        }
+        double e[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) e[w] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            if (cf.c[j] == 0.0) continue;
+            T kv[W];
+            if constexpr (VEC) vload(ks.p[j] + q * W, kv); else kv[0] = ks.p[j][q];
+#pragma unroll
+            for (int w = 0; w < W; ++w) e[w] += cf.c[j] * (double)kv[w];
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (!isfinite((double)a[w])) bad += 1.0;
+            if (PERCELL && ms[w] == (T)0) continue;
+            const double ya = fabs((double)a[w]), yb = fabs((double)b[w]);
+            const double sc = atol + rtol * (ya > yb ? ya : yb);
+            const double r = e[w] / sc;
+            acc += r * r;
+        }
     }
     acc = block_sum(acc);
     bad = block_sum(bad);
@@ -1092,21 +1304,44 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
 // ---------------------------------------------------------------------------
 // Runge-Kutta helpers.
 // ---------------------------------------------------------------------------
+static bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
+
+template <typename T, int NK>
+static hipError_t launch_combine(Plan& p, T* y_out, const T* y, const Coef7& cf, const Ptr7<T>& ks,
+                                 bool vec)
+{
+    const long n3 = 3 * p.N;
+    const long work = vec ? n3 / V16<T>::n : n3;
+    const int blocks = (int)std::min<long>(blocks_for(work, 256), 8192);
+    if (vec)
+        k_rk_combine<T, NK, true><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
+    else
+        k_rk_combine<T, NK, false><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, T* const* k, int nk)
 {
     Coef7 cf{};
-    const T* ks[7] = {};
+    Ptr7<T> ks{};
+    bool vec = (p.N % V16<T>::n) == 0 && aligned16(y_out) && aligned16(y);
     for (int j = 0; j < nk; ++j) {
         cf.c[j] = h * a[j];
-        ks[j] = k[j];
+        ks.p[j] = k[j];
+        vec = vec && aligned16(k[j]);
     }
-    const long n3 = 3 * p.N;
-    const int blocks = (int)std::min<long>(blocks_for(n3, 256), 4096);
     return timed(p, MM_PASS_RK, [&] {
-        k_rk_combine<T><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks[0], ks[1], ks[2], ks[3],
-                                                      ks[4], ks[5], ks[6], nk, n3);
-        return hipGetLastError();
+        switch (nk) {
+        case 1: return launch_combine<T, 1>(p, y_out, y, cf, ks, vec);
+        case 2: return launch_combine<T, 2>(p, y_out, y, cf, ks, vec);
+        case 3: return launch_combine<T, 3>(p, y_out, y, cf, ks, vec);
+        case 4: return launch_combine<T, 4>(p, y_out, y, cf, ks, vec);
+        case 5: return launch_combine<T, 5>(p, y_out, y, cf, ks, vec);
+        case 6: return launch_combine<T, 6>(p, y_out, y, cf, ks, vec);
+        case 7: return launch_combine<T, 7>(p, y_out, y, cf, ks, vec);
+        }
+        return hipErrorInvalidValue;
     });
 }
 
@@ -1115,15 +1350,28 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
                          int nk, double rtol, double atol, double* out_dev)
 {
     Coef7 cf{};
-    const T* ks[7] = {};
-    for (int j = 0; j < nk; ++j) {
-        cf.c[j] = h * e[j];
-        ks[j] = k[j];
+    Ptr7<T> ks{};
+    bool vec = (p.N % V16<T>::n) == 0 && aligned16(y) && aligned16(y1) &&
+               (!p.percell || aligned16(p.Ms_cell));
+    for (int j = 0; j < 7; ++j) {
+        cf.c[j] = j < nk ? h * e[j] : 0.0;
+        ks.p[j] = j < nk ? k[j] : y;
+        vec = vec && aligned16(ks.p[j]);
     }
+    const T* msc = p.percell ? (const T*)p.Ms_cell : nullptr;
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
-        k_err_norm<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
-            y, y1, cf, ks[0], ks[1], ks[2], ks[3], ks[4], ks[5], ks[6], nk, p.N,
-            p.percell ? (const T*)p.Ms_cell : nullptr, rtol, atol, p.red);
+        if (vec && p.percell)
+            k_err_norm<T, true, true><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
+                                                                           rtol, atol, p.red);
+        else if (vec)
+            k_err_norm<T, true, false><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
+                                                                            rtol, atol, p.red);
+        else if (p.percell)
+            k_err_norm<T, false, true><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N,
+                                                                            msc, rtol, atol, p.red);
+        else
+            k_err_norm<T, false, false><<<kRedBlocks, kBlock, 0, p.stream>>>(
+                y, y1, cf, ks, p.N, msc, rtol, atol, p.red);
         return hipGetLastError();
     }));
     const double cnt = 3.0 * (double)p.n_magnetic;
