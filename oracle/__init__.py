@@ -87,6 +87,14 @@ def lib():
         L.or_max_torque.argtypes = [C.c_void_p, dp, C.c_double]
         L.or_max_torque.restype = C.c_double
         L.or_num_threads.restype = C.c_int
+        L.or_heff_vjp.argtypes = [C.c_void_p, dp, dp, C.c_uint, dp, dp]
+        L.or_llg_jvp.argtypes = [C.c_void_p, dp, dp, C.c_double, dp]
+        L.or_llg_vjp.argtypes = [C.c_void_p, dp, C.c_double, dp, dp, dp]
+        L.or_rk4.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, C.c_long, C.c_void_p]
+        L.or_rk4.restype = C.c_double
+        L.or_rk4_adjoint.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, C.c_long, C.c_void_p,
+                                     dp, dp]
+        L.or_rk4_adjoint.restype = C.c_double
         _lib = L
     return _lib
 
@@ -270,3 +278,47 @@ class Oracle:
 
     def max_torque(self, m, t=0.0) -> float:
         return float(lib().or_max_torque(self._c, _dp(self._m(m)), float(t)))
+
+    # ------------------------------------------------------------------
+    # differentiation (inverse design, Sec. 5.2)
+    # ------------------------------------------------------------------
+    def heff_vjp(self, m, w, terms=DEMAG | EXCH | ANIS):
+        """(H^T w, d(w.h)/dMs) for the linear field terms in `terms`."""
+        m, w = self._m(m), self._m(w)
+        gm = np.zeros_like(m)
+        gms = np.zeros(self.shape)
+        lib().or_heff_vjp(self._c, _dp(m), _dp(w), int(terms), _dp(gm), _dp(gms))
+        return gm, gms
+
+    def llg_jvp(self, m, v, t=0.0):
+        """Exact Jacobian-vector product of the LLG right-hand side."""
+        m, v = self._m(m), self._m(v)
+        out = np.zeros_like(m)
+        lib().or_llg_jvp(self._c, _dp(m), _dp(v), float(t), _dp(out))
+        return out
+
+    def llg_vjp(self, m, w, t=0.0):
+        """(J^T w, d(w.f)/dMs) of the LLG right-hand side at (m, t)."""
+        m, w = self._m(m), self._m(w)
+        gm = np.zeros_like(m)
+        gms = np.zeros(self.shape)
+        lib().or_llg_vjp(self._c, _dp(m), float(t), _dp(w), _dp(gm), _dp(gms))
+        return gm, gms
+
+    def rk4(self, m0, dt, nsteps, region, t0=0.0):
+        """Classical RK4; returns (m, loss) with loss = time average of the
+        region mean of m_z over the nsteps steps."""
+        m = self._m(m0).copy()
+        reg = np.ascontiguousarray(np.asarray(region, dtype=np.uint8).reshape(self.shape))
+        loss = lib().or_rk4(self._c, _dp(m), float(t0), float(dt), int(nsteps), reg.ctypes.data)
+        return m, loss
+
+    def rk4_adjoint(self, m0, dt, nsteps, region, t0=0.0):
+        """(loss, dloss/dMs per cell, dloss/dm0) by the discrete adjoint."""
+        m0 = self._m(m0)
+        reg = np.ascontiguousarray(np.asarray(region, dtype=np.uint8).reshape(self.shape))
+        gms = np.zeros(self.shape)
+        gm0 = np.zeros_like(m0)
+        loss = lib().or_rk4_adjoint(self._c, _dp(m0), float(t0), float(dt), int(nsteps),
+                                    reg.ctypes.data, _dp(gms), _dp(gm0))
+        return loss, gms, gm0

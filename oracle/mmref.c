@@ -915,3 +915,297 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* Differentiation: transposed field operator, LLG vector-Jacobian product,   */
+/* classical RK4 with a time-averaged region loss and its discrete adjoint.  */
+/* Supports the inverse-design use of the method (Sec. 5.2): gradients of a  */
+/* scalar objective with respect to the magnetisation and to the per-cell    */
+/* saturation magnetisation.  Pinned by dot-product tests against the        */
+/* forward operators and by central finite differences                       */
+/* (tests/test_oracle_adjoint.py).                                            */
+/* ------------------------------------------------------------------------- */
+
+/* (A~ v)_i = sum_nb (2/D^2) harmonic(A_i, A_nb) (v_nb - v_i): the symmetric
+ * part of the exchange operator, h_ex = diag(2/(mu0 Ms)) A~ m. */
+static void exch_core(const or_ctx *c, const double *v, double *out)
+{
+    long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    for (long t = 0; t < N; t++) {
+        long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+        double acc[3] = {0, 0, 0};
+        long nb[6][3] = {{i + 1, j, k}, {i - 1, j, k}, {i, j + 1, k},
+                         {i, j - 1, k}, {i, j, k + 1}, {i, j, k - 1}};
+        for (int q = 0; q < 6; q++) {
+            long a = nb[q][0], b = nb[q][1], e = nb[q][2];
+            if (a < 0 || a >= nx || b < 0 || b >= ny || e < 0 || e >= nz)
+                continue;
+            long s = cidx(c, a, b, e);
+            double Ai = c->A[t], As = c->A[s];
+            double hm = (Ai + As) != 0.0 ? Ai * As / (Ai + As) : 0.0;
+            double dk = c->d[q / 2];
+            double w = 2.0 / (dk * dk) * hm;
+            for (int comp = 0; comp < 3; comp++)
+                acc[comp] += w * (v[comp * N + s] - v[comp * N + t]);
+        }
+        for (int comp = 0; comp < 3; comp++)
+            out[comp * N + t] = acc[comp];
+    }
+}
+
+/* Demag kernel applied to a field without the Ms factor: (K w)_i. */
+static void demag_raw(or_ctx *c, const double *w, double *out)
+{
+    double *Ms = c->Ms;
+    double *ones = malloc(sizeof(double) * c->N);
+    for (long q = 0; q < c->N; q++)
+        ones[q] = 1.0;
+    c->Ms = ones;
+    or_demag(c, w, out);
+    c->Ms = Ms;
+    free(ones);
+}
+
+/* Transposed (linear part of the) effective field: for the terms in mask
+ * (demag, exchange, anisotropy; the Zeeman field does not depend on m),
+ * grad_m = H^T w and grad_ms_i += d(w . h)/d Ms_i at fixed m.  grad_ms may be
+ * NULL. */
+void or_heff_vjp(or_ctx *c, const double *m, const double *w, unsigned mask, double *grad_m,
+                 double *grad_ms)
+{
+    long N = c->N;
+    double *tmp = malloc(sizeof(double) * 3 * N), *tmp2 = malloc(sizeof(double) * 3 * N);
+    memset(grad_m, 0, sizeof(double) * 3 * N);
+    if (mask & OR_DEMAG) {
+        /* h = K (Ms m) on magnetic targets (zero on vacuum targets):
+         * H^T w = Ms (K w') with w' = w masked to magnetic cells, since
+         * K_ab(r) = K_ba(r) = K_ab(-r); d(w.h)/dMs_j = m_j . (K w')_j */
+        for (long q = 0; q < N; q++)
+            for (int a = 0; a < 3; a++)
+                tmp2[a * N + q] = c->Ms[q] != 0.0 ? w[a * N + q] : 0.0;
+        demag_raw(c, tmp2, tmp);
+        for (long q = 0; q < N; q++) {
+            for (int a = 0; a < 3; a++)
+                grad_m[a * N + q] += c->Ms[q] * tmp[a * N + q];
+            if (grad_ms)
+                grad_ms[q] += m[q] * tmp[q] + m[N + q] * tmp[N + q] + m[2 * N + q] * tmp[2 * N + q];
+        }
+    }
+    if (mask & OR_EXCH) {
+        /* h = diag(2/(mu0 Ms)) A~ m: H^T w = A~ (2 w/(mu0 Ms));
+         * d(w.h)/dMs_i = -2/(mu0 Ms_i^2) w_i . (A~ m)_i */
+        for (long q = 0; q < N; q++)
+            for (int a = 0; a < 3; a++)
+                tmp[a * N + q] = c->Ms[q] != 0.0 ? 2.0 * w[a * N + q] / (OR_MU0 * c->Ms[q]) : 0.0;
+        exch_core(c, tmp, tmp2);
+        for (long q = 0; q < 3 * N; q++)
+            grad_m[q] += tmp2[q];
+        if (grad_ms) {
+            exch_core(c, m, tmp2);
+            for (long q = 0; q < N; q++)
+                if (c->Ms[q] != 0.0)
+                    grad_ms[q] -= 2.0 / (OR_MU0 * c->Ms[q] * c->Ms[q]) *
+                                  (w[q] * tmp2[q] + w[N + q] * tmp2[N + q] + w[2 * N + q] * tmp2[2 * N + q]);
+        }
+    }
+    if (mask & OR_ANIS) {
+        for (long q = 0; q < N; q++) {
+            if (c->Ms[q] == 0.0)
+                continue;
+            double ew = c->eu[0] * w[q] + c->eu[1] * w[N + q] + c->eu[2] * w[2 * N + q];
+            double em = c->eu[0] * m[q] + c->eu[1] * m[N + q] + c->eu[2] * m[2 * N + q];
+            double pre = 2.0 * c->Ku / (OR_MU0 * c->Ms[q]);
+            for (int a = 0; a < 3; a++)
+                grad_m[a * N + q] += pre * c->eu[a] * ew;
+            if (grad_ms)
+                grad_ms[q] -= pre / c->Ms[q] * ew * em;
+        }
+    }
+    free(tmp);
+    free(tmp2);
+}
+
+/* Exact Jacobian-vector product of the LLG right-hand side at (m, t) along v
+ * (forward mode of Eq. llg with h = H m + h_zee(t)). */
+void or_llg_jvp(or_ctx *c, const double *m, const double *v, double t, double *out)
+{
+    long N = c->N;
+    double *h = malloc(sizeof(double) * 3 * N), *hv = malloc(sizeof(double) * 3 * N);
+    or_heff(c, m, t, (unsigned)c->terms, h);
+    or_heff(c, v, t, (unsigned)c->terms & ~(unsigned)OR_ZEEMAN, hv);
+    double g = OR_GAMMA / (1.0 + c->alpha * c->alpha), al = c->alpha;
+    for (long q = 0; q < N; q++) {
+        double M[3] = {m[q], m[N + q], m[2 * N + q]}, V[3] = {v[q], v[N + q], v[2 * N + q]};
+        double H[3] = {h[q], h[N + q], h[2 * N + q]}, HV[3] = {hv[q], hv[N + q], hv[2 * N + q]};
+        if (c->Ms[q] == 0.0) {
+            out[q] = out[N + q] = out[2 * N + q] = 0.0;
+            continue;
+        }
+        double mh[3], vh[3], mhv[3];
+#define CROSS(o, a, b) o[0] = a[1] * b[2] - a[2] * b[1], o[1] = a[2] * b[0] - a[0] * b[2], o[2] = a[0] * b[1] - a[1] * b[0]
+        CROSS(mh, M, H);
+        CROSS(vh, V, H);
+        CROSS(mhv, M, HV);
+        double dmh[3] = {vh[0] + mhv[0], vh[1] + mhv[1], vh[2] + mhv[2]}; /* d(m x h) */
+        double t1[3], t2[3];
+        CROSS(t1, V, mh);  /* v x (m x h) */
+        CROSS(t2, M, dmh); /* m x d(m x h) */
+#undef CROSS
+        for (int a = 0; a < 3; a++)
+            out[a * N + q] = -g * (dmh[a] + al * (t1[a] + t2[a]));
+    }
+    free(h);
+    free(hv);
+}
+
+/* Vector-Jacobian product of the LLG right-hand side at (m, t): grad_m =
+ * J^T w, and grad_ms += d(w . f)/dMs at fixed m (grad_ms may be NULL). */
+void or_llg_vjp(or_ctx *c, const double *m, double t, const double *w, double *grad_m,
+                double *grad_ms)
+{
+    long N = c->N;
+    double *h = malloc(sizeof(double) * 3 * N), *z = malloc(sizeof(double) * 3 * N);
+    double *hz = malloc(sizeof(double) * 3 * N);
+    or_heff(c, m, t, (unsigned)c->terms, h);
+    double g = OR_GAMMA / (1.0 + c->alpha * c->alpha), al = c->alpha;
+    for (long q = 0; q < N; q++) {
+        double M[3] = {m[q], m[N + q], m[2 * N + q]}, W[3] = {w[q], w[N + q], w[2 * N + q]};
+        double H[3] = {h[q], h[N + q], h[2 * N + q]};
+        if (c->Ms[q] == 0.0) {
+            for (int a = 0; a < 3; a++)
+                grad_m[a * N + q] = z[a * N + q] = 0.0;
+            continue;
+        }
+        double mh = M[0] * H[0] + M[1] * H[1] + M[2] * H[2];
+        double wm = W[0] * M[0] + W[1] * M[1] + W[2] * M[2];
+        double wh = W[0] * H[0] + W[1] * H[1] + W[2] * H[2];
+        double mm = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+        double hxw[3] = {H[1] * W[2] - H[2] * W[1], H[2] * W[0] - H[0] * W[2], H[0] * W[1] - H[1] * W[0]};
+        double wxm[3] = {W[1] * M[2] - W[2] * M[1], W[2] * M[0] - W[0] * M[2], W[0] * M[1] - W[1] * M[0]};
+        for (int a = 0; a < 3; a++) {
+            /* d(w.f)/dm at fixed h, and z = d(w.f)/dh */
+            grad_m[a * N + q] = -g * (hxw[a] + al * (W[a] * mh + H[a] * wm - 2.0 * M[a] * wh));
+            z[a * N + q] = -g * (wxm[a] + al * (M[a] * wm - W[a] * mm));
+        }
+    }
+    or_heff_vjp(c, m, z, (unsigned)c->terms & ~(unsigned)OR_ZEEMAN, hz, grad_ms);
+    for (long q = 0; q < 3 * N; q++)
+        grad_m[q] += hz[q];
+    free(h);
+    free(z);
+    free(hz);
+}
+
+static double region_mz(const or_ctx *c, const double *m, const unsigned char *region, long nreg)
+{
+    long double acc = 0.0L;
+    for (long q = 0; q < c->N; q++)
+        if (region[q])
+            acc += m[2 * c->N + q];
+    return (double)(acc / nreg);
+}
+
+static void rk4_step(or_ctx *c, const double *m, double t, double dt, double *out, double *ys[4])
+{
+    long n3 = 3 * c->N;
+    double *h = malloc(sizeof(double) * n3), *k = malloc(sizeof(double) * n3);
+    double *y = malloc(sizeof(double) * n3);
+    const double cs[4] = {0.0, 0.5, 0.5, 1.0}, wts[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    memcpy(y, m, sizeof(double) * n3);
+    memcpy(out, m, sizeof(double) * n3);
+    for (int s = 0; s < 4; s++) {
+        if (ys)
+            memcpy(ys[s], y, sizeof(double) * n3);
+        rhs_at(c, y, t + cs[s] * dt, c->alpha, 1, h, k);
+        for (long q = 0; q < n3; q++)
+            out[q] += dt * wts[s] * k[q];
+        if (s < 3)
+            for (long q = 0; q < n3; q++)
+                y[q] = m[q] + (s == 2 ? dt : 0.5 * dt) * k[q];
+    }
+    free(h);
+    free(k);
+    free(y);
+}
+
+/* Classical RK4 with fixed dt from t0; loss = (1/nsteps) sum_{n=1..nsteps}
+ * mean over the region of m_z(t_n).  m is advanced in place. */
+double or_rk4(or_ctx *c, double *m, double t0, double dt, long nsteps, const unsigned char *region)
+{
+    long n3 = 3 * c->N, nreg = 0;
+    for (long q = 0; q < c->N; q++)
+        nreg += region[q] ? 1 : 0;
+    double *nxt = malloc(sizeof(double) * n3);
+    long double loss = 0.0L;
+    for (long n = 0; n < nsteps; n++) {
+        rk4_step(c, m, t0 + n * dt, dt, nxt, NULL);
+        memcpy(m, nxt, sizeof(double) * n3);
+        loss += region_mz(c, m, region, nreg);
+    }
+    free(nxt);
+    return (double)(loss / nsteps);
+}
+
+/* Discrete adjoint of or_rk4: gradient of the loss with respect to the
+ * per-cell Ms (grad_ms, N values) and to the initial state (grad_m0, 3N,
+ * may be NULL).  Every state is kept (no checkpointing): plain reverse-mode
+ * differentiation of each step y1 = m, y2 = m + dt/2 k1, y3 = m + dt/2 k2,
+ * y4 = m + dt k3, m' = m + dt (k1 + 2 k2 + 2 k3 + k4)/6. */
+double or_rk4_adjoint(or_ctx *c, const double *m0, double t0, double dt, long nsteps,
+                      const unsigned char *region, double *grad_ms, double *grad_m0)
+{
+    long N = c->N, n3 = 3 * N, nreg = 0;
+    for (long q = 0; q < N; q++)
+        nreg += region[q] ? 1 : 0;
+    double *traj = malloc(sizeof(double) * n3 * (nsteps + 1));
+    memcpy(traj, m0, sizeof(double) * n3);
+    long double loss = 0.0L;
+    for (long n = 0; n < nsteps; n++) {
+        rk4_step(c, traj + n * n3, t0 + n * dt, dt, traj + (n + 1) * n3, NULL);
+        loss += region_mz(c, traj + (n + 1) * n3, region, nreg);
+    }
+    double *lam = calloc(n3, sizeof(double)), *kap = malloc(sizeof(double) * n3);
+    double *nu[4], *ys[4];
+    for (int s = 0; s < 4; s++) {
+        nu[s] = malloc(sizeof(double) * n3);
+        ys[s] = malloc(sizeof(double) * n3);
+    }
+    double *scratch = malloc(sizeof(double) * n3);
+    memset(grad_ms, 0, sizeof(double) * N);
+    const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    const double dL = 1.0 / ((double)nsteps * (double)nreg);
+    for (long n = nsteps - 1; n >= 0; n--) {
+        /* explicit dependence of the loss on m_{n+1} */
+        for (long q = 0; q < N; q++)
+            if (region[q])
+                lam[2 * N + q] += dL;
+        rk4_step(c, traj + n * n3, t0 + n * dt, dt, scratch, ys);
+        double tn = t0 + n * dt;
+        /* stage 4, 3, 2, 1 */
+        for (long q = 0; q < n3; q++)
+            kap[q] = dt / 6.0 * lam[q];
+        or_llg_vjp(c, ys[3], tn + cs[3] * dt, kap, nu[3], grad_ms);
+        for (long q = 0; q < n3; q++)
+            kap[q] = dt / 3.0 * lam[q] + dt * nu[3][q];
+        or_llg_vjp(c, ys[2], tn + cs[2] * dt, kap, nu[2], grad_ms);
+        for (long q = 0; q < n3; q++)
+            kap[q] = dt / 3.0 * lam[q] + 0.5 * dt * nu[2][q];
+        or_llg_vjp(c, ys[1], tn + cs[1] * dt, kap, nu[1], grad_ms);
+        for (long q = 0; q < n3; q++)
+            kap[q] = dt / 6.0 * lam[q] + 0.5 * dt * nu[1][q];
+        or_llg_vjp(c, ys[0], tn + cs[0] * dt, kap, nu[0], grad_ms);
+        for (long q = 0; q < n3; q++)
+            lam[q] += nu[0][q] + nu[1][q] + nu[2][q] + nu[3][q];
+    }
+    if (grad_m0)
+        memcpy(grad_m0, lam, sizeof(double) * n3);
+    for (int s = 0; s < 4; s++) {
+        free(nu[s]);
+        free(ys[s]);
+    }
+    free(traj);
+    free(lam);
+    free(kap);
+    free(scratch);
+    return (double)(loss / nsteps);
+}
