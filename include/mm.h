@@ -176,6 +176,56 @@ mm_status mm_energy(mm_plan *p, const void *m, const double h_ext[3], unsigned t
 mm_status mm_max_torque(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,
                         double t, double *out);
 
+/* ---- Differentiation (Sec. 5.2, inverse design by reverse-mode gradients) --
+ * The effective field is affine in m: h = H m + h_zee(t), with H the sum of
+ * the demag, exchange and anisotropy operators (Sec. 4).  These entry points
+ * give the exact transposes used by reverse-mode differentiation; the Zeeman
+ * term carries no m dependence and is ignored by the products.  All vectors
+ * are device buffers of 3N reals of the plan's precision in the component-
+ * major layout of mm_heff; grad_ms is N reals (per-cell saturation
+ * magnetisation), optional (NULL) where stated.  Gradients with respect to
+ * Ms treat the plan's Ms (uniform or per cell) as a per-cell field and are
+ * accumulated in double on the device, then rounded to the plan's precision.
+ * The first call allocates 16 work vectors of 3N reals (and N doubles),
+ * released by mm_plan_destroy.  None of them synchronise except where noted. */
+
+/* Transposed effective field: grad_m = H^T w and grad_ms = d(w . h)/dMs at
+ * fixed m, for the terms in `terms` (the demag transpose reuses the resident
+ * spectral tensor; the operator is symmetric as K_ab(r) = K_ba(-r)).  grad_m
+ * must not alias m or w.  MM_EINVAL on null or aliased vectors. */
+mm_status mm_heff_vjp(mm_plan *p, const void *m, const void *w, unsigned terms, void *grad_m,
+                      void *grad_ms);
+
+/* Vector-Jacobian product of the LLG right-hand side (Eq. llg with the
+ * plan's alpha) at (m, t): grad_m = J^T w, grad_ms = d(w . dm/dt)/dMs at
+ * fixed m (the field of m is recomputed first).  Same aliasing rules. */
+mm_status mm_llg_rhs_vjp(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,
+                         double t, const void *w, void *grad_m, void *grad_ms);
+
+/* Classical fourth-order Runge-Kutta integration with fixed step dt from t0
+ * over nsteps steps (m advanced in place), with the time-averaged region loss
+ *     L = (1/nsteps) sum_{n=1..nsteps} mean_{i in region} m_z,i(t_n)
+ * written to *loss (0 if region is NULL or empty; loss may be NULL).  region
+ * is N device bytes (nonzero = in the region).  If ckpt is not NULL it
+ * receives the state before every step n with n % ckpt_every == 0:
+ * ceil(nsteps / ckpt_every) vectors of 3N reals (the input of
+ * mm_rk4_adjoint).  Synchronises at the end (and once to count the region). */
+mm_status mm_rk4_forward(mm_plan *p, void *m, const double h_ext[3], unsigned terms, double t0,
+                         double dt, long nsteps, const unsigned char *region, long ckpt_every,
+                         void *ckpt, double *loss);
+
+/* Discrete adjoint of mm_rk4_forward (reverse sweep over every RK4 stage, with
+ * the LLG vector-Jacobian products above): from the checkpoints written by a
+ * forward call with the same arguments, recomputes each segment of
+ * ckpt_every steps, storing its 4 stage states and 4 stage fields per step
+ * (a device segment of 8 ckpt_every vectors, allocated and kept by the plan),
+ * and sweeps it backwards.  Writes dL/dMs (N reals, may be NULL) and dL/dm0
+ * (3N reals, may be NULL), and the recomputed loss to *loss (may be NULL).
+ * region must not be NULL.  Synchronises at the end. */
+mm_status mm_rk4_adjoint(mm_plan *p, const void *ckpt, const double h_ext[3], unsigned terms,
+                         double t0, double dt, long nsteps, const unsigned char *region,
+                         long ckpt_every, void *grad_ms, void *grad_m0, double *loss);
+
 /* Per-pass timing with HIP events recorded on the plan's stream around every
  * launch of the field pipeline (diagnostics for roofline measurements).
  * Passes: x forward transform, y forward transform, last-axis transform with

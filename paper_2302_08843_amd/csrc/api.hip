@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <vector>
 
 #include "engine.h"
 
@@ -50,7 +51,7 @@ static void free_plan(Plan* p)
     }
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->mask, p->rk, p->red, p->red_out};
+                    p->mask, p->rk, p->red, p->red_out, p->adj, p->seg, p->gms};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->host_out) (void)hipHostFree(p->host_out);
@@ -99,6 +100,25 @@ static mm_status fetch(Plan* p, int n)
            "reading a reduction");
     MM_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
     return MM_OK;
+}
+
+static mm_status ensure_adj(Plan* p)
+{
+    if (!p->adj) {
+        mm_status s = alloc(p, &p->adj, 16 * 3 * (size_t)p->N * elem_size(*p), "adjoint buffers");
+        if (s != MM_OK) return s;
+    }
+    if (!p->gms) {
+        mm_status s = alloc(p, (void**)&p->gms, sizeof(double) * (size_t)p->N, "Ms gradient");
+        if (s != MM_OK) return s;
+    }
+    return MM_OK;
+}
+
+template <typename T>
+static T* adj_vec(Plan* p, int i)
+{
+    return (T*)p->adj + (size_t)i * 3 * p->N;
 }
 
 // ---------------------------------------------------------------------------
@@ -245,6 +265,190 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
 using namespace mmx;
 
 namespace mmx {
+
+// Adjoint work-space layout (vectors of 3N): 0 y, 1 ynew, 2 ys, 3-6 k1..k4,
+// 7 z, 8 g, 9 lambda, 10 kappa, 11-14 nu1..nu4, 15 field scratch.
+template <typename T>
+static mm_status rk4_step_impl(Plan* p, T* y, T* ynew, const double hext[3], unsigned terms,
+                               double t, double dt, T* const* ys_store, T* const* hs_store)
+{
+    T* k[4] = {adj_vec<T>(p, 3), adj_vec<T>(p, 4), adj_vec<T>(p, 5), adj_vec<T>(p, 6)};
+    T* ys = adj_vec<T>(p, 2);
+    const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    const double half = 0.5, one = 1.0;
+    for (int st = 0; st < 4; ++st) {
+        const T* in = y;
+        if (st > 0) {
+            T* prev = k[st - 1];
+            MM_HIP(rk_combine<T>(*p, ys, y, dt, st == 3 ? &one : &half, &prev, 1), "stage input");
+            in = ys;
+        }
+        if (ys_store)
+            MM_HIP(hipMemcpyAsync(ys_store[st], in, 3 * (size_t)p->N * sizeof(T),
+                                  hipMemcpyDeviceToDevice, p->stream),
+                   "store stage");
+        MM_HIP(eval_field<T>(*p, in, hext, terms, t + cs[st] * dt, hs_store ? hs_store[st] : nullptr,
+                             k[st], p->alpha, true, nullptr),
+               "right-hand side");
+    }
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    MM_HIP(rk_combine<T>(*p, ynew, y, dt, b, k, 4), "RK4 update");
+    return MM_OK;
+}
+
+// number of cells in a region mask: the region sum of m_z for a vector whose
+// z component is one on the region and zero elsewhere
+template <typename T>
+static mm_status count_region(Plan* p, const unsigned char* region, long* nreg)
+{
+    T* ind = adj_vec<T>(p, 15);
+    MM_HIP(hipMemsetAsync(ind, 0, 3 * (size_t)p->N * sizeof(T), p->stream), "clear");
+    MM_HIP(add_region<T>(*p, ind, region, 1.0), "region indicator");
+    MM_HIP(hipMemsetAsync(p->red_out + 7, 0, sizeof(double), p->stream), "clear");
+    MM_HIP(region_mz_accum<T>(*p, ind, region, p->red_out + 7, 1.0), "count region");
+    mm_status s = fetch(p, 8);
+    if (s != MM_OK) return s;
+    *nreg = (long)std::llround(p->host_out[7]);
+    return MM_OK;
+}
+
+template <typename T>
+static mm_status rk4_forward_impl(Plan* p, void* m_user, const double hext[3], unsigned terms,
+                                  double t0, double dt, long nsteps, const unsigned char* region,
+                                  long every, void* ckpt, double* loss)
+{
+    mm_status s = ensure_adj(p);
+    if (s != MM_OK) return s;
+    const size_t vb = 3 * (size_t)p->N * sizeof(T);
+    long nreg = 0;
+    if (region) {
+        s = count_region<T>(p, region, &nreg);
+        if (s != MM_OK) return s;
+    }
+    T* y = adj_vec<T>(p, 0);
+    T* ynew = adj_vec<T>(p, 1);
+    MM_HIP(hipMemcpyAsync(y, m_user, vb, hipMemcpyDeviceToDevice, p->stream), "copy m");
+    MM_HIP(hipMemsetAsync(p->red_out + 6, 0, sizeof(double), p->stream), "clear loss");
+    for (long n = 0; n < nsteps; ++n) {
+        if (ckpt && every > 0 && n % every == 0)
+            MM_HIP(hipMemcpyAsync((T*)ckpt + (size_t)(n / every) * 3 * p->N, y, vb,
+                                  hipMemcpyDeviceToDevice, p->stream),
+                   "checkpoint");
+        s = rk4_step_impl<T>(p, y, ynew, hext, terms, t0 + n * dt, dt, nullptr, nullptr);
+        if (s != MM_OK) return s;
+        std::swap(y, ynew);
+        if (region && nreg > 0) MM_HIP(region_mz_accum<T>(*p, y, region, p->red_out + 6, 1.0), "loss");
+    }
+    MM_HIP(hipMemcpyAsync(m_user, y, vb, hipMemcpyDeviceToDevice, p->stream), "copy m");
+    s = fetch(p, 7);
+    if (s != MM_OK) return s;
+    if (loss) *loss = (region && nreg > 0 && nsteps > 0) ? p->host_out[6] / ((double)nsteps * nreg) : 0.0;
+    return MM_OK;
+}
+
+template <typename T>
+static mm_status rk4_adjoint_impl(Plan* p, const void* ckpt, const double hext[3], unsigned terms,
+                                  double t0, double dt, long nsteps, const unsigned char* region,
+                                  long every, void* grad_ms, void* grad_m0, double* loss)
+{
+    mm_status s = ensure_adj(p);
+    if (s != MM_OK) return s;
+    const size_t vb = 3 * (size_t)p->N * sizeof(T);
+    const size_t need = (size_t)every * 8 * vb;
+    if (p->seg_bytes < need) {
+        if (p->seg) {
+            (void)hipFree(p->seg);
+            p->bytes -= p->seg_bytes;
+            p->seg = nullptr;
+            p->seg_bytes = 0;
+        }
+        s = alloc(p, &p->seg, need, "checkpoint segment");
+        if (s != MM_OK) return s;
+        p->seg_bytes = need;
+    }
+    long nreg = 0;
+    s = count_region<T>(p, region, &nreg);
+    if (s != MM_OK) return s;
+    const double dL = nreg > 0 ? 1.0 / ((double)nsteps * nreg) : 0.0;
+    const unsigned vterms = terms & ~(unsigned)MM_ZEEMAN;
+    T* y = adj_vec<T>(p, 0);
+    T* ynew = adj_vec<T>(p, 1);
+    T* z = adj_vec<T>(p, 7);
+    T* g = adj_vec<T>(p, 8);
+    T* lam = adj_vec<T>(p, 9);
+    T* kap = adj_vec<T>(p, 10);
+    T* nu[4] = {adj_vec<T>(p, 11), adj_vec<T>(p, 12), adj_vec<T>(p, 13), adj_vec<T>(p, 14)};
+    MM_HIP(hipMemsetAsync(lam, 0, vb, p->stream), "clear lambda");
+    MM_HIP(zero_doubles(*p, p->gms, p->N), "clear gradient");
+    MM_HIP(hipMemsetAsync(p->red_out + 6, 0, sizeof(double), p->stream), "clear loss");
+    const long nseg = (nsteps + every - 1) / every;
+    auto Ys = [&](long i, int st) { return (T*)p->seg + ((size_t)i * 8 + st) * 3 * p->N; };
+    auto Hs = [&](long i, int st) { return (T*)p->seg + ((size_t)i * 8 + 4 + st) * 3 * p->N; };
+    for (long sg = nseg - 1; sg >= 0; --sg) {
+        const long n0 = sg * every, n1 = std::min(nsteps, n0 + every);
+        MM_HIP(hipMemcpyAsync(y, (const T*)ckpt + (size_t)sg * 3 * p->N, vb,
+                              hipMemcpyDeviceToDevice, p->stream),
+               "restore checkpoint");
+        for (long n = n0; n < n1; ++n) {
+            T* ysv[4] = {Ys(n - n0, 0), Ys(n - n0, 1), Ys(n - n0, 2), Ys(n - n0, 3)};
+            T* hsv[4] = {Hs(n - n0, 0), Hs(n - n0, 1), Hs(n - n0, 2), Hs(n - n0, 3)};
+            s = rk4_step_impl<T>(p, y, ynew, hext, terms, t0 + n * dt, dt, ysv, hsv);
+            if (s != MM_OK) return s;
+            std::swap(y, ynew);
+            MM_HIP(region_mz_accum<T>(*p, y, region, p->red_out + 6, 1.0), "loss");
+        }
+        for (long n = n1 - 1; n >= n0; --n) {
+            const long i = n - n0;
+            MM_HIP(add_region<T>(*p, lam, region, dL), "loss gradient");
+            // kappa_4 = dt/6 lam;  kappa_3 = dt/3 lam + dt nu_4;
+            // kappa_2 = dt/3 lam + dt/2 nu_3;  kappa_1 = dt/6 lam + dt/2 nu_2
+            const double cl[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+            const double cn[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+            for (int st = 3; st >= 0; --st) {
+                if (st == 3) {
+                    T* v1[1] = {lam};
+                    MM_HIP(lincomb<T>(*p, kap, &cl[3], v1, 1), "cotangent");
+                } else {
+                    T* v2[2] = {lam, nu[st + 1]};
+                    const double c2[2] = {cl[st], cn[st + 1]};
+                    MM_HIP(lincomb<T>(*p, kap, c2, v2, 2), "cotangent");
+                }
+                MM_HIP(field_vjp<T>(*p, Ys(i, st), kap, Hs(i, st), vterms, p->alpha, g, z, nu[st],
+                                    p->gms),
+                       "vector-Jacobian product");
+            }
+            T* v5[5] = {lam, nu[0], nu[1], nu[2], nu[3]};
+            const double c5[5] = {1.0, 1.0, 1.0, 1.0, 1.0};
+            MM_HIP(lincomb<T>(*p, lam, c5, v5, 5), "adjoint update");
+        }
+    }
+    if (grad_m0)
+        MM_HIP(hipMemcpyAsync(grad_m0, lam, vb, hipMemcpyDeviceToDevice, p->stream), "grad m0");
+    if (grad_ms) MM_HIP(from_double<T>(*p, p->gms, (T*)grad_ms, p->N), "grad Ms");
+    s = fetch(p, 7);
+    if (s != MM_OK) return s;
+    if (loss) *loss = nreg > 0 ? p->host_out[6] / ((double)nsteps * nreg) : 0.0;
+    return MM_OK;
+}
+
+template <typename T>
+static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hext[3],
+                               unsigned terms, double t, bool llg, T* grad_m, T* grad_ms)
+{
+    mm_status s = ensure_adj(p);
+    if (s != MM_OK) return s;
+    T* h = nullptr;
+    if (llg) {
+        h = adj_vec<T>(p, 15);
+        MM_HIP(eval_field<T>(*p, m, hext, terms, t, h, nullptr, p->alpha, true, nullptr), "field");
+    }
+    MM_HIP(zero_doubles(*p, p->gms, p->N), "clear gradient");
+    MM_HIP(field_vjp<T>(*p, m, w, h, terms & ~(unsigned)MM_ZEEMAN, p->alpha, adj_vec<T>(p, 8),
+                        adj_vec<T>(p, 7), grad_m, p->gms),
+           "vector-Jacobian product");
+    if (grad_ms) MM_HIP(from_double<T>(*p, p->gms, grad_ms, p->N), "grad Ms");
+    return MM_OK;
+}
 
 template <typename T>
 static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigned terms, double t,
@@ -582,6 +786,66 @@ mm_status mm_max_torque(mm_plan* pl, const void* m, const double h_ext[3], unsig
     if (s != MM_OK) return s;
     *out = p->host_out[1];
     return MM_OK;
+}
+
+mm_status mm_heff_vjp(mm_plan* pl, const void* m, const void* w, unsigned terms, void* grad_m,
+                      void* grad_ms)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !m || !w || !grad_m || grad_m == m || grad_m == w) {
+        set_error("null or aliased argument");
+        return MM_EINVAL;
+    }
+    return p->prec == MM_FP32
+               ? heff_vjp_impl<float>(p, (const float*)m, (const float*)w, nullptr, terms, 0.0, false,
+                                      (float*)grad_m, (float*)grad_ms)
+               : heff_vjp_impl<double>(p, (const double*)m, (const double*)w, nullptr, terms, 0.0,
+                                       false, (double*)grad_m, (double*)grad_ms);
+}
+
+mm_status mm_llg_rhs_vjp(mm_plan* pl, const void* m, const double h_ext[3], unsigned terms,
+                         double t, const void* w, void* grad_m, void* grad_ms)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !m || !w || !grad_m || grad_m == m || grad_m == w) {
+        set_error("null or aliased argument");
+        return MM_EINVAL;
+    }
+    return p->prec == MM_FP32
+               ? heff_vjp_impl<float>(p, (const float*)m, (const float*)w, h_ext, terms, t, true,
+                                      (float*)grad_m, (float*)grad_ms)
+               : heff_vjp_impl<double>(p, (const double*)m, (const double*)w, h_ext, terms, t, true,
+                                       (double*)grad_m, (double*)grad_ms);
+}
+
+mm_status mm_rk4_forward(mm_plan* pl, void* m, const double h_ext[3], unsigned terms, double t0,
+                         double dt, long nsteps, const unsigned char* region, long ckpt_every,
+                         void* ckpt, double* loss)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !m || nsteps < 0 || !(dt > 0.0) || (ckpt && ckpt_every <= 0)) {
+        set_error("invalid argument");
+        return MM_EINVAL;
+    }
+    return p->prec == MM_FP32 ? rk4_forward_impl<float>(p, m, h_ext, terms, t0, dt, nsteps, region,
+                                                        ckpt_every, ckpt, loss)
+                              : rk4_forward_impl<double>(p, m, h_ext, terms, t0, dt, nsteps, region,
+                                                         ckpt_every, ckpt, loss);
+}
+
+mm_status mm_rk4_adjoint(mm_plan* pl, const void* ckpt, const double h_ext[3], unsigned terms,
+                         double t0, double dt, long nsteps, const unsigned char* region,
+                         long ckpt_every, void* grad_ms, void* grad_m0, double* loss)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !ckpt || !region || nsteps <= 0 || !(dt > 0.0) || ckpt_every <= 0) {
+        set_error("invalid argument");
+        return MM_EINVAL;
+    }
+    return p->prec == MM_FP32 ? rk4_adjoint_impl<float>(p, ckpt, h_ext, terms, t0, dt, nsteps, region,
+                                                        ckpt_every, grad_ms, grad_m0, loss)
+                              : rk4_adjoint_impl<double>(p, ckpt, h_ext, terms, t0, dt, nsteps,
+                                                         region, ckpt_every, grad_ms, grad_m0, loss);
 }
 
 mm_status mm_profile(mm_plan* pl, int enable)

@@ -69,6 +69,11 @@ struct Plan {
     double *red = nullptr;    // reduction partials (kRedSlots doubles)
     double *red_out = nullptr;  // reduction results (8 doubles)
     double *host_out = nullptr; // pinned host mirror of red_out
+    // differentiation work space (allocated on first use)
+    void *adj = nullptr;        // 16 vectors of 3N
+    void *seg = nullptr;        // stage states and fields of one checkpoint segment
+    size_t seg_bytes = 0;
+    double *gms = nullptr;      // N doubles: Ms-gradient accumulator
     size_t bytes = 0;
     Profiler prof;
 };
@@ -120,6 +125,26 @@ hipError_t start_norms(Plan &p, const T *y, const T *f0, const T *f1, double rto
 // Count magnetic cells (Ms > 0) into *out_dev.
 template <typename T>
 hipError_t count_magnetic(Plan &p, double *out_dev);
+// Transposed field / LLG right-hand side.  With h == nullptr: nu = H^T w
+// (w masked to magnetic cells).  With h (the field at m): nu = J^T w of the
+// LLG right-hand side with damping alpha.  gms (double, may be null)
+// accumulates d(w.h)/dMs resp. d(w.f)/dMs.  g_tmp and z_tmp are 3N scratch.
+template <typename T>
+hipError_t field_vjp(Plan &p, const T *m, const T *w, const T *h, unsigned terms, double alpha,
+                     T *g_tmp, T *z_tmp, T *nu, double *gms);
+// out = sum_{j < nk} c[j] v[j]  (nk <= 6)
+template <typename T>
+hipError_t lincomb(Plan &p, T *out, const double *c, T *const *v, int nk);
+// *out_dev += scale * sum over region of m_z
+template <typename T>
+hipError_t region_mz_accum(Plan &p, const T *m, const unsigned char *region, double *out_dev,
+                           double scale);
+// lam_z += val on the region
+template <typename T>
+hipError_t add_region(Plan &p, T *lam, const unsigned char *region, double val);
+hipError_t zero_doubles(Plan &p, double *ptr, long n);
+template <typename T>
+hipError_t from_double(Plan &p, const double *in, T *out, long n);
 // Debug: real-space kernel (component s) placed in the padded grid, doubles.
 hipError_t debug_kernel(Plan &p, int s, double *out);
 template <typename T>

@@ -252,9 +252,6 @@ __global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_str
 // spectral kernel, inverse transform, store the first n_valid elements.
 // AXIS = 2: pencils along z, group g = ky.  AXIS = 1: pencils along y (Pz=1).
 // ---------------------------------------------------------------------------
-#ifndef MMX_MID_CHUNK
-#define MMX_MID_CHUNK 0
-#endif
 template <typename T, int L>
 struct Mid {
     using S = FFTShape<L, Regs<T>::mid>;
@@ -291,9 +288,6 @@ __device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Kha
         const long plane = (long)(hy + 1) * Hxp;
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
-            // Keep the scheduler from hoisting every kernel load of the
-            // pencil at once (that alone would hold 6 kE registers).
-            if (MMX_MID_CHUNK > 0 && i > 0 && i % MMX_MID_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
             const int kk = G::S::out_index(t, i);
             int ky, kz;
             if constexpr (AXIS == 2) {
@@ -407,6 +401,72 @@ __device__ inline void atomic_max_nonneg(double* addr, double v)
     atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
+// Inverse real x transform of kRows rows (j0 .. j0+kRows-1 at slab k) of
+// three components from the spectrum S1 into LDS: component c of row rl ends
+// as reals at lds + (rl*3 + c)*kL (x = 0 .. 2M-1, only x < M written).
+// 2M-point real inverse via an M-point complex inverse of
+//   2 Z[n] = (X[n] + conj X[M-n]) + i w^-n (X[n] - conj X[M-n]).
+// Contains barriers: every thread of the block must call it.
+template <typename T, int M>
+__device__ __forceinline__ void x_c2r_rows(const cx<T>* __restrict__ S1, cx<T>* lds, int k, int j0,
+                                           int ny, long s1_comp, int Hxp,
+                                           const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = XC2R<T, M>;
+    if constexpr (M >= 2) {
+        constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows, kL = G::kL;
+        const int t = threadIdx.x % kT;
+        const int c = (threadIdx.x / kT) % 3;
+        const int rl = threadIdx.x / (3 * kT);
+        const int j = j0 + rl;
+        const bool valid = rl < kRows && j < ny;
+        const cx<T>* X = S1 + c * s1_comp + ((long)k * ny + (valid ? j : 0)) * Hxp;
+        const int tws = Lmax / (2 * M);
+        cx<T> v[kE];
+#pragma unroll
+        for (int r = 0; r < kE; ++r) {
+            const int n = t + r * kT;
+            cx<T> z = {0, 0};
+            if (valid) {
+                const cx<T> a = X[n], bb = X[M - n];
+                const cx<T> D = {a.x - bb.x, a.y + bb.y};
+                const cx<T> wD = cmulc(D, tw[n * tws]);
+                z = {a.x + bb.x - wD.y, a.y - bb.y + wD.x};
+            }
+            v[r] = z;
+        }
+        cx<T>* L = lds + (rl * 3 + c) * kL;
+        WgFFT<T, M, Regs<T>::x1, 1>::run(v, t, L, 1, tw, Lmax / M);
+        __syncthreads();
+        T* hd = reinterpret_cast<T*>(L);
+        constexpr int Rl = G::S::kLast;
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            // outputs n >= M/2 are cells x >= M >= nx: never used
+            if ((i % Rl) >= Rl / 2) continue;
+            const int e = G::S::out_index(t, i);
+            hd[2 * e] = v[i].x;
+            hd[2 * e + 1] = v[i].y;
+        }
+        __syncthreads();
+    }
+}
+
+// Demag value of component c at cell i of row rl after x_c2r_rows (or, for a
+// single cell along x, straight from the spectrum).
+template <typename T, int M>
+__device__ __forceinline__ T x_c2r_value(const cx<T>* __restrict__ S1, const cx<T>* lds, int rl,
+                                         int c, int i, int k, int j, int ny, long s1_comp, int Hxp)
+{
+    using G = XC2R<T, M>;
+    if constexpr (M >= 2) {
+        const T* hd = reinterpret_cast<const T*>(lds + (rl * 3 + c) * G::kL);
+        return hd[i];
+    } else {
+        return S1[c * s1_comp + ((long)k * ny + j) * Hxp].x;
+    }
+}
+
 template <typename T, int M, bool PERCELL>
 __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
@@ -414,7 +474,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax)
 {
     using G = XC2R<T, M>;
-    constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows, Mf = G::Mf, kL = G::kL;
+    constexpr int kRows = G::kRows, kL = G::kL;
     __shared__ cx<T> lds[kRows * 3 * kL];
     const long lb = xcd_logical();
     if (lb >= nblocks) return;
@@ -422,45 +482,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     const int j0 = (int)(lb % njt) * kRows;
     const int nx = P.nx, ny = P.ny;
 
-    if constexpr (M >= 2) {
-        if (P.with_demag) {
-            const int t = threadIdx.x % kT;
-            const int c = (threadIdx.x / kT) % 3;
-            const int rl = threadIdx.x / (3 * kT);
-            const int j = j0 + rl;
-            const bool valid = rl < kRows && j < ny;
-            const cx<T>* X = S1 + c * P.s1_comp + ((long)k * ny + (valid ? j : 0)) * P.Hxp;
-            const int tws = Lmax / (2 * M);
-            cx<T> v[kE];
-#pragma unroll
-            for (int r = 0; r < kE; ++r) {
-                const int n = t + r * kT;
-                cx<T> z = {0, 0};
-                if (valid) {
-                    const cx<T> a = X[n], bb = X[M - n];
-                    // 2 Z[n] = (a + conj b) + i w^-n (a - conj b)
-                    const cx<T> D = {a.x - bb.x, a.y + bb.y};
-                    const cx<T> wD = cmulc(D, tw[n * tws]);
-                    z = {a.x + bb.x - wD.y, a.y - bb.y + wD.x};
-                }
-                v[r] = z;
-            }
-            cx<T>* L = lds + (rl * 3 + c) * kL;
-            WgFFT<T, M, Regs<T>::x1, 1>::run(v, t, L, 1, tw, Lmax / M);
-            __syncthreads();
-            T* hd = reinterpret_cast<T*>(L);
-            constexpr int Rl = G::S::kLast;
-#pragma unroll
-            for (int i = 0; i < kE; ++i) {
-                // outputs n >= M/2 are cells x >= M >= nx: never used
-                if ((i % Rl) >= Rl / 2) continue;
-                const int e = G::S::out_index(t, i);
-                hd[2 * e] = v[i].x;
-                hd[2 * e + 1] = v[i].y;
-            }
-            __syncthreads();
-        }
-    }
+    if (P.with_demag) x_c2r_rows<T, M>(S1, lds, k, j0, ny, P.s1_comp, P.Hxp, tw, Lmax);
 
     const long N = P.N;
     const T exch = (T)P.exch, anis = (T)P.anis;
@@ -477,17 +499,9 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
         const T mx = m[cell], my = m[N + cell], mz = m[2 * N + cell];
         if (ms != (T)0) {
             if (P.with_demag) {
-                if constexpr (M >= 2) {
-                    const T* hd = reinterpret_cast<const T*>(lds + rl * 3 * kL);
-                    hx = hd[i];
-                    hy = hd[2 * kL + i];
-                    hz = hd[4 * kL + i];
-                } else {
-                    const cx<T>* X = S1 + ((long)k * ny + j) * P.Hxp;
-                    hx = X[0].x;
-                    hy = X[P.s1_comp].x;
-                    hz = X[2 * P.s1_comp].x;
-                }
+                hx = x_c2r_value<T, M>(S1, lds, rl, 0, i, k, j, ny, P.s1_comp, P.Hxp);
+                hy = x_c2r_value<T, M>(S1, lds, rl, 1, i, k, j, ny, P.s1_comp, P.Hxp);
+                hz = x_c2r_value<T, M>(S1, lds, rl, 2, i, k, j, ny, P.s1_comp, P.Hxp);
             }
             const T inv_ms = (T)1 / ms;
             if (P.with_exch) {
@@ -962,6 +976,236 @@ __global__ __launch_bounds__(kBlock) void k_count_mag(const T* __restrict__ Ms_c
 }
 
 // ---------------------------------------------------------------------------
+// Differentiation (inverse design).  The effective field is h = H m + h_zee
+// with H the demag (K Ms m), exchange (diag(2/(mu0 Ms)) A~ m) and anisotropy
+// parts; K is symmetric and even, A~ symmetric, so
+//   H^T z = Ms (K z) + A~ (2 z/(mu0 Ms)) + (2 Ku/(mu0 Ms)) e (e.z)
+// and at fixed m, d(z.h)/dMs = m.(K z) - 2/(mu0 Ms^2) z.(A~ m)
+//                              - 2 Ku/(mu0 Ms^2) (e.z)(e.m).
+// For the LLG right-hand side f = -g' [m x h + alpha m x (m x h)] and a
+// cotangent w:  d(w.f)/dm|_h = -g' [h x w + alpha (w (m.h) + h (w.m) - 2 m (w.h))]
+//               z = d(w.f)/dh = -g' [w x m + alpha (m (w.m) - w |m|^2)].
+// ---------------------------------------------------------------------------
+// g (may be null: then z is w masked to magnetic cells) and z per cell.
+template <typename T, bool PERCELL>
+__global__ void k_vjp_pre(const T* __restrict__ m, const T* __restrict__ h,
+                          const T* __restrict__ w, const T* __restrict__ Ms_cell, T Ms, long N,
+                          T gp, T alpha, T* __restrict__ g_out, T* __restrict__ z_out)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        const T ms = PERCELL ? Ms_cell[q] : Ms;
+        const T wx = w[q], wy = w[N + q], wz = w[2 * N + q];
+        if (ms == (T)0) {
+            z_out[q] = z_out[N + q] = z_out[2 * N + q] = (T)0;
+            if (g_out) g_out[q] = g_out[N + q] = g_out[2 * N + q] = (T)0;
+            continue;
+        }
+        if (!g_out) {
+            z_out[q] = wx;
+            z_out[N + q] = wy;
+            z_out[2 * N + q] = wz;
+            continue;
+        }
+        const T mx = m[q], my = m[N + q], mz = m[2 * N + q];
+        const T hx = h[q], hy = h[N + q], hz = h[2 * N + q];
+        const T mh = mx * hx + my * hy + mz * hz, wm = wx * mx + wy * my + wz * mz;
+        const T wh = wx * hx + wy * hy + wz * hz, mm = mx * mx + my * my + mz * mz;
+        g_out[q] = -gp * ((hy * wz - hz * wy) + alpha * (wx * mh + hx * wm - (T)2 * mx * wh));
+        g_out[N + q] = -gp * ((hz * wx - hx * wz) + alpha * (wy * mh + hy * wm - (T)2 * my * wh));
+        g_out[2 * N + q] = -gp * ((hx * wy - hy * wx) + alpha * (wz * mh + hz * wm - (T)2 * mz * wh));
+        z_out[q] = -gp * ((wy * mz - wz * my) + alpha * (mx * wm - wx * mm));
+        z_out[N + q] = -gp * ((wz * mx - wx * mz) + alpha * (my * wm - wy * mm));
+        z_out[2 * N + q] = -gp * ((wx * my - wy * mx) + alpha * (mz * wm - wz * mm));
+    }
+}
+
+struct AdjParams {
+    int nx, ny, nz;
+    long N;
+    long s1_comp;
+    int Hxp;
+    int with_demag, with_exch, with_anis;
+    double Ms;
+    double exch;  // 2 A / mu0
+    double idx2, idy2, idz2;
+    double anis;  // 2 Ku / mu0
+    double eu[3];
+};
+
+// nu = g + H^T z (x inverse transform of the spectrum of K z in S1, then the
+// transposed local terms); gms += d(z.h)/dMs (double, may be null).
+template <typename T, int M, bool PERCELL>
+__global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_adj_local(
+    const cx<T>* __restrict__ S1, const T* __restrict__ m, const T* __restrict__ z,
+    const T* __restrict__ g, const T* __restrict__ Ms_cell, AdjParams P, T* __restrict__ nu,
+    double* __restrict__ gms, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax)
+{
+    using G = XC2R<T, M>;
+    constexpr int kRows = G::kRows, kL = G::kL;
+    __shared__ cx<T> lds[kRows * 3 * kL];
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;
+    const int k = (int)(lb / njt);
+    const int j0 = (int)(lb % njt) * kRows;
+    const int nx = P.nx, ny = P.ny;
+    if (P.with_demag) x_c2r_rows<T, M>(S1, lds, k, j0, ny, P.s1_comp, P.Hxp, tw, Lmax);
+    const long N = P.N;
+    const T exch = (T)P.exch, anis = (T)P.anis;
+    const T ix2 = (T)P.idx2, iy2 = (T)P.idy2, iz2 = (T)P.idz2;
+    const T eux = (T)P.eu[0], euy = (T)P.eu[1], euz = (T)P.eu[2];
+    for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
+        const int rl = idx / nx, i = idx - rl * nx;
+        const int j = j0 + rl;
+        if (j >= ny) continue;
+        const long cell = i + (long)nx * (j + (long)ny * k);
+        const T ms = PERCELL ? Ms_cell[cell] : (T)P.Ms;
+        const T mx = m[cell], my = m[N + cell], mz = m[2 * N + cell];
+        T nx_ = g ? g[cell] : (T)0, ny_ = g ? g[N + cell] : (T)0, nz_ = g ? g[2 * N + cell] : (T)0;
+        double dms = 0.0;
+        if (P.with_demag) {
+            const T kx = x_c2r_value<T, M>(S1, lds, rl, 0, i, k, j, ny, P.s1_comp, P.Hxp);
+            const T ky = x_c2r_value<T, M>(S1, lds, rl, 1, i, k, j, ny, P.s1_comp, P.Hxp);
+            const T kz = x_c2r_value<T, M>(S1, lds, rl, 2, i, k, j, ny, P.s1_comp, P.Hxp);
+            nx_ += ms * kx;
+            ny_ += ms * ky;
+            nz_ += ms * kz;
+            dms += (double)mx * kx + (double)my * ky + (double)mz * kz;
+        }
+        if (ms != (T)0) {
+            const T inv_ms = (T)1 / ms;
+            const T zx = z[cell], zy = z[N + cell], zz = z[2 * N + cell];
+            if (P.with_exch) {
+                // A~ (z / Ms) and A~ m over magnetic neighbours
+                T ax = 0, ay = 0, az = 0, lx = 0, ly = 0, lz = 0;
+                const T szx = zx * inv_ms, szy = zy * inv_ms, szz = zz * inv_ms;
+                auto nb = [&](long q, T w) {
+                    const T mq = PERCELL ? Ms_cell[q] : (T)P.Ms;
+                    if (mq == (T)0) return;
+                    const T iq = (T)1 / mq;
+                    ax += w * (z[q] * iq - szx);
+                    ay += w * (z[N + q] * iq - szy);
+                    az += w * (z[2 * N + q] * iq - szz);
+                    lx += w * (m[q] - mx);
+                    ly += w * (m[N + q] - my);
+                    lz += w * (m[2 * N + q] - mz);
+                };
+                if (i > 0) nb(cell - 1, ix2);
+                if (i + 1 < nx) nb(cell + 1, ix2);
+                if (j > 0) nb(cell - nx, iy2);
+                if (j + 1 < ny) nb(cell + nx, iy2);
+                if (k > 0) nb(cell - (long)nx * ny, iz2);
+                if (k + 1 < P.nz) nb(cell + (long)nx * ny, iz2);
+                nx_ += exch * ax;
+                ny_ += exch * ay;
+                nz_ += exch * az;
+                dms -= (double)(exch * inv_ms * inv_ms) * ((double)zx * lx + (double)zy * ly + (double)zz * lz);
+            }
+            if (P.with_anis) {
+                const T ez = eux * zx + euy * zy + euz * zz;
+                const T em = eux * mx + euy * my + euz * mz;
+                const T ca = anis * inv_ms * ez;
+                nx_ += ca * eux;
+                ny_ += ca * euy;
+                nz_ += ca * euz;
+                dms -= (double)(anis * inv_ms * inv_ms) * (double)ez * (double)em;
+            }
+        }
+        nu[cell] = nx_;
+        nu[N + cell] = ny_;
+        nu[2 * N + cell] = nz_;
+        if (gms) gms[cell] += dms;
+    }
+}
+
+// out = sum_{j < NK} c_j v_j
+template <typename T, int NK>
+__global__ void k_lincomb(T* __restrict__ out, Coef7 cf, Ptr7<T> v, long n3)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n3;
+         q += (long)gridDim.x * blockDim.x) {
+        T acc = (T)0;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) acc += (T)cf.c[j] * v.p[j][q];
+        out[q] = acc;
+    }
+}
+
+// partial sums of m_z over a region mask
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_region_mz(const T* __restrict__ m,
+                                                      const unsigned char* __restrict__ region,
+                                                      long N, double* partials)
+{
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x)
+        if (region[q]) acc += (double)m[2 * N + q];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// *out += scale * sum(partials[0..n))
+__global__ void k_final_accum(const double* __restrict__ partials, int n, double* out, double scale)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) *out += scale * v;
+}
+
+// lam_z += val on the region
+template <typename T>
+__global__ void k_add_region(T* __restrict__ lam, const unsigned char* __restrict__ region, long N,
+                             T val)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x)
+        if (region[q]) lam[2 * N + q] += val;
+}
+
+template <typename T>
+__global__ void k_from_double(const double* __restrict__ in, T* __restrict__ out, long n)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        out[q] = (T)in[q];
+}
+
+__global__ void k_zero_d(double* __restrict__ p, long n)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        p[q] = 0.0;
+}
+
+template <typename T, int M, bool PC>
+static hipError_t launch_adj_M(const Plan& p, const T* m, const T* z, const T* g, T* nu,
+                               double* gms, const AdjParams& P)
+{
+    using G = XC2R<T, M>;
+    const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
+    const long nblocks = (long)njt * p.n[2];
+    k_adj_local<T, M, PC><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
+        (const cx<T>*)p.S1, m, z, g, (const T*)p.Ms_cell, P, nu, gms, njt, nblocks,
+        (const cx<T>*)p.tw, p.Lmax);
+    return hipGetLastError();
+}
+
+template <typename T, bool PC>
+static hipError_t launch_adj(const Plan& p, int M, const T* m, const T* z, const T* g, T* nu,
+                             double* gms, const AdjParams& P)
+{
+    switch (M) {
+#define MMX_A(LL) \
+    case LL: return launch_adj_M<T, LL, PC>(p, m, z, g, nu, gms, P);
+        MMX_A(0) MMX_CASES(MMX_A)
+#undef MMX_A
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
 // Demag kernel set-up (once per plan).
 // ---------------------------------------------------------------------------
 // Near field: -N_Newell for offsets 0 <= I < nI etc., all six components,
@@ -1223,6 +1467,47 @@ hipError_t debug_spectrum(Plan& p, int s, double* out)
 // ---------------------------------------------------------------------------
 // Field evaluation.
 // ---------------------------------------------------------------------------
+// Demag convolution up to the x spectrum: S1 <- spectrum of K (Ms src) (or of
+// K src with use_ms = false), i.e. every pass but the last inverse x
+// transform, which the caller fuses with its local terms.
+template <typename T>
+static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
+{
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int Py = p.P[1], Pz = p.P[2];
+    const int M = p.P[0] / 2;
+    const long s1c = (long)nz * ny * p.Hxp;
+    cx<T>* S1 = (cx<T>*)p.S1;
+    cx<T>* S2 = (cx<T>*)p.S2;
+    const bool pc = p.percell && use_ms;
+    const T ms = use_ms ? (T)p.Ms : (T)1;
+    MMX_TRY(timed(p, MM_PASS_X_FWD, [&] {
+        return pc ? launch_x_r2c<T, true>(p, M, m, nx, p.N, nx, (const T*)p.Ms_cell, ms, S1, p.Hxp,
+                                          s1c, ny * nz, 3)
+                  : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, ms, S1, p.Hxp, s1c,
+                                           ny * nz, 3);
+    }));
+    if (Pz > 1) {
+        const long s2c = (long)nz * Py * p.Hxp;
+        if (Py > 1)
+            MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
+                return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s2c,
+                                             nz, (long)ny * p.Hxp, (long)Py * p.Hxp);
+            }));
+        MMX_TRY(timed(p, MM_PASS_MID, [&] {
+            return launch_mid<T, 2>(p, Pz, S2, nz, (long)Py * p.Hxp, s2c, p.Hxp, Py);
+        }));
+        if (Py > 1)
+            MMX_TRY(timed(p, MM_PASS_Y_INV, [&] {
+                return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c, s1c,
+                                            nz, (long)Py * p.Hxp, (long)ny * p.Hxp);
+            }));
+    } else {
+        MMX_TRY(timed(p, MM_PASS_MID, [&] { return launch_mid<T, 1>(p, Py, S1, ny, p.Hxp, s1c, 0, 1); }));
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
                       T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
@@ -1234,34 +1519,7 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     cx<T>* S1 = (cx<T>*)p.S1;
     cx<T>* S2 = (cx<T>*)p.S2;
     const bool pc = p.percell;
-    if (terms & MM_DEMAG) {
-        MMX_TRY(timed(p, MM_PASS_X_FWD, [&] {
-            return pc ? launch_x_r2c<T, true>(p, M, m, nx, p.N, nx, (const T*)p.Ms_cell, (T)p.Ms,
-                                              S1, p.Hxp, s1c, ny * nz, 3)
-                      : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, (T)p.Ms, S1, p.Hxp,
-                                               s1c, ny * nz, 3);
-        }));
-        if (Pz > 1) {
-            const long s2c = (long)nz * Py * p.Hxp;
-            if (Py > 1)
-                MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
-                    return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c,
-                                                 s2c, nz, (long)ny * p.Hxp, (long)Py * p.Hxp);
-                }));
-            MMX_TRY(timed(p, MM_PASS_MID, [&] {
-                return launch_mid<T, 2>(p, Pz, S2, nz, (long)Py * p.Hxp, s2c, p.Hxp, Py);
-            }));
-            if (Py > 1)
-                MMX_TRY(timed(p, MM_PASS_Y_INV, [&] {
-                    return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c,
-                                                s1c, nz, (long)Py * p.Hxp, (long)ny * p.Hxp);
-                }));
-        } else {
-            MMX_TRY(timed(p, MM_PASS_MID, [&] {
-                return launch_mid<T, 1>(p, Py, S1, ny, p.Hxp, s1c, 0, 1);
-            }));
-        }
-    }
+    if (terms & MM_DEMAG) MMX_TRY(demag_to_S1<T>(p, m, true));
     LocalParams P;
     P.nx = nx;
     P.ny = ny;
@@ -1425,6 +1683,108 @@ hipError_t count_magnetic(Plan& p, double* out_dev)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Differentiation host pipeline.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t field_vjp(Plan& p, const T* m, const T* w, const T* h, unsigned terms, double alpha,
+                     T* g_tmp, T* z_tmp, T* nu, double* gms)
+{
+    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    const double gp = kGamma / (1.0 + alpha * alpha);
+    if (p.percell)
+        k_vjp_pre<T, true><<<blocks, 256, 0, p.stream>>>(m, h, w, (const T*)p.Ms_cell, (T)p.Ms, p.N,
+                                                       (T)gp, (T)alpha, h ? g_tmp : nullptr,
+                                                       z_tmp);
+    else
+        k_vjp_pre<T, false><<<blocks, 256, 0, p.stream>>>(m, h, w, nullptr, (T)p.Ms, p.N, (T)gp,
+                                                        (T)alpha, h ? g_tmp : nullptr, z_tmp);
+    MMX_TRY(hipGetLastError());
+    const bool demag = (terms & MM_DEMAG) != 0;
+    if (demag) MMX_TRY(demag_to_S1<T>(p, z_tmp, false));
+    AdjParams P;
+    P.nx = p.n[0];
+    P.ny = p.n[1];
+    P.nz = p.n[2];
+    P.N = p.N;
+    P.s1_comp = (long)p.n[2] * p.n[1] * p.Hxp;
+    P.Hxp = p.Hxp;
+    P.with_demag = demag ? 1 : 0;
+    P.with_exch = (terms & MM_EXCH) && p.A != 0.0 ? 1 : 0;
+    P.with_anis = (terms & MM_ANIS) && p.Ku != 0.0 ? 1 : 0;
+    P.Ms = p.Ms;
+    P.exch = 2.0 * p.A / kMu0;
+    P.idx2 = 1.0 / (p.d[0] * p.d[0]);
+    P.idy2 = 1.0 / (p.d[1] * p.d[1]);
+    P.idz2 = 1.0 / (p.d[2] * p.d[2]);
+    P.anis = 2.0 * p.Ku / kMu0;
+    for (int a = 0; a < 3; ++a) P.eu[a] = p.eu[a];
+    const int M = p.P[0] / 2;
+    const T* g = h ? g_tmp : nullptr;
+    return timed(p, MM_PASS_X_INV_LOCAL, [&] {
+        return p.percell ? launch_adj<T, true>(p, M, m, z_tmp, g, nu, gms, P)
+                         : launch_adj<T, false>(p, M, m, z_tmp, g, nu, gms, P);
+    });
+}
+
+template <typename T>
+hipError_t lincomb(Plan& p, T* out, const double* c, T* const* v, int nk)
+{
+    Coef7 cf{};
+    Ptr7<T> ps{};
+    for (int j = 0; j < nk; ++j) {
+        cf.c[j] = c[j];
+        ps.p[j] = v[j];
+    }
+    const long n3 = 3 * p.N;
+    const int blocks = (int)std::min<long>(blocks_for(n3, 256), 8192);
+    return timed(p, MM_PASS_RK, [&] {
+        switch (nk) {
+        case 1: k_lincomb<T, 1><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        case 2: k_lincomb<T, 2><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        case 3: k_lincomb<T, 3><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        case 4: k_lincomb<T, 4><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        case 5: k_lincomb<T, 5><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        case 6: k_lincomb<T, 6><<<blocks, 256, 0, p.stream>>>(out, cf, ps, n3); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+}
+
+template <typename T>
+hipError_t region_mz_accum(Plan& p, const T* m, const unsigned char* region, double* out_dev,
+                           double scale)
+{
+    k_region_mz<T><<<kRedBlocks, kBlock, 0, p.stream>>>(m, region, p.N, p.red);
+    MMX_TRY(hipGetLastError());
+    k_final_accum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t add_region(Plan& p, T* lam, const unsigned char* region, double val)
+{
+    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    k_add_region<T><<<blocks, 256, 0, p.stream>>>(lam, region, p.N, (T)val);
+    return hipGetLastError();
+}
+
+hipError_t zero_doubles(Plan& p, double* ptr, long n)
+{
+    const int blocks = (int)std::min<long>(blocks_for(n, 256), 4096);
+    k_zero_d<<<blocks, 256, 0, p.stream>>>(ptr, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t from_double(Plan& p, const double* in, T* out, long n)
+{
+    const int blocks = (int)std::min<long>(blocks_for(n, 256), 4096);
+    k_from_double<T><<<blocks, 256, 0, p.stream>>>(in, out, n);
+    return hipGetLastError();
+}
+
 #define MMX_INST(T)                                                                              \
     template hipError_t build_tensor<T>(Plan&);                                                  \
     template hipError_t init_twiddles<T>(Plan&);                                                 \
@@ -1439,7 +1799,14 @@ hipError_t count_magnetic(Plan& p, double* out_dev)
     template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \
                                        double*);                                                 \
     template hipError_t count_magnetic<T>(Plan&, double*);                                       \
-    template hipError_t debug_spectrum<T>(Plan&, int, double*);
+    template hipError_t debug_spectrum<T>(Plan&, int, double*);                                  \
+    template hipError_t field_vjp<T>(Plan&, const T*, const T*, const T*, unsigned, double, T*,  \
+                                     T*, T*, double*);                                           \
+    template hipError_t lincomb<T>(Plan&, T*, const double*, T* const*, int);                    \
+    template hipError_t region_mz_accum<T>(Plan&, const T*, const unsigned char*, double*,       \
+                                           double);                                              \
+    template hipError_t add_region<T>(Plan&, T*, const unsigned char*, double);                  \
+    template hipError_t from_double<T>(Plan&, const double*, T*, long);
 
 MMX_INST(float)
 MMX_INST(double)

@@ -31,7 +31,8 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4:
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
            "mm_plan_padded", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
-           "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error"]
+           "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error", "mm_heff_vjp",
+           "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint"]
 
 PASS_NAMES = ["x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local", "rk"]
 MM_NPASS = len(PASS_NAMES)
@@ -93,10 +94,17 @@ def lib():
         L.mm_profile_read.argtypes = [vp, dp, C.POINTER(C.c_long)]
         L.mm_debug_kernel.argtypes = [vp, C.c_int, vp]
         L.mm_debug_spectrum.argtypes = [vp, C.c_int, vp]
+        L.mm_heff_vjp.argtypes = [vp, vp, vp, C.c_uint, vp, vp]
+        L.mm_llg_rhs_vjp.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp, vp, vp]
+        L.mm_rk4_forward.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
+                                     C.c_long, vp, dp]
+        L.mm_rk4_adjoint.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
+                                     C.c_long, vp, vp, dp]
         L.mm_last_error.restype = C.c_char_p
         for name in ("mm_plan_create", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
-                     "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum"):
+                     "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum", "mm_heff_vjp",
+                     "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +220,36 @@ def mm_debug_kernel(plan, s, out):
 
 def mm_debug_spectrum(plan, s, out):
     _check(lib().mm_debug_spectrum(plan, int(s), _ptr(out)))
+
+
+def _optr(t):
+    return None if t is None else _ptr(t)
+
+
+def mm_heff_vjp(plan, m, w, terms, grad_m, grad_ms):
+    _check(lib().mm_heff_vjp(plan, _ptr(m), _ptr(w), int(terms), _ptr(grad_m), _optr(grad_ms)))
+
+
+def mm_llg_rhs_vjp(plan, m, h_ext, terms, t, w, grad_m, grad_ms):
+    _check(lib().mm_llg_rhs_vjp(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(w),
+                                _ptr(grad_m), _optr(grad_ms)))
+
+
+def mm_rk4_forward(plan, m, h_ext, terms, t0, dt, nsteps, region, ckpt_every, ckpt):
+    loss = C.c_double()
+    _check(lib().mm_rk4_forward(plan, _ptr(m), _vec3(h_ext), int(terms), float(t0), float(dt),
+                                int(nsteps), _optr(region), int(ckpt_every), _optr(ckpt),
+                                C.byref(loss)))
+    return loss.value
+
+
+def mm_rk4_adjoint(plan, ckpt, h_ext, terms, t0, dt, nsteps, region, ckpt_every, grad_ms,
+                   grad_m0):
+    loss = C.c_double()
+    _check(lib().mm_rk4_adjoint(plan, _ptr(ckpt), _vec3(h_ext), int(terms), float(t0), float(dt),
+                                int(nsteps), _optr(region), int(ckpt_every), _optr(grad_ms),
+                                _optr(grad_m0), C.byref(loss)))
+    return loss.value
 
 
 def mm_plan_padded(plan):
@@ -342,6 +380,59 @@ class Plan:
         mm_debug_kernel(self.handle, s, out)
         return out
 
+    def heff_vjp(self, m, w, terms=MM_ALL, want_ms=True):
+        """(H^T w, d(w.h)/dMs) for the linear terms in `terms`."""
+        m, w = self._t(m), self._t(w)
+        gm = self.empty()
+        gms = self._scalar_field() if want_ms else None
+        mm_heff_vjp(self.handle, m, w, terms, gm, gms)
+        return gm, gms
+
+    def llg_rhs_vjp(self, m, w, h_ext=None, terms=MM_ALL, t=0.0, want_ms=True):
+        """(J^T w, d(w.f)/dMs) of the LLG right-hand side at (m, t)."""
+        m, w = self._t(m), self._t(w)
+        gm = self.empty()
+        gms = self._scalar_field() if want_ms else None
+        mm_llg_rhs_vjp(self.handle, m, h_ext, terms, t, w, gm, gms)
+        return gm, gms
+
+    def _scalar_field(self):
+        import torch
+
+        nx, ny, nz = self.grid
+        return torch.empty((nz, ny, nx), dtype=self.dtype, device=self.device)
+
+    def _region(self, region):
+        import torch
+
+        if region is None:
+            return None
+        if isinstance(region, torch.Tensor):
+            return region.to(device=self.device, dtype=torch.uint8).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8)).to(self.device)
+
+    def rk4(self, m, dt, nsteps, region=None, h_ext=None, terms=MM_ALL, t0=0.0, ckpt_every=0):
+        """Fixed-step RK4 (m advanced in place).  Returns (loss, checkpoints or
+        None); checkpoints are the states before every ckpt_every-th step."""
+        import torch
+
+        ck = None
+        if ckpt_every > 0:
+            nck = (int(nsteps) + ckpt_every - 1) // ckpt_every
+            ck = torch.empty((max(nck, 1),) + self.shape, dtype=self.dtype, device=self.device)
+        loss = mm_rk4_forward(self.handle, m, h_ext, terms, t0, dt, nsteps, self._region(region),
+                              ckpt_every, ck)
+        return loss, ck
+
+    def rk4_adjoint(self, ckpt, dt, nsteps, region, h_ext=None, terms=MM_ALL, t0=0.0,
+                    ckpt_every=50, want_m0=True):
+        """(loss, dL/dMs, dL/dm0) of the RK4 region loss, from checkpoints."""
+        gms = self._scalar_field()
+        gm0 = self.empty() if want_m0 else None
+        loss = mm_rk4_adjoint(self.handle, ckpt, h_ext, terms, t0, dt, nsteps,
+                              self._region(region), ckpt_every, gms, gm0)
+        return loss, gms, gm0
+
     def debug_spectrum(self, s):
         import torch
 
@@ -355,3 +446,46 @@ class Plan:
 def _stats(st):
     return dict(accepted=st.accepted, rejected=st.rejected, rhs_evals=st.rhs_evals, t=st.t,
                 dt=st.dt, err_last=st.err_last)
+
+
+class RegionLoss:
+    """Differentiable map Ms (per cell) -> time-averaged region m_z after RK4
+    integration, for gradient-based inverse design (Sec. 5.2).  `apply(Ms)`
+    returns a 0-d tensor whose backward runs the discrete adjoint on the GPU.
+    The plan keeps the checkpoint segment between calls."""
+
+    def __init__(self, plan, m0, dt, nsteps, region, h_ext=None, terms=MM_ALL, t0=0.0,
+                 ckpt_every=50):
+        self.plan, self.m0 = plan, plan._t(m0)
+        self.dt, self.nsteps, self.region = float(dt), int(nsteps), plan._region(region)
+        self.h_ext, self.terms, self.t0, self.every = h_ext, terms, float(t0), int(ckpt_every)
+
+    def apply(self, Ms):
+        import torch
+
+        outer = self
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, ms):
+                p = outer.plan
+                p.set_ms(ms.detach())
+                m = outer.m0.clone()
+                loss, ck = p.rk4(m, outer.dt, outer.nsteps, outer.region, outer.h_ext,
+                                 outer.terms, outer.t0, outer.every)
+                ctx.save_for_backward(ms)
+                ctx.ck = ck
+                return torch.tensor(loss, dtype=torch.float64, device=ms.device)
+
+            @staticmethod
+            def backward(ctx, gout):
+                (ms,) = ctx.saved_tensors
+                p = outer.plan
+                p.set_ms(ms.detach())
+                _, gms, _ = p.rk4_adjoint(ctx.ck, outer.dt, outer.nsteps, outer.region,
+                                          outer.h_ext, outer.terms, outer.t0, outer.every,
+                                          want_m0=False)
+                return (gout.to(gms.dtype) * gms).reshape(ms.shape)
+
+        return _Fn.apply(Ms)
+

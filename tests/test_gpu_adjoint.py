@@ -1,0 +1,269 @@
+"""GPU parity of the differentiation form (Sec. 5.2 inverse design): the
+transposed field operator, the LLG vector-Jacobian product, fixed-step RK4
+with the region loss and its checkpointed discrete adjoint, each through the C
+ABI against the CPU oracle on the same seeded inputs, plus properties that
+hold at any size (dot-product identity of the transposes, independence of the
+checkpoint interval, agreement with a central difference of the loss)."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, rel_l2, to_np
+from paper_2302_08843_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# relative L2 bars against the FP64 oracle
+VJP_TOL = {"fp64": 1e-13, "fp32": 2e-6}
+RK4_TOL = {"fp64": 1e-12, "fp32": 1e-5}
+ADJ_TOL = {"fp64": 1e-12, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2302_08843_amd import mm as _mm
+
+    _mm.lib()
+    return _mm
+
+
+def _problem(grid, seed, vacuum=True):
+    g = W.rng(seed)
+    nx, ny, nz = grid
+    Ms = g.uniform(4e5, 1.2e6, (nz, ny, nx))
+    if vacuum:
+        Ms[g.uniform(size=Ms.shape) < 0.15] = 0.0
+    m = W.random_unit_sphere(grid, seed + 1)
+    w = g.standard_normal((3, nz, ny, nx))
+    return Ms, m, w
+
+
+def _pair(mm, orc, grid, d, Ms, prec, A=1.3e-11, Ku=3e4, eu=(0.0, 0.6, 0.8), alpha=0.2):
+    plan = mm.Plan(grid, d, Ms=1.0, A=A, Ku=Ku, alpha=alpha, prec=prec, ku_axis=eu)
+    plan.set_ms(Ms)
+    o = orc.Oracle(grid, d, Ms=Ms, A=np.where(Ms > 0, A, 0.0), Ku=Ku, eu=eu, alpha=alpha)
+    return plan, o
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid", [(20, 14, 3), (33, 9, 1), (1, 7, 5)])
+def test_heff_vjp_matches_oracle(torch_cuda, mm, orc, prec, grid):
+    banner("heff_vjp %s %s" % (prec, grid))
+    d = (3e-9, 2.5e-9, 2e-9)
+    Ms, m, w = _problem(grid, 11)
+    plan, o = _pair(mm, orc, grid, d, Ms, prec)
+    for terms in (mm.MM_DEMAG, mm.MM_EXCH, mm.MM_ANIS, mm.MM_ALL):
+        gm, gms = plan.heff_vjp(m, w, terms)
+        rgm, rgms = o.heff_vjp(m, w, terms & ~mm.MM_ZEEMAN)
+        e1, e2 = rel_l2(to_np(gm), rgm), rel_l2(to_np(gms), rgms)
+        print("  terms %d grad_m %.2e grad_Ms %.2e" % (terms, e1, e2))
+        assert e1 <= VJP_TOL[prec], (terms, e1)
+        assert e2 <= VJP_TOL[prec], (terms, e2)
+        assert np.abs(to_np(gm)[:, Ms == 0]).max() == 0.0
+
+
+def test_heff_vjp_dot_product_identity(torch_cuda, mm, orc):
+    """<w, H v> = <H^T w, v> with H the GPU's own forward field (FP64)."""
+    grid = (24, 18, 4)
+    banner("heff_vjp dot identity %s" % (grid,))
+    Ms, m, w = _problem(grid, 21)
+    plan, _ = _pair(mm, orc, grid, (2e-9, 2e-9, 3e-9), Ms, "fp64")
+    v = W.rng(22).standard_normal(m.shape)
+    for terms in (mm.MM_DEMAG, mm.MM_EXCH, mm.MM_ANIS, mm.MM_DEMAG | mm.MM_EXCH | mm.MM_ANIS):
+        hv = to_np(plan.heff(v, None, terms))
+        gw, _ = plan.heff_vjp(m, w, terms)
+        lhs, rhs = float(np.sum(w * hv)), float(np.sum(to_np(gw) * v))
+        scale = np.linalg.norm(w) * np.linalg.norm(hv)
+        assert abs(lhs - rhs) <= 1e-12 * scale, (terms, lhs, rhs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_llg_vjp_matches_oracle(torch_cuda, mm, orc, prec):
+    grid = (26, 12, 2)
+    banner("llg_vjp %s %s" % (prec, grid))
+    d = (4e-9, 4e-9, 3e-9)
+    Ms, m, w = _problem(grid, 31)
+    plan, o = _pair(mm, orc, grid, d, Ms, prec, alpha=0.1)
+    H = np.array([2e4, -1e4, 3e4])
+    amp, freq = np.array([0.0, 1.6e4, 0.0]), 15e9
+    mask = np.zeros(Ms.shape, np.uint8)
+    mask[:, :, 3:6] = 1
+    plan.set_drive(amp, freq, mask)
+    o.set_field(H)
+    o.set_drive(amp, freq, mask)
+    t = 7.3e-12
+    gm, gms = plan.llg_rhs_vjp(m, w, H, mm.MM_ALL, t)
+    rgm, rgms = o.llg_vjp(m, w, t)
+    e1, e2 = rel_l2(to_np(gm), rgm), rel_l2(to_np(gms), rgms)
+    print("  grad_m %.2e grad_Ms %.2e" % (e1, e2))
+    assert e1 <= VJP_TOL[prec] and e2 <= VJP_TOL[prec], (e1, e2)
+
+
+def _rk4_case(mm, orc, prec, grid=(24, 20, 2), seed=41):
+    d = (5e-9, 5e-9, 4e-9)
+    Ms, m, _ = _problem(grid, seed)
+    plan, o = _pair(mm, orc, grid, d, Ms, prec, Ku=0.0, alpha=0.05)
+    H = np.array([0.0, 0.0, 1.2e4])
+    amp, freq = np.array([0.0, 1.6e4, 0.0]), 20e9
+    mask = np.zeros(Ms.shape, np.uint8)
+    mask[:, :, 2:5] = 1
+    region = np.zeros(Ms.shape, np.uint8)
+    region[:, 8:14, 15:21] = 1
+    plan.set_drive(amp, freq, mask)
+    o.set_field(H)
+    o.set_drive(amp, freq, mask)
+    return plan, o, m, H, region, Ms
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rk4_forward_matches_oracle(torch_cuda, mm, orc, prec):
+    banner("rk4 forward %s" % prec)
+    plan, o, m0, H, region, _ = _rk4_case(mm, orc, prec)
+    nsteps, dt = 30, 1e-13
+    m = plan._t(m0)
+    loss, ck = plan.rk4(m, dt, nsteps, region, H, mm.MM_ALL, 0.0, ckpt_every=7)
+    ref_m, ref_loss = o.rk4(m0, dt, nsteps, region)
+    e = rel_l2(to_np(m), ref_m)
+    print("  m %.2e loss %.3e vs %.3e" % (e, loss, ref_loss))
+    assert e <= RK4_TOL[prec], e
+    assert abs(loss - ref_loss) <= RK4_TOL[prec] * max(1e-3, abs(ref_loss)) + 1e-15
+    # the checkpoints are the states before steps 0, 7, 14, ...
+    assert ck.shape[0] == 5
+    assert np.array_equal(to_np(ck[0]), to_np(plan._t(m0)))
+    m7 = plan._t(m0)
+    plan.rk4(m7, dt, 7, None, H, mm.MM_ALL, 0.0)
+    assert np.array_equal(to_np(ck[1]), to_np(m7))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rk4_adjoint_matches_oracle(torch_cuda, mm, orc, prec):
+    banner("rk4 adjoint %s" % prec)
+    plan, o, m0, H, region, Ms = _rk4_case(mm, orc, prec)
+    nsteps, dt, every = 30, 1e-13, 7
+    m = plan._t(m0)
+    loss_f, ck = plan.rk4(m, dt, nsteps, region, H, mm.MM_ALL, 0.0, ckpt_every=every)
+    loss, gms, gm0 = plan.rk4_adjoint(ck, dt, nsteps, region, H, mm.MM_ALL, 0.0, every)
+    ref_loss, ref_gms, ref_gm0 = o.rk4_adjoint(m0, dt, nsteps, region)
+    e1, e2 = rel_l2(to_np(gms), ref_gms), rel_l2(to_np(gm0), ref_gm0)
+    print("  loss %.6e (oracle %.6e) grad_Ms %.2e grad_m0 %.2e" % (loss, ref_loss, e1, e2))
+    # the adjoint recomputes the loss segment by segment (other summation order)
+    assert abs(loss - loss_f) <= 1e-12 * abs(loss_f)
+    assert e1 <= ADJ_TOL[prec], e1
+    assert e2 <= ADJ_TOL[prec], e2
+
+
+def test_adjoint_independent_of_checkpoint_interval(torch_cuda, mm, orc):
+    """Recomputation from checkpoints replays the same kernels: the gradient
+    is bit-identical for any interval (ragged last segment included)."""
+    banner("rk4 adjoint checkpoint intervals")
+    plan, _, m0, H, region, _ = _rk4_case(mm, orc, "fp64", seed=43)
+    nsteps, dt = 23, 1e-13
+    res = []
+    for every in (1, 5, 23, 40):
+        m = plan._t(m0)
+        _, ck = plan.rk4(m, dt, nsteps, region, H, mm.MM_ALL, 0.0, ckpt_every=every)
+        res.append(plan.rk4_adjoint(ck, dt, nsteps, region, H, mm.MM_ALL, 0.0, every))
+    for loss, gms, gm0 in res[1:]:
+        assert abs(loss - res[0][0]) <= 1e-12 * abs(res[0][0])
+        assert np.array_equal(to_np(gms), to_np(res[0][1]))
+        assert np.array_equal(to_np(gm0), to_np(res[0][2]))
+
+
+def test_rk4_adjoint_invalid_arguments(torch_cuda, mm, orc):
+    banner("rk4 adjoint invalid arguments")
+    plan, _, m0, H, region, _ = _rk4_case(mm, orc, "fp64")
+    m = plan._t(m0)
+    with pytest.raises(mm.MMError):
+        plan.rk4(m, -1e-13, 3, region, H)
+    _, ck = plan.rk4(m, 1e-13, 3, region, H, ckpt_every=2)
+    with pytest.raises(mm.MMError):
+        plan.rk4_adjoint(ck, 1e-13, 3, None, H, ckpt_every=2)
+    with pytest.raises(mm.MMError):
+        plan.rk4_adjoint(ck, 1e-13, 0, region, H, ckpt_every=2)
+
+
+@pytest.fixture(scope="module")
+def design_case():
+    """Film of 128 x 128 x 1 cells with per-cell density, 500 RK4 steps of
+    0.1 ps under a 20 GHz strip drive; gradient of the time-averaged region
+    m_z with respect to per-cell Ms."""
+    return W.config_adjoint()
+
+
+def _design_plan(mm, c, prec):
+    plan = mm.Plan(c["n"], c["d"], Ms=1.0, A=c["A"], alpha=c["alpha"], prec=prec)
+    plan.set_ms(c["Ms0"] * c["rho"])
+    plan.set_drive(c["drive_amp"], c["drive_freq"], c["strip"])
+    return plan
+
+
+def _design_grad(mm, plan, c, nsteps=None):
+    nsteps = c["steps"] if nsteps is None else nsteps
+    m = plan._t(c["m0"])
+    _, ck = plan.rk4(m, c["dt"], nsteps, c["region"], None, mm.MM_ALL, 0.0,
+                     ckpt_every=c["checkpoint_every"])
+    return plan.rk4_adjoint(ck, c["dt"], nsteps, c["region"], None, mm.MM_ALL, 0.0,
+                            c["checkpoint_every"])
+
+
+def test_design_gradient_full_size_matches_oracle(torch_cuda, mm, orc, design_case):
+    c = design_case
+    banner("design gradient %s %d steps" % (c["n"], c["steps"]))
+    o = orc.Oracle(c["n"], c["d"], Ms=c["Ms0"] * c["rho"], A=c["A"], alpha=c["alpha"])
+    o.set_field(np.zeros(3))
+    o.set_drive(c["drive_amp"], c["drive_freq"], c["strip"])
+    ref_loss, ref_gms, _ = o.rk4_adjoint(c["m0"], c["dt"], c["steps"], c["region"])
+    for prec in ("fp64", "fp32"):
+        plan = _design_plan(mm, c, prec)
+        loss, gms, _ = _design_grad(mm, plan, c)
+        e = rel_l2(to_np(gms), ref_gms)
+        cos = float(np.sum(to_np(gms) * ref_gms) /
+                    (np.linalg.norm(to_np(gms)) * np.linalg.norm(ref_gms)))
+        print("  %s loss %.9e (oracle %.9e) grad_Ms rel-L2 %.2e cosine %.8f"
+              % (prec, loss, ref_loss, e, cos))
+        assert e <= ADJ_TOL[prec], (prec, e)
+
+
+def test_design_gradient_central_difference(torch_cuda, mm, orc, design_case):
+    """Directional derivative of the loss along a random smooth density
+    perturbation: adjoint inner product vs central difference (FP64 GPU)."""
+    c = design_case
+    nsteps = 200
+    banner("design gradient vs central difference %s %d steps" % (c["n"], nsteps))
+    plan = _design_plan(mm, c, "fp64")
+    _, gms, _ = _design_grad(mm, plan, c, nsteps)
+    v = W.smooth_random(c["n"], 5, seed=7)[0] * c["Ms0"]
+    eps = 1e-4
+    Ls = []
+    for s in (+1, -1):
+        plan.set_ms(c["Ms0"] * c["rho"] + s * eps * v)
+        m = plan._t(c["m0"])
+        Ls.append(plan.rk4(m, c["dt"], nsteps, c["region"], None, mm.MM_ALL, 0.0)[0])
+    fd = (Ls[0] - Ls[1]) / (2 * eps)
+    ad = float(np.sum(to_np(gms) * v))
+    print("  directional derivative: adjoint %.9e central difference %.9e" % (ad, fd))
+    assert abs(ad - fd) <= 1e-5 * abs(fd)
+
+
+def test_design_descent_lowers_loss(torch_cuda, mm, orc, design_case):
+    """A small step of the density against the gradient lowers the loss
+    (the sign convention that inverse design relies on)."""
+    c = design_case
+    nsteps = 200
+    banner("design descent %s" % (c["n"],))
+    plan = _design_plan(mm, c, "fp32")
+    loss0, gms, _ = _design_grad(mm, plan, c, nsteps)
+    g = to_np(gms)
+    Ms1 = c["Ms0"] * c["rho"] - 0.02 * c["Ms0"] * g / np.abs(g).max()
+    plan.set_ms(Ms1)
+    m = plan._t(c["m0"])
+    loss1 = plan.rk4(m, c["dt"], nsteps, c["region"], None, mm.MM_ALL, 0.0)[0]
+    print("  loss %.6e -> %.6e" % (loss0, loss1))
+    assert loss1 < loss0
