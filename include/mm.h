@@ -226,6 +226,89 @@ mm_status mm_rk4_adjoint(mm_plan *p, const void *ckpt, const double h_ext[3], un
                          double t0, double dt, long nsteps, const unsigned char *region,
                          long ckpt_every, void *grad_ms, void *grad_m0, double *loss);
 
+/* ---- Serving: a request server with continuous batching ---------------------
+ * Relaxations (Sec. 3: alpha = 1, no precession, renormalised steps, until
+ * max_i |m_i x h_i| / Ms_i < tol) and time integrations (Eq. llg with the
+ * request's alpha up to t_end) on grids of different sizes, run concurrently
+ * on one GPU.  Each admitted request gets a plan (spectra, Runge-Kutta
+ * vectors and a device-side step controller) and one of max_active streams;
+ * its Dormand-Prince steps are decided on the device (the same accept/reject
+ * and step-size rules as mm_llg_step) and replayed from a HIP graph of
+ * steps_per_launch steps, so no step waits for the host.  Requests are
+ * admitted first come first served as slots and device memory (hbm_budget)
+ * free up; graphs of different requests overlap on the device.  Plans of one
+ * grid class (grid, precision, near-field order and cell proportions) share
+ * one resident spectral kernel (the demag tensor depends on the cell shape,
+ * not its size); finished plans stay resident for reuse by later requests of
+ * the same grid and are released, least recently used first, when memory is
+ * needed.  A request's arithmetic does not depend on what else runs, so its
+ * result is bit-identical alone and in a mix.  Fields must be static (no
+ * drive); the material is uniform per request.  The server is not
+ * thread-safe: one host thread submits and polls. */
+typedef struct mm_server mm_server;
+
+typedef struct {
+    size_t hbm_budget;     /* device bytes the server may hold; 0: 80 % of free memory */
+    int max_active;        /* requests on the device at once (streams), 1..64 */
+    int steps_per_launch;  /* device-controlled steps per graph launch, 1..64 */
+    mm_prec prec;          /* arithmetic of every request */
+    int demag_p;           /* near-field order as in mm_opts */
+} mm_serve_opts;
+void mm_serve_opts_default(mm_serve_opts *o); /* 0, 16, 8, MM_FP32, 20 */
+
+enum { MM_SERVE_RELAX = 0, MM_SERVE_INTEGRATE = 1 };
+
+typedef struct {
+    int grid[3];
+    double cell[3];
+    double Ms, A, Ku, ku_axis[3], alpha; /* alpha unused by relaxations (1) */
+    double h_ext[3];
+    unsigned terms;
+    int kind;          /* MM_SERVE_RELAX or MM_SERVE_INTEGRATE */
+    double tol;        /* relaxation: torque criterion */
+    double rtol, atol; /* step-size control */
+    double t_end;      /* integration: end time (s) */
+    long max_steps;    /* cap on accepted steps */
+    void *m;           /* device, 3N reals of the server precision: start state in,
+                          result out; owned by the caller, kept alive until completed */
+    void *stream;      /* hipStream_t whose work so far produces m (NULL: the null
+                          stream); the server reads m only after that work */
+    long tag;          /* caller's identifier, returned in the completion */
+} mm_request;
+
+typedef struct {
+    long tag;
+    int status;        /* MM_OK, MM_ENOTCONV (relaxation hit max_steps), MM_EDTMIN,
+                          MM_ENONFINITE, MM_ENOMEM (larger than the budget), MM_EHIP */
+    long accepted, rejected, rhs_evals;
+    double t, torque;  /* final time; final torque (relaxations) */
+    double t_submit, t_admit, t_done; /* mm_serve_clock() seconds */
+} mm_completion;
+
+typedef struct {
+    long submitted, admitted, completed, queued, active;
+    long waited_memory, waited_slot; /* requests that waited at the head of the queue */
+    size_t bytes_in_use, bytes_peak, budget;
+    long tensors_built, plans_created, plans_reused, graph_launches;
+} mm_serve_stats;
+
+/* MM_EINVAL for options out of range; MM_ENOMEM/MM_EHIP on allocation. */
+mm_status mm_serve_create(mm_server **out, const mm_serve_opts *o);
+/* Queue a request (copied).  MM_EINVAL for invalid grids, materials or
+ * tolerances; the request is then not queued. */
+mm_status mm_serve_submit(mm_server *s, const mm_request *r);
+/* Advance the server without blocking: collect finished graph launches,
+ * relaunch running requests, retire finished ones, admit queued ones (an
+ * admission synchronises on the new request's stream for its starting step).
+ * Writes up to max_out completions (oldest first) and their count to *n_out;
+ * more stay for the next call. */
+mm_status mm_serve_poll(mm_server *s, mm_completion *out, int max_out, int *n_out);
+mm_status mm_serve_get_stats(const mm_server *s, mm_serve_stats *st);
+/* Waits for the device work of active requests, then frees everything. */
+void mm_serve_destroy(mm_server *s);
+/* Host monotonic clock (seconds) of the completion timestamps. */
+double mm_serve_clock(void);
+
 /* Per-pass timing with HIP events recorded on the plan's stream around every
  * launch of the field pipeline (diagnostics for roofline measurements).
  * Passes: x forward transform, y forward transform, last-axis transform with

@@ -29,7 +29,7 @@ static int padded_extent(int n)
 
 static size_t elem_size(const Plan& p) { return p.prec == MM_FP32 ? 4 : 8; }
 
-static mm_status hip_fail(hipError_t e, const char* what)
+mm_status hip_fail(hipError_t e, const char* what)
 {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? MM_ENOMEM : MM_EHIP;
@@ -41,7 +41,7 @@ static mm_status hip_fail(hipError_t e, const char* what)
         if (e__ != hipSuccess) return hip_fail(e__, what); \
     } while (0)
 
-static void free_plan(Plan* p)
+void free_plan(Plan* p)
 {
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
@@ -50,12 +50,24 @@ static void free_plan(Plan* p)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+    if (p->shared) {
+        release_tensor(p->shared);
+        p->Khat = p->tw = nullptr;
+    }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->mask, p->rk, p->red, p->red_out, p->adj, p->seg, p->gms};
+                    p->mask, p->rk, p->red, p->red_out, p->adj, p->seg, p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->host_out) (void)hipHostFree(p->host_out);
     delete p;
+}
+
+void release_tensor(SharedTensor* t)
+{
+    if (!t || --t->refs > 0) return;
+    if (t->Khat) (void)hipFree(t->Khat);
+    if (t->tw) (void)hipFree(t->tw);
+    delete t;
 }
 
 static mm_status alloc(Plan* p, void** out, size_t bytes, const char* what)
@@ -81,10 +93,14 @@ static const double kB5[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
 static const double kB4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                               -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
 
-static mm_status ensure_rk(Plan* p)
+mm_status ensure_rk(Plan* p)
 {
-    if (p->rk) return MM_OK;
-    return alloc(p, &p->rk, 10 * 3 * (size_t)p->N * elem_size(*p), "Runge-Kutta buffers");
+    if (!p->rk) {
+        mm_status s = alloc(p, &p->rk, 10 * 3 * (size_t)p->N * elem_size(*p), "Runge-Kutta buffers");
+        if (s != MM_OK) return s;
+    }
+    if (!p->ctl) return alloc(p, (void**)&p->ctl, sizeof(DevCtl), "step controller");
+    return MM_OK;
 }
 
 template <typename T>
@@ -121,6 +137,120 @@ static T* adj_vec(Plan* p, int i)
     return (T*)p->adj + (size_t)i * 3 * p->N;
 }
 
+// Hairer-Norsett-Wanner starting step from y and f0 = f(t, y) (one extra
+// right-hand side into f1, using ys as scratch).  Synchronises twice.
+template <typename T>
+static mm_status start_step(Plan* p, const T* y, T* f0, T* f1, T* ys, const double hext[3],
+                            unsigned terms, double t, double alpha, bool precess, double rtol,
+                            double atol, double* dt, long* evals)
+{
+    MM_HIP(start_norms<T>(*p, y, f0, nullptr, rtol, atol, p->red_out + 2), "start norms");
+    mm_status s = fetch(p, 5);
+    if (s != MM_OK) return s;
+    const double cnt = 3.0 * (double)p->n_magnetic;
+    const double d0 = cnt > 0 ? std::sqrt(p->host_out[2] / cnt) : 0.0;
+    const double d1 = cnt > 0 ? std::sqrt(p->host_out[3] / cnt) : 0.0;
+    const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    const double one = 1.0;
+    T* fs = f0;
+    MM_HIP(rk_combine<T>(*p, ys, y, h0, &one, &fs, 1), "start step");
+    MM_HIP(eval_field<T>(*p, ys, hext, terms, t + h0, nullptr, f1, alpha, precess, nullptr),
+           "right-hand side");
+    (*evals)++;
+    MM_HIP(start_norms<T>(*p, y, f0, f1, rtol, atol, p->red_out + 2), "start norms");
+    s = fetch(p, 5);
+    if (s != MM_OK) return s;
+    const double d2 = (cnt > 0 ? std::sqrt(p->host_out[4] / cnt) : 0.0) / h0;
+    const double mx = std::max(d1, d2);
+    const double h1 = mx <= 1e-15 ? std::max(1e-6, h0 * 1e-3) : std::pow(0.01 / mx, 0.2);
+    *dt = std::min(100.0 * h0, h1);
+    return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-controlled Dormand-Prince steps (used by the request server): the
+// state stays in rk vector 8, the trial state in 9, stage derivatives in 0..6
+// and the stage input in 7; the controller state is p->ctl.
+// ---------------------------------------------------------------------------
+template <typename T>
+mm_status dev_prepare(Plan* p, const void* m0, const double hext[3], unsigned terms,
+                      const DevCtl& init, double rtol, double atol)
+{
+    mm_status s = ensure_rk(p);
+    if (s != MM_OK) return s;
+    const bool relax = init.relax != 0;
+    const double alpha = relax ? 1.0 : p->alpha;
+    T* y = rk_vec<T>(p, 8);
+    T* k0 = rk_vec<T>(p, 0);
+    MM_HIP(hipMemcpyAsync(y, m0, 3 * (size_t)p->N * sizeof(T), hipMemcpyDeviceToDevice, p->stream),
+           "copy m");
+    MM_HIP(eval_field<T>(*p, y, hext, terms, init.t, nullptr, k0, alpha, !relax,
+                         relax ? p->red_out + 1 : nullptr),
+           "right-hand side");
+    DevCtl c = init;
+    c.rhs_evals = 1;
+    if (!(c.dt > 0.0)) {
+        s = start_step<T>(p, y, k0, rk_vec<T>(p, 1), rk_vec<T>(p, 7), hext, terms, c.t, alpha,
+                          !relax, rtol, atol, &c.dt, &c.rhs_evals);
+        if (s != MM_OK) return s;
+    }
+    c.torque = std::numeric_limits<double>::infinity();
+    MM_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(DevCtl), hipMemcpyHostToDevice, p->stream), "controller");
+    if (relax) MM_HIP(dp_torque(*p, p->ctl), "torque");
+    // the controller copy reads from the stack: finish it before returning
+    MM_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
+    return MM_OK;
+}
+
+// One device-controlled step (no host synchronisation; capturable).  Fields
+// must not depend on time (no drive).
+template <typename T>
+mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, double atol,
+                   bool relax, bool renorm)
+{
+    const double alpha = relax ? 1.0 : p->alpha;
+    T* k[7];
+    for (int i = 0; i < 7; ++i) k[i] = rk_vec<T>(p, i);
+    T* ys = rk_vec<T>(p, 7);
+    T* y = rk_vec<T>(p, 8);
+    T* y1 = rk_vec<T>(p, 9);
+    double* hdev = &p->ctl->h;
+    MM_HIP(dp_begin(*p, p->ctl), "controller");
+    for (int sg = 1; sg < 7; ++sg) {
+        T* target = sg == 6 ? y1 : ys;
+        MM_HIP(rk_combine<T>(*p, target, y, 0.0, kA[sg], k, sg, hdev), "stage input");
+        MM_HIP(eval_field<T>(*p, target, hext, terms, 0.0, nullptr, k[sg], alpha, !relax, nullptr),
+               "right-hand side");
+    }
+    double E[7];
+    for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
+    MM_HIP(rk_error_norm<T>(*p, y, y1, 0.0, E, k, 7, rtol, atol, p->red_out, hdev), "error norm");
+    MM_HIP(dp_control(*p, p->ctl), "controller");
+    MM_HIP(dp_commit<T>(*p, p->ctl, y, y1, k[0], k[6]), "commit");
+    if (renorm) {
+        MM_HIP(eval_field<T>(*p, y, hext, terms, 0.0, nullptr, k[0], alpha, !relax,
+                             relax ? p->red_out + 1 : nullptr),
+               "right-hand side");
+        if (relax) MM_HIP(dp_torque(*p, p->ctl), "torque");
+    }
+    return MM_OK;
+}
+
+template <typename T>
+T* dev_state(Plan* p)
+{
+    return rk_vec<T>(p, 8);
+}
+
+template mm_status dev_prepare<float>(Plan*, const void*, const double*, unsigned, const DevCtl&,
+                                      double, double);
+template mm_status dev_prepare<double>(Plan*, const void*, const double*, unsigned, const DevCtl&,
+                                       double, double);
+template mm_status dev_step<float>(Plan*, const double*, unsigned, double, double, bool, bool);
+template mm_status dev_step<double>(Plan*, const double*, unsigned, double, double, bool, bool);
+template float* dev_state<float>(Plan*);
+template double* dev_state<double>(Plan*);
+
 // ---------------------------------------------------------------------------
 // Dormand-Prince driver.  mode_relax: alpha = 1, no precession, renormalise,
 // stop on the torque criterion.
@@ -150,27 +280,9 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
            "right-hand side");
     loc.rhs_evals++;
     if (*dt <= 0.0) {
-        // Hairer-Norsett-Wanner starting step
-        MM_HIP(start_norms<T>(*p, y, k[0], nullptr, rtol, atol, p->red_out + 2), "start norms");
-        s = fetch(p, 5);
+        s = start_step<T>(p, y, k[0], k[1], ys, hext, terms, *t, alpha, precess, rtol, atol, dt,
+                          &loc.rhs_evals);
         if (s != MM_OK) return s;
-        const double cnt = 3.0 * (double)p->n_magnetic;
-        const double d0 = cnt > 0 ? std::sqrt(p->host_out[2] / cnt) : 0.0;
-        const double d1 = cnt > 0 ? std::sqrt(p->host_out[3] / cnt) : 0.0;
-        const double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-        const double one = 1.0;
-        T* f0 = k[0];
-        MM_HIP(rk_combine<T>(*p, ys, y, h0, &one, &f0, 1), "start step");
-        MM_HIP(eval_field<T>(*p, ys, hext, terms, *t + h0, nullptr, k[1], alpha, precess, nullptr),
-               "right-hand side");
-        loc.rhs_evals++;
-        MM_HIP(start_norms<T>(*p, y, k[0], k[1], rtol, atol, p->red_out + 2), "start norms");
-        s = fetch(p, 5);
-        if (s != MM_OK) return s;
-        const double d2 = (cnt > 0 ? std::sqrt(p->host_out[4] / cnt) : 0.0) / h0;
-        const double mx = std::max(d1, d2);
-        const double h1 = mx <= 1e-15 ? std::max(1e-6, h0 * 1e-3) : std::pow(0.01 / mx, 0.2);
-        *dt = std::min(100.0 * h0, h1);
     }
     double E[7];
     for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
@@ -258,6 +370,123 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
     loc.dt = *dt;
     if (st) *st = loc;
     return status;
+}
+
+// Allocate and set up a plan from validated arguments.  With `share`, the
+// spectral kernel and twiddles of another plan of the same grid class are
+// reused (reference counted) instead of built.
+mm_status plan_build(const int grid[3], const double cell[3], double Ms, double A, double Ku,
+                     double alpha, const mm_opts& o, SharedTensor* share, Plan** out)
+{
+    *out = nullptr;
+    const double nrm = std::sqrt(o.ku_axis[0] * o.ku_axis[0] + o.ku_axis[1] * o.ku_axis[1] +
+                                 o.ku_axis[2] * o.ku_axis[2]);
+    Plan* p = new Plan();
+    for (int a = 0; a < 3; ++a) {
+        p->n[a] = grid[a];
+        p->d[a] = cell[a];
+        p->P[a] = padded_extent(grid[a]);
+        p->eu[a] = o.ku_axis[a] / nrm;
+    }
+    p->N = (long)grid[0] * grid[1] * grid[2];
+    p->Hx = p->P[0] > 1 ? p->P[0] / 2 + 1 : 1;
+    // spectral rows start on 128-byte boundaries for the real kernel array
+    // (32 floats or 16 doubles) and therefore for the complex spectra too
+    const int row_align = o.prec == MM_FP32 ? 32 : 16;
+    p->Hxp = (p->Hx + row_align - 1) / row_align * row_align;
+    p->S1n = 3L * grid[2] * grid[1] * p->Hxp;
+    p->S2n = 3L * grid[2] * p->P[1] * p->Hxp;
+    p->Kn = (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
+    p->Lmax = std::max(p->P[0], std::max(p->P[1], p->P[2]));
+    p->prec = o.prec;
+    p->Ms = Ms;
+    p->A = A;
+    p->Ku = Ku;
+    p->alpha = alpha;
+    p->demag_p = o.demag_p;
+    p->percell = false;
+    p->n_magnetic = Ms > 0.0 ? p->N : 0;
+    p->drive = false;
+    p->stream = (hipStream_t)o.stream;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            p->ncu = ncu;
+    }
+    const size_t es = elem_size(*p);
+    mm_status s;
+    (void)s;
+#define MM_ALLOC(ptr, bytes, what)                              \
+    do {                                                        \
+        s = alloc(p, (void**)&(ptr), (bytes), what);            \
+        if (s != MM_OK) {                                       \
+            free_plan(p);                                       \
+            return s;                                           \
+        }                                                       \
+    } while (0)
+    if (!share) MM_ALLOC(p->Khat, 6 * (size_t)p->Kn * es, "spectral kernel");
+    MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es, "spectrum S1");
+    if (p->P[2] > 1 && p->P[1] > 1)
+        MM_ALLOC(p->S2, (size_t)p->S2n * 2 * es, "spectrum S2");
+    else
+        p->S2 = p->S1;
+    if (!share) MM_ALLOC(p->tw, (size_t)p->Lmax * 2 * es, "twiddles");
+    MM_ALLOC(p->red, sizeof(double) * kRedSlots, "reduction partials");
+    MM_ALLOC(p->red_out, sizeof(double) * 8, "reduction results");
+#undef MM_ALLOC
+    hipError_t e = hipHostMalloc((void**)&p->host_out, sizeof(double) * 8, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "pinned host buffer");
+    }
+    if (share) {
+        p->Khat = share->Khat;
+        p->tw = share->tw;
+        p->shared = share;
+        share->refs++;
+        *out = p;
+        return MM_OK;
+    }
+    e = p->prec == MM_FP32 ? init_twiddles<float>(*p) : init_twiddles<double>(*p);
+    if (e == hipSuccess) e = p->prec == MM_FP32 ? build_tensor<float>(*p) : build_tensor<double>(*p);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        mm_status st = hip_fail(e, "building the demag kernel");
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return MM_OK;
+}
+
+
+// Device bytes a plan of this grid allocates for a device-controlled run
+// (spectra, reduction buffers, Runge-Kutta vectors, controller), plus the
+// spectral kernel and twiddles when with_tensor.  Mirrors plan_build and
+// ensure_rk.
+size_t plan_footprint(const int grid[3], int prec, bool with_tensor)
+{
+    const size_t es = prec == MM_FP32 ? 4 : 8;
+    int P[3];
+    for (int a = 0; a < 3; ++a) P[a] = padded_extent(grid[a]);
+    const long N = (long)grid[0] * grid[1] * grid[2];
+    const int Hx = P[0] > 1 ? P[0] / 2 + 1 : 1;
+    const int row_align = prec == MM_FP32 ? 32 : 16;
+    const long Hxp = (Hx + row_align - 1) / row_align * row_align;
+    const long S1n = 3L * grid[2] * grid[1] * Hxp;
+    const long S2n = 3L * grid[2] * P[1] * Hxp;
+    size_t b = (size_t)S1n * 2 * es;
+    if (P[2] > 1 && P[1] > 1) b += (size_t)S2n * 2 * es;
+    b += sizeof(double) * kRedSlots + sizeof(double) * 8;
+    b += 10 * 3 * (size_t)N * es + sizeof(DevCtl);
+    if (with_tensor) {
+        const long Kn = (long)(P[2] / 2 + 1) * (P[1] / 2 + 1) * Hxp;
+        const int Lmax = std::max(P[0], std::max(P[1], P[2]));
+        b += 6 * (size_t)Kn * es + (size_t)Lmax * 2 * es;
+    }
+    return b;
 }
 
 }  // namespace mmx
@@ -532,73 +761,9 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
         set_error("anisotropy axis must be a non-zero finite vector");
         return MM_EINVAL;
     }
-    Plan* p = new Plan();
-    for (int a = 0; a < 3; ++a) {
-        p->n[a] = grid[a];
-        p->d[a] = cell[a];
-        p->P[a] = padded_extent(grid[a]);
-        p->eu[a] = o.ku_axis[a] / nrm;
-    }
-    p->N = (long)grid[0] * grid[1] * grid[2];
-    p->Hx = p->P[0] > 1 ? p->P[0] / 2 + 1 : 1;
-    // spectral rows start on 128-byte boundaries for the real kernel array
-    // (32 floats or 16 doubles) and therefore for the complex spectra too
-    const int row_align = o.prec == MM_FP32 ? 32 : 16;
-    p->Hxp = (p->Hx + row_align - 1) / row_align * row_align;
-    p->S1n = 3L * grid[2] * grid[1] * p->Hxp;
-    p->S2n = 3L * grid[2] * p->P[1] * p->Hxp;
-    p->Kn = (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
-    p->Lmax = std::max(p->P[0], std::max(p->P[1], p->P[2]));
-    p->prec = o.prec;
-    p->Ms = Ms;
-    p->A = A;
-    p->Ku = Ku;
-    p->alpha = alpha;
-    p->demag_p = o.demag_p;
-    p->percell = false;
-    p->n_magnetic = Ms > 0.0 ? p->N : 0;
-    p->drive = false;
-    p->stream = (hipStream_t)o.stream;
-    {
-        int dev = 0, ncu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            ncu > 0)
-            p->ncu = ncu;
-    }
-    const size_t es = elem_size(*p);
-    mm_status s;
-#define MM_ALLOC(ptr, bytes, what)                              \
-    do {                                                        \
-        s = alloc(p, (void**)&(ptr), (bytes), what);            \
-        if (s != MM_OK) {                                       \
-            free_plan(p);                                       \
-            return s;                                           \
-        }                                                       \
-    } while (0)
-    MM_ALLOC(p->Khat, 6 * (size_t)p->Kn * es, "spectral kernel");
-    MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es, "spectrum S1");
-    if (p->P[2] > 1 && p->P[1] > 1)
-        MM_ALLOC(p->S2, (size_t)p->S2n * 2 * es, "spectrum S2");
-    else
-        p->S2 = p->S1;
-    MM_ALLOC(p->tw, (size_t)p->Lmax * 2 * es, "twiddles");
-    MM_ALLOC(p->red, sizeof(double) * kRedSlots, "reduction partials");
-    MM_ALLOC(p->red_out, sizeof(double) * 8, "reduction results");
-#undef MM_ALLOC
-    hipError_t e = hipHostMalloc((void**)&p->host_out, sizeof(double) * 8, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        free_plan(p);
-        return hip_fail(e, "pinned host buffer");
-    }
-    e = p->prec == MM_FP32 ? init_twiddles<float>(*p) : init_twiddles<double>(*p);
-    if (e == hipSuccess) e = p->prec == MM_FP32 ? build_tensor<float>(*p) : build_tensor<double>(*p);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) {
-        mm_status st = hip_fail(e, "building the demag kernel");
-        free_plan(p);
-        return st;
-    }
+    Plan* p = nullptr;
+    mm_status s = plan_build(grid, cell, Ms, A, Ku, alpha, o, nullptr, &p);
+    if (s != MM_OK) return s;
     *out = reinterpret_cast<mm_plan*>(p);
     return MM_OK;
 }

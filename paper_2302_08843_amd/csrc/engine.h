@@ -33,6 +33,17 @@ struct Profiler {
     long cnt[MM_NPASS] = {};
 };
 
+struct DevCtl;
+// A spectral kernel and twiddle table shared by plans of one grid class
+// (same grid, precision, near-field order and cell proportions: the demag
+// tensor depends only on the cell shape, not its size).  Freed with its last
+// owner.
+struct SharedTensor {
+    void *Khat = nullptr, *tw = nullptr;
+    size_t bytes = 0;
+    int refs = 0;
+};
+
 struct Plan {
     // geometry
     int n[3];      // nx, ny, nz
@@ -74,6 +85,8 @@ struct Plan {
     void *seg = nullptr;        // stage states and fields of one checkpoint segment
     size_t seg_bytes = 0;
     double *gms = nullptr;      // N doubles: Ms-gradient accumulator
+    DevCtl *ctl = nullptr;      // device-side step controller
+    SharedTensor *shared = nullptr;  // Khat and tw owned jointly with other plans
     size_t bytes = 0;
     Profiler prof;
 };
@@ -101,16 +114,42 @@ template <typename T>
 hipError_t eval_field(Plan &p, const T *m, const double hext[3], unsigned terms, double t,
                       T *h_out, T *dm_out, double alpha_eff, bool precess, double *torque);
 
-// y_out = y + h * sum_j a[j] k[j]  (nk <= 7)
+// y_out = y + h * sum_j a[j] k[j]  (nk <= 7).  hdev: if not null, h is read
+// from this device double instead (device-side step control).
 template <typename T>
 hipError_t rk_combine(Plan &p, T *y_out, const T *y, double h, const double *a, T *const *k,
-                      int nk);
+                      int nk, const double *hdev = nullptr);
 // RMS error norm of e = h sum_j e[j] k[j] scaled by atol + rtol max(|y|,|y1|)
 // over magnetic components into out_dev[0]; the number of non-finite entries
 // of y into out_dev[5].
 template <typename T>
 hipError_t rk_error_norm(Plan &p, const T *y, const T *y1, double h, const double *e,
-                         T *const *k, int nk, double rtol, double atol, double *out_dev);
+                         T *const *k, int nk, double rtol, double atol, double *out_dev,
+                         const double *hdev = nullptr);
+
+// Device-side Dormand-Prince controller state (one per plan in device
+// memory).  Every decision the host-driven loop takes from a synchronised
+// read-back is taken here by single-thread kernels, so a sequence of steps can
+// be enqueued (or captured in a HIP graph) without a host round trip.
+struct DevCtl {
+    double t, dt, h, t_end, dt_min, torque_tol, torque, err_last;
+    long accepted, rejected, rhs_evals, max_steps;
+    int done;      // 0 while stepping, 1 once finished (then every step is a no-op)
+    int result;    // mm_status of a finished run
+    int last_rejected, commit, relax, renorm;
+};
+// start of a step: finish on the torque criterion / step cap / t_end, else
+// set the trial step h = min(dt, t_end - t)
+hipError_t dp_begin(Plan &p, DevCtl *c);
+// accept / reject from the error norm in p.red_out[0] (non-finite count in
+// p.red_out[5]) and the new step size
+hipError_t dp_control(Plan &p, DevCtl *c);
+// on acceptance: y = y1 (renormalised if c->renorm) and, without renorm,
+// k0 = k6 (first-same-as-last)
+template <typename T>
+hipError_t dp_commit(Plan &p, DevCtl *c, T *y, const T *y1, T *k0, const T *k6);
+// c->torque = p.red_out[1] while running
+hipError_t dp_torque(Plan &p, DevCtl *c);
 // Renormalise |m| = 1 on magnetic cells, zero m on vacuum cells.
 template <typename T>
 hipError_t renormalise(Plan &p, T *m);
@@ -146,6 +185,28 @@ hipError_t zero_doubles(Plan &p, double *ptr, long n);
 template <typename T>
 hipError_t from_double(Plan &p, const double *in, T *out, long n);
 // Debug: real-space kernel (component s) placed in the padded grid, doubles.
+// ---- Host-side plan services (api.hip), also used by the request server ----
+void set_error(const std::string &msg);
+mm_status hip_fail(hipError_t e, const char *what);
+void free_plan(Plan *p);
+void release_tensor(SharedTensor *t);
+mm_status ensure_rk(Plan *p);
+mm_status plan_build(const int grid[3], const double cell[3], double Ms, double A, double Ku,
+                     double alpha, const mm_opts &o, SharedTensor *share, Plan **out);
+size_t plan_footprint(const int grid[3], int prec, bool with_tensor);
+// Device-controlled Dormand-Prince run: dev_prepare copies m0 into the
+// state, evaluates f(y0) (and the torque for relaxation), picks the starting
+// step if init.dt <= 0, uploads the controller (synchronises); dev_step
+// enqueues one step without synchronising; dev_state is the state buffer.
+template <typename T>
+mm_status dev_prepare(Plan *p, const void *m0, const double hext[3], unsigned terms,
+                      const DevCtl &init, double rtol, double atol);
+template <typename T>
+mm_status dev_step(Plan *p, const double hext[3], unsigned terms, double rtol, double atol,
+                   bool relax, bool renorm);
+template <typename T>
+T *dev_state(Plan *p);
+
 hipError_t debug_kernel(Plan &p, int s, double *out);
 template <typename T>
 hipError_t debug_spectrum(Plan &p, int s, double *out);

@@ -771,8 +771,12 @@ __global__ void k_fill(double* p, int n, double v)
     if (i < n) p[i] = v;
 }
 
+// Coefficients of a stage combination.  h: if not null, every coefficient is
+// multiplied by *h (the step size held on the device by the device-side
+// controller); the host-driven path folds h into c and leaves h null.
 struct Coef7 {
     double c[7];
+    const double* h;
 };
 
 template <typename T>
@@ -824,9 +828,10 @@ __global__ __launch_bounds__(kBlock) void k_rk_combine(T* __restrict__ y_out,
                                                        Ptr7<T> ks, long n3)
 {
     constexpr int W = VEC ? V16<T>::n : 1;
+    const double hs = cf.h ? *cf.h : 1.0;
     T cj[NK];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) cj[j] = (T)cf.c[j];
+    for (int j = 0; j < NK; ++j) cj[j] = (T)(cf.c[j] * hs);
     const long nv = n3 / W;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
          q += (long)gridDim.x * blockDim.x) {
@@ -853,6 +858,10 @@ __global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
                                                      double rtol, double atol, double* partials)
 {
     constexpr int W = VEC ? V16<T>::n : 1;
+    const double hs = cf.h ? *cf.h : 1.0;
+    double cj[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) cj[j] = cf.c[j] * hs;
     double acc = 0.0, bad = 0.0;
     const long nv = 3 * N / W;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
@@ -879,7 +888,7 @@ __global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
             T kv[W];
             if constexpr (VEC) vload(ks.p[j] + q * W, kv); else kv[0] = ks.p[j][q];
 #pragma unroll
-            for (int w = 0; w < W; ++w) e[w] += cf.c[j] * (double)kv[w];
+            for (int w = 0; w < W; ++w) e[w] += cj[j] * (double)kv[w];
         }
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -913,6 +922,108 @@ __global__ void k_renorm(T* __restrict__ m, const T* __restrict__ Ms_cell, long 
         m[q] = x * inv;
         m[N + q] = y * inv;
         m[2 * N + q] = z * inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device-side Dormand-Prince control (single-thread kernels on DevCtl).  The
+// rules are those of the host-driven loop: accept iff err <= 1, factor
+// min(10, max(0.2, 0.9 err^-1/5)) (no growth right after a rejection, a step
+// clipped to t_end keeps the proposal), a non-finite trial error is a
+// rejection with factor 0.2 unless the state itself is non-finite.
+// ---------------------------------------------------------------------------
+__global__ void k_dp_begin(DevCtl* c)
+{
+    if (c->done) return;
+    if (c->relax && c->torque < c->torque_tol) {
+        c->done = 1;
+        c->result = MM_OK;
+    } else if (c->accepted >= c->max_steps) {
+        c->done = 1;
+        c->result = c->relax ? MM_ENOTCONV : MM_OK;
+    } else if (!(c->t < c->t_end)) {
+        c->done = 1;
+        c->result = MM_OK;
+    }
+    if (c->done) {
+        c->h = 0.0;  // the rest of the step leaves every buffer that matters unchanged
+        return;
+    }
+    double h = c->dt;
+    if (c->t + h > c->t_end) h = c->t_end - c->t;
+    c->h = h;
+}
+
+__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red)
+{
+    c->commit = 0;
+    if (c->done) return;
+    c->rhs_evals += 6;
+    double err = red[0];
+    c->err_last = err;
+    const double h = c->h;
+    if (!isfinite(err)) {
+        if (red[5] != 0.0) {
+            c->done = 1;
+            c->result = MM_ENONFINITE;
+            return;
+        }
+        err = HUGE_VAL;
+    }
+    if (err <= 1.0) {
+        c->t += h;
+        c->accepted++;
+        c->commit = 1;
+        if (c->renorm) c->rhs_evals += 1;
+        double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+        if (c->last_rejected && fac > 1.0) fac = 1.0;
+        if (!(h < c->dt)) c->dt = fac * h;
+        c->last_rejected = 0;
+    } else {
+        c->rejected++;
+        c->dt = fmax(0.2, 0.9 * pow(err, -0.2)) * h;
+        c->last_rejected = 1;
+    }
+    if (c->dt < c->dt_min) {
+        c->done = 1;
+        c->result = MM_EDTMIN;
+    }
+}
+
+__global__ void k_dp_torque(DevCtl* c, const double* __restrict__ red)
+{
+    if (!c->done) c->torque = red[1];
+}
+
+// y = y1 (renormalised on magnetic cells, zero on vacuum cells, when
+// c->renorm) and k0 = k6 (without renorm), on acceptance only.
+template <typename T>
+__global__ void k_dp_commit(const DevCtl* __restrict__ c, T* __restrict__ y,
+                            const T* __restrict__ y1, T* __restrict__ k0,
+                            const T* __restrict__ k6, const T* __restrict__ Ms_cell, long N)
+{
+    if (!c->commit) return;
+    const bool renorm = c->renorm != 0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        T x = y1[q], yy = y1[N + q], z = y1[2 * N + q];
+        if (renorm) {
+            if (Ms_cell && Ms_cell[q] == (T)0) {
+                x = yy = z = (T)0;
+            } else {
+                const T inv = (T)1 / sqrt(x * x + yy * yy + z * z);
+                x *= inv;
+                yy *= inv;
+                z *= inv;
+            }
+        } else {
+            k0[q] = k6[q];
+            k0[N + q] = k6[N + q];
+            k0[2 * N + q] = k6[2 * N + q];
+        }
+        y[q] = x;
+        y[N + q] = yy;
+        y[2 * N + q] = z;
     }
 }
 
@@ -1579,13 +1690,15 @@ static hipError_t launch_combine(Plan& p, T* y_out, const T* y, const Coef7& cf,
 }
 
 template <typename T>
-hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, T* const* k, int nk)
+hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, T* const* k, int nk,
+                      const double* hdev)
 {
     Coef7 cf{};
     Ptr7<T> ks{};
+    cf.h = hdev;
     bool vec = (p.N % V16<T>::n) == 0 && aligned16(y_out) && aligned16(y);
     for (int j = 0; j < nk; ++j) {
-        cf.c[j] = h * a[j];
+        cf.c[j] = hdev ? a[j] : h * a[j];
         ks.p[j] = k[j];
         vec = vec && aligned16(k[j]);
     }
@@ -1605,14 +1718,15 @@ hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, 
 
 template <typename T>
 hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const double* e, T* const* k,
-                         int nk, double rtol, double atol, double* out_dev)
+                         int nk, double rtol, double atol, double* out_dev, const double* hdev)
 {
     Coef7 cf{};
     Ptr7<T> ks{};
+    cf.h = hdev;
     bool vec = (p.N % V16<T>::n) == 0 && aligned16(y) && aligned16(y1) &&
                (!p.percell || aligned16(p.Ms_cell));
     for (int j = 0; j < 7; ++j) {
-        cf.c[j] = j < nk ? h * e[j] : 0.0;
+        cf.c[j] = j < nk ? (hdev ? e[j] : h * e[j]) : 0.0;
         ks.p[j] = j < nk ? k[j] : y;
         vec = vec && aligned16(ks.p[j]);
     }
@@ -1646,6 +1760,33 @@ hipError_t renormalise(Plan& p, T* m)
 {
     const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
     k_renorm<T><<<blocks, 256, 0, p.stream>>>(m, p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
+    return hipGetLastError();
+}
+
+hipError_t dp_begin(Plan& p, DevCtl* c)
+{
+    k_dp_begin<<<1, 1, 0, p.stream>>>(c);
+    return hipGetLastError();
+}
+
+hipError_t dp_control(Plan& p, DevCtl* c)
+{
+    k_dp_control<<<1, 1, 0, p.stream>>>(c, p.red_out);
+    return hipGetLastError();
+}
+
+hipError_t dp_torque(Plan& p, DevCtl* c)
+{
+    k_dp_torque<<<1, 1, 0, p.stream>>>(c, p.red_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dp_commit(Plan& p, DevCtl* c, T* y, const T* y1, T* k0, const T* k6)
+{
+    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    k_dp_commit<T><<<blocks, 256, 0, p.stream>>>(c, y, y1, k0, k6,
+                                                 p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
     return hipGetLastError();
 }
 
@@ -1791,9 +1932,10 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t eval_field<T>(Plan&, const T*, const double*, unsigned, double, T*, T*, \
                                       double, bool, double*);                                    \
     template hipError_t rk_combine<T>(Plan&, T*, const T*, double, const double*, T* const*,     \
-                                      int);                                                      \
+                                      int, const double*);                                       \
     template hipError_t rk_error_norm<T>(Plan&, const T*, const T*, double, const double*,       \
-                                         T* const*, int, double, double, double*);               \
+                                         T* const*, int, double, double, double*, const double*); \
+    template hipError_t dp_commit<T>(Plan&, DevCtl*, T*, const T*, T*, const T*);                \
     template hipError_t renormalise<T>(Plan&, T*);                                               \
     template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*);                           \
     template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \

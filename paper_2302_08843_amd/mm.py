@@ -32,10 +32,43 @@ EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_devi
            "mm_plan_padded", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
            "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error", "mm_heff_vjp",
-           "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint"]
+           "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_opts_default",
+           "mm_serve_create", "mm_serve_submit", "mm_serve_poll", "mm_serve_get_stats",
+           "mm_serve_destroy", "mm_serve_clock"]
+
+MM_SERVE_RELAX, MM_SERVE_INTEGRATE = 0, 1
 
 PASS_NAMES = ["x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local", "rk"]
 MM_NPASS = len(PASS_NAMES)
+
+
+class mm_serve_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("steps_per_launch", C.c_int),
+                ("prec", C.c_int), ("demag_p", C.c_int)]
+
+
+class mm_request(C.Structure):
+    _fields_ = [("grid", C.c_int * 3), ("cell", C.c_double * 3), ("Ms", C.c_double),
+                ("A", C.c_double), ("Ku", C.c_double), ("ku_axis", C.c_double * 3),
+                ("alpha", C.c_double), ("h_ext", C.c_double * 3), ("terms", C.c_uint),
+                ("kind", C.c_int), ("tol", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("t_end", C.c_double), ("max_steps", C.c_long), ("m", C.c_void_p),
+                ("stream", C.c_void_p), ("tag", C.c_long)]
+
+
+class mm_completion(C.Structure):
+    _fields_ = [("tag", C.c_long), ("status", C.c_int), ("accepted", C.c_long),
+                ("rejected", C.c_long), ("rhs_evals", C.c_long), ("t", C.c_double),
+                ("torque", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class mm_serve_stats(C.Structure):
+    _fields_ = [(n, C.c_long) for n in ("submitted", "admitted", "completed", "queued", "active",
+                                        "waited_memory", "waited_slot")] + \
+               [(n, C.c_size_t) for n in ("bytes_in_use", "bytes_peak", "budget")] + \
+               [(n, C.c_long) for n in ("tensors_built", "plans_created", "plans_reused",
+                                        "graph_launches")]
 
 
 class mm_opts(C.Structure):
@@ -94,6 +127,16 @@ def lib():
         L.mm_profile_read.argtypes = [vp, dp, C.POINTER(C.c_long)]
         L.mm_debug_kernel.argtypes = [vp, C.c_int, vp]
         L.mm_debug_spectrum.argtypes = [vp, C.c_int, vp]
+        L.mm_serve_opts_default.argtypes = [C.POINTER(mm_serve_opts)]
+        L.mm_serve_opts_default.restype = None
+        L.mm_serve_create.argtypes = [C.POINTER(vp), C.POINTER(mm_serve_opts)]
+        L.mm_serve_submit.argtypes = [vp, C.POINTER(mm_request)]
+        L.mm_serve_poll.argtypes = [vp, C.POINTER(mm_completion), C.c_int, C.POINTER(C.c_int)]
+        L.mm_serve_get_stats.argtypes = [vp, C.POINTER(mm_serve_stats)]
+        L.mm_serve_destroy.argtypes = [vp]
+        L.mm_serve_destroy.restype = None
+        L.mm_serve_clock.argtypes = []
+        L.mm_serve_clock.restype = C.c_double
         L.mm_heff_vjp.argtypes = [vp, vp, vp, C.c_uint, vp, vp]
         L.mm_llg_rhs_vjp.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp, vp, vp]
         L.mm_rk4_forward.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
@@ -104,7 +147,8 @@ def lib():
         for name in ("mm_plan_create", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
                      "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum", "mm_heff_vjp",
-                     "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint"):
+                     "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_create",
+                     "mm_serve_submit", "mm_serve_poll", "mm_serve_get_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -250,6 +294,43 @@ def mm_rk4_adjoint(plan, ckpt, h_ext, terms, t0, dt, nsteps, region, ckpt_every,
                                 int(nsteps), _optr(region), int(ckpt_every), _optr(grad_ms),
                                 _optr(grad_m0), C.byref(loss)))
     return loss.value
+
+
+def mm_serve_opts_default():
+    o = mm_serve_opts()
+    lib().mm_serve_opts_default(C.byref(o))
+    return o
+
+
+def mm_serve_create(opts=None):
+    h = C.c_void_p()
+    _check(lib().mm_serve_create(C.byref(h), None if opts is None else C.byref(opts)))
+    return h
+
+
+def mm_serve_submit(server, req):
+    _check(lib().mm_serve_submit(server, C.byref(req)))
+
+
+def mm_serve_poll(server, max_out=256):
+    buf = (mm_completion * max_out)()
+    n = C.c_int()
+    _check(lib().mm_serve_poll(server, buf, int(max_out), C.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def mm_serve_get_stats(server):
+    st = mm_serve_stats()
+    _check(lib().mm_serve_get_stats(server, C.byref(st)))
+    return st
+
+
+def mm_serve_destroy(server):
+    lib().mm_serve_destroy(server)
+
+
+def mm_serve_clock():
+    return float(lib().mm_serve_clock())
 
 
 def mm_plan_padded(plan):
@@ -488,4 +569,75 @@ class RegionLoss:
                 return (gout.to(gms.dtype) * gms).reshape(ms.shape)
 
         return _Fn.apply(Ms)
+
+
+class Server:
+    """Request server (mm_serve_*): submit relaxations / integrations with
+    device-resident start states, poll for completions.  Results are written
+    into each request's state tensor in place."""
+
+    def __init__(self, budget=0, max_active=16, steps_per_launch=8, prec="fp32", demag_p=20):
+        import torch
+
+        o = mm_serve_opts_default()
+        o.hbm_budget = int(budget)
+        o.max_active = int(max_active)
+        o.steps_per_launch = int(steps_per_launch)
+        o.prec = MM_FP32 if prec in ("fp32", MM_FP32, "f32") else MM_FP64
+        o.demag_p = int(demag_p)
+        self.prec = o.prec
+        self.dtype = torch.float32 if o.prec == MM_FP32 else torch.float64
+        self.handle = mm_serve_create(o)
+        self._held = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            mm_serve_destroy(h)
+            self.handle = None
+
+    def close(self):
+        self.__del__()
+
+    def submit(self, m, grid, cell, Ms, A=0.0, Ku=0.0, ku_axis=(0, 0, 1), alpha=1.0, h_ext=None,
+               terms=MM_ALL, kind=MM_SERVE_RELAX, tol=1e-5, rtol=1e-6, atol=None, t_end=0.0,
+               max_steps=50000, tag=0):
+        """m: contiguous (3, nz, ny, nx) device tensor of the server dtype,
+        kept alive by the server until its completion is polled."""
+        if m.dtype != self.dtype or not m.is_cuda or not m.is_contiguous():
+            raise ValueError("state must be a contiguous device tensor of the server precision")
+        r = mm_request()
+        for a in range(3):
+            r.grid[a] = int(grid[a])
+            r.cell[a] = float(cell[a])
+            r.ku_axis[a] = float(ku_axis[a])
+            r.h_ext[a] = 0.0 if h_ext is None else float(h_ext[a])
+        r.Ms, r.A, r.Ku, r.alpha = float(Ms), float(A), float(Ku), float(alpha)
+        r.terms, r.kind, r.tol = int(terms), int(kind), float(tol)
+        r.rtol = float(rtol)
+        r.atol = float(rtol if atol is None else atol)
+        r.t_end, r.max_steps = float(t_end), int(max_steps)
+        r.m = C.c_void_p(m.data_ptr())
+        r.stream = _stream_handle(None)  # the server waits for the caller's stream
+        r.tag = int(tag)
+        mm_serve_submit(self.handle, r)
+        self._held[int(tag)] = m
+
+    def poll(self):
+        """List of completion dicts (tag, status, accepted, rejected,
+        rhs_evals, t, torque, t_submit, t_admit, t_done)."""
+        out = []
+        for c in mm_serve_poll(self.handle):
+            d = {f: getattr(c, f) for f, _ in mm_completion._fields_}
+            self._held.pop(int(c.tag), None)
+            out.append(d)
+        return out
+
+    def stats(self):
+        st = mm_serve_get_stats(self.handle)
+        return {f: getattr(st, f) for f, _ in mm_serve_stats._fields_}
+
+    @staticmethod
+    def clock():
+        return mm_serve_clock()
 

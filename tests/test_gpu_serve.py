@@ -1,0 +1,203 @@
+"""GPU tests of the serving form: the request server (mm_serve_*) runs
+relaxations and time integrations with device-side step control replayed from
+HIP graphs, admits requests by slots and device memory, and shares spectral
+kernels per grid class.  Checked against the oracle (FP64), against the
+host-controlled entry points, and for bit-identical results alone and in a
+mix."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, rel_l2, to_np
+from paper_2302_08843_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2302_08843_amd import mm as _mm
+
+    _mm.lib()
+    return _mm
+
+
+def _drain(srv, n, limit_s=100.0):
+    import time
+
+    out, t0 = [], time.time()
+    while len(out) < n:
+        out += srv.poll()
+        assert time.time() - t0 < limit_s, "server did not finish"
+    return {c["tag"]: c for c in out}
+
+
+def _req(seed, grid, cell=3e-9):
+    g = W.rng(seed)
+    d = g.standard_normal(3)
+    d /= np.linalg.norm(d)
+    return dict(grid=grid, cell=(cell, cell, cell), Ms=float(g.uniform(4e5, 1.4e6)),
+                A=float(g.uniform(5e-12, 2e-11)), Ku=float(g.uniform(0.0, 5e4)),
+                H=W.mT(float(g.uniform(10.0, 50.0))) * d,
+                m0=W.smooth_random(grid, 4.0, seed=seed + 100))
+
+
+def test_serve_relax_matches_oracle_fp64(torch_cuda, mm, orc):
+    grid = (12, 10, 2)
+    banner("serve relax fp64 vs oracle %s" % (grid,))
+    r = _req(1, grid)
+    srv = mm.Server(max_active=4, steps_per_launch=4, prec="fp64")
+    m = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float64, device="cuda").contiguous()
+    tol = 1e-6
+    srv.submit(m, grid, r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=r["H"], tol=tol, rtol=1e-8,
+               tag=7)
+    c = _drain(srv, 1)[7]
+    assert c["status"] == mm.MM_OK, c
+    assert c["torque"] < tol
+    o = orc.Oracle(grid, r["cell"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], alpha=1.0)
+    o.set_field(r["H"])
+    ref = o.relax(r["m0"], tol=tol, rtol=1e-8)[0]
+    got = to_np(m)
+    e = rel_l2(got, ref)
+    print("  accepted %d rejected %d torque %.2e  rel-L2 vs oracle %.2e"
+          % (c["accepted"], c["rejected"], c["torque"], e))
+    assert e <= 1e-4
+    # the relaxed state's torque measured independently by the oracle
+    assert o.max_torque(got) < 2 * tol
+
+
+def test_serve_relax_matches_host_controlled_relax(torch_cuda, mm):
+    """FP32: the device-side controller against mm_relax's host-side one
+    (same rules; the step-size factor may round differently, so the states
+    agree to the relaxation tolerance rather than bitwise)."""
+    grid = (32, 24, 1)
+    banner("serve relax fp32 vs mm_relax %s" % (grid,))
+    r = _req(2, grid)
+    H = W.mT(60.0) * np.array([0.6, 0.0, 0.8])
+    srv = mm.Server(max_active=2, steps_per_launch=8, prec="fp32")
+    m = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float32, device="cuda").contiguous()
+    srv.submit(m, grid, r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=H, tol=1e-4, rtol=1e-7,
+               max_steps=20000, tag=1)
+    c = _drain(srv, 1)[1]
+    plan = mm.Plan(grid, r["cell"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], alpha=1.0, prec="fp32")
+    mh = plan._t(r["m0"])
+    status, st = plan.relax(mh, H, mm.MM_ALL, tol=1e-4, max_steps=20000, rtol=1e-7)
+    e = rel_l2(to_np(m), to_np(mh))
+    print("  server: %d steps torque %.2e | host: %d steps status %d | rel-L2 %.2e"
+          % (c["accepted"], c["torque"], st["accepted"], status, e))
+    assert status == mm.MM_OK and c["status"] == mm.MM_OK
+    assert e <= 1e-3
+    assert plan.max_torque(m, H) < 1e-4
+
+
+def test_serve_integrate_matches_oracle(torch_cuda, mm, orc):
+    grid = (16, 12, 2)
+    banner("serve integrate fp64 vs oracle %s" % (grid,))
+    r = _req(3, grid)
+    alpha, t_end = 0.1, 5e-11
+    srv = mm.Server(max_active=2, steps_per_launch=5, prec="fp64")
+    m = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float64, device="cuda").contiguous()
+    srv.submit(m, grid, r["cell"], r["Ms"], r["A"], r["Ku"], alpha=alpha, h_ext=r["H"],
+               kind=mm.MM_SERVE_INTEGRATE, rtol=1e-8, t_end=t_end, tag=3)
+    c = _drain(srv, 1)[3]
+    assert c["status"] == mm.MM_OK and c["t"] == t_end
+    o = orc.Oracle(grid, r["cell"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], alpha=alpha)
+    o.set_field(r["H"])
+    ref, t, _, _, _ = o.dp45(r["m0"], rtol=1e-8, t_end=t_end)
+    e = rel_l2(to_np(m), ref)
+    print("  accepted %d rejected %d rel-L2 vs oracle %.2e" % (c["accepted"], c["rejected"], e))
+    assert e <= 1e-7
+
+
+def _mix(n):
+    grids = [(16, 16, 1), (24, 8, 2), (32, 32, 1), (20, 12, 3)]
+    reqs = []
+    for i in range(n):
+        r = _req(50 + i, grids[i % len(grids)], cell=(2.0 + 0.25 * (i % 5)) * 1e-9)
+        r["tag"] = i
+        reqs.append(r)
+    return reqs
+
+
+def _run(torch, mm, reqs, **kw):
+    # a step cap keeps the test short: capped and converged requests alike
+    # must give the same result alone and in the mix
+    srv = mm.Server(prec="fp32", **kw)
+    ms = {}
+    for r in reqs:
+        m = torch.tensor(r["m0"], dtype=torch.float32, device="cuda").contiguous()
+        ms[r["tag"]] = m
+        srv.submit(m, r["grid"], r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=r["H"], tol=1e-4,
+                   rtol=1e-7, max_steps=1200, tag=r["tag"])
+    comps = _drain(srv, len(reqs))
+    return srv, comps, {k: to_np(v) for k, v in ms.items()}
+
+
+def test_serve_alone_and_in_mix_bit_identical(torch_cuda, mm):
+    banner("serve alone vs mix, 16 requests")
+    reqs = _mix(16)
+    alone_m, alone_c = {}, {}
+    for r in reqs:
+        _, c, m = _run(torch_cuda, mm, [r], max_active=1)
+        alone_m.update(m)
+        alone_c.update(c)
+    srv, mix_c, mix_m = _run(torch_cuda, mm, reqs, max_active=16, steps_per_launch=4)
+    st = srv.stats()
+    print("  stats", st)
+    for r in reqs:
+        k = r["tag"]
+        assert mix_c[k]["status"] in (mm.MM_OK, mm.MM_ENOTCONV)
+        assert np.array_equal(alone_m[k], mix_m[k]), k
+        for f in ("status", "accepted", "rejected", "rhs_evals", "torque"):
+            assert alone_c[k][f] == mix_c[k][f], (k, f)
+    # four grid classes, five cell sizes each: one resident kernel per class
+    assert st["tensors_built"] == 4
+
+
+def test_serve_admission_by_memory_budget(torch_cuda, mm):
+    banner("serve admission under a memory budget")
+    reqs = _mix(8)
+    # room for the four resident kernels (about 0.23 MB) and two or three
+    # plans (0.11 - 0.36 MB each) at a time
+    budget = 800 * 1024
+    srv, comps, _ = _run(torch_cuda, mm, reqs, max_active=8, budget=budget)
+    st = srv.stats()
+    print("  stats", st)
+    assert all(c["status"] in (mm.MM_OK, mm.MM_ENOTCONV) for c in comps.values())
+    assert st["bytes_peak"] <= budget
+    assert st["waited_memory"] > 0
+    assert st["completed"] == 8
+
+
+def test_serve_rejects_oversized_and_invalid(torch_cuda, mm):
+    banner("serve oversized / invalid requests")
+    srv = mm.Server(max_active=2, budget=1 << 20, prec="fp32")
+    grid = (128, 128, 2)
+    m = torch_cuda.zeros((3, 2, 128, 128), dtype=torch_cuda.float32, device="cuda")
+    m[0] = 1.0
+    srv.submit(m, grid, (3e-9,) * 3, 8e5, 1e-11, tag=11)
+    c = _drain(srv, 1)[11]
+    assert c["status"] == mm.MM_ENOMEM
+    with pytest.raises(mm.MMError):
+        srv.submit(m, grid, (3e-9, 3e-9, -1.0), 8e5, 1e-11, tag=12)
+    with pytest.raises(mm.MMError):
+        srv.submit(m, grid, (3e-9,) * 3, 8e5, 1e-11, tol=0.0, tag=13)
+
+
+def test_serve_step_cap_reports_not_converged(torch_cuda, mm):
+    banner("serve step cap")
+    r = _req(9, (16, 16, 1))
+    srv = mm.Server(max_active=1, steps_per_launch=8, prec="fp32")
+    m = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float32, device="cuda").contiguous()
+    srv.submit(m, r["grid"], r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=r["H"], tol=1e-12,
+               rtol=1e-5, max_steps=13, tag=5)
+    c = _drain(srv, 1)[5]
+    assert c["status"] == mm.MM_ENOTCONV
+    assert c["accepted"] == 13
