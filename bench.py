@@ -81,6 +81,92 @@ def heff_only(mm, plan, m, cfg, iters):
     return (time.perf_counter() - t0) / iters
 
 
+def _serve_once(mm, reqs, states, arrivals, opts):
+    """Run the request server over `reqs` (start states already in HBM) with
+    the given arrival offsets (s); returns completions, makespan and stats."""
+    import torch
+
+    srv = mm.Server(budget=opts["budget"], max_active=opts["max_active"],
+                    steps_per_launch=opts["steps_per_launch"], prec="fp32")
+    # resident kernels and plans for every grid class before the clock starts
+    seen = set()
+    for r in reqs:
+        if r["n"] in seen:
+            continue
+        seen.add(r["n"])
+        warm = states[reqs.index(r)].clone()
+        srv.submit(warm, r["n"], r["d"], r["Ms"], r["A"], r["Ku"], ku_axis=r["eu"], h_ext=r["H"],
+                   tol=opts["tol"], rtol=opts["rtol"], max_steps=0, tag=-1 - len(seen))
+    warm_done = 0
+    while warm_done < len(seen):
+        warm_done += len(srv.poll())
+    ms = [m.clone() for m in states]
+    torch.cuda.synchronize()
+    t0 = srv.clock()
+    done, i, n = {}, 0, len(reqs)
+    while len(done) < n:
+        now = srv.clock() - t0
+        while i < n and arrivals[i] <= now:
+            r = reqs[i]
+            srv.submit(ms[i], r["n"], r["d"], r["Ms"], r["A"], r["Ku"], ku_axis=r["eu"],
+                       h_ext=r["H"], tol=opts["tol"], rtol=opts["rtol"],
+                       max_steps=opts["max_steps"], tag=i)
+            i += 1
+        for c in srv.poll():
+            done[c["tag"]] = c
+    st = srv.stats()
+    srv.close()
+    return done, t0, st
+
+
+def serving(mm, W, nreq, opts):
+    """Serving measurement on the relaxation request stream (grids 64x64x1,
+    128x128x2, 256x64x4, 256x256x8; seeded material, field and smooth start
+    per request): a saturated pilot (all requests at t = 0), then Poisson
+    arrivals at 0.7 x the pilot's solves/s.  Latency = completion - scheduled
+    arrival on the host monotonic clock."""
+    import torch
+
+    reqs = W.serving_requests(nreq, seed=0, rate=1.0)
+    states = [torch.tensor(W.smooth_random(r["n"], 8.0, seed=r["seed"]), dtype=torch.float32,
+                           device="cuda").contiguous() for r in reqs]
+    torch.cuda.synchronize()
+    print("[bench] serving pilot: %d requests at t=0" % nreq, file=sys.stderr, flush=True)
+    done, t0, _ = _serve_once(mm, reqs, states, [0.0] * nreq, opts)
+    span = max(c["t_done"] for c in done.values()) - t0
+    sat = nreq / span
+    rate = 0.7 * sat
+    g = W.rng(1)
+    arrivals = list(np.cumsum(g.exponential(1.0 / rate, nreq)) - 0.0)
+    arrivals = [a - arrivals[0] for a in arrivals]
+    print("[bench] serving: Poisson arrivals at %.2f solves/s" % rate, file=sys.stderr, flush=True)
+    done, t0, st = _serve_once(mm, reqs, states, arrivals, opts)
+    lat = np.array([done[k]["t_done"] - (t0 + arrivals[k]) for k in range(nreq)])
+    last = max(c["t_done"] for c in done.values())
+    per = {}
+    for cls in W.SERVING_GRIDS:
+        idx = [k for k in range(nreq) if reqs[k]["n"] == cls]
+        if idx:
+            lc = lat[idx]
+            per["%dx%dx%d" % cls] = {"n": len(idx), "p50_s": float(np.percentile(lc, 50)),
+                                     "p99_s": float(np.percentile(lc, 99)),
+                                     "converged": sum(done[k]["status"] == mm.MM_OK for k in idx)}
+    steps = [done[k]["accepted"] for k in range(nreq)]
+    return {
+        "requests": nreq, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "solves_per_s": nreq / (last - t0), "saturated_solves_per_s": sat, "arrival_rate": rate,
+        "converged": sum(c["status"] == mm.MM_OK for c in done.values()),
+        "capped": sum(c["status"] == mm.MM_ENOTCONV for c in done.values()),
+        "mean_accepted_steps": float(np.mean(steps)), "per_class": per,
+        "tol": opts["tol"], "rtol": opts["rtol"], "max_steps": opts["max_steps"],
+        "max_active": opts["max_active"], "steps_per_launch": opts["steps_per_launch"],
+        "hbm_budget_bytes": st["budget"], "hbm_peak_bytes": st["bytes_peak"],
+        "waited_memory": st["waited_memory"], "waited_slot": st["waited_slot"],
+        "graph_launches": st["graph_launches"], "plans_created": st["plans_created"],
+        "plans_reused": st["plans_reused"],
+    }
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The CPU oracle (plain FP64 C, OpenMP over FFT lines) on a bounded sample:
     the same material and start state on a 256 x 256 x 32 grid."""
@@ -117,6 +203,10 @@ def main():
     ap.add_argument("--heff-iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving sample (0: skip serving)")
+    ap.add_argument("--serve-max-steps", type=int, default=4000)
+    ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
@@ -201,6 +291,11 @@ def main():
         "heff_only": {"fp32_cell_evals_per_s": N / r32["heff_s"], "fp32_ms": 1e3 * r32["heff_s"]},
         "serving": None,
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(mm, W, args.serve_requests,
+                                 dict(budget=args.serve_budget_mib << 20, max_active=16,
+                                      steps_per_launch=8, tol=1e-5, rtol=1e-7,
+                                      max_steps=args.serve_max_steps))
     if "fp64" in res:
         r64 = res["fp64"]
         out["fp64"] = {"value": r64["stats"]["rhs_evals"] * N / r64["wall"],

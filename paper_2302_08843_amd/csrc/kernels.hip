@@ -67,10 +67,16 @@ namespace mmx {
 #define MMX_MBLOCK 256
 #endif
 #ifndef MMX_XBLOCK
-#define MMX_XBLOCK 128
+#define MMX_XBLOCK 64
 #endif
 #ifndef MMX_X1BLOCK
-#define MMX_X1BLOCK 512
+#define MMX_X1BLOCK 256
+#endif
+#ifndef MMX_X1_KFAST
+#define MMX_X1_KFAST 1  // x inverse / local pass: consecutive blocks walk z first
+#endif
+#ifndef MMX_XVEC
+#define MMX_XVEC 1  // x forward pass: paired (8 / 16-byte) loads when aligned
 #endif
 #ifndef MMX_X1BLOCK_F64
 #define MMX_X1BLOCK_F64 256
@@ -145,7 +151,7 @@ template <typename T, int M, bool PERCELL, bool HALF>
 __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) void k_x_r2c(
     const T* __restrict__ in, long in_row, long in_comp, int n_in, const T* __restrict__ Ms_cell,
     T Ms, cx<T>* __restrict__ out, long out_row, long out_comp, int nrows, int ncomp,
-    const cx<T>* __restrict__ tw, int Lmax)
+    const cx<T>* __restrict__ tw, int Lmax, bool vec)
 {
     using G = XR2C<T, M>;
     constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows;
@@ -158,17 +164,37 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) void k_x_r2c(
     const T* src = in + c * in_comp + r * in_row;
     const T* msrc = PERCELL ? Ms_cell + r * in_row : nullptr;
     cx<T> v[kE];
+    if (MMX_XVEC && vec) {
+        // n_in even and every row start aligned to two reals: one paired load
+        // per element (x[2n], x[2n+1])
 #pragma unroll
-    for (int q = 0; q < kE; ++q) {
-        const int n = t + q * kT;  // first-stage input index
-        const int i0 = 2 * n, i1 = 2 * n + 1;
-        T a = 0, b = 0;
-        // HALF: n_in <= M, so inputs q >= kE/2 (n >= M/2) are zero padding
-        if (!(HALF && q >= kE / 2)) {
-            if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
-            if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+        for (int q = 0; q < kE; ++q) {
+            const int n = t + q * kT;
+            cx<T> ab = {0, 0};
+            if (!(HALF && q >= kE / 2) && valid && 2 * n < n_in) {
+                ab = *reinterpret_cast<const cx<T>*>(src + 2 * n);
+                if (PERCELL) {
+                    const cx<T> mm = *reinterpret_cast<const cx<T>*>(msrc + 2 * n);
+                    ab = {ab.x * mm.x, ab.y * mm.y};
+                } else {
+                    ab = {ab.x * Ms, ab.y * Ms};
+                }
+            }
+            v[q] = ab;
         }
-        v[q] = {a, b};
+    } else {
+#pragma unroll
+        for (int q = 0; q < kE; ++q) {
+            const int n = t + q * kT;  // first-stage input index
+            const int i0 = 2 * n, i1 = 2 * n + 1;
+            T a = 0, b = 0;
+            // HALF: n_in <= M, so inputs q >= kE/2 (n >= M/2) are zero padding
+            if (!(HALF && q >= kE / 2)) {
+                if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
+                if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+            }
+            v[q] = {a, b};
+        }
     }
     cx<T>* L = lds + rl * kL;
     WgFFT<T, M, Regs<T>::x, -1, HALF>::run(v, t, L, 1, tw, Lmax / M);
@@ -478,8 +504,10 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     __shared__ cx<T> lds[kRows * 3 * kL];
     const long lb = xcd_logical();
     if (lb >= nblocks) return;
-    const int k = (int)(lb / njt);
-    const int j0 = (int)(lb % njt) * kRows;
+    // z fastest: the blocks of rows (j, k-1), (j, k), (j, k+1) run together
+    // on one XCD, so the z neighbours of m come from its L2
+    const int k = MMX_X1_KFAST ? (int)(lb % P.nz) : (int)(lb / njt);
+    const int j0 = (MMX_X1_KFAST ? (int)(lb / P.nz) : (int)(lb % njt)) * kRows;
     const int nx = P.nx, ny = P.ny;
 
     if (P.with_demag) x_c2r_rows<T, M>(S1, lds, k, j0, ny, P.s1_comp, P.Hxp, tw, Lmax);
@@ -661,14 +689,17 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
     } else {
         using G = XR2C<T, M>;
         const long grid = (rows + G::kRows - 1) / G::kRows;
+        const uintptr_t al = 2 * sizeof(T) - 1;
+        const bool vec = n_in % 2 == 0 && in_row % 2 == 0 && in_comp % 2 == 0 &&
+                         ((uintptr_t)in & al) == 0 && (!PC || ((uintptr_t)Ms_cell & al) == 0);
         if (n_in <= M)
             k_x_r2c<T, M, PC, true><<<grid, G::kRows * G::kT, 0, p.stream>>>(
                 in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
-                (const cx<T>*)p.tw, p.Lmax);
+                (const cx<T>*)p.tw, p.Lmax, vec);
         else
             k_x_r2c<T, M, PC, false><<<grid, G::kRows * G::kT, 0, p.stream>>>(
                 in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
-                (const cx<T>*)p.tw, p.Lmax);
+                (const cx<T>*)p.tw, p.Lmax, vec);
     }
     return hipGetLastError();
 }
@@ -677,10 +708,10 @@ template <typename T, int L, int AXIS>
 static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, long cs,
                                long gstride, int G)
 {
-    using Gm = Mid<T, L>;
-    const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
     // AXIS = 2 pairs ky with Py - ky: groups 0 .. Py/2
     const int groups = (AXIS == 2 && G > 1) ? G / 2 + 1 : G;
+    using Gm = Mid<T, L>;
+    const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
     const long nblocks = (long)ntile * groups;
     if (2 * n_valid <= L && L > 1)
         k_mid<T, L, AXIS, true><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(
@@ -1157,8 +1188,8 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_ad
     __shared__ cx<T> lds[kRows * 3 * kL];
     const long lb = xcd_logical();
     if (lb >= nblocks) return;
-    const int k = (int)(lb / njt);
-    const int j0 = (int)(lb % njt) * kRows;
+    const int k = MMX_X1_KFAST ? (int)(lb % P.nz) : (int)(lb / njt);
+    const int j0 = (MMX_X1_KFAST ? (int)(lb / P.nz) : (int)(lb % njt)) * kRows;
     const int nx = P.nx, ny = P.ny;
     if (P.with_demag) x_c2r_rows<T, M>(S1, lds, k, j0, ny, P.s1_comp, P.Hxp, tw, Lmax);
     const long N = P.N;
