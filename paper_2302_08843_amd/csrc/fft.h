@@ -177,11 +177,55 @@ struct FFTShape {
 // All threads of the workgroup must call run() (it contains barriers), also
 // those whose transform is masked out.  HALF_IN: the inputs x[L/2..L) are zero
 // (the caller leaves v[kE/2..kE) zero; the first stage skips them).
-template <typename T, int L, int E, int DIR, bool HALF_IN = false>
+// SPLIT: the scratch holds S::kLds reals (slot s at ((T*)lds)[s * lstride])
+// and every exchange moves the real parts, then the imaginary parts -- half
+// the LDS per transform for two more barriers per exchange.
+template <typename T, int L, int E, int DIR, bool HALF_IN = false, bool SPLIT = false>
 struct WgFFT {
     using S = FFTShape<L, E>;
     static constexpr int kE = S::kE;
     static constexpr int kT = S::kT;
+
+    // Exchange after stage s: element base_j + r*Ns of butterfly j written by
+    // stage s, element j + r*(L/R') read for stage s+1 (radix R'), one real
+    // half at a time.
+    template <int s>
+    __device__ static __forceinline__ void split_exchange(cx<T> (&v)[kE], int t, T* lr, int lstride)
+    {
+        constexpr int R = stage_radix(L, kE, s);
+        constexpr int Ns = stage_ns(L, kE, s);
+        constexpr int NB = kE / R;
+        constexpr int R2 = stage_radix(L, kE, s + 1);
+        constexpr int NB2 = kE / R2;
+        cx<T> w[kE];
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();  // previous readers of the scratch are done
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int j = t + q * kT;
+                const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    lr[S::lds_slot(base + r * Ns) * lstride] = half ? v[q * R + r].y : v[q * R + r].x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NB2; ++q) {
+                const int j = t + q * kT;
+#pragma unroll
+                for (int r = 0; r < R2; ++r) {
+                    const T x = lr[S::lds_slot(j + r * (L / R2)) * lstride];
+                    if (half)
+                        w[q * R2 + r].y = x;
+                    else
+                        w[q * R2 + r].x = x;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kE; ++i) v[i] = w[i];
+    }
 
     template <int s>
     __device__ static __forceinline__ void stage(cx<T> (&v)[kE], int t, cx<T>* lds, int lstride,
@@ -190,7 +234,7 @@ struct WgFFT {
         constexpr int R = stage_radix(L, kE, s);
         constexpr int Ns = stage_ns(L, kE, s);
         constexpr int NB = kE / R;  // butterflies per thread
-        if constexpr (s > 0) {
+        if constexpr (s > 0 && !SPLIT) {
             // read this stage's inputs: element j + r*(L/R) for butterfly j
             __syncthreads();
 #pragma unroll
@@ -207,21 +251,29 @@ struct WgFFT {
                 const int jm = j % Ns;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    // exp(DIR 2 pi i r jm / (Ns R)) = w_Lmax^(r jm Lmax/(Ns R))
-                    cx<T> w = tw[(r * jm) * (L / (Ns * R)) * twstride];
+                    // exp(DIR 2 pi i r jm / (Ns R)) = w_Lmax^(r jm Lmax/(Ns R)); the
+                    // table is small, so a 32-bit byte offset from its base
+                    const unsigned ti = (unsigned)((r * jm) * (L / (Ns * R)) * twstride);
+                    const cx<T> w = *reinterpret_cast<const cx<T>*>(
+                        reinterpret_cast<const char*>(tw) + ti * (unsigned)sizeof(cx<T>));
                     v[q * R + r] = DIR < 0 ? cmul(v[q * R + r], w) : cmulc(v[q * R + r], w);
                 }
             }
             dft<R, DIR, HALF_IN && s == 0>(&v[q * R]);
         }
         if constexpr (s + 1 < S::kStages) {
-            __syncthreads();  // previous readers of lds are done
+            if constexpr (SPLIT) {
+                split_exchange<s>(v, t, reinterpret_cast<T*>(lds), lstride);
+            } else {
+                __syncthreads();  // previous readers of lds are done
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int j = t + q * kT;
-                const int base = (j / Ns) * Ns * R + (j % Ns);
+                for (int q = 0; q < NB; ++q) {
+                    const int j = t + q * kT;
+                    const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[S::lds_slot(base + r * Ns) * lstride] = v[q * R + r];
+                    for (int r = 0; r < R; ++r)
+                        lds[S::lds_slot(base + r * Ns) * lstride] = v[q * R + r];
+                }
             }
             stage<s + 1>(v, t, lds, lstride, tw, twstride);
         }

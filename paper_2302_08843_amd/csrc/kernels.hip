@@ -23,6 +23,8 @@
 // contractions; everything here is VALU + LDS, bounded by HBM traffic.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdint>
 #include <vector>
@@ -71,6 +73,9 @@ namespace mmx {
 #endif
 #ifndef MMX_X1BLOCK
 #define MMX_X1BLOCK 256
+#endif
+#ifndef MMX_SSPLIT
+#define MMX_SSPLIT 1  // strided passes: exchange real and imaginary parts separately
 #endif
 #ifndef MMX_X1_KFAST
 #define MMX_X1_KFAST 1  // x inverse / local pass: consecutive blocks walk z first
@@ -235,16 +240,21 @@ struct Strided {
 
 // HALF (forward): n_in <= L/2, the upper half of the inputs is zero padding.
 // HALF (inverse): n_out <= L/2, outputs e >= L/2 are never stored.
-template <typename T, int L, int DIR, bool HALF>
+// O32: every element offset of `in` and `out` times its size is below 4 GiB
+// (32-bit index arithmetic, scalar base + vector byte offset accesses).
+template <typename T, int L, int DIR, bool HALF, bool O32>
 __global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_strided(
     const cx<T>* in, cx<T>* out, int n_in, int n_out, long es_in, long es_out, int ncols,
     int ntile, int G2, long nblocks, long g1_in, long g1_out, long g2_in, long g2_out,
     const cx<T>* __restrict__ tw, int Lmax)
 {
+    using I = typename std::conditional<O32, unsigned, long>::type;
     using G = Strided<T, L>;
     constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
     constexpr bool HIN = HALF && DIR < 0, HOUT = HALF && DIR > 0;
-    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * G::S::kLds : 1];
+    constexpr bool SPL = MMX_SSPLIT != 0;
+    // complex slots, or (SPL) real slots in half of the same array
+    __shared__ cx<T> lds[G::S::kStages > 1 ? (SPL ? (kB * G::S::kLds + 1) / 2 : kB * G::S::kLds) : 1];
     const long lb = xcd_logical();
     if (lb >= nblocks) return;
     const int tile = (int)(lb % ntile);
@@ -253,22 +263,24 @@ __global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_str
     const int b = threadIdx.x % kB, t = threadIdx.x / kB;
     const int col = tile * kB + b;
     const bool cv = col < ncols;
-    const cx<T>* src = in + g1 * g1_in + g2 * g2_in + col;
-    cx<T>* dst = out + g1 * g1_out + g2 * g2_out + col;
+    const I so = (I)g1 * (I)g1_in + (I)g2 * (I)g2_in + (I)col;
+    const I dof = (I)g1 * (I)g1_out + (I)g2 * (I)g2_out + (I)col;
     cx<T> v[kE];
 #pragma unroll
     for (int r = 0; r < kE; ++r) {
         const int e = t + r * kT;
-        v[r] = (!(HIN && r >= kE / 2) && cv && e < n_in) ? src[(long)e * es_in] : cx<T>{0, 0};
+        v[r] = (!(HIN && r >= kE / 2) && cv && e < n_in) ? elem<O32>(in, so + (I)e * (I)es_in)
+                                                          : cx<T>{0, 0};
     }
-    WgFFT<T, L, Regs<T>::s, DIR, HIN>::run(v, t, lds + b, kB, tw, Lmax / L);
+    cx<T>* lb_ = SPL ? reinterpret_cast<cx<T>*>(reinterpret_cast<T*>(lds) + b) : lds + b;
+    WgFFT<T, L, Regs<T>::s, DIR, HIN, SPL>::run(v, t, lb_, kB, tw, Lmax / L);
     if (!cv) return;
     constexpr int Rl = G::S::kLast;
 #pragma unroll
     for (int i = 0; i < kE; ++i) {
         if (HOUT && (i % Rl) >= Rl / 2) continue;  // e >= L/2
         const int e = G::S::out_index(t, i);
-        if (e < n_out) dst[(long)e * es_out] = v[i];
+        if (e < n_out) elem<O32>(out, dof + (I)e * (I)es_out) = v[i];
     }
 }
 
@@ -288,22 +300,55 @@ struct Mid {
 // One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
 // components, forward transform, product with the spectral kernel, inverse
 // transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
-template <typename T, int L, int AXIS, bool HALF>
-__device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Khat, int n_valid,
-                                          long es, long cs, bool cv, int col, int g, int t, int b,
-                                          cx<T>* lds, int Py, int Pz, long Kn, int Hxp,
-                                          const cx<T>* __restrict__ tw, int Lmax)
+// One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
+// components, forward transform, product with the spectral kernel, inverse
+// transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
+// Element idx of a uniformly addressed array.  O32: idx * sizeof(P) is below
+// 4 GiB, and the access becomes a scalar base plus a 32-bit vector byte
+// offset (no 64-bit address arithmetic per access).
+template <bool O32, typename P, typename I>
+__device__ __forceinline__ P& elem(P* base, I idx)
 {
+    if constexpr (O32)
+        return *reinterpret_cast<P*>(reinterpret_cast<char*>(base) +
+                                     (unsigned)idx * (unsigned)sizeof(P));
+    else
+        return base[idx];
+}
+template <bool O32, typename P, typename I>
+__device__ __forceinline__ const P& elem(const P* base, I idx)
+{
+    if constexpr (O32)
+        return *reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) +
+                                           (unsigned)idx * (unsigned)sizeof(P));
+    else
+        return base[idx];
+}
+
+// One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
+// components, forward transform, product with the spectral kernel, inverse
+// transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
+// Element (c, e) of the group is S[o + c*cs + e*es]; index arithmetic is done
+// in 32 bits when O32.
+template <typename T, int L, int AXIS, bool HALF, bool O32>
+__device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict__ Khat,
+                                          int n_valid, long es_, long cs_, bool cv, int col, int g,
+                                          int t, int b, cx<T>* lds, int Py, int Pz, long Kn_,
+                                          int Hxp, const cx<T>* __restrict__ tw, int Lmax)
+{
+    using I = typename std::conditional<O32, unsigned, long>::type;
     using G = Mid<T, L>;
     constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
+    const I o = (I)o_, es = (I)es_, cs = (I)cs_, Kn = (I)Kn_;
     cx<T> v[3][kE];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < kE; ++r) {
             const int e = t + r * kT;
-            v[c][r] = (!(HALF && r >= kE / 2) && cv && e < n_valid) ? base[c * cs + (long)e * es]
-                                                                  : cx<T>{0, 0};
+            v[c][r] = (!(HALF && r >= kE / 2) && cv && e < n_valid)
+                          ? elem<O32>((const cx<T>*)S, o + (I)c * cs + (I)e * es)
+                          : cx<T>{0, 0};
         }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -311,7 +356,7 @@ __device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Kha
 
     if (cv) {
         const int hy = Py / 2, hz = Pz / 2;
-        const long plane = (long)(hy + 1) * Hxp;
+        const I plane = (I)(hy + 1) * (I)Hxp;
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
             const int kk = G::S::out_index(t, i);
@@ -326,9 +371,11 @@ __device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Kha
             const bool fy = ky > hy, fz = kz > hz;
             const int kyf = fy ? Py - ky : ky, kzf = fz ? Pz - kz : kz;
             const T sy = fy ? (T)-1 : (T)1, sz = fz ? (T)-1 : (T)1;
-            const T* K = Khat + kzf * plane + (long)kyf * Hxp + col;
-            const T kxx = K[0], kyy = K[Kn], kzz = K[2 * Kn];
-            const T kxy = sy * K[3 * Kn], kxz = sz * K[4 * Kn], kyz = sy * sz * K[5 * Kn];
+            const I kb = (I)kzf * plane + (I)kyf * (I)Hxp + (I)col;
+            const T kxx = elem<O32>(Khat, kb), kyy = elem<O32>(Khat, kb + Kn);
+            const T kzz = elem<O32>(Khat, kb + 2 * Kn);
+            const T kxy = sy * elem<O32>(Khat, kb + 3 * Kn), kxz = sz * elem<O32>(Khat, kb + 4 * Kn);
+            const T kyz = sy * sz * elem<O32>(Khat, kb + 5 * Kn);
             const cx<T> mx = v[0][i], my = v[1][i], mz = v[2][i];
             v[0][i] = {kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y};
             v[1][i] = {kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y};
@@ -356,15 +403,16 @@ __device__ __forceinline__ void mid_group(cx<T>* base, const T* __restrict__ Kha
         for (int i = 0; i < kE; ++i) {
             if (HALF && (i % Rl) >= Rl / 2) continue;  // e >= L/2
             const int e = G::S::out_index(t, i);
-            if (e < n_valid) base[c * cs + (long)e * es] = v[c][i];
+            if (e < n_valid) elem<O32>(S, o + (I)c * cs + (I)e * es) = v[c][i];
         }
 }
 
 // AXIS = 2: pencils along z; a block owns the column tile at ky = g and, for
 // 0 < g < Py/2, also ky = Py - g, which uses the same (folded) rows of the
 // spectral kernel -- the second read comes from L2, so HBM sees the kernel
-// once.  AXIS = 1: pencils along y (single layer), one group.
-template <typename T, int L, int AXIS, bool HALF>
+// once.  AXIS = 1: pencils along y (single layer), one group.  O32: spectra
+// and kernel arrays below 4 GiB.
+template <typename T, int L, int AXIS, bool HALF, bool O32>
 __global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(cx<T>* S, const T* __restrict__ Khat, int n_valid,
                                                 long es, long cs, long gstride, int ncols,
                                                 int ntile, long nblocks, int Py, int Pz, long Kn,
@@ -381,12 +429,12 @@ __global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(cx<T>* 
     const int col = tile * kB + b;
     const bool cv = col < ncols;
     (void)kT;
-    mid_group<T, L, AXIS, HALF>(S + (long)g * gstride + col, Khat, n_valid, es, cs, cv, col, g, t,
-                                b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    mid_group<T, L, AXIS, HALF, O32>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv, col, g,
+                                     t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
     if (AXIS == 2 && g > 0 && 2 * g < Py) {
         const int g2 = Py - g;
-        mid_group<T, L, AXIS, HALF>(S + (long)g2 * gstride + col, Khat, n_valid, es, cs, cv, col,
-                                    g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+        mid_group<T, L, AXIS, HALF, O32>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs, cv,
+                                         col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
     }
 }
 
@@ -615,14 +663,25 @@ static hipError_t launch_strided_L(const Plan& p, const cx<T>* in, cx<T>* out, i
     const long nblocks = (long)ntile * G2 * G1;
     const long grid = xcd_grid(nblocks);
     const bool half = DIR < 0 ? 2 * n_in <= L : 2 * n_out <= L;
-    if (half && L > 1)
-        k_strided<T, L, DIR, true><<<grid, G::kB * G::kT, 0, p.stream>>>(
-            in, out, n_in, n_out, es_in, es_out, ncols, ntile, G2, nblocks, g1_in, g1_out, g2_in,
-            g2_out, (const cx<T>*)p.tw, p.Lmax);
+    // one past the largest element offset touched in `in` / `out`
+    const long top_in = (long)(G1 - 1) * g1_in + (long)(G2 - 1) * g2_in + ncols +
+                        (long)(n_in > 0 ? n_in - 1 : 0) * es_in;
+    const long top_out = (long)(G1 - 1) * g1_out + (long)(G2 - 1) * g2_out + ncols +
+                         (long)(n_out > 0 ? n_out - 1 : 0) * es_out;
+    const bool o32 = (size_t)std::max(top_in, top_out) * sizeof(cx<T>) < (1ull << 32);
+#define MMX_KS(H, O)                                                                              \
+    k_strided<T, L, DIR, H, O><<<grid, G::kB * G::kT, 0, p.stream>>>(                             \
+        in, out, n_in, n_out, es_in, es_out, ncols, ntile, G2, nblocks, g1_in, g1_out, g2_in,    \
+        g2_out, (const cx<T>*)p.tw, p.Lmax)
+    if (half && L > 1 && o32)
+        MMX_KS(true, true);
+    else if (half && L > 1)
+        MMX_KS(true, false);
+    else if (o32)
+        MMX_KS(false, true);
     else
-        k_strided<T, L, DIR, false><<<grid, G::kB * G::kT, 0, p.stream>>>(
-            in, out, n_in, n_out, es_in, es_out, ncols, ntile, G2, nblocks, g1_in, g1_out, g2_in,
-            g2_out, (const cx<T>*)p.tw, p.Lmax);
+        MMX_KS(false, false);
+#undef MMX_KS
     return hipGetLastError();
 }
 
@@ -713,14 +772,22 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
     using Gm = Mid<T, L>;
     const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
     const long nblocks = (long)ntile * groups;
-    if (2 * n_valid <= L && L > 1)
-        k_mid<T, L, AXIS, true><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(
-            S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nblocks, p.P[1], p.P[2],
-            p.Kn, p.Hxp, (const cx<T>*)p.tw, p.Lmax);
+    const bool o32 = (size_t)p.S2n * 2 * sizeof(T) < (1ull << 32) &&
+                     (size_t)p.Kn * 6 * sizeof(T) < (1ull << 32);
+    const bool half = 2 * n_valid <= L && L > 1;
+#define MMX_KMID(H, O)                                                                           \
+    k_mid<T, L, AXIS, H, O><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(                \
+        S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nblocks, p.P[1], p.P[2], p.Kn, \
+        p.Hxp, (const cx<T>*)p.tw, p.Lmax)
+    if (half && o32)
+        MMX_KMID(true, true);
+    else if (half)
+        MMX_KMID(true, false);
+    else if (o32)
+        MMX_KMID(false, true);
     else
-        k_mid<T, L, AXIS, false><<<xcd_grid(nblocks), Gm::kB * Gm::kT, 0, p.stream>>>(
-            S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nblocks, p.P[1], p.P[2],
-            p.Kn, p.Hxp, (const cx<T>*)p.tw, p.Lmax);
+        MMX_KMID(false, false);
+#undef MMX_KMID
     return hipGetLastError();
 }
 
