@@ -47,6 +47,27 @@ def pass_bytes(grid, prec):
             "x_inv_local": S1 + m + m}
 
 
+def measured_traffic(grid):
+    """HBM bytes per launch of the z pass (FETCH_SIZE + WRITE_SIZE, each scaled
+    by a 1 GiB copy) from the committed rocprofv3 counter summary -- only if
+    the kernel sources are the ones it was measured on and the grid is its
+    grid; else None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "mid_512x512x64_fp32_hbm_traffic.json")
+    if tuple(grid) != (512, 512, 64) or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for fn in rec["sources"]:
+        with open(os.path.join(ROOT, fn), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def run_steps(mm, plan, m, cfg, steps, warmup, rtol, profile=False):
     import torch
 
@@ -284,8 +305,8 @@ def main():
                    "grid": list(grid), "cells": N, "cell_m": list(cfg["d"]), "rtol": args.rtol,
                    "rhs_evals": evals, "rejected": r32["stats"]["rejected"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_mid<float,128,2> (z forward + spectral product + z inverse)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(grid),
+                     "kernel": "k_mid<float,128,2,...> (z forward + spectral product + z inverse)",
                      "bytes_per_launch": pb["mid"], "avg_us": mid_avg_s * 1e6},
         "passes_fp32": passes,
         "heff_only": {"fp32_cell_evals_per_s": N / r32["heff_s"], "fp32_ms": 1e3 * r32["heff_s"]},
