@@ -74,16 +74,17 @@ namespace mmx {
 #ifndef MMX_X1BLOCK
 #define MMX_X1BLOCK 256
 #endif
-// z pass: ky and Py - ky in the two halves of one block (measured: helps
-// FP64 with 128-thread halves, costs FP32)
-#ifndef MMX_MID_PAR_F32
-#define MMX_MID_PAR_F32 0
-#endif
-#ifndef MMX_MID_PAR_F64
-#define MMX_MID_PAR_F64 1
-#endif
+// z pass: ky and Py - ky in adjacent blocks (ADJ) instead of one after the
+// other in one block; block size per precision (measured: ADJ helps FP64 and
+// costs FP32)
 #ifndef MMX_MBLOCK_F64
-#define MMX_MBLOCK_F64 128
+#define MMX_MBLOCK_F64 256
+#endif
+#ifndef MMX_MID_ADJ_F32
+#define MMX_MID_ADJ_F32 0
+#endif
+#ifndef MMX_MID_ADJ_F64
+#define MMX_MID_ADJ_F64 1
 #endif
 #ifndef MMX_SSPLIT
 #define MMX_SSPLIT 1  // strided passes: exchange real and imaginary parts separately
@@ -421,47 +422,45 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
 
 // AXIS = 2: pencils along z; a block owns the column tile at ky = g and, for
 // 0 < g < Py/2, also ky = Py - g, which uses the same (folded) rows of the
-// spectral kernel.  PAR: the two groups run in the two halves of the block at
-// the same time, so the second read of each kernel row is an L1/L2 hit (run
-// one after the other, the rows have left L2 before the second group reads
-// them).  AXIS = 1: pencils along y (single layer), one group.  O32: spectra
-// and kernel arrays below 4 GiB.
-template <typename T, int L, int AXIS, bool HALF, bool O32, bool PAR>
-__global__ __launch_bounds__(((PAR ? 2 : 1) * Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(
+// spectral kernel.  ADJ: the two groups go to adjacent blocks instead (same
+// XCD, same time), so the second read of each kernel row is an L2 hit rather
+// than a re-read after the rows have left L2.  AXIS = 1: pencils along y
+// (single layer), one group.  O32: spectra and kernel arrays below 4 GiB.
+template <typename T, int L, int AXIS, bool HALF, bool O32, bool ADJ>
+__global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(
     cx<T>* S, const T* __restrict__ Khat, int n_valid, long es, long cs, long gstride, int ncols,
     int ntile, long nblocks, int Py, int Pz, long Kn, int Hxp, const cx<T>* __restrict__ tw,
     int Lmax)
 {
     using G = Mid<T, L>;
-    constexpr int kT = G::kT, kB = G::kB;
-    constexpr int kRegion = G::S::kStages > 1 ? kB * G::S::kLds : 1;
-    __shared__ cx<T> lds[(PAR ? 2 : 1) * kRegion];
+    constexpr int kB = G::kB;
+    __shared__ cx<T> lds[G::S::kStages > 1 ? kB * G::S::kLds : 1];
     const long lb = xcd_logical();
     if (lb >= nblocks) return;
-    const int tile = (int)(lb % ntile);
-    const int g = (int)(lb / ntile);
-    const int half = PAR ? (int)threadIdx.x / (kB * kT) : 0;
-    const int tid = (int)threadIdx.x % (kB * kT);
-    const int b = tid % kB, t = tid / kB;
+    int tile, g;
+    bool paired;
+    if constexpr (ADJ) {
+        const int which = (int)(lb & 1);
+        const long rest = lb >> 1;
+        tile = (int)(rest % ntile);
+        const int gp = (int)(rest / ntile);
+        if (which && (gp == 0 || 2 * gp == Py)) return;  // its own mirror
+        g = which ? Py - gp : gp;
+        paired = false;
+    } else {
+        tile = (int)(lb % ntile);
+        g = (int)(lb / ntile);
+        paired = AXIS == 2 && g > 0 && 2 * g < Py;
+    }
+    const int b = threadIdx.x % kB, t = threadIdx.x / kB;
     const int col = tile * kB + b;
     const bool cv = col < ncols;
-    const bool paired = AXIS == 2 && g > 0 && 2 * g < Py;
-    if constexpr (PAR) {
-        // half 1 takes ky = Py - g (idle, but still at every barrier, if g
-        // has no partner)
-        const int gg = half ? Py - g : g;
-        mid_group<T, L, AXIS, HALF, O32>(S, (long)gg * gstride + col, Khat, n_valid, es, cs,
-                                         cv && (half == 0 || paired), col, gg, t, b,
-                                         lds + half * kRegion, Py, Pz, Kn, Hxp, tw, Lmax);
-    } else {
-        (void)kT;
-        mid_group<T, L, AXIS, HALF, O32>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv,
-                                         col, g, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
-        if (paired) {
-            const int g2 = Py - g;
-            mid_group<T, L, AXIS, HALF, O32>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs,
-                                             cv, col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
-        }
+    mid_group<T, L, AXIS, HALF, O32>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv, col, g,
+                                     t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    if (paired) {
+        const int g2 = Py - g;
+        mid_group<T, L, AXIS, HALF, O32>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs, cv,
+                                         col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
     }
 }
 
@@ -802,16 +801,16 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
     const bool o32 = (size_t)p.S2n * 2 * sizeof(T) < (1ull << 32) &&
                      (size_t)p.Kn * 6 * sizeof(T) < (1ull << 32);
     const bool half = 2 * n_valid <= L && L > 1;
-    const bool par = (sizeof(T) == 4 ? MMX_MID_PAR_F32 : MMX_MID_PAR_F64) && AXIS == 2 && G > 1;
-#define MMX_KMID(H, O, PA)                                                                        \
-    k_mid<T, L, AXIS, H, O, PA><<<xcd_grid(nblocks), (PA ? 2 : 1) * Gm::kB * Gm::kT, 0,          \
-                                  p.stream>>>(S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, \
-                                              ntile, nblocks, p.P[1], p.P[2], p.Kn, p.Hxp,        \
-                                              (const cx<T>*)p.tw, p.Lmax)
-#define MMX_KMID2(H, O)        \
-    if (par)                   \
-        MMX_KMID(H, O, true);  \
-    else                       \
+    const bool adj = (sizeof(T) == 4 ? MMX_MID_ADJ_F32 : MMX_MID_ADJ_F64) && AXIS == 2 && G > 1;
+    const long nb = adj ? 2 * nblocks : nblocks;
+#define MMX_KMID(H, O, AD)                                                                        \
+    k_mid<T, L, AXIS, H, O, AD><<<xcd_grid(nb), Gm::kB * Gm::kT, 0, p.stream>>>(                  \
+        S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nb, p.P[1], p.P[2], p.Kn,     \
+        p.Hxp, (const cx<T>*)p.tw, p.Lmax)
+#define MMX_KMID2(H, O)            \
+    if (adj)                       \
+        MMX_KMID(H, O, true);      \
+    else                           \
         MMX_KMID(H, O, false);
     if (half && o32) {
         MMX_KMID2(true, true)
