@@ -61,6 +61,9 @@ def lib():
         L.or_newell.argtypes = [dp, C.c_long, C.c_long, C.c_long, dp]
         L.or_dipole.argtypes = [dp, C.c_long, C.c_long, C.c_long, dp]
         L.or_tensor_entry.argtypes = [dp, C.c_long, C.c_long, C.c_long, C.c_int, dp]
+        L.or_demag_at.argtypes = [C.POINTER(C.c_long), dp, C.c_int, C.c_void_p, C.c_double, dp,
+                                  C.c_long, C.POINTER(C.c_long), dp]
+        L.or_demag_at.restype = C.c_int
         L.or_fft1d.argtypes = [C.c_long, C.c_void_p, C.c_int]
         L.or_dft1d.argtypes = [C.c_long, C.c_void_p, C.c_void_p, C.c_int]
         L.or_padded.argtypes = [C.c_long]
@@ -128,6 +131,26 @@ def tensor_entry(d, I, J, K, p=20) -> np.ndarray:
     dipole beyond (Sec. 4.4)."""
     out = np.zeros(6)
     lib().or_tensor_entry(_dp(_d3(d)), int(I), int(J), int(K), int(p), _dp(out))
+    return out
+
+
+def demag_at(n, d, m, cells, Ms=1.0, p=20) -> np.ndarray:
+    """Demag field at the given linear cell indices by direct summation over
+    every source cell (no padded grid): shape (len(cells), 3).  Ms is a
+    scalar or an (nz, ny, nx) array; m is (3, nz, ny, nx)."""
+    nn = (C.c_long * 3)(*[int(v) for v in n])
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+    cl = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.zeros((len(cl), 3))
+    if np.ndim(Ms) == 0:
+        ms_ptr, ms0 = None, float(Ms)
+    else:
+        msa = np.ascontiguousarray(np.asarray(Ms, dtype=np.float64))
+        ms_ptr, ms0 = msa.ctypes.data, 0.0
+    rc = lib().or_demag_at(nn, _dp(_d3(d)), int(p), ms_ptr, ms0, _dp(m), len(cl),
+                           cl.ctypes.data_as(C.POINTER(C.c_long)), _dp(out))
+    if rc != 0:
+        raise ValueError("or_demag_at needs p >= 0")
     return out
 
 

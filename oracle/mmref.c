@@ -161,6 +161,59 @@ void or_tensor_entry(const double d[3], long oi, long oj, long ok, int p, double
     }
 }
 
+/* Demagnetisation field at selected target cells by direct summation of the
+ * discrete convolution h_i = sum_j K_{i-j} Ms_j m_j (Sec. 4.4) over every
+ * source cell -- no padded grid and no FFT, so it serves grids far too large
+ * for the FFT path.  Near-field entries (Chebyshev index distance <= p) are
+ * tabulated once; the rest are dipole entries.  Ms: per cell, or NULL for the
+ * uniform value Ms0.  m is [3][N], x fastest; cells holds ncell linear cell
+ * indices; out receives 3 values (x, y, z) per target.  Returns 0, or -1 for
+ * p < 0 (Newell everywhere is not tabulated here). */
+int or_demag_at(const long n[3], const double d[3], int p, const double *Ms, double Ms0,
+                const double *m, long ncell, const long *cells, double *out)
+{
+    if (p < 0)
+        return -1;
+    long nx = n[0], ny = n[1], nz = n[2], N = nx * ny * nz;
+    long rx = p < nx - 1 ? p : nx - 1, ry = p < ny - 1 ? p : ny - 1, rz = p < nz - 1 ? p : nz - 1;
+    long tx = 2 * rx + 1, ty = 2 * ry + 1, tz = 2 * rz + 1, nt = tx * ty * tz;
+    double *T = malloc(sizeof(double) * 6 * nt);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long q = 0; q < nt; q++) {
+        long oi = q % tx - rx, oj = (q / tx) % ty - ry, ok = q / (tx * ty) - rz;
+        or_tensor_entry(d, oi, oj, ok, p, T + 6 * q);
+    }
+    for (long s = 0; s < ncell; s++) {
+        long t = cells[s];
+        long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+        long double hx = 0.0L, hy = 0.0L, hz = 0.0L;
+#pragma omp parallel for reduction(+ : hx, hy, hz) schedule(static)
+        for (long src = 0; src < N; src++) {
+            long si = src % nx, sj = (src / nx) % ny, sk = src / (nx * ny);
+            long oi = i - si, oj = j - sj, ok = k - sk;
+            double e[6];
+            /* |oi| <= nx - 1 always, so |oi| <= rx exactly when |oi| <= p */
+            if (labs(oi) <= rx && labs(oj) <= ry && labs(ok) <= rz) {
+                const double *te = T + 6 * ((oi + rx) + tx * ((oj + ry) + ty * (ok + rz)));
+                for (int c = 0; c < 6; c++)
+                    e[c] = te[c];
+            } else {
+                or_dipole(d, oi, oj, ok, e);
+            }
+            double ms = Ms ? Ms[src] : Ms0;
+            double Mx = ms * m[src], My = ms * m[N + src], Mz = ms * m[2 * N + src];
+            hx += e[0] * Mx + e[3] * My + e[4] * Mz;
+            hy += e[3] * Mx + e[1] * My + e[5] * Mz;
+            hz += e[4] * Mx + e[5] * My + e[2] * Mz;
+        }
+        out[3 * s] = (double)hx;
+        out[3 * s + 1] = (double)hy;
+        out[3 * s + 2] = (double)hz;
+    }
+    free(T);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* FFT: iterative radix-2 Cooley-Tukey with bit reversal, twiddles from long  */
 /* double sin/cos.  sign = -1 forward, +1 inverse (unnormalised).  Pinned by  */

@@ -151,3 +151,57 @@ def test_trace_invariant_full_large_grid(torch_cuda, mm):
         tot += h[a].double()
     err = (tot + 1e6).abs().max().item() / 1e6
     assert err < 2e-5, err
+
+
+@pytest.fixture(scope="module")
+def throughput_case(orc):
+    """256 x 256 x 16 cells of 3 nm (padded 512 x 512 x 32), Ms and A drawn
+    per run, Ku 5e4 along z, smooth random m: the field-throughput
+    workload, with the oracle's FFT-path field."""
+    c = W.config_throughput()
+    o = orc.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], Ku=c["Ku"], eu=c["eu"], alpha=c["alpha"])
+    o.set_field(c["H"])
+    return c, o.heff(c["m0"], 0.0, c["terms"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_throughput_config_full_field(torch_cuda, mm, throughput_case, prec):
+    c, ref = throughput_case
+    banner("full field %s %s" % (c["n"], prec))
+    plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], Ku=c["Ku"], alpha=c["alpha"], prec=prec,
+                   ku_axis=c["eu"])
+    h = to_np(plan.heff(c["m0"], c["H"], c["terms"]))
+    e = rel_l2(h, ref)
+    print("  rel-L2 vs oracle %.2e" % e)
+    assert e <= TOL[prec], e
+
+
+@pytest.fixture(scope="module")
+def large_case(orc):
+    """512 x 512 x 64 cells (padded 1024 x 1024 x 128), the benchmark
+    workload: the oracle's direct sum of the demag convolution at sampled
+    cells (corners, edges, centre, seeded random cells)."""
+    c = W.config_large()
+    nx, ny, nz = c["n"]
+    g = W.rng(11)
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx - 1, 0, 0), (0, ny - 1, nz - 1),
+           (nx // 2, ny // 2, nz // 2), (0, ny // 2, nz // 2), (nx // 2, 0, 0)]
+    pts += [(int(g.integers(nx)), int(g.integers(ny)), int(g.integers(nz))) for _ in range(9)]
+    cells = np.array([i + nx * (j + ny * k) for i, j, k in pts])
+    ref = orc.demag_at(c["n"], c["d"], c["m0"], cells, Ms=c["Ms"])
+    return c, cells, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_config_sampled_demag(torch_cuda, mm, large_case, prec):
+    """The benchmark grid in the benchmark's launch configuration: the GPU
+    FFT demag field at sampled cells against the direct sum over all 16.7 M
+    source cells."""
+    c, cells, ref = large_case
+    banner("large demag sampled %s %s" % (c["n"], prec))
+    plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec=prec)
+    h = plan.heff(c["m0"], None, mm.MM_DEMAG).reshape(3, -1)
+    got = to_np(h[:, torch_cuda.as_tensor(cells, device=h.device)]).T
+    e = rel_l2(got, ref)
+    print("  rel-L2 over %d sampled cells %.2e" % (len(cells), e))
+    assert e <= TOL[prec], e
