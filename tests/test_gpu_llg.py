@@ -137,3 +137,36 @@ def test_failure_paths(torch_cuda, mm):
     status, st = plan.relax(m, None, mm.MM_ALL, tol=1e-9, max_steps=2)
     assert status == mm.MM_ENOTCONV and st["accepted"] == 2
     torch.cuda.synchronize()
+
+
+def test_large_workload_crop_precision(torch_cuda, mm, orc):
+    """The benchmark material and vortex start on the 64 x 64 x 8 crop: 100
+    adaptive steps in FP64 on the GPU against the FP64 oracle at equal time
+    (bar: rtol), and FP32 on the GPU against FP64 at equal time (bar 1e-4)."""
+    c = W.config_large(n=(64, 64, 8))
+    banner("crop %s 100 steps" % (c["n"],))
+    rtol, steps = 1e-6, 100
+    res = {}
+    for prec in ("fp64", "fp32"):
+        plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec=prec)
+        m = plan._t(c["m0"])
+        if prec == "fp64":
+            status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, max_steps=steps)
+            assert st["accepted"] == steps
+            t_end = t
+        else:
+            status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, t_end=t_end)
+            assert t == t_end
+        res[prec] = (to_np(m), plan.energy(m, c["H"], c["terms"]), st)
+    o = orc.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    o.set_field(c["H"], terms=c["terms"])
+    m_o, t_o, _, st_o, status_o = o.dp45(c["m0"], rtol=rtol, t_end=t_end)
+    assert status_o == 0
+    d64 = np.abs(res["fp64"][0] - m_o).max()
+    d32 = np.abs(res["fp32"][0] - res["fp64"][0]).max()
+    E_o = o.energy(m_o)
+    print("  t %.3e s: |m64 - oracle| %.2e, |m32 - m64| %.2e, E64 %s, E oracle %s, E32 %s"
+          % (t_end, d64, d32, res["fp64"][1][4], E_o[4], res["fp32"][1][4]))
+    assert d64 <= rtol
+    assert d32 <= 1e-4
+    assert abs(res["fp64"][1][4] - E_o[4]) <= 1e-6 * abs(E_o[4])
