@@ -85,6 +85,10 @@ def lib():
                               C.c_long, C.c_int, C.c_int, C.c_double, C.c_int,
                               C.POINTER(_Stats), C.c_double]
         L.or_dp45.restype = C.c_int
+        L.or_rk_adaptive.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, C.c_double, C.c_double,
+                                     C.c_double, C.c_long, C.c_int, C.c_int, C.c_double, C.c_int,
+                                     C.POINTER(_Stats), C.c_double]
+        L.or_rk_adaptive.restype = C.c_int
         L.or_relax.argtypes = [C.c_void_p, dp, C.c_double, C.c_long, C.c_double, C.POINTER(_Stats)]
         L.or_relax.restype = C.c_int
         L.or_max_torque.argtypes = [C.c_void_p, dp, C.c_double]
@@ -274,20 +278,26 @@ class Oracle:
         return E
 
     def dp45(self, m, t=0.0, dt=-1.0, rtol=1e-6, atol=None, t_end=np.inf, max_steps=1 << 40,
-             renorm=False, precess=True, alpha=None, fixed=False, torque_tol=0.0):
-        """Dormand-Prince 5(4) integration; returns (m, t, dt, stats, status)."""
+             renorm=False, precess=True, alpha=None, fixed=False, torque_tol=0.0, method=0):
+        """Adaptive embedded Runge-Kutta integration (method 0: Dormand-Prince
+        5(4), 1: Runge-Kutta-Fehlberg 4(5)); returns (m, t, dt, stats, status)."""
         y = self._m(m).copy()
         tt = C.c_double(t)
         dd = C.c_double(dt)
         st = _Stats()
-        status = lib().or_dp45(self._c, _dp(y), C.byref(tt), C.byref(dd), float(rtol),
-                               float(rtol if atol is None else atol), float(t_end), int(max_steps),
-                               int(bool(renorm)), int(bool(precess)),
-                               float(self.alpha if alpha is None else alpha), int(bool(fixed)),
-                               C.byref(st), float(torque_tol))
+        status = lib().or_rk_adaptive(self._c, int(method), _dp(y), C.byref(tt), C.byref(dd),
+                                      float(rtol), float(rtol if atol is None else atol),
+                                      float(t_end), int(max_steps), int(bool(renorm)),
+                                      int(bool(precess)),
+                                      float(self.alpha if alpha is None else alpha),
+                                      int(bool(fixed)), C.byref(st), float(torque_tol))
         stats = dict(accepted=st.accepted, rejected=st.rejected, rhs_evals=st.rhs_evals,
                      t=st.t, dt=st.dt, err_last=st.err_last)
         return y, tt.value, dd.value, stats, status
+
+    def rkf45(self, m, **kw):
+        """Runge-Kutta-Fehlberg 4(5), the paper's default integrator (Sec. 3)."""
+        return self.dp45(m, method=1, **kw)
 
     def relax(self, m, tol=1e-5, max_steps=50000, rtol=1e-4):
         """Precession-free alpha = 1 relaxation (Sec. 3) until the maximum

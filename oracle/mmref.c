@@ -700,6 +700,56 @@ static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
 static const double DP_BS[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                                 -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
 
+/* Runge-Kutta-Fehlberg 4(5) (Fehlberg 1969), the paper's default (Sec. 3):
+ * six stages, the 4th-order solution is propagated and the difference to the
+ * 5th-order one is the error estimate; no first-same-as-last stage. */
+static const double RKF_C[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double RKF_A[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+static const double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+static const double RKF_B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0,
+                                 -9.0 / 50.0, 2.0 / 55.0};
+
+/* An embedded explicit pair: stages, nodes c, coefficients a (row s uses
+ * a[s][0..s-1]), propagated weights b, error weights e (b minus the other
+ * solution's weights); fsal: the last stage is evaluated at the propagated
+ * solution, so it is the next step's first stage. */
+typedef struct {
+    int stages, fsal;
+    double c[7], a[7][6], b[7], e[7];
+} or_tableau;
+
+static void tableau(int method, or_tableau *T)
+{
+    memset(T, 0, sizeof(*T));
+    if (method == 1) {
+        T->stages = 6;
+        T->fsal = 0;
+        for (int s = 0; s < 6; s++) {
+            T->c[s] = RKF_C[s];
+            for (int j = 0; j < 5; j++)
+                T->a[s][j] = RKF_A[s][j];
+            T->b[s] = RKF_B4[s];
+            T->e[s] = RKF_B4[s] - RKF_B5[s];
+        }
+    } else {
+        T->stages = 7;
+        T->fsal = 1;
+        for (int s = 0; s < 7; s++) {
+            T->c[s] = DP_C[s];
+            for (int j = 0; j < 6; j++)
+                T->a[s][j] = DP_A[s][j];
+            T->b[s] = DP_B[s];
+            T->e[s] = DP_B[s] - DP_BS[s];
+        }
+    }
+}
+
 enum { OR_OK = 0, OR_EDTMIN = -5, OR_ENOTCONV = -6, OR_ENONFINITE = -4 };
 
 typedef struct {
@@ -792,16 +842,34 @@ static double initial_dt(const or_ctx *c, const double *y, const double *f0, dou
  * accepted step (then FSAL cannot be used and k1 is re-evaluated).
  * fixed != 0 disables error control (every step accepted, dt constant): used
  * by the order test only.  *dt <= 0 asks for the automatic initial step. */
+int or_rk_adaptive(or_ctx *c, int method, double *m, double *t, double *dt, double rtol,
+                   double atol, double t_end, long max_steps, int renorm, int precess, double alpha,
+                   int fixed, or_stats *st, double torque_tol);
+
 int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double atol, double t_end,
             long max_steps, int renorm, int precess, double alpha, int fixed, or_stats *st,
             double torque_tol)
 {
+    return or_rk_adaptive(c, 0, m, t, dt, rtol, atol, t_end, max_steps, renorm, precess, alpha,
+                          fixed, st, torque_tol);
+}
+
+/* The same integration with the pair chosen by method: 0 Dormand-Prince 5(4),
+ * 1 Runge-Kutta-Fehlberg 4(5).  Same controller for both. */
+int or_rk_adaptive(or_ctx *c, int method, double *m, double *t, double *dt, double rtol,
+                   double atol, double t_end, long max_steps, int renorm, int precess, double alpha,
+                   int fixed, or_stats *st, double torque_tol)
+{
+    or_tableau T;
+    tableau(method, &T);
+    const int S = T.stages;
     long N = c->N, n3 = 3 * N;
     double *k[7];
     for (int s = 0; s < 7; s++)
         k[s] = malloc(sizeof(double) * n3);
     double *y = malloc(sizeof(double) * n3), *ys = malloc(sizeof(double) * n3);
     double *h = malloc(sizeof(double) * n3), *e = malloc(sizeof(double) * n3);
+    double *yn = malloc(sizeof(double) * n3);
     memset(st, 0, sizeof(*st));
     int status = OR_OK;
 
@@ -833,24 +901,34 @@ int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double ato
         double hstep = *dt;
         if (*t + hstep > t_end)
             hstep = t_end - *t;
-        for (int s = 1; s < 7; s++) {
+        for (int s = 1; s < S; s++) {
             for (long q = 0; q < n3; q++) {
                 double acc = 0.0;
                 for (int j = 0; j < s; j++)
-                    acc += DP_A[s][j] * k[j][q];
+                    acc += T.a[s][j] * k[j][q];
                 ys[q] = y[q] + hstep * acc;
             }
-            rhs_at(c, ys, *t + DP_C[s] * hstep, alpha, precess, h, k[s]);
+            rhs_at(c, ys, *t + T.c[s] * hstep, alpha, precess, h, k[s]);
             st->rhs_evals++;
         }
-        /* ys now holds the 5th-order solution (stage 7 input = b-weighted sum) */
+        /* the propagated solution: with FSAL it is the last stage's input */
+        if (T.fsal) {
+            memcpy(yn, ys, sizeof(double) * n3);
+        } else {
+            for (long q = 0; q < n3; q++) {
+                double acc = 0.0;
+                for (int j = 0; j < S; j++)
+                    acc += T.b[j] * k[j][q];
+                yn[q] = y[q] + hstep * acc;
+            }
+        }
         for (long q = 0; q < n3; q++) {
             double acc = 0.0;
-            for (int j = 0; j < 7; j++)
-                acc += (DP_B[j] - DP_BS[j]) * k[j][q];
+            for (int j = 0; j < S; j++)
+                acc += T.e[j] * k[j][q];
             e[q] = hstep * acc;
         }
-        double err = fixed ? 0.0 : err_norm(c, y, ys, e, rtol, atol);
+        double err = fixed ? 0.0 : err_norm(c, y, yn, e, rtol, atol);
         st->err_last = err;
         if (!isfinite(err)) {
             /* A trial step that overflows is rejected like any too-large step
@@ -870,16 +948,19 @@ int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double ato
         }
         if (err <= 1.0) {
             *t += hstep;
-            memcpy(y, ys, sizeof(double) * n3);
+            memcpy(y, yn, sizeof(double) * n3);
             st->accepted++;
             if (renorm) {
                 renormalise(c, y);
                 rhs_at(c, y, *t, alpha, precess, h, k[0]);
                 st->rhs_evals++;
-            } else {
+            } else if (T.fsal) {
                 double *tmp = k[0];
-                k[0] = k[6];
-                k[6] = tmp; /* first same as last; h holds the field at y */
+                k[0] = k[S - 1];
+                k[S - 1] = tmp; /* first same as last; h holds the field at y */
+            } else {
+                rhs_at(c, y, *t, alpha, precess, h, k[0]);
+                st->rhs_evals++;
             }
             if (!fixed) {
                 double fac = err == 0.0 ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
@@ -926,6 +1007,7 @@ int or_dp45(or_ctx *c, double *m, double *t, double *dt, double rtol, double ato
         free(k[s]);
     free(y);
     free(ys);
+    free(yn);
     free(h);
     free(e);
     return status;

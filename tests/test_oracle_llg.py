@@ -181,3 +181,41 @@ def test_overflowing_trial_step_is_rejected_not_fatal(orc):
     bad = m0.copy()
     bad[1, 0, 0, 0] = np.nan
     assert o.dp45(bad, dt=1e-13, max_steps=3)[4] == orc.ENONFINITE
+
+
+def test_rkf45_fourth_order(orc):
+    # the paper's default pair propagates the 4th-order solution: halving dt
+    # divides the global error by ~2^4 (fixed steps, Larmor problem)
+    H, alpha, th0, ph0 = 1e5, 0.1, 1.0, 0.3
+    o = orc.Oracle((1, 1, 1), (2e-9,) * 3, Ms=8e5, alpha=alpha)
+    o.set_field((0, 0, H), terms=orc.DEMAG | orc.ZEEMAN)
+    m0 = cell_vec(larmor(th0, ph0, H, alpha, 0.0))
+    t_end = 100e-12
+    errs = []
+    for dt in (10e-12, 5e-12, 2.5e-12):
+        m, t, _, st, _ = o.rkf45(m0, dt=dt, t_end=t_end, fixed=True)
+        assert abs(t - t_end) < 1e-24
+        assert st["rhs_evals"] == 1 + 6 * st["accepted"]  # no first-same-as-last
+        errs.append(np.abs(m.ravel() - larmor(th0, ph0, H, alpha, t_end)).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 13 < r1 < 20 and 13 < r2 < 20, errs
+
+
+def test_rkf45_closed_forms(orc):
+    # adaptive Fehlberg against the Larmor and damped-switching closed forms
+    H, alpha, th0, ph0 = 1e5, 0.1, 1.0, 0.3
+    o = orc.Oracle((1, 1, 1), (2e-9,) * 3, Ms=8e5, alpha=alpha)
+    o.set_field((0, 0, H), terms=orc.DEMAG | orc.ZEEMAN)
+    m0 = cell_vec(larmor(th0, ph0, H, alpha, 0.0))
+    m, t, dt, st, status = o.rkf45(m0, rtol=1e-11, t_end=200e-12)
+    assert status == 0
+    assert np.abs(m.ravel() - larmor(th0, ph0, H, alpha, 200e-12)).max() < 1e-8
+    # on a field-coupled grid Fehlberg converges, as rtol shrinks, to the
+    # Dormand-Prince solution at rtol 1e-13
+    c = W.config_small_llg()
+    o2 = orc.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    o2.set_field(c["H"], terms=c["terms"])
+    ref = o2.dp45(c["m0"], rtol=1e-13, t_end=1e-12)[0]
+    e8 = np.abs(o2.rkf45(c["m0"], rtol=1e-8, t_end=1e-12)[0] - ref).max()
+    e10 = np.abs(o2.rkf45(c["m0"], rtol=1e-10, t_end=1e-12)[0] - ref).max()
+    assert e10 < 1e-7 and e10 < e8 / 10, (e8, e10)
