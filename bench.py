@@ -68,18 +68,20 @@ def measured_traffic(grid):
     return rec["read_bytes"] + rec["write_bytes"]
 
 
-def run_steps(mm, plan, m, cfg, steps, warmup, rtol, profile=False):
+def run_steps(mm, plan, m, cfg, steps, warmup, rtol, profile=False, method=0):
     import torch
 
     H = cfg["H"]
     t, dt = 0.0, -1.0
     if warmup:
-        _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=warmup)
+        _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=warmup,
+                                     method=method)
     torch.cuda.synchronize()
     if profile:
         plan.profile(True)
     t0 = time.perf_counter()
-    _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=steps)
+    _, t, dt, st = plan.llg_step(m, H, cfg["terms"], t, dt, rtol=rtol, max_steps=steps,
+                                 method=method)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = plan.profile_read() if profile else None
@@ -270,6 +272,12 @@ def main():
               file=sys.stderr, flush=True)
         th = heff_only(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters)
         res[prec] = dict(wall=wall, stats=st, prof=prof, heff_s=th, device_bytes=plan.device_bytes())
+        if prec == "fp32":
+            # the paper's default pair, same steps from the same start
+            m = plan._t(cfg["m0"])
+            wall_f, st_f, _ = run_steps(mm, plan, m, cfg, args.steps, args.warmup, args.rtol,
+                                        method=mm.MM_RKF45)
+            res["rkf45"] = dict(wall=wall_f, stats=st_f)
         del plan, m
         torch.cuda.empty_cache()
 
@@ -317,6 +325,12 @@ def main():
                                  dict(budget=args.serve_budget_mib << 20, max_active=16,
                                       steps_per_launch=8, tol=1e-5, rtol=1e-7,
                                       max_steps=args.serve_max_steps))
+    if "rkf45" in res:
+        rf = res["rkf45"]
+        out["rkf45_fp32"] = {"value": rf["stats"]["rhs_evals"] * N / rf["wall"],
+                             "ms_per_step": 1e3 * rf["wall"] / max(1, rf["stats"]["accepted"]),
+                             "rhs_evals": rf["stats"]["rhs_evals"],
+                             "rejected": rf["stats"]["rejected"]}
     if "fp64" in res:
         r64 = res["fp64"]
         out["fp64"] = {"value": r64["stats"]["rhs_evals"] * N / r64["wall"],

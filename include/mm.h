@@ -138,15 +138,23 @@ typedef struct {
     long max_steps;     /* ... or until max_steps steps have been accepted   */
     double dt_min;      /* a step below dt_min gives MM_EDTMIN (0 -> 1e-20)  */
     int renorm;         /* renormalise |m| = 1 after each accepted step      */
+    int method;         /* MM_DP45 (default) or MM_RKF45                     */
 } mm_step_opts;
+
+/* Embedded pairs of mm_llg_step: Dormand-Prince 5(4) (7 stages, the last
+ * evaluated at the propagated 5th-order solution and reused as the next
+ * step's first), and Runge-Kutta-Fehlberg 4(5), the paper's default (Sec. 3:
+ * 6 stages, the 4th-order solution propagated, the 5th-order one used for the
+ * error).  Both cost 6 right-hand sides per accepted step. */
+enum { MM_DP45 = 0, MM_RKF45 = 1 };
 
 typedef struct {
     long accepted, rejected, rhs_evals;
     double t, dt, err_last;
 } mm_step_stats;
 
-/* Adaptive Dormand-Prince 5(4) integration of the LLG equation (Sec. 3) with
- * first-same-as-last, propagating the 5th-order solution.  The error norm is
+/* Adaptive integration of the LLG equation (Sec. 3) with the pair o->method
+ * (Dormand-Prince 5(4) with first-same-as-last by default).  The error norm is
  * the RMS over magnetic components of e/(atol + rtol max(|y|,|y_new|)),
  * computed in double on the device; a step is accepted iff the norm <= 1 and
  * dt is rescaled by min(10, max(0.2, 0.9 err^-1/5)) (no growth right after a
@@ -154,7 +162,7 @@ typedef struct {
  * rejected with the factor 0.2; MM_ENONFINITE is returned only when the
  * current state itself holds a NaN or infinity.  *dt <= 0 selects the Hairer-Norsett-Wanner starting step.  m is
  * updated in place; *t and *dt are advanced.  st may be NULL.  Synchronises
- * once per step (8 bytes to the host). */
+ * once per step (8 bytes to the host).  MM_EINVAL for an unknown method. */
 mm_status mm_llg_step(mm_plan *p, void *m, const double h_ext[3], unsigned terms, double *t,
                       double *dt, const mm_step_opts *o, mm_step_stats *st);
 

@@ -93,6 +93,55 @@ static const double kB5[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
 static const double kB4[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0,
                               -92097.0 / 339200.0, 187.0 / 2100.0, 1.0 / 40.0};
 
+// Runge-Kutta-Fehlberg 4(5) (Fehlberg 1969): 4th-order solution propagated.
+static const double kFC[6] = {0.0, 1.0 / 4.0, 3.0 / 8.0, 12.0 / 13.0, 1.0, 1.0 / 2.0};
+static const double kFA[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0}};
+static const double kFB4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+static const double kFB5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0,
+                               -9.0 / 50.0, 2.0 / 55.0};
+
+// An embedded pair as the controller uses it: stage count, nodes, rows of
+// coefficients, propagated weights b, error weights e; fsal: the last stage's
+// input is the propagated solution and its derivative the next first stage.
+struct Tableau {
+    int stages;
+    bool fsal;
+    const double* c;
+    const double* a[7];
+    double b[7], e[7];
+};
+
+static Tableau tableau(int method)
+{
+    Tableau T{};
+    if (method == MM_RKF45) {
+        T.stages = 6;
+        T.fsal = false;
+        T.c = kFC;
+        for (int s = 0; s < 6; ++s) {
+            T.a[s] = kFA[s];
+            T.b[s] = kFB4[s];
+            T.e[s] = kFB4[s] - kFB5[s];
+        }
+    } else {
+        T.stages = 7;
+        T.fsal = true;
+        T.c = kC;
+        for (int s = 0; s < 7; ++s) {
+            T.a[s] = kA[s];
+            T.b[s] = kB5[s];
+            T.e[s] = kB5[s] - kB4[s];
+        }
+    }
+    return T;
+}
+
 mm_status ensure_rk(Plan* p)
 {
     if (!p->rk) {
@@ -259,8 +308,10 @@ template <typename T>
 static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned terms, double* t,
                       double* dt, double rtol, double atol, double t_end, long max_steps,
                       double dt_min, bool renorm, bool relax, double torque_tol,
-                      mm_step_stats* st)
+                      mm_step_stats* st, int method = MM_DP45)
 {
+    const Tableau TB = tableau(method);
+    const int S = TB.stages;
     mm_status s = ensure_rk(p);
     if (s != MM_OK) return s;
     const double alpha = relax ? 1.0 : p->alpha;
@@ -284,8 +335,6 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
                           &loc.rhs_evals);
         if (s != MM_OK) return s;
     }
-    double E[7];
-    for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
     bool last_rejected = false;
     double torque = std::numeric_limits<double>::infinity();
     bool torque_known = false;
@@ -301,15 +350,16 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
         }
         double h = *dt;
         if (*t + h > t_end) h = t_end - *t;
-        for (int sg = 1; sg < 7; ++sg) {
-            T* target = sg == 6 ? y1 : ys;
-            MM_HIP(rk_combine<T>(*p, target, y, h, kA[sg], k, sg), "stage input");
-            MM_HIP(eval_field<T>(*p, target, hext, terms, *t + kC[sg] * h, nullptr, k[sg], alpha,
+        for (int sg = 1; sg < S; ++sg) {
+            T* target = (TB.fsal && sg == S - 1) ? y1 : ys;
+            MM_HIP(rk_combine<T>(*p, target, y, h, TB.a[sg], k, sg), "stage input");
+            MM_HIP(eval_field<T>(*p, target, hext, terms, *t + TB.c[sg] * h, nullptr, k[sg], alpha,
                                  precess, nullptr),
                    "right-hand side");
             loc.rhs_evals++;
         }
-        MM_HIP(rk_error_norm<T>(*p, y, y1, h, E, k, 7, rtol, atol, p->red_out), "error norm");
+        if (!TB.fsal) MM_HIP(rk_combine<T>(*p, y1, y, h, TB.b, k, S), "solution");
+        MM_HIP(rk_error_norm<T>(*p, y, y1, h, TB.e, k, S, rtol, atol, p->red_out), "error norm");
         s = fetch(p, 6);
         if (s != MM_OK) break;
         double err = p->host_out[0];
@@ -328,8 +378,8 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
             *t += h;
             std::swap(y, y1);
             loc.accepted++;
-            if (renorm) {
-                MM_HIP(renormalise<T>(*p, y), "renormalise");
+            if (renorm || !TB.fsal) {
+                if (renorm) MM_HIP(renormalise<T>(*p, y), "renormalise");
                 MM_HIP(eval_field<T>(*p, y, hext, terms, *t, nullptr, k[0], alpha, precess,
                                      torque_dev),
                        "right-hand side");
@@ -888,16 +938,17 @@ mm_status mm_llg_step(mm_plan* pl, void* m, const double h_ext[3], unsigned term
         set_error("null argument");
         return MM_EINVAL;
     }
-    if (!(o->rtol > 0.0) || !(o->atol > 0.0) || o->max_steps < 0) {
-        set_error("rtol and atol must be positive, max_steps non-negative");
+    if (!(o->rtol > 0.0) || !(o->atol > 0.0) || o->max_steps < 0 ||
+        (o->method != MM_DP45 && o->method != MM_RKF45)) {
+        set_error("rtol and atol must be positive, max_steps non-negative, method DP45 or RKF45");
         return MM_EINVAL;
     }
     const double dt_min = o->dt_min > 0.0 ? o->dt_min : 1e-20;
     return p->prec == MM_FP32
                ? dp45<float>(p, m, h_ext, terms, t, dt, o->rtol, o->atol, o->t_end, o->max_steps,
-                             dt_min, o->renorm != 0, false, 0.0, st)
+                             dt_min, o->renorm != 0, false, 0.0, st, o->method)
                : dp45<double>(p, m, h_ext, terms, t, dt, o->rtol, o->atol, o->t_end, o->max_steps,
-                              dt_min, o->renorm != 0, false, 0.0, st);
+                              dt_min, o->renorm != 0, false, 0.0, st, o->method);
 }
 
 mm_status mm_relax(mm_plan* pl, void* m, const double h_ext[3], unsigned terms, double tol,

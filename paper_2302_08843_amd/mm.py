@@ -37,6 +37,7 @@ EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_devi
            "mm_serve_destroy", "mm_serve_clock"]
 
 MM_SERVE_RELAX, MM_SERVE_INTEGRATE = 0, 1
+MM_DP45, MM_RKF45 = 0, 1
 
 PASS_NAMES = ["x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local", "rk"]
 MM_NPASS = len(PASS_NAMES)
@@ -78,7 +79,8 @@ class mm_opts(C.Structure):
 
 class mm_step_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("t_end", C.c_double),
-                ("max_steps", C.c_long), ("dt_min", C.c_double), ("renorm", C.c_int)]
+                ("max_steps", C.c_long), ("dt_min", C.c_double), ("renorm", C.c_int),
+                ("method", C.c_int)]
 
 
 class mm_step_stats(C.Structure):
@@ -421,10 +423,12 @@ class Plan:
         torch.cuda.current_stream().synchronize()
 
     def llg_step(self, m, h_ext=None, terms=MM_ALL, t=0.0, dt=-1.0, rtol=1e-6, atol=None,
-                 t_end=float("inf"), max_steps=1 << 40, renorm=False, dt_min=0.0, check=True):
+                 t_end=float("inf"), max_steps=1 << 40, renorm=False, dt_min=0.0, check=True,
+                 method=MM_DP45):
         """Advance m (a plan-dtype device tensor, updated in place)."""
         o = mm_step_opts(rtol=rtol, atol=rtol if atol is None else atol, t_end=t_end,
-                         max_steps=max_steps, dt_min=dt_min, renorm=int(bool(renorm)))
+                         max_steps=max_steps, dt_min=dt_min, renorm=int(bool(renorm)),
+                         method=int(method))
         status, t, dt, st = mm_llg_step(self.handle, m, h_ext, terms, t, dt, o)
         if check:
             _check(status)

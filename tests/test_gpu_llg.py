@@ -170,3 +170,39 @@ def test_large_workload_crop_precision(torch_cuda, mm, orc):
     assert d64 <= rtol
     assert d32 <= 1e-4
     assert abs(res["fp64"][1][4] - E_o[4]) <= 1e-6 * abs(E_o[4])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rkf45_matches_oracle(torch_cuda, mm, orc, prec):
+    """The paper's default pair (Runge-Kutta-Fehlberg 4(5)) on the 32x32x4
+    case: 100 adaptive steps, same step counts as the oracle in FP64, m at
+    equal time within rtol (FP64) / 1e-3 (FP32, own step sequence)."""
+    c = W.config_small_llg()
+    banner("rkf45 %s %s" % (c["n"], prec))
+    rtol, steps = c["rtol"], 100
+    o = orc.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    o.set_field(c["H"], terms=c["terms"])
+    m_o, t_o, _, st_o, status_o = o.rkf45(c["m0"], rtol=rtol, max_steps=steps)
+    assert status_o == 0
+    plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec=prec)
+    m = plan._t(c["m0"])
+    if prec == "fp64":
+        status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, max_steps=steps,
+                                          method=mm.MM_RKF45)
+        assert st["accepted"] == steps
+        assert st["rejected"] == st_o["rejected"] and st["rhs_evals"] == st_o["rhs_evals"]
+        assert abs(t - t_o) <= 1e-4 * t_o
+        m_ref = o.rkf45(c["m0"], rtol=rtol, t_end=t)[0]
+        bar = rtol
+    else:
+        status, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, t_end=t_o,
+                                          method=mm.MM_RKF45)
+        m_ref = m_o
+        # FP32 takes its own step sequence; two runs of this 4th-order pair
+        # agree to its truncation error, which at rtol 1e-6 on this rough
+        # random start is ~1e-4 (Dormand-Prince's 5th order: ~1e-5)
+        bar = 1e-3
+    d = np.abs(to_np(m) - m_ref).max()
+    print("  %d steps, %d rejected, %d evals, |m - oracle| %.2e" % (st["accepted"], st["rejected"],
+                                                                   st["rhs_evals"], d))
+    assert d <= bar
