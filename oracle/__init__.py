@@ -75,6 +75,7 @@ def lib():
         L.or_set_field.argtypes = [C.c_void_p, dp, C.c_uint]
         L.or_set_drive.argtypes = [C.c_void_p, dp, C.c_double, C.c_void_p]
         L.or_set_Ms.argtypes = [C.c_void_p, dp]
+        L.or_set_anisotropy2.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp, dp]
         for name in ("or_demag", "or_exchange", "or_anisotropy"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
         L.or_zeeman.argtypes = [C.c_void_p, C.c_double, dp]
@@ -227,6 +228,12 @@ class Oracle:
         """Add H += mask * amp * sin(2 pi freq t) to the Zeeman term."""
         mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(self.shape))
         lib().or_set_drive(self._c, _dp(_d3(amp)), float(freq), mk.ctypes.data)
+
+    def set_anisotropy2(self, Ku2=0.0, Kc1=0.0, Kc2=0.0, c1=(1, 0, 0), c2=(0, 1, 0)):
+        """Second-order uniaxial (Ku2, along the Ku axis) and cubic (Kc1, Kc2,
+        principal axes c1, c2, c1 x c2) anisotropy (Sec. 4.3)."""
+        lib().or_set_anisotropy2(self._c, float(Ku2), float(Kc1), float(Kc2), _dp(_d3(c1)),
+                                 _dp(_d3(c2)))
 
     def set_Ms(self, Ms):
         self.Ms = np.ascontiguousarray(np.broadcast_to(np.asarray(Ms, np.float64), self.shape).copy())

@@ -340,6 +340,9 @@ typedef struct or_ctx {
     double *A;       /* per cell exchange constant, J/m                    */
     double Ku;       /* first-order uniaxial anisotropy constant, J/m^3    */
     double eu[3];    /* easy axis (unit)                                   */
+    double Ku2;      /* second-order uniaxial constant, J/m^3              */
+    double Kc1, Kc2; /* first- and second-order cubic constants, J/m^3     */
+    double ec[3][3]; /* cubic principal axes (orthonormal)                 */
     double alpha;
     double Hext[3];  /* uniform external field, A/m                        */
     /* sinusoidal drive: H += mask_i * amp * sin(2 pi f t) */
@@ -416,12 +419,41 @@ or_ctx *or_create(const long n[3], const double d[3], int p, const double *Ms, c
     memcpy(c->Ms, Ms, sizeof(double) * c->N);
     memcpy(c->A, A, sizeof(double) * c->N);
     c->Ku = Ku;
+    for (int i = 0; i < 3; i++)
+        for (int a = 0; a < 3; a++)
+            c->ec[i][a] = i == a ? 1.0 : 0.0;
     c->alpha = alpha;
     c->demag_direct = demag_direct;
     c->drive_mask = calloc(c->N, 1);
     c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN;
     build_kernel(c);
     return c;
+}
+
+/* Higher-order anisotropy (Sec. 4.3): second-order uniaxial Ku2 along the
+ * easy axis of Ku, and cubic Kc1, Kc2 with principal axes c1, c2 and
+ * c3 = c1 x c2 (c1, c2 orthonormalised here). */
+void or_set_anisotropy2(or_ctx *c, double Ku2, double Kc1, double Kc2, const double c1[3],
+                        const double c2[3])
+{
+    c->Ku2 = Ku2;
+    c->Kc1 = Kc1;
+    c->Kc2 = Kc2;
+    double n1 = sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+    for (int a = 0; a < 3; a++)
+        c->ec[0][a] = c1[a] / n1;
+    double dp = c2[0] * c->ec[0][0] + c2[1] * c->ec[0][1] + c2[2] * c->ec[0][2];
+    double v[3], nv = 0.0;
+    for (int a = 0; a < 3; a++) {
+        v[a] = c2[a] - dp * c->ec[0][a];
+        nv += v[a] * v[a];
+    }
+    nv = sqrt(nv);
+    for (int a = 0; a < 3; a++)
+        c->ec[1][a] = v[a] / nv;
+    c->ec[2][0] = c->ec[0][1] * c->ec[1][2] - c->ec[0][2] * c->ec[1][1];
+    c->ec[2][1] = c->ec[0][2] * c->ec[1][0] - c->ec[0][0] * c->ec[1][2];
+    c->ec[2][2] = c->ec[0][0] * c->ec[1][1] - c->ec[0][1] * c->ec[1][0];
 }
 
 void or_destroy(or_ctx *c)
@@ -565,11 +597,53 @@ void or_anisotropy(const or_ctx *c, const double *m, double *h)
 {
     long N = c->N;
     for (long t = 0; t < N; t++) {
-        double em = c->eu[0] * m[t] + c->eu[1] * m[N + t] + c->eu[2] * m[2 * N + t];
-        double pre = c->Ms[t] != 0.0 ? 2.0 * c->Ku / (OR_MU0 * c->Ms[t]) : 0.0;
+        if (c->Ms[t] == 0.0) {
+            h[t] = h[N + t] = h[2 * N + t] = 0.0;
+            continue;
+        }
+        double M[3] = {m[t], m[N + t], m[2 * N + t]};
+        double em = c->eu[0] * M[0] + c->eu[1] * M[1] + c->eu[2] * M[2];
+        /* uniaxial: (2 Ku1 em + 4 Ku2 em^3) e / (mu0 Ms) */
+        double pu = (2.0 * c->Ku * em + 4.0 * c->Ku2 * em * em * em) / (OR_MU0 * c->Ms[t]);
+        /* cubic, in the principal axes: -2 Kc1 m_i (m_j^2 + m_k^2) - 2 Kc2 m_i m_j^2 m_k^2,
+         * over mu0 Ms, mapped back along c_i */
+        double p[3];
+        for (int i = 0; i < 3; i++)
+            p[i] = c->ec[i][0] * M[0] + c->ec[i][1] * M[1] + c->ec[i][2] * M[2];
+        double hc[3];
+        for (int i = 0; i < 3; i++) {
+            double pj = p[(i + 1) % 3], pk = p[(i + 2) % 3];
+            hc[i] = -(2.0 * c->Kc1 * p[i] * (pj * pj + pk * pk) +
+                      2.0 * c->Kc2 * p[i] * pj * pj * pk * pk) /
+                    (OR_MU0 * c->Ms[t]);
+        }
         for (int a = 0; a < 3; a++)
-            h[a * N + t] = pre * c->eu[a] * em;
+            h[a * N + t] = pu * c->eu[a] + hc[0] * c->ec[0][a] + hc[1] * c->ec[1][a] +
+                           hc[2] * c->ec[2][a];
     }
+}
+
+/* Anisotropy energy from its density (the linear-term formula of Sec. 4 does
+ * not apply to the higher orders):
+ * V sum_i [-Ku1 (e.m)^2 - Ku2 (e.m)^4 + Kc1 (m1^2 m2^2 + m2^2 m3^2 + m3^2 m1^2)
+ *          + Kc2 m1^2 m2^2 m3^2] over magnetic cells. */
+static double anisotropy_energy(const or_ctx *c, const double *m)
+{
+    long N = c->N;
+    long double acc = 0.0L;
+    for (long t = 0; t < N; t++) {
+        if (c->Ms[t] == 0.0)
+            continue;
+        double M[3] = {m[t], m[N + t], m[2 * N + t]};
+        double em = c->eu[0] * M[0] + c->eu[1] * M[1] + c->eu[2] * M[2];
+        double p[3];
+        for (int i = 0; i < 3; i++)
+            p[i] = c->ec[i][0] * M[0] + c->ec[i][1] * M[1] + c->ec[i][2] * M[2];
+        double q1 = p[0] * p[0], q2 = p[1] * p[1], q3 = p[2] * p[2];
+        acc += -c->Ku * em * em - c->Ku2 * em * em * em * em +
+               c->Kc1 * (q1 * q2 + q2 * q3 + q3 * q1) + c->Kc2 * q1 * q2 * q3;
+    }
+    return (double)(acc * c->d[0] * c->d[1] * c->d[2]);
 }
 
 /* Zeeman field at time t: uniform Hext plus the masked sinusoidal drive. */
@@ -662,6 +736,11 @@ void or_energy(const or_ctx *c, const double *m, double t, double E[5])
     double tot = 0;
     for (int e = 0; e < 4; e++) {
         long double acc = 0.0L;
+        if (e == 2) {
+            E[e] = (c->terms & (int)masks[e]) ? anisotropy_energy(c, m) : 0.0;
+            tot += E[e];
+            continue;
+        }
         if (c->terms & (int)masks[e]) {
             or_heff(c, m, t, masks[e], h);
             for (long q = 0; q < N; q++)
@@ -1102,7 +1181,9 @@ static void demag_raw(or_ctx *c, const double *w, double *out)
 }
 
 /* Transposed (linear part of the) effective field: for the terms in mask
- * (demag, exchange, anisotropy; the Zeeman field does not depend on m),
+ * (demag, exchange, first-order uniaxial anisotropy -- the higher-order
+ * anisotropy terms are not linear in m and are not covered; the Zeeman field
+ * does not depend on m),
  * grad_m = H^T w and grad_ms_i += d(w . h)/d Ms_i at fixed m.  grad_ms may be
  * NULL. */
 void or_heff_vjp(or_ctx *c, const double *m, const double *w, unsigned mask, double *grad_m,

@@ -219,3 +219,29 @@ def test_rkf45_closed_forms(orc):
     e8 = np.abs(o2.rkf45(c["m0"], rtol=1e-8, t_end=1e-12)[0] - ref).max()
     e10 = np.abs(o2.rkf45(c["m0"], rtol=1e-10, t_end=1e-12)[0] - ref).max()
     assert e10 < 1e-7 and e10 < e8 / 10, (e8, e10)
+
+
+def test_relax_second_order_uniaxial(orc):
+    # Ku1, Ku2 along z and a transverse field H along x: the equilibrium
+    # angle from z solves sin th (2 Ku1 + 4 Ku2 cos^2 th) = mu0 Ms H
+    Ms, Ku1, Ku2 = 8e5, 3e4, 2e4
+    H = 0.4 * (2 * Ku1 + 4 * Ku2) / (MU0 * Ms)
+    o = orc.Oracle((1, 1, 1), (2e-9,) * 3, Ms=Ms, Ku=Ku1, eu=(0, 0, 1))
+    o.set_anisotropy2(Ku2=Ku2)
+    o.set_field((H, 0, 0), terms=orc.ANIS | orc.ZEEMAN)
+    m0 = cell_vec([math.sin(0.05), 0.0, math.cos(0.05)])
+    m, st, status = o.relax(m0, tol=1e-8, max_steps=20000, rtol=1e-10)
+    assert status == 0
+    lo, hi = 0.0, math.pi / 2
+
+    def g(th):
+        return math.sin(th) * (2 * Ku1 + 4 * Ku2 * math.cos(th) ** 2) - MU0 * Ms * H
+
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(lo) * g(mid) <= 0:
+            hi = mid
+        else:
+            lo = mid
+    th = math.atan2(m[0].item(), m[2].item())
+    assert abs(th - lo) < 1e-7, (th, lo)

@@ -156,3 +156,61 @@ def test_energy_gradient_is_minus_mu0_V_Ms_h(orc, term):
         grad[q] = (o.energy(mp_)[idx] - o.energy(mm_)[idx]) / (2 * eps)
     expect = -MU0 * V * Ms[None] * h
     assert np.abs(grad - expect).max() < 1e-7 * np.abs(expect).max()
+
+
+def _rotation(seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 2] = -q[:, 2]
+    return q
+
+
+@pytest.mark.parametrize("which", ["Ku2", "Kc1", "Kc2", "all"])
+def test_higher_anisotropy_energy_gradient(orc, which):
+    """h = -(1 / (mu0 V Ms)) dE/dm for the second-order uniaxial and the cubic
+    terms (central differences of the energy density sum; pins the factors 2
+    and 4 and the signs of Sec. 4.3), with rotated cubic axes and per-cell Ms."""
+    n, d = (4, 3, 2), (2e-9, 3e-9, 2.5e-9)
+    g = np.random.default_rng(5)
+    Ms = g.uniform(4e5, 1e6, (2, 3, 4))
+    R = _rotation(3)
+    k = dict(Ku2=3e4 if which in ("Ku2", "all") else 0.0, Kc1=-2e4 if which in ("Kc1", "all") else 0.0,
+             Kc2=5e4 if which in ("Kc2", "all") else 0.0)
+    o = orc.Oracle(n, d, Ms=Ms, Ku=1e4 if which == "all" else 0.0, eu=R[:, 2])
+    o.set_anisotropy2(c1=R[:, 0], c2=R[:, 1], **k)
+    o.set_field((0, 0, 0), terms=orc.ANIS)
+    m = g.standard_normal((3, 2, 3, 4))
+    h = o.anisotropy(m)
+    V = np.prod(d)
+    eps = 1e-6
+    for idx in [(0, 0, 1, 2), (1, 1, 2, 3), (2, 0, 0, 0), (0, 1, 1, 1)]:
+        mp, mm_ = m.copy(), m.copy()
+        mp[idx] += eps
+        mm_[idx] -= eps
+        dE = (o.energy(mp)[2] - o.energy(mm_)[2]) / (2 * eps)
+        expect = -MU0 * V * Ms[idx[1:]] * h[idx]
+        assert abs(dE - expect) <= 1e-6 * abs(expect) + 1e-30, (idx, dE, expect)
+
+
+def test_cubic_axes_and_covariance(orc):
+    """Kc1 > 0: no field along a principal axis; Kc1 < 0: the body diagonal
+    is a stationary point (field parallel to m); rotating the axes and m
+    together rotates the field."""
+    n, d = (1, 1, 1), (2e-9,) * 3
+    R = _rotation(9)
+    o = orc.Oracle(n, d, Ms=8e5)
+    o.set_anisotropy2(Kc1=4e4, Kc2=1e4, c1=R[:, 0], c2=R[:, 1])
+    h = o.anisotropy(R[:, 0].reshape(3, 1, 1, 1))
+    assert np.abs(h).max() < 1e-9
+    o.set_anisotropy2(Kc1=-4e4, Kc2=1e4, c1=R[:, 0], c2=R[:, 1])
+    diag = (R[:, 0] + R[:, 1] + R[:, 2]) / np.sqrt(3)
+    h = o.anisotropy(diag.reshape(3, 1, 1, 1)).ravel()
+    assert np.linalg.norm(np.cross(diag, h)) < 1e-9 * np.linalg.norm(h)
+    m = np.random.default_rng(2).standard_normal(3)
+    o0 = orc.Oracle(n, d, Ms=8e5, Ku=2e4, eu=(0, 0, 1))
+    o0.set_anisotropy2(Ku2=1e4, Kc1=3e4, Kc2=-2e4)
+    o1 = orc.Oracle(n, d, Ms=8e5, Ku=2e4, eu=R[:, 2])
+    o1.set_anisotropy2(Ku2=1e4, Kc1=3e4, Kc2=-2e4, c1=R[:, 0], c2=R[:, 1])
+    h0 = o0.anisotropy(m.reshape(3, 1, 1, 1)).ravel()
+    h1 = o1.anisotropy((R @ m).reshape(3, 1, 1, 1)).ravel()
+    assert np.abs(h1 - R @ h0).max() <= 1e-12 * np.abs(h0).max()
