@@ -77,6 +77,13 @@ typedef struct {
                             distance, Sec. 4.4 default 20); < 0: Newell at
                             every distance                                    */
     void *stream;        /* hipStream_t for all device work; NULL = null stream */
+    /* higher-order anisotropy (Sec. 4.3): second-order uniaxial ku2 along
+     * ku_axis, h += 4 ku2 (e.m)^3 e / (mu0 Ms); cubic kc1, kc2 with principal
+     * axes kc_axis1, kc_axis2 (orthonormalised by the library) and their
+     * cross product.  Default 0.  Not linear in m: the differentiation entry
+     * points reject plans that use them. */
+    double ku2, kc1, kc2;
+    double kc_axis1[3], kc_axis2[3];
 } mm_opts;
 
 /* Fill *o with defaults: MM_FP64, axis (0,0,1), demag_p 20, stream NULL. */

@@ -453,6 +453,30 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     p->A = A;
     p->Ku = Ku;
     p->alpha = alpha;
+    p->Ku2 = o.ku2;
+    p->Kc1 = o.kc1;
+    p->Kc2 = o.kc2;
+    {
+        // cubic axes: c1 normalised, c2 made orthogonal to it, c3 = c1 x c2
+        double a1[3], a2[3];
+        const double n1 = std::sqrt(o.kc_axis1[0] * o.kc_axis1[0] + o.kc_axis1[1] * o.kc_axis1[1] +
+                                    o.kc_axis1[2] * o.kc_axis1[2]);
+        for (int a = 0; a < 3; ++a) a1[a] = o.kc_axis1[a] / n1;
+        const double pr = o.kc_axis2[0] * a1[0] + o.kc_axis2[1] * a1[1] + o.kc_axis2[2] * a1[2];
+        double n2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            a2[a] = o.kc_axis2[a] - pr * a1[a];
+            n2 += a2[a] * a2[a];
+        }
+        n2 = std::sqrt(n2);
+        for (int a = 0; a < 3; ++a) {
+            p->ec[0][a] = a1[a];
+            p->ec[1][a] = a2[a] / n2;
+        }
+        p->ec[2][0] = p->ec[0][1] * p->ec[1][2] - p->ec[0][2] * p->ec[1][1];
+        p->ec[2][1] = p->ec[0][2] * p->ec[1][0] - p->ec[0][0] * p->ec[1][2];
+        p->ec[2][2] = p->ec[0][0] * p->ec[1][1] - p->ec[0][1] * p->ec[1][0];
+    }
     p->demag_p = o.demag_p;
     p->percell = false;
     p->n_magnetic = Ms > 0.0 ? p->N : 0;
@@ -710,10 +734,19 @@ static mm_status rk4_adjoint_impl(Plan* p, const void* ckpt, const double hext[3
     return MM_OK;
 }
 
+static bool nonlinear_anis(const Plan* p, unsigned terms)
+{
+    return (terms & MM_ANIS) && (p->Ku2 != 0.0 || p->Kc1 != 0.0 || p->Kc2 != 0.0);
+}
+
 template <typename T>
 static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hext[3],
                                unsigned terms, double t, bool llg, T* grad_m, T* grad_ms)
 {
+    if (nonlinear_anis(p, terms)) {
+        set_error("higher-order anisotropy is not linear in m: no transposed operator");
+        return MM_EINVAL;
+    }
     mm_status s = ensure_adj(p);
     if (s != MM_OK) return s;
     T* h = nullptr;
@@ -742,6 +775,12 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
             MM_HIP(hipMemsetAsync(p->red_out + e, 0, sizeof(double), p->stream), "clear");
             continue;
         }
+        if (bits[e] == MM_ANIS) {
+            // from the energy density (the linear-term formula does not hold
+            // for the higher orders)
+            MM_HIP(anis_energy<T>(*p, m, p->red_out + e), "anisotropy energy");
+            continue;
+        }
         MM_HIP(eval_field<T>(*p, m, h_ext, bits[e], t, h, nullptr, p->alpha, true, nullptr),
                "field");
         MM_HIP(dot_ms<T>(*p, m, h, p->red_out + e), "energy reduction");
@@ -751,7 +790,7 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
     const double V = p->d[0] * p->d[1] * p->d[2];
     double tot = 0.0;
     for (int e = 0; e < 4; ++e) {
-        E[e] = (e == 3 ? -1.0 : -0.5) * kMu0 * V * p->host_out[e];
+        E[e] = e == 2 ? V * p->host_out[e] : (e == 3 ? -1.0 : -0.5) * kMu0 * V * p->host_out[e];
         tot += E[e];
     }
     E[4] = tot;
@@ -773,6 +812,11 @@ void mm_opts_default(mm_opts* o)
     o->ku_axis[2] = 1.0;
     o->demag_p = 20;
     o->stream = nullptr;
+    o->ku2 = o->kc1 = o->kc2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        o->kc_axis1[a] = a == 0 ? 1.0 : 0.0;
+        o->kc_axis2[a] = a == 1 ? 1.0 : 0.0;
+    }
 }
 
 mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3], double Ms,
@@ -810,6 +854,18 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
     if (!(nrm > 0.0) || !std::isfinite(nrm)) {
         set_error("anisotropy axis must be a non-zero finite vector");
         return MM_EINVAL;
+    }
+    {
+        const double* c1 = o.kc_axis1;
+        const double* c2 = o.kc_axis2;
+        const double n1 = std::sqrt(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+        const double cx = c1[1] * c2[2] - c1[2] * c2[1], cy = c1[2] * c2[0] - c1[0] * c2[2],
+                     cz = c1[0] * c2[1] - c1[1] * c2[0];
+        if (!std::isfinite(o.ku2) || !std::isfinite(o.kc1) || !std::isfinite(o.kc2) ||
+            !(n1 > 0.0) || !(cx * cx + cy * cy + cz * cz > 0.0) || !std::isfinite(cx + cy + cz)) {
+            set_error("ku2, kc1, kc2 must be finite and the cubic axes independent");
+            return MM_EINVAL;
+        }
     }
     Plan* p = nullptr;
     mm_status s = plan_build(grid, cell, Ms, A, Ku, alpha, o, nullptr, &p);
@@ -1054,6 +1110,10 @@ mm_status mm_rk4_adjoint(mm_plan* pl, const void* ckpt, const double h_ext[3], u
                          long ckpt_every, void* grad_ms, void* grad_m0, double* loss)
 {
     Plan* p = reinterpret_cast<Plan*>(pl);
+    if (p && nonlinear_anis(p, terms)) {
+        set_error("higher-order anisotropy is not linear in m: no adjoint");
+        return MM_EINVAL;
+    }
     if (!p || !ckpt || !region || nsteps <= 0 || !(dt > 0.0) || ckpt_every <= 0) {
         set_error("invalid argument");
         return MM_EINVAL;

@@ -60,6 +60,8 @@ struct Plan {
     int prec;      // MM_FP32 / MM_FP64
     double Ms, A, Ku, alpha;
     double eu[3];
+    double Ku2, Kc1, Kc2;  // higher-order anisotropy
+    double ec[3][3];       // cubic principal axes (orthonormal rows)
     int demag_p;
     bool percell;  // per-cell Ms present
     long n_magnetic;  // magnetic cells (Ms > 0)
@@ -153,6 +155,9 @@ hipError_t dp_torque(Plan &p, DevCtl *c);
 // Renormalise |m| = 1 on magnetic cells, zero m on vacuum cells.
 template <typename T>
 hipError_t renormalise(Plan &p, T *m);
+// anisotropy energy density (all orders) summed over magnetic cells -> *out_dev
+template <typename T>
+hipError_t anis_energy(Plan &p, const T *m, double *out_dev);
 // sum over cells of Ms * (a . b) in double -> *out_dev
 template <typename T>
 hipError_t dot_ms(Plan &p, const T *a, const T *b, double *out_dev);

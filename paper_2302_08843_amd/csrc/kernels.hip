@@ -478,6 +478,10 @@ struct LocalParams {
     double idx2, idy2, idz2;  // 1/dx^2 ...
     double anis;      // 2 Ku / mu0 (divided by Ms_i per cell)
     double eu[3];
+    int with_anis_hi;  // higher-order anisotropy present
+    double anis2;     // 4 Ku2 / mu0
+    double cub1, cub2;  // 2 Kc1 / mu0, 2 Kc2 / mu0
+    double ec[3][3];  // cubic principal axes
     double H[3];      // uniform external field
     double Hd[3];     // drive field at time t on masked cells
     double gp;        // gamma / (1 + alpha^2)
@@ -626,10 +630,32 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                 hz += ce * az;
             }
             if (P.with_anis) {
-                const T ca = anis * inv_ms * (eux * mx + euy * my + euz * mz);
+                const T em = eux * mx + euy * my + euz * mz;
+                const T ca = anis * inv_ms * em;
                 hx += ca * eux;
                 hy += ca * euy;
                 hz += ca * euz;
+                if (P.with_anis_hi) {
+                    // second-order uniaxial: 4 Ku2 (e.m)^3 e / (mu0 Ms)
+                    const T cb = (T)P.anis2 * inv_ms * em * em * em;
+                    hx += cb * eux;
+                    hy += cb * euy;
+                    hz += cb * euz;
+                    // cubic, in the principal axes c_i: -2 Kc1 m_i (m_j^2 + m_k^2)
+                    // - 2 Kc2 m_i m_j^2 m_k^2, over mu0 Ms, mapped back along c_i
+                    T pr[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        pr[a] = (T)P.ec[a][0] * mx + (T)P.ec[a][1] * my + (T)P.ec[a][2] * mz;
+                    const T q0 = pr[0] * pr[0], q1 = pr[1] * pr[1], q2 = pr[2] * pr[2];
+                    const T c1 = (T)P.cub1 * inv_ms, c2 = (T)P.cub2 * inv_ms;
+                    const T g0 = -(c1 * pr[0] * (q1 + q2) + c2 * pr[0] * q1 * q2);
+                    const T g1 = -(c1 * pr[1] * (q2 + q0) + c2 * pr[1] * q2 * q0);
+                    const T g2 = -(c1 * pr[2] * (q0 + q1) + c2 * pr[2] * q0 * q1);
+                    hx += g0 * (T)P.ec[0][0] + g1 * (T)P.ec[1][0] + g2 * (T)P.ec[2][0];
+                    hy += g0 * (T)P.ec[0][1] + g1 * (T)P.ec[1][1] + g2 * (T)P.ec[2][1];
+                    hz += g0 * (T)P.ec[0][2] + g1 * (T)P.ec[1][2] + g2 * (T)P.ec[2][2];
+                }
             }
             if (P.with_zee) {
                 hx += (T)P.H[0];
@@ -1158,6 +1184,37 @@ __global__ void k_dp_commit(const DevCtl* __restrict__ c, T* __restrict__ y,
         y[N + q] = yy;
         y[2 * N + q] = z;
     }
+}
+
+// Anisotropy energy density summed over magnetic cells (per block, in
+// double): -Ku1 (e.m)^2 - Ku2 (e.m)^4 + Kc1 (m1^2 m2^2 + m2^2 m3^2 + m3^2 m1^2)
+// + Kc2 m1^2 m2^2 m3^2, m_i along the cubic axes.
+struct AnisE {
+    double ku1, ku2, kc1, kc2;
+    double eu[3];
+    double ec[3][3];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
+                                                        const T* __restrict__ Ms_cell, double Ms,
+                                                        long N, AnisE A, double* partials)
+{
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        const double ms = Ms_cell ? (double)Ms_cell[q] : Ms;
+        if (ms == 0.0) continue;
+        const double mx = m[q], my = m[N + q], mz = m[2 * N + q];
+        const double em = A.eu[0] * mx + A.eu[1] * my + A.eu[2] * mz;
+        double pr[3];
+        for (int a = 0; a < 3; ++a) pr[a] = A.ec[a][0] * mx + A.ec[a][1] * my + A.ec[a][2] * mz;
+        const double q0 = pr[0] * pr[0], q1 = pr[1] * pr[1], q2 = pr[2] * pr[2];
+        acc += -A.ku1 * em * em - A.ku2 * em * em * em * em + A.kc1 * (q0 * q1 + q1 * q2 + q2 * q0) +
+               A.kc2 * q0 * q1 * q2;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
 template <typename T>
@@ -1773,8 +1830,14 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.Hxp = p.Hxp;
     P.with_demag = (terms & MM_DEMAG) ? 1 : 0;
     P.with_exch = (terms & MM_EXCH) && p.A != 0.0 ? 1 : 0;
-    P.with_anis = (terms & MM_ANIS) && p.Ku != 0.0 ? 1 : 0;
+    P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
+    P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi) ? 1 : 0;
     P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
+    P.anis2 = 4.0 * p.Ku2 / kMu0;
+    P.cub1 = 2.0 * p.Kc1 / kMu0;
+    P.cub2 = 2.0 * p.Kc2 / kMu0;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) P.ec[i][a] = p.ec[i][a];
     P.Ms = p.Ms;
     P.exch = 2.0 * p.A / kMu0;
     P.idx2 = 1.0 / (p.d[0] * p.d[0]);
@@ -1920,6 +1983,25 @@ hipError_t dp_commit(Plan& p, DevCtl* c, T* y, const T* y1, T* k0, const T* k6)
     const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
     k_dp_commit<T><<<blocks, 256, 0, p.stream>>>(c, y, y1, k0, k6,
                                                  p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t anis_energy(Plan& p, const T* m, double* out_dev)
+{
+    AnisE A;
+    A.ku1 = p.Ku;
+    A.ku2 = p.Ku2;
+    A.kc1 = p.Kc1;
+    A.kc2 = p.Kc2;
+    for (int a = 0; a < 3; ++a) {
+        A.eu[a] = p.eu[a];
+        for (int b = 0; b < 3; ++b) A.ec[a][b] = p.ec[a][b];
+    }
+    k_anis_energy<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
+        m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, p.red);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();
 }
 
@@ -2071,6 +2153,7 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t dp_commit<T>(Plan&, DevCtl*, T*, const T*, T*, const T*);                \
     template hipError_t renormalise<T>(Plan&, T*);                                               \
     template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*);                           \
+    template hipError_t anis_energy<T>(Plan&, const T*, double*);                                \
     template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \
                                        double*);                                                 \
     template hipError_t count_magnetic<T>(Plan&, double*);                                       \

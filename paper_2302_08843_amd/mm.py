@@ -74,7 +74,8 @@ class mm_serve_stats(C.Structure):
 
 class mm_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("ku_axis", C.c_double * 3), ("demag_p", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("ku2", C.c_double), ("kc1", C.c_double),
+                ("kc2", C.c_double), ("kc_axis1", C.c_double * 3), ("kc_axis2", C.c_double * 3)]
 
 
 class mm_step_opts(C.Structure):
@@ -353,7 +354,7 @@ class Plan:
     """A plan on the current CUDA (HIP) device; see mm_plan_create."""
 
     def __init__(self, grid, cell, Ms, A=0.0, Ku=0.0, alpha=0.5, prec="fp64", ku_axis=(0, 0, 1),
-                 demag_p=20, stream=None):
+                 demag_p=20, stream=None, Ku2=0.0, Kc1=0.0, Kc2=0.0, kc_axes=((1, 0, 0), (0, 1, 0))):
         import torch
 
         self.grid = tuple(int(v) for v in grid)
@@ -367,6 +368,10 @@ class Plan:
             o.ku_axis[a] = float(ku_axis[a])
         o.demag_p = int(demag_p)
         o.stream = _stream_handle(stream)
+        o.ku2, o.kc1, o.kc2 = float(Ku2), float(Kc1), float(Kc2)
+        for a in range(3):
+            o.kc_axis1[a] = float(kc_axes[0][a])
+            o.kc_axis2[a] = float(kc_axes[1][a])
         self._stream = stream
         self.handle = mm_plan_create(self.grid, self.cell, Ms, A, Ku, alpha, o)
         nx, ny, nz = self.grid
