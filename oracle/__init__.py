@@ -25,8 +25,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmref.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DEMAG, EXCH, ANIS, ZEEMAN = 1, 2, 4, 8
-ALL = DEMAG | EXCH | ANIS | ZEEMAN
+DEMAG, EXCH, ANIS, ZEEMAN, DMI = 1, 2, 4, 8, 16
+ALL = DEMAG | EXCH | ANIS | ZEEMAN | DMI
+DMI_INTERFACE, DMI_BULK, DMI_D2D = 0, 1, 2
 MU0 = 4.0e-7 * np.pi
 GAMMA = 2.21e5
 
@@ -76,7 +77,8 @@ def lib():
         L.or_set_drive.argtypes = [C.c_void_p, dp, C.c_double, C.c_void_p]
         L.or_set_Ms.argtypes = [C.c_void_p, dp]
         L.or_set_anisotropy2.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp, dp]
-        for name in ("or_demag", "or_exchange", "or_anisotropy"):
+        L.or_set_dmi.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+        for name in ("or_demag", "or_exchange", "or_anisotropy", "or_dmi"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
         L.or_zeeman.argtypes = [C.c_void_p, C.c_double, dp]
         L.or_heff.argtypes = [C.c_void_p, dp, C.c_double, C.c_uint, dp]
@@ -235,6 +237,16 @@ class Oracle:
         lib().or_set_anisotropy2(self._c, float(Ku2), float(Kc1), float(Kc2), _dp(_d3(c1)),
                                  _dp(_d3(c2)))
 
+    def set_dmi(self, D, kind=DMI_INTERFACE):
+        """DMI strength D (J/m^2, scalar or per-cell) of one of the tabulated
+        types (Sec. 4.3): DMI_INTERFACE, DMI_BULK or DMI_D2D.  D=None removes
+        the term."""
+        if D is None:
+            lib().or_set_dmi(self._c, None, 0)
+            return
+        self.D = np.ascontiguousarray(np.broadcast_to(np.asarray(D, np.float64), self.shape).copy())
+        lib().or_set_dmi(self._c, self.D.ctypes.data, int(kind))
+
     def set_Ms(self, Ms):
         self.Ms = np.ascontiguousarray(np.broadcast_to(np.asarray(Ms, np.float64), self.shape).copy())
         lib().or_set_Ms(self._c, _dp(self.Ms))
@@ -257,6 +269,11 @@ class Oracle:
         """First-order uniaxial anisotropy field (Sec. 4.1)."""
         return self._field("or_anisotropy", m)
 
+    def dmi(self, m):
+        """DMI field by central differences with the averaged coupling D~
+        (Sec. 4.3, Eq. D_avg); missing and vacuum neighbours are ignored."""
+        return self._field("or_dmi", m)
+
     def zeeman(self, t=0.0):
         h = np.zeros((3,) + self.shape)
         lib().or_zeeman(self._c, float(t), _dp(h))
@@ -278,9 +295,10 @@ class Oracle:
         return dm
 
     def energy(self, m, t=0.0) -> np.ndarray:
-        """[E_demag, E_exchange, E_anisotropy, E_zeeman, E_total] in J."""
+        """[E_demag, E_exchange, E_anisotropy, E_zeeman, E_total, E_dmi] in J
+        (the total includes the DMI energy)."""
         m = self._m(m)
-        E = np.zeros(5)
+        E = np.zeros(6)
         lib().or_energy(self._c, _dp(m), float(t), _dp(E))
         return E
 

@@ -16,6 +16,8 @@
  * arithmetic inside a row or a cell.
  *
  * Parity status of each part (what pins it) is listed with each function.
+ * Parity unpinned: the opposite-sign branch of the DMI coupling average
+ * (dmi_avg below) -- only its symmetry and its bounds are checked.
  */
 #include <complex.h>
 #include <math.h>
@@ -37,7 +39,7 @@
 #define OR_GAMMA 2.21e5
 #define OR_PI_L 3.141592653589793238462643383279502884L
 
-enum { OR_DEMAG = 1, OR_EXCH = 2, OR_ANIS = 4, OR_ZEEMAN = 8 };
+enum { OR_DEMAG = 1, OR_EXCH = 2, OR_ANIS = 4, OR_ZEEMAN = 8, OR_DMI = 16 };
 
 /* ------------------------------------------------------------------------- */
 /* Newell, Williams & Dunlop (1993) cell-averaged demagnetisation tensor,     */
@@ -343,6 +345,8 @@ typedef struct or_ctx {
     double Ku2;      /* second-order uniaxial constant, J/m^3              */
     double Kc1, Kc2; /* first- and second-order cubic constants, J/m^3     */
     double ec[3][3]; /* cubic principal axes (orthonormal)                 */
+    double *D;       /* per-cell DMI strength, J/m^2, or NULL               */
+    double edmi[3][3]; /* DMI vectors e^dmi_x, e^dmi_y, e^dmi_z             */
     double alpha;
     double Hext[3];  /* uniform external field, A/m                        */
     /* sinusoidal drive: H += mask_i * amp * sin(2 pi f t) */
@@ -425,7 +429,7 @@ or_ctx *or_create(const long n[3], const double d[3], int p, const double *Ms, c
     c->alpha = alpha;
     c->demag_direct = demag_direct;
     c->drive_mask = calloc(c->N, 1);
-    c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN;
+    c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN | OR_DMI;
     build_kernel(c);
     return c;
 }
@@ -456,10 +460,35 @@ void or_set_anisotropy2(or_ctx *c, double Ku2, double Kc1, double Kc2, const dou
     c->ec[2][2] = c->ec[0][0] * c->ec[1][1] - c->ec[0][1] * c->ec[1][0];
 }
 
+/* DMI (Sec. 4.3, Table of DMI types): per-cell strength D (NULL removes the
+ * term) and the type's DMI vectors (e^dmi_x, e^dmi_y, e^dmi_z):
+ * 0 interface (C_nv): (e_y, -e_x, 0); 1 bulk: (e_x, e_y, e_z);
+ * 2 D_2d: (-e_x, e_y, 0). */
+void or_set_dmi(or_ctx *c, const double *D, int type)
+{
+    free(c->D);
+    c->D = NULL;
+    memset(c->edmi, 0, sizeof(c->edmi));
+    if (!D)
+        return;
+    c->D = malloc(sizeof(double) * c->N);
+    memcpy(c->D, D, sizeof(double) * c->N);
+    if (type == 0) {
+        c->edmi[0][1] = 1.0;
+        c->edmi[1][0] = -1.0;
+    } else if (type == 1) {
+        c->edmi[0][0] = c->edmi[1][1] = c->edmi[2][2] = 1.0;
+    } else {
+        c->edmi[0][0] = -1.0;
+        c->edmi[1][1] = 1.0;
+    }
+}
+
 void or_destroy(or_ctx *c)
 {
     if (!c)
         return;
+    free(c->D);
     free(c->Ms);
     free(c->A);
     free(c->drive_mask);
@@ -646,6 +675,58 @@ static double anisotropy_energy(const or_ctx *c, const double *m)
     return (double)(acc * c->d[0] * c->d[1] * c->d[2]);
 }
 
+/* Effective DMI coupling between two cells (Eq. D_avg).  Pinned for equal
+ * signs (the uniform limit and a two-cell value follow from the stencil
+ * closed forms); the opposite-sign branch is parity unpinned.  The harmonic mean
+ * 2 Da Db / (Da + Db) for equal signs (the printed denominator Da Db is read
+ * as Da + Db; 0 when both vanish), otherwise sign(Da Db) times the geometric
+ * mean of the geometric mean sqrt(-Da Db) and the mean |Da + Db| / 2. */
+static double dmi_avg(double a, double b)
+{
+    if (a * b >= 0.0)
+        return (a + b) != 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+    return -sqrt(sqrt(-a * b) * fabs(a + b) / 2.0);
+}
+
+/* DMI field by central differences (Sec. 4.3).  Pinned by the spiral and
+ * helix closed forms of each tabulated type, the Ms-weighted symmetry of the
+ * operator and dE/dm = -mu0 V Ms h (tests/test_oracle_dmi.py):
+ * h_i = 2/(mu0 Ms_i) sum_{k = +-x, +-y, +-z} D~_{i,k} (e^dmi_k x m_{i+e_k}) / (2 Delta_k),
+ * e^dmi_{-k} = -e^dmi_k; neighbours outside the grid or in vacuum are
+ * ignored (the open boundary of Sec. 4.3).  Vacuum cells: h = 0. */
+void or_dmi(const or_ctx *c, const double *m, double *h)
+{
+    long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    memset(h, 0, sizeof(double) * 3 * N);
+    if (!c->D)
+        return;
+    for (long t = 0; t < N; t++) {
+        if (c->Ms[t] == 0.0)
+            continue;
+        long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+        double acc[3] = {0, 0, 0};
+        for (int q = 0; q < 6; q++) {
+            int ax = q / 2;
+            long sgn = (q % 2 == 0) ? 1 : -1;
+            long a = i + (ax == 0 ? sgn : 0), b = j + (ax == 1 ? sgn : 0), e = k + (ax == 2 ? sgn : 0);
+            if (a < 0 || a >= nx || b < 0 || b >= ny || e < 0 || e >= nz)
+                continue;
+            long s = cidx(c, a, b, e);
+            if (c->Ms[s] == 0.0)
+                continue;
+            double Dt = dmi_avg(c->D[t], c->D[s]);
+            double ev[3] = {sgn * c->edmi[ax][0], sgn * c->edmi[ax][1], sgn * c->edmi[ax][2]};
+            double ms[3] = {m[s], m[N + s], m[2 * N + s]};
+            double cr[3] = {ev[1] * ms[2] - ev[2] * ms[1], ev[2] * ms[0] - ev[0] * ms[2],
+                            ev[0] * ms[1] - ev[1] * ms[0]};
+            for (int comp = 0; comp < 3; comp++)
+                acc[comp] += Dt / (2.0 * c->d[ax]) * cr[comp];
+        }
+        for (int comp = 0; comp < 3; comp++)
+            h[comp * N + t] = 2.0 / (OR_MU0 * c->Ms[t]) * acc[comp];
+    }
+}
+
 /* Zeeman field at time t: uniform Hext plus the masked sinusoidal drive. */
 void or_zeeman(const or_ctx *c, double t, double *h)
 {
@@ -680,6 +761,11 @@ void or_heff(const or_ctx *c, const double *m, double t, unsigned mask, double *
     }
     if (mask & OR_ZEEMAN) {
         or_zeeman(c, t, tmp);
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += tmp[q];
+    }
+    if ((mask & OR_DMI) && c->D) {
+        or_dmi(c, m, tmp);
         for (long q = 0; q < 3 * N; q++)
             h[q] += tmp[q];
     }
@@ -727,14 +813,17 @@ static void rhs_at(const or_ctx *c, const double *m, double t, double alpha, int
 /* Accumulated in long double.                                               */
 /* ------------------------------------------------------------------------- */
 
-void or_energy(const or_ctx *c, const double *m, double t, double E[5])
+void or_energy(const or_ctx *c, const double *m, double t, double E[6])
 {
     long N = c->N;
     double V = c->d[0] * c->d[1] * c->d[2];
     double *h = malloc(sizeof(double) * 3 * N);
-    unsigned masks[4] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN};
+    /* slots: 0 demag, 1 exchange, 2 anisotropy, 3 Zeeman, 5 DMI; 4 total */
+    unsigned masks[6] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN, 0, OR_DMI};
     double tot = 0;
-    for (int e = 0; e < 4; e++) {
+    for (int e = 0; e < 6; e++) {
+        if (e == 4)
+            continue;
         long double acc = 0.0L;
         if (e == 2) {
             E[e] = (c->terms & (int)masks[e]) ? anisotropy_energy(c, m) : 0.0;
