@@ -104,6 +104,45 @@ def heff_only(mm, plan, m, cfg, iters):
     return (time.perf_counter() - t0) / iters
 
 
+def extended_stencil(mm, plan, m, cfg, iters):
+    """Field evaluation with per-cell exchange constants and per-cell
+    interface DMI (the extended stencil of the x inverse / local pass) on the
+    same plan and state; the uniform-A kernel is timed beside it."""
+    import torch
+
+    nx, ny, nz = plan.grid
+    g = np.random.Generator(np.random.PCG64(5))
+    A = cfg["A"] * g.uniform(0.5, 1.5, (nz, ny, nx))
+    D = g.uniform(2e-3, 4e-3, (nz, ny, nx))
+    out = plan.empty()
+    res = {}
+    for name, on in (("plain", False), ("extended", True)):
+        if on:
+            plan.set_exchange(A)
+            plan.set_dmi(D, mm.MM_DMI_INTERFACE)
+        terms = cfg["terms"] | (mm.MM_DMI if on else 0)
+        for _ in range(3):
+            plan.heff(m, cfg["H"], terms, out=out)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            plan.heff(m, cfg["H"], terms, out=out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / iters
+        ms, n = plan.profile_read()["x_inv_local"]
+        plan.profile(False)
+        res[name] = (wall, 1e3 * ms / n)
+    plan.set_exchange(None)
+    plan.set_dmi(0.0, mm.MM_DMI_INTERFACE)
+    N = nx * ny * nz
+    ext_bytes = pass_bytes(plan.grid, "fp32")["x_inv_local"] + 2 * N * 4
+    return {"heff_ms": 1e3 * res["extended"][0], "heff_plain_ms": 1e3 * res["plain"][0],
+            "x_inv_local_us": res["extended"][1], "x_inv_local_plain_us": res["plain"][1],
+            "model_bytes": ext_bytes, "GBs": ext_bytes / (res["extended"][1] * 1e-6) / 1e9,
+            "terms": "demag + per-cell exchange + per-cell interface DMI"}
+
+
 def _serve_once(mm, reqs, states, arrivals, opts):
     """Run the request server over `reqs` (start states already in HBM) with
     the given arrival offsets (s); returns completions, makespan and stats."""
@@ -278,6 +317,8 @@ def main():
             wall_f, st_f, _ = run_steps(mm, plan, m, cfg, args.steps, args.warmup, args.rtol,
                                         method=mm.MM_RKF45)
             res["rkf45"] = dict(wall=wall_f, stats=st_f)
+            print("[bench] extended stencil (per-cell A + DMI)", file=sys.stderr, flush=True)
+            res["ext"] = extended_stencil(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters)
         del plan, m
         torch.cuda.empty_cache()
 
@@ -331,6 +372,8 @@ def main():
                              "ms_per_step": 1e3 * rf["wall"] / max(1, rf["stats"]["accepted"]),
                              "rhs_evals": rf["stats"]["rhs_evals"],
                              "rejected": rf["stats"]["rejected"]}
+    if "ext" in res:
+        out["extended_stencil_fp32"] = res["ext"]
     if "fp64" in res:
         r64 = res["fp64"]
         out["fp64"] = {"value": r64["stats"]["rhs_evals"] * N / r64["wall"],

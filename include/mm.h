@@ -66,8 +66,14 @@ typedef enum {
 
 typedef enum { MM_FP32 = 0, MM_FP64 = 1 } mm_prec;
 
-/* Field-term mask (Sec. 4). */
-enum { MM_DEMAG = 1, MM_EXCH = 2, MM_ANIS = 4, MM_ZEEMAN = 8, MM_ALL = 15 };
+/* Field-term mask (Sec. 4).  MM_DMI only acts once mm_set_dmi gave a
+ * strength. */
+enum { MM_DEMAG = 1, MM_EXCH = 2, MM_ANIS = 4, MM_ZEEMAN = 8, MM_DMI = 16, MM_ALL = 31 };
+
+/* DMI types of Sec. 4.3 (table of DMI types), by their DMI vectors
+ * (e^dmi_x, e^dmi_y, e^dmi_z): interface (C_nv) (e_y, -e_x, 0), bulk (T or O)
+ * (e_x, e_y, e_z), D_2d (-e_x, e_y, 0). */
+enum { MM_DMI_INTERFACE = 0, MM_DMI_BULK = 1, MM_DMI_D2D = 2 };
 
 typedef struct {
     int prec;            /* MM_FP32 (bulk arithmetic in float; tensor set up and
@@ -120,6 +126,28 @@ void mm_plan_padded(const mm_plan *p, int P[3]);
  * neighbours see dm/dn = 0 there.  NULL restores the uniform Ms of
  * mm_plan_create. */
 mm_status mm_set_ms(mm_plan *p, const void *Ms_cell);
+
+/* Set a per-cell exchange constant (Sec. 4.2): A_cell is a device buffer of
+ * N values (J/m, >= 0, finite; not checked) in the plan's precision, copied
+ * into the plan (stream-ordered).  The coupling of neighbours i and j is the
+ * harmonic mean 2 A_i A_j / (A_i + A_j) (0 when both vanish); a missing or
+ * vacuum (Ms = 0) neighbour is skipped, so dm/dn = 0 there.  NULL restores
+ * the uniform A of mm_plan_create.  The differentiation entry points reject
+ * a plan that uses it with MM_EXCH. */
+mm_status mm_set_exchange(mm_plan *p, const void *A_cell);
+
+/* Set the DMI term (Sec. 4.3): h_i = 2/(mu0 Ms_i) sum_{k=+-x,+-y,+-z}
+ * D~_{i,k} (e^dmi_k x m_{i+e_k}) / (2 Delta_k) with e^dmi_{-k} = -e^dmi_k and
+ * the DMI vectors of `type` (MM_DMI_*).  D is a uniform strength in J/m^2;
+ * if D_cell (a device buffer of N values in the plan's precision, copied into
+ * the plan) is not NULL it gives per-cell strengths instead and D~ is their
+ * average of Eq. D_avg: 2 D_i D_j / (D_i + D_j) for equal signs (0 when both
+ * vanish), -sqrt(sqrt(-D_i D_j) |D_i + D_j| / 2) for opposite signs.  Missing
+ * and vacuum neighbours are ignored (the open boundary of Sec. 4.3).
+ * D = 0 with D_cell NULL removes the term.  MM_EINVAL for an unknown type or
+ * a non-finite D.  The differentiation entry points reject a plan that uses
+ * it with MM_DMI. */
+mm_status mm_set_dmi(mm_plan *p, int type, double D, const void *D_cell);
 
 /* Time-dependent Zeeman drive added to the external field on masked cells:
  * H(t) += mask_i * amp * sin(2 pi freq t).  mask is a device buffer of N
@@ -181,11 +209,13 @@ mm_status mm_relax(mm_plan *p, void *m, const double h_ext[3], unsigned terms, d
                    long max_steps, double rtol, mm_step_stats *st);
 
 /* Energies (Sec. 4, Eq. linear_energy_discrete) in J, accumulated in double:
- * E[0] demag, E[1] exchange, E[2] anisotropy, each -1/2 mu0 V sum Ms m.h_t;
+ * E[0] demag, E[1] exchange and E[5] DMI, each -1/2 mu0 V sum Ms m.h_t;
+ * E[2] anisotropy, V times the sum of the anisotropy energy density (Sec.
+ * 4.1 and 4.3: -Ku1 (e.m)^2 - Ku2 (e.m)^4 + Kc1 (cubic) + Kc2 (cubic));
  * E[3] Zeeman, -mu0 V sum Ms m.H; E[4] total of the terms in `terms`.
- * Synchronises. */
+ * Terms left out of `terms` read 0.  Synchronises. */
 mm_status mm_energy(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
-                    double E[5]);
+                    double E[6]);
 
 /* max_i |m_i x h_i| / Ms_i over magnetic cells.  Synchronises. */
 mm_status mm_max_torque(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,

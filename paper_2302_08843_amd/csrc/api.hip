@@ -55,7 +55,8 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->mask, p->rk, p->red, p->red_out, p->adj, p->seg, p->gms, p->ctl};
+                    p->A_cell, p->D_cell, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
+                    p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->host_out) (void)hipHostFree(p->host_out);
@@ -479,6 +480,10 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     }
     p->demag_p = o.demag_p;
     p->percell = false;
+    p->percell_A = p->percell_D = p->dmi = false;
+    p->dmi_type = MM_DMI_INTERFACE;
+    p->D = 0.0;
+    std::memset(p->edmi, 0, sizeof(p->edmi));
     p->n_magnetic = Ms > 0.0 ? p->N : 0;
     p->drive = false;
     p->stream = (hipStream_t)o.stream;
@@ -739,12 +744,22 @@ static bool nonlinear_anis(const Plan* p, unsigned terms)
     return (terms & MM_ANIS) && (p->Ku2 != 0.0 || p->Kc1 != 0.0 || p->Kc2 != 0.0);
 }
 
+// The transposed operators cover the uniform-A exchange stencil only.
+static bool stencil_extended(const Plan* p, unsigned terms)
+{
+    return ((terms & MM_EXCH) && p->percell_A) || ((terms & MM_DMI) && p->dmi);
+}
+
 template <typename T>
 static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hext[3],
                                unsigned terms, double t, bool llg, T* grad_m, T* grad_ms)
 {
     if (nonlinear_anis(p, terms)) {
         set_error("higher-order anisotropy is not linear in m: no transposed operator");
+        return MM_EINVAL;
+    }
+    if (stencil_extended(p, terms)) {
+        set_error("per-cell exchange and DMI have no transposed operator");
         return MM_EINVAL;
     }
     mm_status s = ensure_adj(p);
@@ -764,13 +779,14 @@ static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hex
 
 template <typename T>
 static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigned terms, double t,
-                             double E[5])
+                             double E[6])
 {
     mm_status s = ensure_rk(p);
     if (s != MM_OK) return s;
     T* h = rk_vec<T>(p, 0);
-    const unsigned bits[4] = {MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN};
-    for (int e = 0; e < 4; ++e) {
+    // reduction slots 0..3 demag, exchange, anisotropy, Zeeman; 4 DMI
+    const unsigned bits[5] = {MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_DMI};
+    for (int e = 0; e < 5; ++e) {
         if (!(terms & bits[e])) {
             MM_HIP(hipMemsetAsync(p->red_out + e, 0, sizeof(double), p->stream), "clear");
             continue;
@@ -785,7 +801,7 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
                "field");
         MM_HIP(dot_ms<T>(*p, m, h, p->red_out + e), "energy reduction");
     }
-    s = fetch(p, 4);
+    s = fetch(p, 5);
     if (s != MM_OK) return s;
     const double V = p->d[0] * p->d[1] * p->d[2];
     double tot = 0.0;
@@ -793,7 +809,10 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
         E[e] = e == 2 ? V * p->host_out[e] : (e == 3 ? -1.0 : -0.5) * kMu0 * V * p->host_out[e];
         tot += E[e];
     }
-    E[4] = tot;
+    // the DMI operator is symmetric in the Ms-weighted product, so the
+    // linear-term formula holds
+    E[5] = -0.5 * kMu0 * V * p->host_out[4];
+    E[4] = tot + E[5];
     return MM_OK;
 }
 
@@ -916,6 +935,68 @@ mm_status mm_set_ms(mm_plan* pl, const void* Ms_cell)
     return MM_OK;
 }
 
+// Copy N values of the plan's precision into *dst (allocated on first use).
+static mm_status copy_cell_field(Plan* p, void** dst, const void* src, const char* what)
+{
+    const size_t bytes = (size_t)p->N * elem_size(*p);
+    if (!*dst) {
+        mm_status s = alloc(p, dst, bytes, what);
+        if (s != MM_OK) return s;
+    }
+    MM_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyDeviceToDevice, p->stream), what);
+    return MM_OK;
+}
+
+mm_status mm_set_exchange(mm_plan* pl, const void* A_cell)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p) {
+        set_error("null plan");
+        return MM_EINVAL;
+    }
+    if (!A_cell) {
+        p->percell_A = false;
+        return MM_OK;
+    }
+    mm_status s = copy_cell_field(p, &p->A_cell, A_cell, "per-cell exchange constant");
+    if (s != MM_OK) return s;
+    p->percell_A = true;
+    return MM_OK;
+}
+
+mm_status mm_set_dmi(mm_plan* pl, int type, double D, const void* D_cell)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p) {
+        set_error("null plan");
+        return MM_EINVAL;
+    }
+    if (type < MM_DMI_INTERFACE || type > MM_DMI_D2D || !std::isfinite(D)) {
+        set_error("invalid DMI type or strength");
+        return MM_EINVAL;
+    }
+    if (D_cell) {
+        mm_status s = copy_cell_field(p, &p->D_cell, D_cell, "per-cell DMI strength");
+        if (s != MM_OK) return s;
+    }
+    p->percell_D = D_cell != nullptr;
+    p->D = D_cell ? 0.0 : D;
+    p->dmi = D_cell != nullptr || D != 0.0;
+    p->dmi_type = type;
+    // DMI vectors (e^dmi_x, e^dmi_y, e^dmi_z) of the tabulated types
+    std::memset(p->edmi, 0, sizeof(p->edmi));
+    if (type == MM_DMI_INTERFACE) {
+        p->edmi[0][1] = 1.0;   // e_y
+        p->edmi[1][0] = -1.0;  // -e_x
+    } else if (type == MM_DMI_BULK) {
+        p->edmi[0][0] = p->edmi[1][1] = p->edmi[2][2] = 1.0;
+    } else {
+        p->edmi[0][0] = -1.0;  // -e_x
+        p->edmi[1][1] = 1.0;   // e_y
+    }
+    return MM_OK;
+}
+
 mm_status mm_set_drive(mm_plan* pl, const double amp[3], double freq, const unsigned char* mask)
 {
     Plan* p = reinterpret_cast<Plan*>(pl);
@@ -1029,7 +1110,7 @@ mm_status mm_relax(mm_plan* pl, void* m, const double h_ext[3], unsigned terms, 
 }
 
 mm_status mm_energy(mm_plan* pl, const void* m, const double h_ext[3], unsigned terms, double t,
-                    double E[5])
+                    double E[6])
 {
     Plan* p = reinterpret_cast<Plan*>(pl);
     if (!p || !m || !E) {
@@ -1112,6 +1193,10 @@ mm_status mm_rk4_adjoint(mm_plan* pl, const void* ckpt, const double h_ext[3], u
     Plan* p = reinterpret_cast<Plan*>(pl);
     if (p && nonlinear_anis(p, terms)) {
         set_error("higher-order anisotropy is not linear in m: no adjoint");
+        return MM_EINVAL;
+    }
+    if (p && stencil_extended(p, terms)) {
+        set_error("per-cell exchange and DMI have no adjoint");
         return MM_EINVAL;
     }
     if (!p || !ckpt || !region || nsteps <= 0 || !(dt > 0.0) || ckpt_every <= 0) {

@@ -64,6 +64,12 @@ struct Plan {
     double ec[3][3];       // cubic principal axes (orthonormal rows)
     int demag_p;
     bool percell;  // per-cell Ms present
+    bool percell_A;  // per-cell exchange constant present (A_cell)
+    bool dmi;        // DMI term present
+    int dmi_type;    // MM_DMI_INTERFACE / _BULK / _D2D
+    double D;        // uniform DMI strength (ignored with D_cell)
+    bool percell_D;  // per-cell DMI strength present (D_cell)
+    double edmi[3][3];  // DMI vectors e^dmi_x, e^dmi_y, e^dmi_z
     long n_magnetic;  // magnetic cells (Ms > 0)
     // drive
     bool drive;
@@ -76,6 +82,8 @@ struct Plan {
     void *S2 = nullptr;       // [3][nz][Py][Hxp] complex (aliases S1 when Py == 1)
     void *tw = nullptr;       // Lmax complex roots exp(-2 pi i n / Lmax)
     void *Ms_cell = nullptr;  // N reals, or null
+    void *A_cell = nullptr;   // N reals (per-cell exchange constant), or null
+    void *D_cell = nullptr;   // N reals (per-cell DMI strength), or null
     unsigned char *mask = nullptr;  // N bytes drive mask, or null
     // Runge-Kutta work space (allocated on first use)
     void *rk = nullptr;       // 10 vectors of 3N

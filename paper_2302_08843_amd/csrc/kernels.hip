@@ -482,6 +482,9 @@ struct LocalParams {
     double anis2;     // 4 Ku2 / mu0
     double cub1, cub2;  // 2 Kc1 / mu0, 2 Kc2 / mu0
     double ec[3][3];  // cubic principal axes
+    int with_dmi;     // DMI term present
+    double dmi;       // 2 D / mu0, or 2 / mu0 with per-cell D (divided by Ms_i per cell)
+    double edmi[3][3];  // DMI vector of axis k divided by 2 Delta_k
     double H[3];      // uniform external field
     double Hd[3];     // drive field at time t on masked cells
     double gp;        // gamma / (1 + alpha^2)
@@ -571,11 +574,25 @@ __device__ __forceinline__ T x_c2r_value(const cx<T>* __restrict__ S1, const cx<
     }
 }
 
-template <typename T, int M, bool PERCELL>
+// Effective DMI coupling of two cells (Eq. D_avg): the harmonic mean for
+// equal signs (0 when both vanish), otherwise minus the geometric mean of
+// sqrt(-Da Db) and |Da + Db| / 2.
+template <typename T>
+__device__ __forceinline__ T dmi_avg(T a, T b)
+{
+    const T ab = a * b;
+    if (ab >= (T)0) return (a + b) != (T)0 ? (T)2 * ab / (a + b) : (T)0;
+    return -sqrt(sqrt(-ab) * fabs(a + b) * (T)0.5);
+}
+
+// EXT: the stencil with per-cell exchange constants (harmonic mean, Sec. 4.2)
+// and/or DMI (Sec. 4.3) -- A_cell / D_cell are null when uniform.
+template <typename T, int M, bool PERCELL, bool EXT>
 __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
-    LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax)
+    LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
+    const T* __restrict__ A_cell, const T* __restrict__ D_cell)
 {
     using G = XC2R<T, M>;
     constexpr int kRows = G::kRows, kL = G::kL;
@@ -610,7 +627,45 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                 hz = x_c2r_value<T, M>(S1, lds, rl, 2, i, k, j, ny, P.s1_comp, P.Hxp);
             }
             const T inv_ms = (T)1 / ms;
-            if (P.with_exch) {
+            if constexpr (EXT) {
+                // one pass over the six neighbours serves both terms
+                T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+                const T Ai = A_cell ? A_cell[cell] : (T)0;
+                const T Di = D_cell ? D_cell[cell] : (T)0;
+                auto nb = [&](long q, T w, int dir, T sg) {
+                    if (PERCELL && Ms_cell[q] == (T)0) return;
+                    const T qx = m[q], qy = m[N + q], qz = m[2 * N + q];
+                    if (P.with_exch) {
+                        T wq = w;
+                        if (A_cell) {
+                            const T Aq = A_cell[q], sa = Ai + Aq;
+                            wq *= sa != (T)0 ? (T)2 * Ai * Aq / sa : (T)0;
+                        }
+                        ax += wq * (qx - mx);
+                        ay += wq * (qy - my);
+                        az += wq * (qz - mz);
+                    }
+                    if (P.with_dmi) {
+                        // D~ (e^dmi_k x m_{i+k}) / (2 Delta_k), e^dmi_{-k} = -e^dmi_k
+                        const T c = D_cell ? sg * dmi_avg(Di, D_cell[q]) : sg;
+                        const T ex = c * (T)P.edmi[dir][0], ey = c * (T)P.edmi[dir][1],
+                                ez = c * (T)P.edmi[dir][2];
+                        bx += ey * qz - ez * qy;
+                        by += ez * qx - ex * qz;
+                        bz += ex * qy - ey * qx;
+                    }
+                };
+                if (i > 0) nb(cell - 1, ix2, 0, (T)-1);
+                if (i + 1 < nx) nb(cell + 1, ix2, 0, (T)1);
+                if (j > 0) nb(cell - nx, iy2, 1, (T)-1);
+                if (j + 1 < ny) nb(cell + nx, iy2, 1, (T)1);
+                if (k > 0) nb(cell - (long)nx * ny, iz2, 2, (T)-1);
+                if (k + 1 < P.nz) nb(cell + (long)nx * ny, iz2, 2, (T)1);
+                const T ce = exch * inv_ms, cd = (T)P.dmi * inv_ms;
+                hx += ce * ax + cd * bx;
+                hy += ce * ay + cd * by;
+                hz += ce * az + cd * bz;
+            } else if (P.with_exch) {
                 T ax = 0, ay = 0, az = 0;
                 auto nb = [&](long q, T w) {
                     if (PERCELL && Ms_cell[q] == (T)0) return;
@@ -865,26 +920,27 @@ static hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long e
     return hipErrorInvalidValue;
 }
 
-template <typename T, int M, bool PC>
+template <typename T, int M, bool PC, bool EXT>
 static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
                                  double* torque)
 {
     using G = XC2R<T, M>;
     const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
     const long nblocks = (long)njt * p.n[2];
-    k_x_c2r_local<T, M, PC><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
+    k_x_c2r_local<T, M, PC, EXT><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
-        (const cx<T>*)p.tw, p.Lmax);
+        (const cx<T>*)p.tw, p.Lmax, p.percell_A ? (const T*)p.A_cell : nullptr,
+        p.percell_D ? (const T*)p.D_cell : nullptr);
     return hipGetLastError();
 }
 
-template <typename T, bool PC>
+template <typename T, bool PC, bool EXT>
 static hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
                                const LocalParams& P, double* torque)
 {
     switch (M) {
 #define MMX_L(LL) \
-    case LL: return launch_local_M<T, LL, PC>(p, m, h, dm, P, torque);
+    case LL: return launch_local_M<T, LL, PC, EXT>(p, m, h, dm, P, torque);
         MMX_L(0) MMX_CASES(MMX_L)
 #undef MMX_L
     }
@@ -1829,7 +1885,11 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.s1_comp = s1c;
     P.Hxp = p.Hxp;
     P.with_demag = (terms & MM_DEMAG) ? 1 : 0;
-    P.with_exch = (terms & MM_EXCH) && p.A != 0.0 ? 1 : 0;
+    P.with_exch = (terms & MM_EXCH) && (p.A != 0.0 || p.percell_A) ? 1 : 0;
+    P.with_dmi = (terms & MM_DMI) && p.dmi ? 1 : 0;
+    P.dmi = 2.0 * (p.percell_D ? 1.0 : p.D) / kMu0;
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) P.edmi[k][a] = p.edmi[k][a] / (2.0 * p.d[k]);
     P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
     P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi) ? 1 : 0;
     P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
@@ -1839,7 +1899,7 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     for (int i = 0; i < 3; ++i)
         for (int a = 0; a < 3; ++a) P.ec[i][a] = p.ec[i][a];
     P.Ms = p.Ms;
-    P.exch = 2.0 * p.A / kMu0;
+    P.exch = 2.0 * (p.percell_A ? 1.0 : p.A) / kMu0;
     P.idx2 = 1.0 / (p.d[0] * p.d[0]);
     P.idy2 = 1.0 / (p.d[1] * p.d[1]);
     P.idz2 = 1.0 / (p.d[2] * p.d[2]);
@@ -1860,9 +1920,15 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
         k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
         MMX_TRY(hipGetLastError());
     }
+    // the extended stencil only when a term needs it: the uniform-A kernel
+    // is left exactly as it was
+    const bool ext = (P.with_exch && p.percell_A) || P.with_dmi;
     return timed(p, MM_PASS_X_INV_LOCAL, [&] {
-        return pc ? launch_local<T, true>(p, M, m, h_out, dm_out, P, torque)
-                  : launch_local<T, false>(p, M, m, h_out, dm_out, P, torque);
+        if (ext)
+            return pc ? launch_local<T, true, true>(p, M, m, h_out, dm_out, P, torque)
+                      : launch_local<T, false, true>(p, M, m, h_out, dm_out, P, torque);
+        return pc ? launch_local<T, true, false>(p, M, m, h_out, dm_out, P, torque)
+                  : launch_local<T, false, false>(p, M, m, h_out, dm_out, P, torque);
     });
 }
 

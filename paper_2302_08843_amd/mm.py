@@ -22,14 +22,15 @@ LIB_PATH = os.path.join(HERE, "libmmx.so")
 MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ENONFINITE, MM_EDTMIN, MM_ENOTCONV, MM_EBUSY = (
     0, -1, -2, -3, -4, -5, -6, -7)
 MM_FP32, MM_FP64 = 0, 1
-MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_ALL = 1, 2, 4, 8, 15
+MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_DMI, MM_ALL = 1, 2, 4, 8, 16, 31
+MM_DMI_INTERFACE, MM_DMI_BULK, MM_DMI_D2D = 0, 1, 2
 
 STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4: "MM_ENONFINITE",
                 -5: "MM_EDTMIN", -6: "MM_ENOTCONV", -7: "MM_EBUSY"}
 
 # Every entry point declared in include/mm.h.
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
-           "mm_plan_padded", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
+           "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
            "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error", "mm_heff_vjp",
            "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_opts_default",
@@ -117,6 +118,8 @@ def lib():
         L.mm_plan_padded.argtypes = [vp, ip]
         L.mm_plan_padded.restype = None
         L.mm_set_ms.argtypes = [vp, vp]
+        L.mm_set_exchange.argtypes = [vp, vp]
+        L.mm_set_dmi.argtypes = [vp, C.c_int, C.c_double, vp]
         L.mm_set_drive.argtypes = [vp, dp, C.c_double, vp]
         L.mm_heff.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
         L.mm_llg_rhs.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
@@ -147,7 +150,7 @@ def lib():
         L.mm_rk4_adjoint.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
                                      C.c_long, vp, vp, dp]
         L.mm_last_error.restype = C.c_char_p
-        for name in ("mm_plan_create", "mm_set_ms", "mm_set_drive", "mm_heff", "mm_llg_rhs",
+        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
                      "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum", "mm_heff_vjp",
                      "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_create",
@@ -219,6 +222,14 @@ def mm_set_ms(plan, Ms_cell):
     _check(lib().mm_set_ms(plan, None if Ms_cell is None else _ptr(Ms_cell)))
 
 
+def mm_set_exchange(plan, A_cell):
+    _check(lib().mm_set_exchange(plan, None if A_cell is None else _ptr(A_cell)))
+
+
+def mm_set_dmi(plan, kind, D, D_cell):
+    _check(lib().mm_set_dmi(plan, int(kind), float(D), None if D_cell is None else _ptr(D_cell)))
+
+
 def mm_set_drive(plan, amp, freq, mask):
     _check(lib().mm_set_drive(plan, _vec3(amp), float(freq), None if mask is None else _ptr(mask)))
 
@@ -239,7 +250,7 @@ def mm_relax(plan, m, h_ext, terms, tol, max_steps, rtol):
 
 
 def mm_energy(plan, m, h_ext, terms, t):
-    E = (C.c_double * 5)()
+    E = (C.c_double * 6)()
     _check(lib().mm_energy(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), E))
     return np.array(list(E))
 
@@ -415,6 +426,29 @@ class Plan:
             return
         nx, ny, nz = self.grid
         mm_set_ms(self.handle, self._t(Ms_cell).reshape(nz, ny, nx).contiguous())
+        torch.cuda.current_stream().synchronize()
+
+    def set_exchange(self, A_cell):
+        """Per-cell exchange constant (None: the uniform A of the plan)."""
+        import torch
+
+        if A_cell is None:
+            mm_set_exchange(self.handle, None)
+            return
+        nx, ny, nz = self.grid
+        mm_set_exchange(self.handle, self._t(A_cell).reshape(nz, ny, nx).contiguous())
+        torch.cuda.current_stream().synchronize()
+
+    def set_dmi(self, D, kind=MM_DMI_INTERFACE):
+        """DMI of type `kind` with a uniform (scalar) or per-cell strength D
+        in J/m^2; D=None or 0 removes it."""
+        import torch
+
+        if D is None or (np.ndim(D) == 0 and not hasattr(D, "device")):
+            mm_set_dmi(self.handle, kind, 0.0 if D is None else float(D), None)
+            return
+        nx, ny, nz = self.grid
+        mm_set_dmi(self.handle, kind, 0.0, self._t(D).reshape(nz, ny, nx).contiguous())
         torch.cuda.current_stream().synchronize()
 
     def set_drive(self, amp, freq, mask):
