@@ -480,7 +480,7 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     }
     p->demag_p = o.demag_p;
     p->percell = false;
-    p->percell_A = p->percell_D = p->dmi = false;
+    p->percell_A = p->percell_D = p->dmi = p->dmi_mixed = false;
     p->dmi_type = MM_DMI_INTERFACE;
     p->D = 0.0;
     std::memset(p->edmi, 0, sizeof(p->edmi));
@@ -975,9 +975,17 @@ mm_status mm_set_dmi(mm_plan* pl, int type, double D, const void* D_cell)
         set_error("invalid DMI type or strength");
         return MM_EINVAL;
     }
+    p->dmi_mixed = false;
     if (D_cell) {
         mm_status s = copy_cell_field(p, &p->D_cell, D_cell, "per-cell DMI strength");
         if (s != MM_OK) return s;
+        // opposite-sign neighbour pairs need the second case of Eq. D_avg
+        MM_HIP(p->prec == MM_FP32 ? count_signs<float>(*p, (const float*)p->D_cell, p->red_out)
+                                  : count_signs<double>(*p, (const double*)p->D_cell, p->red_out),
+               "DMI signs");
+        s = fetch(p, 2);
+        if (s != MM_OK) return s;
+        p->dmi_mixed = p->host_out[0] > 0.0 && p->host_out[1] > 0.0;
     }
     p->percell_D = D_cell != nullptr;
     p->D = D_cell ? 0.0 : D;

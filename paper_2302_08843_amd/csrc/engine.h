@@ -69,6 +69,7 @@ struct Plan {
     int dmi_type;    // MM_DMI_INTERFACE / _BULK / _D2D
     double D;        // uniform DMI strength (ignored with D_cell)
     bool percell_D;  // per-cell DMI strength present (D_cell)
+    bool dmi_mixed;  // D_cell holds strengths of both signs
     double edmi[3][3];  // DMI vectors e^dmi_x, e^dmi_y, e^dmi_z
     long n_magnetic;  // magnetic cells (Ms > 0)
     // drive
@@ -177,6 +178,9 @@ hipError_t start_norms(Plan &p, const T *y, const T *f0, const T *f1, double rto
 // Count magnetic cells (Ms > 0) into *out_dev.
 template <typename T>
 hipError_t count_magnetic(Plan &p, double *out_dev);
+// Numbers of negative and positive entries of v (N values) into out_dev[0..1].
+template <typename T>
+hipError_t count_signs(Plan &p, const T *v, double *out_dev);
 // Transposed field / LLG right-hand side.  With h == nullptr: nu = H^T w
 // (w masked to magnetic cells).  With h (the field at m): nu = J^T w of the
 // LLG right-hand side with damping alpha.  gms (double, may be null)

@@ -89,6 +89,9 @@ namespace mmx {
 #ifndef MMX_SSPLIT
 #define MMX_SSPLIT 1  // strided passes: exchange real and imaginary parts separately
 #endif
+#ifndef MMX_EXT_RCP
+#define MMX_EXT_RCP 1  // FP32 harmonic means through the hardware reciprocal
+#endif
 #ifndef MMX_X1_KFAST
 #define MMX_X1_KFAST 1  // x inverse / local pass: consecutive blocks walk z first
 #endif
@@ -574,26 +577,55 @@ __device__ __forceinline__ T x_c2r_value(const cx<T>* __restrict__ S1, const cx<
     }
 }
 
+// 2 a b / (a + b) for a + b != 0, else 0 -- the harmonic-mean coupling of
+// the exchange (Sec. 4.2) and of equal-sign DMI strengths (Eq. D_avg).  The
+// quotient uses the hardware reciprocal (FP32: 1 ulp; FP64: refined) instead
+// of the correctly rounded division sequence.
+template <typename T>
+__device__ __forceinline__ T harmonic2(T a, T b)
+{
+    const T s = a + b;
+    if (s == (T)0) return (T)0;
+    if constexpr (!MMX_EXT_RCP) {
+        return (T)2 * a * b / s;
+    } else if constexpr (sizeof(T) == 4) {
+        return (T)2 * a * b * __builtin_amdgcn_rcpf(s);
+    } else {
+        // hardware reciprocal refined by two Newton steps (error ~1 ulp)
+        double r = __builtin_amdgcn_rcp(s);
+        r = fma(r, fma(-s, r, 1.0), r);
+        r = fma(r, fma(-s, r, 1.0), r);
+        return (T)2 * a * b * r;
+    }
+}
+
 // Effective DMI coupling of two cells (Eq. D_avg): the harmonic mean for
-// equal signs (0 when both vanish), otherwise minus the geometric mean of
-// sqrt(-Da Db) and |Da + Db| / 2.
+// equal signs, otherwise minus the geometric mean of sqrt(-Da Db) and
+// |Da + Db| / 2.
 template <typename T>
 __device__ __forceinline__ T dmi_avg(T a, T b)
 {
     const T ab = a * b;
-    if (ab >= (T)0) return (a + b) != (T)0 ? (T)2 * ab / (a + b) : (T)0;
+    if (ab >= (T)0) return harmonic2(a, b);
     return -sqrt(sqrt(-ab) * fabs(a + b) * (T)0.5);
 }
 
-// EXT: the stencil with per-cell exchange constants (harmonic mean, Sec. 4.2)
-// and/or DMI (Sec. 4.3) -- A_cell / D_cell are null when uniform.
-template <typename T, int M, bool PERCELL, bool EXT>
+// Stencil variant bits: EXT_DMI adds the DMI term (Sec. 4.3); EXT_PA takes
+// per-cell exchange constants A_cell with the harmonic-mean coupling (Sec.
+// 4.2), P.exch then being 2 / mu0; EXT_PD takes per-cell DMI strengths D_cell
+// with the coupling of Eq. D_avg, P.dmi then being 2 / mu0; EXT_MIX adds the
+// opposite-sign case of that average (D_cell holds both signs).
+constexpr int EXT_DMI = 1, EXT_PA = 2, EXT_PD = 4, EXT_MIX = 8;
+
+template <typename T, int M, bool PERCELL, int EXT>
 __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
     LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
     const T* __restrict__ A_cell, const T* __restrict__ D_cell)
 {
+    constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
+    constexpr bool kMIX = EXT & EXT_MIX;
     using G = XC2R<T, M>;
     constexpr int kRows = G::kRows, kL = G::kL;
     __shared__ cx<T> lds[kRows * 3 * kL];
@@ -627,62 +659,54 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                 hz = x_c2r_value<T, M>(S1, lds, rl, 2, i, k, j, ny, P.s1_comp, P.Hxp);
             }
             const T inv_ms = (T)1 / ms;
-            if constexpr (EXT) {
-                // one pass over the six neighbours serves both terms
+            if (EXT != 0 || P.with_exch) {
+                // One pass over the six neighbours serves exchange and DMI,
+                // free of branches around loads: an absent neighbour reads
+                // the cell itself with weight 0.
                 T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
-                const T Ai = A_cell ? A_cell[cell] : (T)0;
-                const T Di = D_cell ? D_cell[cell] : (T)0;
-                auto nb = [&](long q, T w, int dir, T sg) {
-                    if (PERCELL && Ms_cell[q] == (T)0) return;
+                T Ai = 0, Di = 0;
+                if constexpr (kPA) Ai = A_cell[cell];
+                if constexpr (kPD) Di = D_cell[cell];
+#pragma unroll
+                for (int nbi = 0; nbi < 6; ++nbi) {
+                    const int dir = nbi >> 1;
+                    const bool plus = nbi & 1;
+                    const bool has = dir == 0 ? (plus ? i + 1 < nx : i > 0)
+                                   : dir == 1 ? (plus ? j + 1 < ny : j > 0)
+                                              : (plus ? k + 1 < P.nz : k > 0);
+                    const long off = dir == 0 ? 1L : dir == 1 ? (long)nx : (long)nx * ny;
+                    const long q = has ? (plus ? cell + off : cell - off) : cell;
                     const T qx = m[q], qy = m[N + q], qz = m[2 * N + q];
-                    if (P.with_exch) {
-                        T wq = w;
-                        if (A_cell) {
-                            const T Aq = A_cell[q], sa = Ai + Aq;
-                            wq *= sa != (T)0 ? (T)2 * Ai * Aq / sa : (T)0;
-                        }
-                        ax += wq * (qx - mx);
-                        ay += wq * (qy - my);
-                        az += wq * (qz - mz);
-                    }
-                    if (P.with_dmi) {
+                    const bool ok = has && (!PERCELL || Ms_cell[q] != (T)0);
+                    T wq = ok ? (dir == 0 ? ix2 : dir == 1 ? iy2 : iz2) : (T)0;
+                    if constexpr (kPA) wq *= harmonic2(Ai, A_cell[q]);
+                    ax += wq * (qx - mx);
+                    ay += wq * (qy - my);
+                    az += wq * (qz - mz);
+                    if constexpr (kDMI) {
                         // D~ (e^dmi_k x m_{i+k}) / (2 Delta_k), e^dmi_{-k} = -e^dmi_k
-                        const T c = D_cell ? sg * dmi_avg(Di, D_cell[q]) : sg;
+                        T c = ok ? (plus ? (T)1 : (T)-1) : (T)0;
+                        if constexpr (kMIX)
+                            c *= dmi_avg(Di, D_cell[q]);
+                        else if constexpr (kPD)
+                            c *= harmonic2(Di, D_cell[q]);
                         const T ex = c * (T)P.edmi[dir][0], ey = c * (T)P.edmi[dir][1],
                                 ez = c * (T)P.edmi[dir][2];
                         bx += ey * qz - ez * qy;
                         by += ez * qx - ex * qz;
                         bz += ex * qy - ey * qx;
                     }
-                };
-                if (i > 0) nb(cell - 1, ix2, 0, (T)-1);
-                if (i + 1 < nx) nb(cell + 1, ix2, 0, (T)1);
-                if (j > 0) nb(cell - nx, iy2, 1, (T)-1);
-                if (j + 1 < ny) nb(cell + nx, iy2, 1, (T)1);
-                if (k > 0) nb(cell - (long)nx * ny, iz2, 2, (T)-1);
-                if (k + 1 < P.nz) nb(cell + (long)nx * ny, iz2, 2, (T)1);
-                const T ce = exch * inv_ms, cd = (T)P.dmi * inv_ms;
-                hx += ce * ax + cd * bx;
-                hy += ce * ay + cd * by;
-                hz += ce * az + cd * bz;
-            } else if (P.with_exch) {
-                T ax = 0, ay = 0, az = 0;
-                auto nb = [&](long q, T w) {
-                    if (PERCELL && Ms_cell[q] == (T)0) return;
-                    ax += w * (m[q] - mx);
-                    ay += w * (m[N + q] - my);
-                    az += w * (m[2 * N + q] - mz);
-                };
-                if (i > 0) nb(cell - 1, ix2);
-                if (i + 1 < nx) nb(cell + 1, ix2);
-                if (j > 0) nb(cell - nx, iy2);
-                if (j + 1 < ny) nb(cell + nx, iy2);
-                if (k > 0) nb(cell - (long)nx * ny, iz2);
-                if (k + 1 < P.nz) nb(cell + (long)nx * ny, iz2);
-                const T ce = exch * inv_ms;
+                }
+                const T ce = P.with_exch ? exch * inv_ms : (T)0;
                 hx += ce * ax;
                 hy += ce * ay;
                 hz += ce * az;
+                if constexpr (kDMI) {
+                    const T cd = (T)P.dmi * inv_ms;
+                    hx += cd * bx;
+                    hy += cd * by;
+                    hz += cd * bz;
+                }
             }
             if (P.with_anis) {
                 const T em = eux * mx + euy * my + euz * mz;
@@ -920,7 +944,7 @@ static hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long e
     return hipErrorInvalidValue;
 }
 
-template <typename T, int M, bool PC, bool EXT>
+template <typename T, int M, bool PC, int EXT>
 static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
                                  double* torque)
 {
@@ -929,12 +953,12 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
     const long nblocks = (long)njt * p.n[2];
     k_x_c2r_local<T, M, PC, EXT><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
-        (const cx<T>*)p.tw, p.Lmax, p.percell_A ? (const T*)p.A_cell : nullptr,
-        p.percell_D ? (const T*)p.D_cell : nullptr);
+        (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
+        (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr);
     return hipGetLastError();
 }
 
-template <typename T, bool PC, bool EXT>
+template <typename T, bool PC, int EXT>
 static hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
                                const LocalParams& P, double* torque)
 {
@@ -1330,6 +1354,26 @@ __global__ __launch_bounds__(kBlock) void k_count_mag(const T* __restrict__ Ms_c
         acc += Ms_cell[q] != (T)0 ? 1.0 : 0.0;
     acc = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// Numbers of negative and of positive entries of v[0..N) into partials
+// [0, kRedBlocks) and [kRedBlocks, 2 kRedBlocks).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_count_signs(const T* __restrict__ v, long N,
+                                                        double* partials)
+{
+    double neg = 0.0, pos = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        neg += v[q] < (T)0 ? 1.0 : 0.0;
+        pos += v[q] > (T)0 ? 1.0 : 0.0;
+    }
+    neg = block_sum(neg);
+    pos = block_sum(pos);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = neg;
+        partials[kRedBlocks + blockIdx.x] = pos;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1887,7 +1931,12 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.with_demag = (terms & MM_DEMAG) ? 1 : 0;
     P.with_exch = (terms & MM_EXCH) && (p.A != 0.0 || p.percell_A) ? 1 : 0;
     P.with_dmi = (terms & MM_DMI) && p.dmi ? 1 : 0;
-    P.dmi = 2.0 * (p.percell_D ? 1.0 : p.D) / kMu0;
+    // stencil variant (EXT_* bits); a per-cell constant moves into the
+    // neighbour-pair average, leaving 2 / mu0 as the prefactor
+    const int ext = (P.with_dmi ? EXT_DMI : 0) | (P.with_exch && p.percell_A ? EXT_PA : 0) |
+                    (P.with_dmi && p.percell_D ? EXT_PD : 0) |
+                    (P.with_dmi && p.percell_D && p.dmi_mixed ? EXT_MIX : 0);
+    P.dmi = 2.0 * ((ext & EXT_PD) ? 1.0 : p.D) / kMu0;
     for (int k = 0; k < 3; ++k)
         for (int a = 0; a < 3; ++a) P.edmi[k][a] = p.edmi[k][a] / (2.0 * p.d[k]);
     P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
@@ -1899,7 +1948,7 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     for (int i = 0; i < 3; ++i)
         for (int a = 0; a < 3; ++a) P.ec[i][a] = p.ec[i][a];
     P.Ms = p.Ms;
-    P.exch = 2.0 * (p.percell_A ? 1.0 : p.A) / kMu0;
+    P.exch = 2.0 * ((ext & EXT_PA) ? 1.0 : p.A) / kMu0;
     P.idx2 = 1.0 / (p.d[0] * p.d[0]);
     P.idy2 = 1.0 / (p.d[1] * p.d[1]);
     P.idz2 = 1.0 / (p.d[2] * p.d[2]);
@@ -1920,15 +1969,24 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
         k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
         MMX_TRY(hipGetLastError());
     }
-    // the extended stencil only when a term needs it: the uniform-A kernel
-    // is left exactly as it was
-    const bool ext = (P.with_exch && p.percell_A) || P.with_dmi;
+    // DMI and the coupling averages only in the variants that need them
     return timed(p, MM_PASS_X_INV_LOCAL, [&] {
-        if (ext)
-            return pc ? launch_local<T, true, true>(p, M, m, h_out, dm_out, P, torque)
-                      : launch_local<T, false, true>(p, M, m, h_out, dm_out, P, torque);
-        return pc ? launch_local<T, true, false>(p, M, m, h_out, dm_out, P, torque)
-                  : launch_local<T, false, false>(p, M, m, h_out, dm_out, P, torque);
+        switch (ext) {
+#define MMX_X(E)                                                                  \
+    case E:                                                                       \
+        return pc ? launch_local<T, true, E>(p, M, m, h_out, dm_out, P, torque)   \
+                  : launch_local<T, false, E>(p, M, m, h_out, dm_out, P, torque);
+            MMX_X(0)
+            MMX_X(EXT_DMI)
+            MMX_X(EXT_PA)
+            MMX_X(EXT_DMI | EXT_PA)
+            MMX_X(EXT_DMI | EXT_PD)
+            MMX_X(EXT_DMI | EXT_PA | EXT_PD)
+            MMX_X(EXT_DMI | EXT_PD | EXT_MIX)
+            MMX_X(EXT_DMI | EXT_PA | EXT_PD | EXT_MIX)
+#undef MMX_X
+        }
+        return hipErrorInvalidValue;
     });
 }
 
@@ -2105,6 +2163,17 @@ hipError_t count_magnetic(Plan& p, double* out_dev)
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t count_signs(Plan& p, const T* v, double* out_dev)
+{
+    k_count_signs<T><<<kRedBlocks, kBlock, 0, p.stream>>>(v, p.N, p.red);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + kRedBlocks, kRedBlocks, out_dev, 1, 1.0, 0);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Differentiation host pipeline.
 // ---------------------------------------------------------------------------
@@ -2223,6 +2292,7 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \
                                        double*);                                                 \
     template hipError_t count_magnetic<T>(Plan&, double*);                                       \
+    template hipError_t count_signs<T>(Plan&, const T*, double*);                                \
     template hipError_t debug_spectrum<T>(Plan&, int, double*);                                  \
     template hipError_t field_vjp<T>(Plan&, const T*, const T*, const T*, unsigned, double, T*,  \
                                      T*, T*, double*);                                           \
