@@ -78,6 +78,11 @@ def lib():
         L.or_set_Ms.argtypes = [C.c_void_p, dp]
         L.or_set_anisotropy2.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp, dp]
         L.or_set_dmi.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
+        L.or_set_layers.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_newell_box.argtypes = [C.c_double, C.c_double, C.c_long, C.c_long, C.c_double,
+                                    C.c_double, C.c_double, dp]
+        L.or_layer_entry.argtypes = [C.c_double, C.c_double, dp, C.c_long, C.c_long, C.c_long,
+                                     C.c_long, C.c_int, dp]
         for name in ("or_demag", "or_exchange", "or_anisotropy", "or_dmi"):
             getattr(L, name).argtypes = [C.c_void_p, dp, dp]
         L.or_zeeman.argtypes = [C.c_void_p, C.c_double, dp]
@@ -161,6 +166,26 @@ def demag_at(n, d, m, cells, Ms=1.0, p=20) -> np.ndarray:
     return out
 
 
+def newell_box(dx, dy, I, J, Bz, ct, cs) -> np.ndarray:
+    """Newell tensor between a target cell of height ct and a source cell of
+    height cs whose bottom is Bz above the target's bottom, laterally offset by
+    (I dx, J dy) (source minus target).  Order xx, yy, zz, xy, xz, yz."""
+    out = np.zeros(6)
+    lib().or_newell_box(float(dx), float(dy), int(I), int(J), float(Bz), float(ct), float(cs),
+                        _dp(out))
+    return out
+
+
+def layer_entry(dx, dy, dz, t, s, I, J, p=20) -> np.ndarray:
+    """Layered demag kernel K^{ts}(I, J) (h_t = sum K M_s; I = i_t - i_s) for
+    layer heights dz stacked from 0."""
+    zb = np.concatenate([[0.0], np.cumsum(np.asarray(dz, dtype=np.float64))])
+    out = np.zeros(6)
+    lib().or_layer_entry(float(dx), float(dy), _dp(zb), int(t), int(s), int(I), int(J), int(p),
+                         _dp(out))
+    return out
+
+
 def padded(n: int) -> int:
     """Zero-padding extent: 1 for n == 1, else next power of two >= 2n-1."""
     return int(lib().or_padded(int(n)))
@@ -193,7 +218,8 @@ class Oracle:
     evaluates demag as the O(N^2) direct sum instead of the FFT convolution.
     """
 
-    def __init__(self, n, d, Ms, A=0.0, Ku=0.0, eu=(0, 0, 1), alpha=0.5, p=20, direct=False):
+    def __init__(self, n, d, Ms, A=0.0, Ku=0.0, eu=(0, 0, 1), alpha=0.5, p=20, direct=False,
+                 layers=None):
         self.n = tuple(int(v) for v in n)
         self.d = tuple(float(v) for v in d)
         nx, ny, nz = self.n
@@ -208,6 +234,19 @@ class Oracle:
                                   float(Ku), _dp(_d3(eu)), self.alpha, int(bool(direct)))
         self.Hext = np.zeros(3)
         self.terms = ALL
+        self.layers = None
+        if layers is not None:
+            self.set_layers(layers)
+
+    def set_layers(self, dz):
+        """Thin layers of heights dz[0..nz) (the non-equidistant case of
+        Sec. 4.4); None restores equal layers of height d[2]."""
+        if dz is None:
+            self.layers = None
+            lib().or_set_layers(self._c, None)
+            return
+        self.layers = np.ascontiguousarray(np.asarray(dz, dtype=np.float64).reshape(self.n[2]))
+        lib().or_set_layers(self._c, self.layers.ctypes.data)
 
     def __del__(self):
         if getattr(self, "_c", None):

@@ -163,6 +163,110 @@ void or_tensor_entry(const double d[3], long oi, long oj, long ok, int p, double
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* Thin layers of unequal thickness (Sec. 4.4, the non-equidistant case):     */
+/* the cell-averaged tensor between a target box and a source box of another  */
+/* height.  Along an axis where the target spans [0, t] and the source        */
+/* [B, B + s], the double integral of a second derivative F'' over the pair   */
+/* is F(B + s) - F(B + s - t) - F(B) + F(B - t); for t = s it is the second   */
+/* difference of Newell's equal-cell stencil.  The result is normalised by    */
+/* the target volume (the field is averaged over the target).  Pinned by the  */
+/* equal-height limit, additivity in the source, volume-weighted averaging    */
+/* over the target and the dipole limit (tests/test_oracle_layers.py).        */
+/* ------------------------------------------------------------------------- */
+
+/* Points and weights of one axis: bottom offset B, target size t, source
+ * size s.  The weights carry the sign of Newell's equal-cell stencil
+ * (positive self term). */
+static void axis_points(long double B, long double t, long double s, long double pt[4],
+                        long double w[4])
+{
+    pt[0] = B + s;
+    w[0] = -1.0L;
+    pt[1] = B + s - t;
+    w[1] = 1.0L;
+    pt[2] = B;
+    w[2] = 1.0L;
+    pt[3] = B - t;
+    w[3] = -1.0L;
+}
+
+/* One component from f (which 0) or g (which 1) with the argument slots
+ * (u, v, q): bottom offsets Bu, Bv, Bq, target sizes tu, tv, tq, source sizes
+ * su, sv, sq. */
+static long double box_stencil(int which, const long double B[3], const long double tz[3],
+                               const long double sz[3])
+{
+    long double pu[4], wu[4], pv[4], wv[4], pq[4], wq[4];
+    axis_points(B[0], tz[0], sz[0], pu, wu);
+    axis_points(B[1], tz[1], sz[1], pv, wv);
+    axis_points(B[2], tz[2], sz[2], pq, wq);
+    long double acc = 0.0L;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++)
+            for (int e = 0; e < 4; e++)
+                acc += wu[a] * wv[b] * wq[e] *
+                       (which == 0 ? newell_f(pu[a], pv[b], pq[e]) : newell_g(pu[a], pv[b], pq[e]));
+    return acc / (4.0L * OR_PI_L * tz[0] * tz[1] * tz[2]);
+}
+
+/* Newell tensor N between a target cell of height ct and a source cell of
+ * height cs whose bottom lies Bz above the target's bottom and which sits
+ * (oi dx, oj dy) from the target laterally (source minus target).
+ * out = {Nxx, Nyy, Nzz, Nxy, Nxz, Nyz}. */
+void or_newell_box(double dx, double dy, long oi, long oj, double Bz, double ct, double cs,
+                   double out[6])
+{
+    long double X = oi * (long double)dx, Y = oj * (long double)dy;
+    long double a = dx, b = dy;
+    /* slot orders as in or_newell: xx f(x,y,z), yy f(y,x,z), zz f(z,y,x),
+     * xy g(x,y,z), xz g(x,z,y), yz g(y,z,x) */
+    long double B[3], T[3], S[3];
+#define SLOT(k, base, tt, ss) (B[k] = (base), T[k] = (tt), S[k] = (ss))
+    SLOT(0, X, a, a); SLOT(1, Y, b, b); SLOT(2, Bz, ct, cs);
+    out[0] = (double)box_stencil(0, B, T, S);
+    out[3] = (double)box_stencil(1, B, T, S);
+    SLOT(0, Y, b, b); SLOT(1, X, a, a); SLOT(2, Bz, ct, cs);
+    out[1] = (double)box_stencil(0, B, T, S);
+    SLOT(0, Bz, ct, cs); SLOT(1, Y, b, b); SLOT(2, X, a, a);
+    out[2] = (double)box_stencil(0, B, T, S);
+    SLOT(0, X, a, a); SLOT(1, Bz, ct, cs); SLOT(2, Y, b, b);
+    out[4] = (double)box_stencil(1, B, T, S);
+    SLOT(0, Y, b, b); SLOT(1, Bz, ct, cs); SLOT(2, X, a, a);
+    out[5] = (double)box_stencil(1, B, T, S);
+#undef SLOT
+}
+
+/* Layered demag kernel entry K^{ts}(I, J) (h_t = sum K M_s) for the lateral
+ * offset I = i_t - i_s, J = j_t - j_s: -N within Chebyshev index distance p
+ * in (I, J, s - t), else the dipole of the source cell's moment (volume
+ * dx dy dz_s) at the centre offset.  zb: layer bottoms (nz + 1 values,
+ * zb[0] = 0). */
+void or_layer_entry(double dx, double dy, const double *zb, long t, long s, long oi, long oj, int p,
+                    double out[6])
+{
+    double ct = zb[t + 1] - zb[t], cs = zb[s + 1] - zb[s];
+    long cheb = labs(oi);
+    if (labs(oj) > cheb) cheb = labs(oj);
+    if (labs(s - t) > cheb) cheb = labs(s - t);
+    if (p < 0 || cheb <= p) {
+        or_newell_box(dx, dy, -oi, -oj, zb[s] - zb[t], ct, cs, out);
+        for (int q = 0; q < 6; q++)
+            out[q] = -out[q];
+        return;
+    }
+    /* r from the source centre to the target centre */
+    double r[3] = {oi * dx, oj * dy, 0.5 * (zb[t] + zb[t + 1]) - 0.5 * (zb[s] + zb[s + 1])};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double pre = dx * dy * cs / (4.0 * M_PI) / (r2 * r2 * sqrt(r2));
+    out[0] = pre * (3.0 * r[0] * r[0] - r2);
+    out[1] = pre * (3.0 * r[1] * r[1] - r2);
+    out[2] = pre * (3.0 * r[2] * r[2] - r2);
+    out[3] = pre * 3.0 * r[0] * r[1];
+    out[4] = pre * 3.0 * r[0] * r[2];
+    out[5] = pre * 3.0 * r[1] * r[2];
+}
+
 /* Demagnetisation field at selected target cells by direct summation of the
  * discrete convolution h_i = sum_j K_{i-j} Ms_j m_j (Sec. 4.4) over every
  * source cell -- no padded grid and no FFT, so it serves grids far too large
@@ -360,8 +464,18 @@ typedef struct or_ctx {
     double complex *Khat;      /* 6 x PN spectra of the padded kernel     */
     /* direct path: kernel per offset, (2nx-1)(2ny-1)(2nz-1) x 6            */
     double *Koff;
+    /* thin layers of unequal height (or_set_layers): layer bottoms zb
+     * (nz + 1 values) and the kernel per (component, t, s, I, J) */
+    double *zb;
+    double *Klay;
     int terms;                 /* field-term mask used by heff            */
 } or_ctx;
+
+/* Height of layer k (d[2] without layers). */
+static double layer_dz(const or_ctx *c, long k) { return c->zb ? c->zb[k + 1] - c->zb[k] : c->d[2]; }
+
+/* Volume of the cells of layer k. */
+static double layer_volume(const or_ctx *c, long k) { return c->d[0] * c->d[1] * layer_dz(c, k); }
 
 static long cidx(const or_ctx *c, long i, long j, long k) { return i + c->n[0] * (j + c->n[1] * k); }
 
@@ -484,10 +598,44 @@ void or_set_dmi(or_ctx *c, const double *D, int type)
     }
 }
 
+/* Thin layers of unequal height dz[0..nz) stacked from z = 0 (Sec. 4.4, the
+ * non-equidistant case): the demag field becomes the direct sum with the
+ * layered kernel, the z exchange and DMI couplings use the layer heights, and
+ * energies use each layer's cell volume.  dz = NULL restores equal layers. */
+void or_set_layers(or_ctx *c, const double *dz)
+{
+    free(c->zb);
+    free(c->Klay);
+    c->zb = NULL;
+    c->Klay = NULL;
+    if (!dz)
+        return;
+    long nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    c->zb = malloc(sizeof(double) * (nz + 1));
+    c->zb[0] = 0.0;
+    for (long k = 0; k < nz; k++)
+        c->zb[k + 1] = c->zb[k] + dz[k];
+    long ox = 2 * nx - 1, oy = 2 * ny - 1, nl = ox * oy;
+    long total = nz * nz * nl;
+    c->Klay = malloc(sizeof(double) * 6 * total);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < total; q++) {
+        long l = q % nl, ts = q / nl;
+        long t = ts / nz, s = ts % nz;
+        long oi = l % ox - (nx - 1), oj = l / ox - (ny - 1);
+        double e[6];
+        or_layer_entry(c->d[0], c->d[1], c->zb, t, s, oi, oj, c->p, e);
+        for (int a = 0; a < 6; a++)
+            c->Klay[a * total + q] = e[a];
+    }
+}
+
 void or_destroy(or_ctx *c)
 {
     if (!c)
         return;
+    free(c->zb);
+    free(c->Klay);
     free(c->D);
     free(c->Ms);
     free(c->A);
@@ -523,6 +671,30 @@ void or_set_Ms(or_ctx *c, const double *Ms) { memcpy(c->Ms, Ms, sizeof(double) *
 void or_demag(const or_ctx *c, const double *m, double *h)
 {
     long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    if (c->zb) {
+        /* layers: h_t(i, j) = sum_s sum K^{ts}(i - i', j - j') Ms m (direct) */
+        long ox = 2 * nx - 1, oy = 2 * ny - 1, nl = ox * oy, total = nz * nz * nl;
+        const double *K = c->Klay;
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < N; t++) {
+            long i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+            double hx = 0, hy = 0, hz = 0;
+            for (long s = 0; s < N; s++) {
+                long si = s % nx, sj = (s / nx) % ny, sk = s / (nx * ny);
+                long q = (k * nz + sk) * nl + (i - si + nx - 1) + ox * (j - sj + ny - 1);
+                double Mx = c->Ms[s] * m[s], My = c->Ms[s] * m[N + s], Mz = c->Ms[s] * m[2 * N + s];
+                double kxx = K[q], kyy = K[total + q], kzz = K[2 * total + q];
+                double kxy = K[3 * total + q], kxz = K[4 * total + q], kyz = K[5 * total + q];
+                hx += kxx * Mx + kxy * My + kxz * Mz;
+                hy += kxy * Mx + kyy * My + kyz * Mz;
+                hz += kxz * Mx + kyz * My + kzz * Mz;
+            }
+            h[t] = hx;
+            h[N + t] = hy;
+            h[2 * N + t] = hz;
+        }
+        return;
+    }
     if (c->demag_direct) {
         long ox = 2 * nx - 1, oy = 2 * ny - 1, oz = 2 * nz - 1, noff = ox * oy * oz;
         const double *K = c->Koff;
@@ -609,6 +781,12 @@ void or_exchange(const or_ctx *c, const double *m, double *h)
                 double hm = (Ai + As) != 0.0 ? Ai * As / (Ai + As) : 0.0;
                 double dk = c->d[q / 2];
                 double w = 2.0 / (dk * dk) * hm;
+                if (q / 2 == 2 && c->zb) {
+                    /* layers: the flux between the centres, per height of
+                     * this cell: 2 / (dz_k (dz_k + dz_e)) in place of 1/dz^2 */
+                    double hk = layer_dz(c, k), he = layer_dz(c, e);
+                    w = 2.0 * hm * 2.0 / (hk * (hk + he));
+                }
                 for (int comp = 0; comp < 3; comp++)
                     acc[comp] += w * (m[comp * N + s] - m[comp * N + t]);
             }
@@ -669,10 +847,11 @@ static double anisotropy_energy(const or_ctx *c, const double *m)
         for (int i = 0; i < 3; i++)
             p[i] = c->ec[i][0] * M[0] + c->ec[i][1] * M[1] + c->ec[i][2] * M[2];
         double q1 = p[0] * p[0], q2 = p[1] * p[1], q3 = p[2] * p[2];
-        acc += -c->Ku * em * em - c->Ku2 * em * em * em * em +
-               c->Kc1 * (q1 * q2 + q2 * q3 + q3 * q1) + c->Kc2 * q1 * q2 * q3;
+        acc += (long double)layer_volume(c, t / (c->n[0] * c->n[1])) *
+               (-c->Ku * em * em - c->Ku2 * em * em * em * em +
+                c->Kc1 * (q1 * q2 + q2 * q3 + q3 * q1) + c->Kc2 * q1 * q2 * q3);
     }
-    return (double)(acc * c->d[0] * c->d[1] * c->d[2]);
+    return (double)acc;
 }
 
 /* Effective DMI coupling between two cells (Eq. D_avg).  Pinned for equal
@@ -719,8 +898,12 @@ void or_dmi(const or_ctx *c, const double *m, double *h)
             double ms[3] = {m[s], m[N + s], m[2 * N + s]};
             double cr[3] = {ev[1] * ms[2] - ev[2] * ms[1], ev[2] * ms[0] - ev[0] * ms[2],
                             ev[0] * ms[1] - ev[1] * ms[0]};
+            /* layers: the height of this cell's layer in place of dz (the
+             * finite-volume form: face values averaged, divided by the
+             * cell height, which keeps the operator Ms V-weighted symmetric) */
+            double two_delta = 2.0 * (ax == 2 ? layer_dz(c, k) : c->d[ax]);
             for (int comp = 0; comp < 3; comp++)
-                acc[comp] += Dt / (2.0 * c->d[ax]) * cr[comp];
+                acc[comp] += Dt / two_delta * cr[comp];
         }
         for (int comp = 0; comp < 3; comp++)
             h[comp * N + t] = 2.0 / (OR_MU0 * c->Ms[t]) * acc[comp];
@@ -815,8 +998,7 @@ static void rhs_at(const or_ctx *c, const double *m, double t, double alpha, int
 
 void or_energy(const or_ctx *c, const double *m, double t, double E[6])
 {
-    long N = c->N;
-    double V = c->d[0] * c->d[1] * c->d[2];
+    long N = c->N, nxy = c->n[0] * c->n[1];
     double *h = malloc(sizeof(double) * 3 * N);
     /* slots: 0 demag, 1 exchange, 2 anisotropy, 3 Zeeman, 5 DMI; 4 total */
     unsigned masks[6] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN, 0, OR_DMI};
@@ -833,11 +1015,11 @@ void or_energy(const or_ctx *c, const double *m, double t, double E[6])
         if (c->terms & (int)masks[e]) {
             or_heff(c, m, t, masks[e], h);
             for (long q = 0; q < N; q++)
-                acc += (long double)c->Ms[q] *
+                acc += (long double)layer_volume(c, q / nxy) * c->Ms[q] *
                        ((long double)m[q] * h[q] + (long double)m[N + q] * h[N + q] +
                         (long double)m[2 * N + q] * h[2 * N + q]);
         }
-        double pre = (e == 3 ? -1.0 : -0.5) * OR_MU0 * V;
+        double pre = (e == 3 ? -1.0 : -0.5) * OR_MU0;
         E[e] = (double)(pre * acc);
         tot += E[e];
     }
