@@ -90,9 +90,22 @@ typedef struct {
      * points reject plans that use them. */
     double ku2, kc1, kc2;
     double kc_axis1[3], kc_axis2[3];
+    /* Thin layers of unequal height (Sec. 4.4, the non-equidistant case):
+     * NULL for equal layers of height cell[2]; else a host array of nz
+     * heights (m, positive; nz <= 16), stacked from z = 0, read during
+     * mm_plan_create only.  The demag field then couples the layers densely
+     * per lateral frequency (2-D FFT in x and y, O(nx ny log(nx ny) nz^2));
+     * the z exchange uses 2/(dz_k (dz_k + dz_j)) in place of 1/dz^2 (the
+     * flux between layer centres per layer height), the z part of DMI
+     * 1/(2 dz_k) in place of 1/(2 dz), and the energies each layer's cell
+     * volume.  cell[2] is ignored.  Such plans have no transposed operator
+     * (mm_heff_vjp, mm_llg_rhs_vjp, mm_rk4_adjoint and the debug entry
+     * points return MM_EINVAL). */
+    const double *dz_layers;
 } mm_opts;
 
-/* Fill *o with defaults: MM_FP64, axis (0,0,1), demag_p 20, stream NULL. */
+/* Fill *o with defaults: MM_FP64, axis (0,0,1), demag_p 20, stream NULL,
+ * no higher-order anisotropy, equal layers. */
 void mm_opts_default(mm_opts *o);
 
 /* Create a plan for grid[3] = (nx, ny, nz) cells of size cell[3] = (dx, dy,

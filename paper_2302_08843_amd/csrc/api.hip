@@ -55,7 +55,7 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->A_cell, p->D_cell, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
+                    p->A_cell, p->D_cell, p->zw, p->lw, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -440,6 +440,14 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
         p->eu[a] = o.ku_axis[a] / nrm;
     }
     p->N = (long)grid[0] * grid[1] * grid[2];
+    if (o.dz_layers && grid[2] > 1) {
+        // thin layers of unequal height: no z padding, dense layer coupling
+        p->layered = true;
+        p->P[2] = 1;
+        p->zb.assign(grid[2] + 1, 0.0);
+        for (int k = 0; k < grid[2]; ++k) p->zb[k + 1] = p->zb[k] + o.dz_layers[k];
+        p->d[2] = o.dz_layers[0];
+    }
     p->Hx = p->P[0] > 1 ? p->P[0] / 2 + 1 : 1;
     // spectral rows start on 128-byte boundaries for the real kernel array
     // (32 floats or 16 doubles) and therefore for the complex spectra too
@@ -447,7 +455,8 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     p->Hxp = (p->Hx + row_align - 1) / row_align * row_align;
     p->S1n = 3L * grid[2] * grid[1] * p->Hxp;
     p->S2n = 3L * grid[2] * p->P[1] * p->Hxp;
-    p->Kn = (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
+    p->Kn = p->layered ? (long)grid[2] * grid[2] * (p->P[1] / 2 + 1) * p->Hxp
+                       : (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
     p->Lmax = std::max(p->P[0], std::max(p->P[1], p->P[2]));
     p->prec = o.prec;
     p->Ms = Ms;
@@ -507,14 +516,45 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     } while (0)
     if (!share) MM_ALLOC(p->Khat, 6 * (size_t)p->Kn * es, "spectral kernel");
     MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es, "spectrum S1");
-    if (p->P[2] > 1 && p->P[1] > 1)
+    if ((p->P[2] > 1 || p->layered) && p->P[1] > 1)
         MM_ALLOC(p->S2, (size_t)p->S2n * 2 * es, "spectrum S2");
     else
         p->S2 = p->S1;
     if (!share) MM_ALLOC(p->tw, (size_t)p->Lmax * 2 * es, "twiddles");
     MM_ALLOC(p->red, sizeof(double) * kRedSlots, "reduction partials");
     MM_ALLOC(p->red_out, sizeof(double) * 8, "reduction results");
+    if (p->layered) {
+        MM_ALLOC(p->zw, 4 * (size_t)grid[2] * es, "layer couplings");
+        MM_ALLOC(p->lw, sizeof(double) * grid[2], "layer heights");
+    }
 #undef MM_ALLOC
+    if (p->layered) {
+        // z exchange to the layer below / above, 2/(dz_k (dz_k + dz_j)) (the
+        // flux between the centres per height of the layer), and 1/(2 dz_k)
+        // for the DMI difference; heights for the energies
+        const int nz = grid[2];
+        std::vector<double> zw(4 * nz, 0.0), lw(nz);
+        for (int k = 0; k < nz; ++k) {
+            const double hk = p->zb[k + 1] - p->zb[k];
+            lw[k] = hk;
+            if (k > 0) zw[4 * k] = 2.0 / (hk * (hk + (p->zb[k] - p->zb[k - 1])));
+            if (k + 1 < nz) zw[4 * k + 1] = 2.0 / (hk * (hk + (p->zb[k + 2] - p->zb[k + 1])));
+            zw[4 * k + 2] = 1.0 / (2.0 * hk);
+        }
+        hipError_t e1 = hipSuccess;
+        if (p->prec == MM_FP32) {
+            std::vector<float> zf(zw.begin(), zw.end());
+            e1 = hipMemcpy(p->zw, zf.data(), sizeof(float) * zf.size(), hipMemcpyHostToDevice);
+        } else {
+            e1 = hipMemcpy(p->zw, zw.data(), sizeof(double) * zw.size(), hipMemcpyHostToDevice);
+        }
+        if (e1 == hipSuccess)
+            e1 = hipMemcpy(p->lw, lw.data(), sizeof(double) * nz, hipMemcpyHostToDevice);
+        if (e1 != hipSuccess) {
+            free_plan(p);
+            return hip_fail(e1, "layer tables");
+        }
+    }
     hipError_t e = hipHostMalloc((void**)&p->host_out, sizeof(double) * 8, hipHostMallocDefault);
     if (e != hipSuccess) {
         free_plan(p);
@@ -762,6 +802,10 @@ static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hex
         set_error("per-cell exchange and DMI have no transposed operator");
         return MM_EINVAL;
     }
+    if (p->layered) {
+        set_error("thin layers of unequal height have no transposed operator");
+        return MM_EINVAL;
+    }
     mm_status s = ensure_adj(p);
     if (s != MM_OK) return s;
     T* h = nullptr;
@@ -803,7 +847,8 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
     }
     s = fetch(p, 5);
     if (s != MM_OK) return s;
-    const double V = p->d[0] * p->d[1] * p->d[2];
+    // thin layers: the reductions carry each layer's height
+    const double V = p->d[0] * p->d[1] * (p->layered ? 1.0 : p->d[2]);
     double tot = 0.0;
     for (int e = 0; e < 4; ++e) {
         E[e] = e == 2 ? V * p->host_out[e] : (e == 3 ? -1.0 : -0.5) * kMu0 * V * p->host_out[e];
@@ -832,6 +877,7 @@ void mm_opts_default(mm_opts* o)
     o->demag_p = 20;
     o->stream = nullptr;
     o->ku2 = o->kc1 = o->kc2 = 0.0;
+    o->dz_layers = nullptr;
     for (int a = 0; a < 3; ++a) {
         o->kc_axis1[a] = a == 0 ? 1.0 : 0.0;
         o->kc_axis2[a] = a == 1 ? 1.0 : 0.0;
@@ -885,6 +931,17 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
             set_error("ku2, kc1, kc2 must be finite and the cubic axes independent");
             return MM_EINVAL;
         }
+    }
+    if (o.dz_layers) {
+        if (grid[2] > kMaxLayers) {
+            set_error("thin layers: at most 16 layers");
+            return MM_EINVAL;
+        }
+        for (int k = 0; k < grid[2]; ++k)
+            if (!(o.dz_layers[k] > 0.0) || !std::isfinite(o.dz_layers[k])) {
+                set_error("layer heights must be positive and finite");
+                return MM_EINVAL;
+            }
     }
     Plan* p = nullptr;
     mm_status s = plan_build(grid, cell, Ms, A, Ku, alpha, o, nullptr, &p);
@@ -1203,8 +1260,8 @@ mm_status mm_rk4_adjoint(mm_plan* pl, const void* ckpt, const double h_ext[3], u
         set_error("higher-order anisotropy is not linear in m: no adjoint");
         return MM_EINVAL;
     }
-    if (p && stencil_extended(p, terms)) {
-        set_error("per-cell exchange and DMI have no adjoint");
+    if (p && (stencil_extended(p, terms) || p->layered)) {
+        set_error("per-cell exchange, DMI and thin layers have no adjoint");
         return MM_EINVAL;
     }
     if (!p || !ckpt || !region || nsteps <= 0 || !(dt > 0.0) || ckpt_every <= 0) {
@@ -1255,8 +1312,8 @@ mm_status mm_profile_read(mm_plan* pl, double ms[], long count[])
 mm_status mm_debug_kernel(mm_plan* pl, int s, void* out)
 {
     Plan* p = reinterpret_cast<Plan*>(pl);
-    if (!p || !out || s < 0 || s > 5) {
-        set_error("invalid argument");
+    if (!p || !out || s < 0 || s > 5 || p->layered) {
+        set_error("invalid argument (not available for thin layers)");
         return MM_EINVAL;
     }
     hipError_t e = debug_kernel(*p, s, (double*)out);
@@ -1267,8 +1324,8 @@ mm_status mm_debug_kernel(mm_plan* pl, int s, void* out)
 mm_status mm_debug_spectrum(mm_plan* pl, int s, void* out)
 {
     Plan* p = reinterpret_cast<Plan*>(pl);
-    if (!p || !out || s < 0 || s > 5) {
-        set_error("invalid argument");
+    if (!p || !out || s < 0 || s > 5 || p->layered) {
+        set_error("invalid argument (not available for thin layers)");
         return MM_EINVAL;
     }
     hipError_t e = p->prec == MM_FP32 ? debug_spectrum<float>(*p, s, (double*)out)

@@ -17,6 +17,7 @@ constexpr double kGamma = 2.21e5;
 
 // Largest padded FFT length per axis handled by the kernels.
 constexpr int kMaxFFT = 1024;
+constexpr int kMaxLayers = 16;  // thin layers of unequal height per plan
 
 constexpr int kRedSlots = 8192;
 
@@ -70,6 +71,10 @@ struct Plan {
     double D;        // uniform DMI strength (ignored with D_cell)
     bool percell_D;  // per-cell DMI strength present (D_cell)
     bool dmi_mixed;  // D_cell holds strengths of both signs
+    // thin layers of unequal height (Sec. 4.4): nz > 1 layers, no z padding;
+    // the demag spectrum is coupled densely across layers per (kx, ky)
+    bool layered = false;
+    std::vector<double> zb;  // layer bottoms, nz + 1 values (zb[0] = 0)
     double edmi[3][3];  // DMI vectors e^dmi_x, e^dmi_y, e^dmi_z
     long n_magnetic;  // magnetic cells (Ms > 0)
     // drive
@@ -85,6 +90,8 @@ struct Plan {
     void *Ms_cell = nullptr;  // N reals, or null
     void *A_cell = nullptr;   // N reals (per-cell exchange constant), or null
     void *D_cell = nullptr;   // N reals (per-cell DMI strength), or null
+    void *zw = nullptr;       // layered: 4 reals per layer (z exchange down/up, 1/(2 dz_k), 0)
+    double *lw = nullptr;     // layered: nz doubles, the layer heights (energy weights)
     unsigned char *mask = nullptr;  // N bytes drive mask, or null
     // Runge-Kutta work space (allocated on first use)
     void *rk = nullptr;       // 10 vectors of 3N

@@ -622,7 +622,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
     LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
-    const T* __restrict__ A_cell, const T* __restrict__ D_cell)
+    const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
     constexpr bool kMIX = EXT & EXT_MIX;
@@ -642,6 +642,16 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     const long N = P.N;
     const T exch = (T)P.exch, anis = (T)P.anis;
     const T ix2 = (T)P.idx2, iy2 = (T)P.idy2, iz2 = (T)P.idz2;
+    // z couplings of this block's layer: exchange to the layer below / above
+    // and the DMI difference scale (equal layers: 1/dz^2, 1/dz^2 and 1, the
+    // DMI vector of z being divided by 2 dz already; thin layers of unequal
+    // height: 2/(dz_k (dz_k + dz_k-+1)) and 1/(2 dz_k))
+    T wz_dn = iz2, wz_up = iz2, dz_s = (T)1;
+    if (zw) {
+        wz_dn = zw[4 * k];
+        wz_up = zw[4 * k + 1];
+        dz_s = zw[4 * k + 2];
+    }
     const T eux = (T)P.eu[0], euy = (T)P.eu[1], euz = (T)P.eu[2];
     double tmax = 0.0;
     for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
@@ -678,7 +688,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                     const long q = has ? (plus ? cell + off : cell - off) : cell;
                     const T qx = m[q], qy = m[N + q], qz = m[2 * N + q];
                     const bool ok = has && (!PERCELL || Ms_cell[q] != (T)0);
-                    T wq = ok ? (dir == 0 ? ix2 : dir == 1 ? iy2 : iz2) : (T)0;
+                    T wq = ok ? (dir == 0 ? ix2 : dir == 1 ? iy2 : plus ? wz_up : wz_dn) : (T)0;
                     if constexpr (kPA) wq *= harmonic2(Ai, A_cell[q]);
                     ax += wq * (qx - mx);
                     ay += wq * (qy - my);
@@ -686,6 +696,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                     if constexpr (kDMI) {
                         // D~ (e^dmi_k x m_{i+k}) / (2 Delta_k), e^dmi_{-k} = -e^dmi_k
                         T c = ok ? (plus ? (T)1 : (T)-1) : (T)0;
+                        if (dir == 2) c *= dz_s;
                         if constexpr (kMIX)
                             c *= dmi_avg(Di, D_cell[q]);
                         else if constexpr (kPD)
@@ -954,7 +965,7 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
     k_x_c2r_local<T, M, PC, EXT><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
         (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
-        (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr);
+        (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr);
     return hipGetLastError();
 }
 
@@ -1278,7 +1289,8 @@ struct AnisE {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
                                                         const T* __restrict__ Ms_cell, double Ms,
-                                                        long N, AnisE A, double* partials)
+                                                        long N, AnisE A, double* partials,
+                                                        const double* __restrict__ lw, long nxy)
 {
     double acc = 0.0;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
@@ -1290,8 +1302,9 @@ __global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
         double pr[3];
         for (int a = 0; a < 3; ++a) pr[a] = A.ec[a][0] * mx + A.ec[a][1] * my + A.ec[a][2] * mz;
         const double q0 = pr[0] * pr[0], q1 = pr[1] * pr[1], q2 = pr[2] * pr[2];
-        acc += -A.ku1 * em * em - A.ku2 * em * em * em * em + A.kc1 * (q0 * q1 + q1 * q2 + q2 * q0) +
-               A.kc2 * q0 * q1 * q2;
+        acc += (lw ? lw[q / nxy] : 1.0) *
+               (-A.ku1 * em * em - A.ku2 * em * em * em * em +
+                A.kc1 * (q0 * q1 + q1 * q2 + q2 * q0) + A.kc2 * q0 * q1 * q2);
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
@@ -1300,12 +1313,13 @@ __global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dot_ms(const T* __restrict__ a, const T* __restrict__ b,
                                                    const T* __restrict__ Ms_cell, double Ms,
-                                                   long N, double* partials)
+                                                   long N, double* partials,
+                                                   const double* __restrict__ lw, long nxy)
 {
     double acc = 0.0;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
          q += (long)gridDim.x * blockDim.x) {
-        const double ms = Ms_cell ? (double)Ms_cell[q] : Ms;
+        const double ms = (Ms_cell ? (double)Ms_cell[q] : Ms) * (lw ? lw[q / nxy] : 1.0);
         acc += ms * ((double)a[q] * b[q] + (double)a[N + q] * b[N + q] +
                      (double)a[2 * N + q] * b[2 * N + q]);
     }
@@ -1799,9 +1813,124 @@ hipError_t debug_kernel(Plan& p, int s, double* out)
     return hipStreamSynchronize(p.stream);
 }
 
+// Thin layers: near-field table of K^{ts}(I, J) for 0 <= I < nI, 0 <= J < nJ
+// and every layer pair with |t - s| <= p, all six components.
+__global__ void k_near_layer(double* __restrict__ near, int nI, int nJ, int nz,
+                             const double* __restrict__ zb, double dx, double dy, int p)
+{
+    const long per = (long)nz * nz * nJ * nI;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 6 * per) return;
+    const int comp = (int)(q / per);
+    const long o = q % per;
+    const int I = (int)(o % nI), J = (int)((o / nI) % nJ);
+    const int ts = (int)(o / ((long)nI * nJ));
+    const int t = ts / nz, s = ts % nz;
+    const int dts = t > s ? t - s : s - t;
+    near[q] = (p < 0 || dts <= p) ? kernel_near_layer(comp, I, J, zb, t, s, dx, dy) : 0.0;
+}
+
+// Place K^{ts}_comp into the zero-padded lateral grid (Px x Py).
+__global__ void k_place_layer(double* __restrict__ R, int comp, int t, int s, int nx, int ny,
+                              int nz, int Px, int Py, const double* __restrict__ near, int nI,
+                              int nJ, const double* __restrict__ zb, int p, double dx, double dy)
+{
+    const long total = (long)Px * Py;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int pi = (int)(q % Px), pj = (int)(q / Px);
+    auto off = [](int pp, int n, int P, int& o) {
+        if (pp < n) { o = pp; return true; }
+        if (pp > P - n) { o = pp - P; return true; }
+        return false;
+    };
+    int I, J;
+    double v = 0.0;
+    if (off(pi, nx, Px, I) && off(pj, ny, Py, J)) {
+        const int aI = I < 0 ? -I : I, aJ = J < 0 ? -J : J, dts = t > s ? t - s : s - t;
+        int cheb = aI > aJ ? aI : aJ;
+        cheb = cheb > dts ? cheb : dts;
+        if (p < 0 || cheb <= p) {
+            // lateral mirror symmetry: xy odd in x and y, xz odd in x, yz odd in y
+            double sg = 1.0;
+            if (comp == 3) sg = ((I < 0) != (J < 0)) ? -1.0 : 1.0;
+            if (comp == 4) sg = I < 0 ? -1.0 : 1.0;
+            if (comp == 5) sg = J < 0 ? -1.0 : 1.0;
+            v = sg * near[(((long)comp * nz + t) * nz + s) * nJ * nI + (long)aJ * nI + aI];
+        } else {
+            v = kernel_dipole_layer(comp, I, J, zb, t, s, dx, dy);
+        }
+    }
+    R[q] = v;
+}
+
+// Keep ky <= Py/2 of the lateral transform of one layer pair, scaled by
+// 1/(Px Py): the real part for xx, yy, zz, xy, the imaginary part for xz, yz
+// (odd in x only, so their transform is imaginary).
+template <typename T>
+__global__ void k_fold_layer(T* __restrict__ Khat, const cx<double>* __restrict__ C, int Hx,
+                             int Hxp, int Py, int imag, double scale)
+{
+    const int hy = Py / 2 + 1;
+    const long total = (long)hy * Hxp;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int kx = (int)(q % Hxp), ky = (int)(q / Hxp);
+    const cx<double> c = C[(long)ky * Hxp + kx];
+    Khat[q] = kx < Hx ? (T)((imag ? c.y : c.x) * scale) : (T)0;
+}
+
+template <typename T>
+static hipError_t build_tensor_layers(Plan& p)
+{
+    Scratch sc;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int lim = p.demag_p < 0 ? (1 << 30) : p.demag_p;
+    const int nI = std::min(nx - 1, lim) + 1, nJ = std::min(ny - 1, lim) + 1;
+    const int Px = p.P[0], Py = p.P[1];
+    const long PN = (long)Px * Py;
+    double *zb, *near, *R;
+    cx<double>* C;
+    cx<double>* tw64;
+    MMX_TRY(sc.get(&zb, sizeof(double) * (nz + 1)));
+    MMX_TRY(hipMemcpyAsync(zb, p.zb.data(), sizeof(double) * (nz + 1), hipMemcpyHostToDevice,
+                           p.stream));
+    const long ntab = 6L * nz * nz * nJ * nI;
+    MMX_TRY(sc.get(&near, sizeof(double) * ntab));
+    k_near_layer<<<blocks_for(ntab, 64), 64, 0, p.stream>>>(near, nI, nJ, nz, zb, p.d[0], p.d[1],
+                                                          p.demag_p);
+    MMX_TRY(hipGetLastError());
+    MMX_TRY(sc.get(&R, sizeof(double) * PN));
+    MMX_TRY(sc.get(&C, sizeof(cx<double>) * (long)Py * p.Hxp));
+    MMX_TRY(sc.get(&tw64, sizeof(cx<double>) * p.Lmax));
+    k_twiddles<double><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>(tw64, p.Lmax);
+    MMX_TRY(hipGetLastError());
+    Plan q = p;
+    q.tw = tw64;
+    const long hyx = (long)(Py / 2 + 1) * p.Hxp;
+    for (int comp = 0; comp < 6; ++comp)
+        for (int t = 0; t < nz; ++t)
+            for (int s = 0; s < nz; ++s) {
+                k_place_layer<<<blocks_for(PN, 256), 256, 0, p.stream>>>(
+                    R, comp, t, s, nx, ny, nz, Px, Py, near, nI, nJ, zb, p.demag_p, p.d[0], p.d[1]);
+                MMX_TRY(hipGetLastError());
+                MMX_TRY((launch_x_r2c<double, false>(q, Px / 2, R, Px, 0, Px, nullptr, 1.0, C,
+                                                     p.Hxp, 0, Py, 1)));
+                if (Py > 1)
+                    MMX_TRY((launch_strided<double, -1>(q, Py, C, C, Py, Py, p.Hxp, p.Hxp, p.Hx, 1,
+                                                        0, 0, 1, 0, 0)));
+                k_fold_layer<T><<<blocks_for(hyx, 256), 256, 0, p.stream>>>(
+                    (T*)p.Khat + comp * p.Kn + ((long)t * nz + s) * hyx, C, p.Hx, p.Hxp, Py,
+                    comp >= 4 ? 1 : 0, 1.0 / (double)PN);
+                MMX_TRY(hipGetLastError());
+            }
+    return hipStreamSynchronize(p.stream);
+}
+
 template <typename T>
 hipError_t build_tensor(Plan& p)
 {
+    if (p.layered) return build_tensor_layers<T>(p);
     Scratch sc;
     double* near;
     int nI, nJ, nK;
@@ -1871,6 +2000,75 @@ hipError_t debug_spectrum(Plan& p, int s, double* out)
 // Demag convolution up to the x spectrum: S1 <- spectrum of K (Ms src) (or of
 // K src with use_ms = false), i.e. every pass but the last inverse x
 // transform, which the caller fuses with its local terms.
+// ---------------------------------------------------------------------------
+// Thin layers: dense coupling of the layers per lateral frequency,
+//   h^_t(kx, ky) = sum_s K^^{ts}(kx, ky) M^_s(kx, ky),
+// in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  A block holds
+// 64 consecutive kx of one ky row: the spectra of all layers are staged in
+// LDS, then thread (kx, g) accumulates targets t = g, g + G, ... .  K^ is
+// [6][nz][nz][Py/2+1][Hxp]: xx, yy, zz, xy real, xz, yz imaginary (stored as
+// their imaginary part); rows ky > Py/2 use row Py - ky with the y-odd
+// components (xy, yz) negated.
+// ---------------------------------------------------------------------------
+constexpr int kZdMaxLayers = 16;
+
+template <typename T>
+__global__ __launch_bounds__(64 * kZdMaxLayers) void k_zdense(cx<T>* __restrict__ S,
+                                                              const T* __restrict__ K, int nz,
+                                                              int Py, int Hx, int Hxp, long s_comp,
+                                                              long k_comp)
+{
+    extern __shared__ unsigned char zd_smem[];
+    cx<T>* st = reinterpret_cast<cx<T>*>(zd_smem);  // [3][nz][64]
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6, G = blockDim.x >> 6;
+    const int kx = blockIdx.x * 64 + lane, ky = blockIdx.y;
+    const bool valid = kx < Hx;
+    for (int r = g; r < 3 * nz; r += G) {
+        const int c = r / nz, k = r - c * nz;
+        st[r * 64 + lane] = valid ? S[c * s_comp + ((long)k * Py + ky) * Hxp + kx] : cx<T>{0, 0};
+    }
+    __syncthreads();
+    if (!valid) return;
+    const bool upper = ky > Py / 2;
+    const int kyf = upper ? Py - ky : ky;
+    const T sy = upper ? (T)-1 : (T)1;
+    const long hy = Py / 2 + 1;
+    for (int t = g; t < nz; t += G) {
+        T hxr = 0, hxi = 0, hyr = 0, hyi = 0, hzr = 0, hzi = 0;
+        for (int sidx = 0; sidx < nz; ++sidx) {
+            const long kb = (((long)t * nz + sidx) * hy + kyf) * Hxp + kx;
+            const T kxx = K[kb], kyy = K[k_comp + kb], kzz = K[2 * k_comp + kb];
+            const T kxy = sy * K[3 * k_comp + kb];
+            const T vxz = K[4 * k_comp + kb], vyz = sy * K[5 * k_comp + kb];  // K^ = i v
+            const cx<T> Mx = st[sidx * 64 + lane], My = st[(nz + sidx) * 64 + lane],
+                        Mz = st[(2 * nz + sidx) * 64 + lane];
+            // real parts times M, plus i v times M = (-v M.im, v M.re)
+            hxr += kxx * Mx.x + kxy * My.x - vxz * Mz.y;
+            hxi += kxx * Mx.y + kxy * My.y + vxz * Mz.x;
+            hyr += kxy * Mx.x + kyy * My.x - vyz * Mz.y;
+            hyi += kxy * Mx.y + kyy * My.y + vyz * Mz.x;
+            hzr += kzz * Mz.x - vxz * Mx.y - vyz * My.y;
+            hzi += kzz * Mz.y + vxz * Mx.x + vyz * My.x;
+        }
+        const long o = ((long)t * Py + ky) * Hxp + kx;
+        S[o] = {hxr, hxi};
+        S[s_comp + o] = {hyr, hyi};
+        S[2 * s_comp + o] = {hzr, hzi};
+    }
+}
+
+template <typename T>
+static hipError_t launch_zdense(Plan& p, cx<T>* S)
+{
+    const int nz = p.n[2], Py = p.P[1];
+    const int G = nz < kZdMaxLayers ? nz : kZdMaxLayers;
+    dim3 grid((unsigned)((p.Hx + 63) / 64), (unsigned)Py);
+    const size_t lds = sizeof(cx<T>) * 3 * nz * 64;
+    k_zdense<T><<<grid, 64 * G, lds, p.stream>>>(S, (const T*)p.Khat, nz, Py, p.Hx, p.Hxp,
+                                                 (long)nz * Py * p.Hxp, p.Kn);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
 {
@@ -1888,7 +2086,20 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
                   : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, ms, S1, p.Hxp, s1c,
                                            ny * nz, 3);
     }));
-    if (Pz > 1) {
+    if (p.layered) {
+        const long s2c = (long)nz * Py * p.Hxp;
+        if (Py > 1)
+            MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
+                return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s2c,
+                                             nz, (long)ny * p.Hxp, (long)Py * p.Hxp);
+            }));
+        MMX_TRY(timed(p, MM_PASS_MID, [&] { return launch_zdense<T>(p, Py > 1 ? S2 : S1); }));
+        if (Py > 1)
+            MMX_TRY(timed(p, MM_PASS_Y_INV, [&] {
+                return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c, s1c,
+                                            nz, (long)Py * p.Hxp, (long)ny * p.Hxp);
+            }));
+    } else if (Pz > 1) {
         const long s2c = (long)nz * Py * p.Hxp;
         if (Py > 1)
             MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
@@ -1938,7 +2149,8 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
                     (P.with_dmi && p.percell_D && p.dmi_mixed ? EXT_MIX : 0);
     P.dmi = 2.0 * ((ext & EXT_PD) ? 1.0 : p.D) / kMu0;
     for (int k = 0; k < 3; ++k)
-        for (int a = 0; a < 3; ++a) P.edmi[k][a] = p.edmi[k][a] / (2.0 * p.d[k]);
+        for (int a = 0; a < 3; ++a)
+            P.edmi[k][a] = p.edmi[k][a] / (k == 2 && p.layered ? 1.0 : 2.0 * p.d[k]);
     P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
     P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi) ? 1 : 0;
     P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
@@ -2123,7 +2335,8 @@ hipError_t anis_energy(Plan& p, const T* m, double* out_dev)
         for (int b = 0; b < 3; ++b) A.ec[a][b] = p.ec[a][b];
     }
     k_anis_energy<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
-        m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, p.red);
+        m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, p.red,
+        p.layered ? p.lw : nullptr, (long)p.n[0] * p.n[1]);
     MMX_TRY(hipGetLastError());
     k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();
@@ -2133,7 +2346,8 @@ template <typename T>
 hipError_t dot_ms(Plan& p, const T* a, const T* b, double* out_dev)
 {
     k_dot_ms<T><<<kRedBlocks, kBlock, 0, p.stream>>>(a, b, p.percell ? (const T*)p.Ms_cell : nullptr,
-                                                     p.Ms, p.N, p.red);
+                                                     p.Ms, p.N, p.red, p.layered ? p.lw : nullptr,
+                                                     (long)p.n[0] * p.n[1]);
     MMX_TRY(hipGetLastError());
     k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();

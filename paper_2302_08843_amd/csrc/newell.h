@@ -142,6 +142,117 @@ __host__ __device__ inline double kernel_dipole(int s, int I, int J, int K, doub
     }
 }
 
+// ---------------------------------------------------------------------------
+// Thin layers of unequal height (Sec. 4.4, non-equidistant case).  Along an
+// axis where the target spans [0, t] and the source [B, B + s], the double
+// integral of a second derivative F'' is F(B + s) - F(B + s - t) - F(B) +
+// F(B - t); with t = s it is the second difference of the equal-cell stencil.
+// The entry is normalised by the target volume.
+struct AxisPts {
+    dd x[4];
+    double w[4];  // sign of Newell's equal-cell stencil (positive self term)
+    int n;
+};
+
+// Equal cells along a lateral axis: offset I cells of size a (source minus
+// target), the three points (I - 1) a, I a, (I + 1) a, exact in double-double.
+__host__ __device__ inline AxisPts axis_equal(int I, double a)
+{
+    AxisPts r;
+    r.n = 3;
+    r.x[0] = two_prod((double)(I - 1), a);
+    r.w[0] = -1.0;
+    r.x[1] = two_prod((double)I, a);
+    r.w[1] = 2.0;
+    r.x[2] = two_prod((double)(I + 1), a);
+    r.w[2] = -1.0;
+    r.x[3] = dd_from(0.0);
+    r.w[3] = 0.0;
+    return r;
+}
+
+// Unequal heights: source bottom B above the target bottom, target height t,
+// source height s.
+__host__ __device__ inline AxisPts axis_layer(dd B, double t, double s)
+{
+    AxisPts r;
+    r.n = 4;
+    r.x[0] = dd_add(B, dd_from(s));
+    r.w[0] = -1.0;
+    r.x[1] = dd_sub(dd_add(B, dd_from(s)), dd_from(t));
+    r.w[1] = 1.0;
+    r.x[2] = B;
+    r.w[2] = 1.0;
+    r.x[3] = dd_sub(B, dd_from(t));
+    r.w[3] = -1.0;
+    return r;
+}
+
+// Stencil sum of f (which 0) or g (which 1) over the argument slots (u, v, q)
+// divided by den; g is odd in its first two arguments, f even in all.
+__host__ __device__ inline double box_component(int which, const AxisPts& u, const AxisPts& v,
+                                                const AxisPts& q, dd den)
+{
+    dd acc = dd_from(0.0);
+    for (int a = 0; a < u.n; ++a)
+        for (int b = 0; b < v.n; ++b)
+            for (int e = 0; e < q.n; ++e) {
+                dd X = u.x[a], Y = v.x[b], Z = q.x[e];
+                double sg = u.w[a] * v.w[b] * q.w[e];
+                if (X.hi < 0.0) {
+                    X = dd_neg(X);
+                    if (which == 1) sg = -sg;
+                }
+                if (Y.hi < 0.0) {
+                    Y = dd_neg(Y);
+                    if (which == 1) sg = -sg;
+                }
+                if (Z.hi < 0.0) Z = dd_neg(Z);
+                dd val = which == 0 ? newell_f(X, Y, Z) : newell_g(X, Y, Z);
+                acc = dd_add(acc, dd_mul_d(val, sg));
+            }
+    dd r = dd_div(acc, den);
+    return r.hi + r.lo;
+}
+
+// Layered demag kernel entry K^{ts}_s (h_t = sum K M_s) near field, -N, for
+// the lateral offset I = i_t - i_s, J = j_t - j_s and the layer bottoms zb.
+__host__ __device__ inline double kernel_near_layer(int comp, int I, int J, const double* zb, int t,
+                                                    int s, double dx, double dy)
+{
+    const double ct = zb[t + 1] - zb[t], cs = zb[s + 1] - zb[s];
+    const AxisPts X = axis_equal(-I, dx), Y = axis_equal(-J, dy);
+    const AxisPts Z = axis_layer(two_sum(zb[s], -zb[t]), ct, cs);
+    const dd den = dd_mul_d(dd_mul_d(dd_mul_d(dd_mul_d(dd_pi(), 4.0), dx), dy), ct);
+    switch (comp) {
+    case 0: return -box_component(0, X, Y, Z, den);
+    case 1: return -box_component(0, Y, X, Z, den);
+    case 2: return -box_component(0, Z, Y, X, den);
+    case 3: return -box_component(1, X, Y, Z, den);
+    case 4: return -box_component(1, X, Z, Y, den);
+    default: return -box_component(1, Y, Z, X, den);
+    }
+}
+
+// Layered far field: the dipole of the source cell's moment (volume
+// dx dy dz_s) at the centre offset (target minus source).
+__host__ __device__ inline double kernel_dipole_layer(int comp, int I, int J, const double* zb,
+                                                      int t, int s, double dx, double dy)
+{
+    const double rx = I * dx, ry = J * dy;
+    const double rz = 0.5 * (zb[t] + zb[t + 1]) - 0.5 * (zb[s] + zb[s + 1]);
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double pre = dx * dy * (zb[s + 1] - zb[s]) / (4.0 * M_PI) / (r2 * r2 * sqrt(r2));
+    switch (comp) {
+    case 0: return pre * (3.0 * rx * rx - r2);
+    case 1: return pre * (3.0 * ry * ry - r2);
+    case 2: return pre * (3.0 * rz * rz - r2);
+    case 3: return pre * 3.0 * rx * ry;
+    case 4: return pre * 3.0 * rx * rz;
+    default: return pre * 3.0 * ry * rz;
+    }
+}
+
 }  // namespace mmx
 
 // restore the compiler default for the code that follows

@@ -76,7 +76,8 @@ class mm_serve_stats(C.Structure):
 class mm_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("ku_axis", C.c_double * 3), ("demag_p", C.c_int),
                 ("stream", C.c_void_p), ("ku2", C.c_double), ("kc1", C.c_double),
-                ("kc2", C.c_double), ("kc_axis1", C.c_double * 3), ("kc_axis2", C.c_double * 3)]
+                ("kc2", C.c_double), ("kc_axis1", C.c_double * 3), ("kc_axis2", C.c_double * 3),
+                ("dz_layers", C.POINTER(C.c_double))]
 
 
 class mm_step_opts(C.Structure):
@@ -365,7 +366,8 @@ class Plan:
     """A plan on the current CUDA (HIP) device; see mm_plan_create."""
 
     def __init__(self, grid, cell, Ms, A=0.0, Ku=0.0, alpha=0.5, prec="fp64", ku_axis=(0, 0, 1),
-                 demag_p=20, stream=None, Ku2=0.0, Kc1=0.0, Kc2=0.0, kc_axes=((1, 0, 0), (0, 1, 0))):
+                 demag_p=20, stream=None, Ku2=0.0, Kc1=0.0, Kc2=0.0, kc_axes=((1, 0, 0), (0, 1, 0)),
+                 layers=None):
         import torch
 
         self.grid = tuple(int(v) for v in grid)
@@ -384,6 +386,12 @@ class Plan:
             o.kc_axis1[a] = float(kc_axes[0][a])
             o.kc_axis2[a] = float(kc_axes[1][a])
         self._stream = stream
+        self.layers = None
+        if layers is not None:
+            # thin layers of unequal height (read during creation only)
+            self.layers = np.ascontiguousarray(np.asarray(layers, dtype=np.float64))
+            assert self.layers.shape == (self.grid[2],), "one height per layer"
+            o.dz_layers = self.layers.ctypes.data_as(C.POINTER(C.c_double))
         self.handle = mm_plan_create(self.grid, self.cell, Ms, A, Ku, alpha, o)
         nx, ny, nz = self.grid
         self.shape = (3, nz, ny, nx)
