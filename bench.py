@@ -143,6 +143,55 @@ def extended_stencil(mm, plan, m, cfg, iters):
             "terms": "demag + per-cell exchange + per-cell interface DMI"}
 
 
+def zdense_bytes(grid, prec):
+    """Algorithmic HBM bytes per launch of the dense layer-coupling pass: the
+    kernel spectra 6 nz^2 (Py/2+1) Hx reals, the y-transformed spectrum
+    3 nz Py Hx complex read and written."""
+    nx, ny, nz = grid
+    Px = 1 if nx == 1 else 1 << (2 * nx - 2).bit_length()
+    Py = 1 if ny == 1 else 1 << (2 * ny - 2).bit_length()
+    hx = Px // 2 + 1 if Px > 1 else 1
+    w = 4 if prec == "fp32" else 8
+    return 6 * nz * nz * (Py // 2 + 1) * hx * w + 2 * 3 * nz * Py * hx * 2 * w
+
+
+def layers(mm, W, iters):
+    """Field evaluation of the thin-layer form (unequal heights, dense layer
+    coupling) on 512 x 512 x 8, FP32, beside the equidistant plan of the same
+    grid (zero-padded 3-D convolution)."""
+    import torch
+
+    cfg = W.config_layers()
+    grid = cfg["n"]
+    out = {}
+    for name, lay in (("layers", cfg["dz"]), ("equidistant", None)):
+        plan = mm.Plan(grid, cfg["d"], Ms=cfg["Ms"], A=cfg["A"], alpha=cfg["alpha"], prec="fp32",
+                       layers=lay)
+        m = plan._t(cfg["m0"])
+        h = plan.empty()
+        for _ in range(3):
+            plan.heff(m, None, cfg["terms"], out=h)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            plan.heff(m, None, cfg["terms"], out=h)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / iters
+        prof = plan.profile_read()
+        plan.profile(False)
+        out[name] = (wall, {k: 1e3 * v[0] / v[1] for k, v in prof.items() if v[1]})
+        del plan, m, h
+        torch.cuda.empty_cache()
+    zb = zdense_bytes(grid, "fp32")
+    zus = out["layers"][1]["mid"]
+    return {"grid": list(grid), "dz_nm": [round(v * 1e9, 4) for v in cfg["dz"]],
+            "heff_ms": 1e3 * out["layers"][0], "passes_us": out["layers"][1],
+            "zdense_us": zus, "zdense_model_bytes": zb, "zdense_GBs": zb / (zus * 1e-6) / 1e9,
+            "equidistant_heff_ms": 1e3 * out["equidistant"][0],
+            "equidistant_passes_us": out["equidistant"][1]}
+
+
 def _serve_once(mm, reqs, states, arrivals, opts):
     """Run the request server over `reqs` (start states already in HBM) with
     the given arrival offsets (s); returns completions, makespan and stats."""
@@ -265,6 +314,10 @@ def main():
     ap.add_argument("--heff-iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-layers", dest="layers", action="store_false",
+                    help="skip the thin-layer field evaluation")
+    ap.add_argument("--layers-only", action="store_true",
+                    help="only the thin-layer field evaluation (profiling its kernels alone)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving sample (0: skip serving)")
     ap.add_argument("--serve-max-steps", type=int, default=4000)
@@ -295,6 +348,9 @@ def main():
         print("[bench] calibration copy: 3 x (1 GiB read + 1 GiB write)", file=sys.stderr,
               flush=True)
         del a, b
+    if args.layers_only:
+        print(json.dumps({"layers_fp32": layers(mm, W, args.heff_iters)}), flush=True)
+        return
     grid = tuple(int(v) for v in args.grid.split(","))
     cfg = W.config_large(n=grid)
     N = int(np.prod(grid))
@@ -374,6 +430,9 @@ def main():
                              "rejected": rf["stats"]["rejected"]}
     if "ext" in res:
         out["extended_stencil_fp32"] = res["ext"]
+    if args.layers:
+        print("[bench] thin layers 512x512x8", file=sys.stderr, flush=True)
+        out["layers_fp32"] = layers(mm, W, args.heff_iters)
     if "fp64" in res:
         r64 = res["fp64"]
         out["fp64"] = {"value": r64["stats"]["rhs_evals"] * N / r64["wall"],

@@ -2003,68 +2003,87 @@ hipError_t debug_spectrum(Plan& p, int s, double* out)
 // ---------------------------------------------------------------------------
 // Thin layers: dense coupling of the layers per lateral frequency,
 //   h^_t(kx, ky) = sum_s K^^{ts}(kx, ky) M^_s(kx, ky),
-// in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  A block holds
-// 64 consecutive kx of one ky row: the spectra of all layers are staged in
-// LDS, then thread (kx, g) accumulates targets t = g, g + G, ... .  K^ is
+// in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  K^ is
 // [6][nz][nz][Py/2+1][Hxp]: xx, yy, zz, xy real, xz, yz imaginary (stored as
-// their imaginary part); rows ky > Py/2 use row Py - ky with the y-odd
-// components (xy, yz) negated.
+// their imaginary part); row Py - ky uses row ky with the y-odd components
+// (xy, yz) negated.  A block holds TW consecutive kx of the row pair (ky,
+// Py - ky), so every kernel row is read once for both: the spectra of all
+// layers of both rows are staged in LDS, then thread (kx, g) accumulates
+// targets t = g, g + G, ... .
 // ---------------------------------------------------------------------------
 constexpr int kZdMaxLayers = 16;
 
 template <typename T>
-__global__ __launch_bounds__(64 * kZdMaxLayers) void k_zdense(cx<T>* __restrict__ S,
-                                                              const T* __restrict__ K, int nz,
-                                                              int Py, int Hx, int Hxp, long s_comp,
-                                                              long k_comp)
+struct ZdTile {
+    static constexpr int kTW = sizeof(T) == 4 ? 64 : 32;  // kx per block
+};
+
+template <typename T>
+__global__ __launch_bounds__(ZdTile<T>::kTW * kZdMaxLayers) void k_zdense(
+    cx<T>* __restrict__ S, const T* __restrict__ K, int nz, int Py, int Hx, int Hxp, long s_comp,
+    long k_comp)
 {
+    constexpr int TW = ZdTile<T>::kTW;
     extern __shared__ unsigned char zd_smem[];
-    cx<T>* st = reinterpret_cast<cx<T>*>(zd_smem);  // [3][nz][64]
-    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6, G = blockDim.x >> 6;
-    const int kx = blockIdx.x * 64 + lane, ky = blockIdx.y;
+    cx<T>* st = reinterpret_cast<cx<T>*>(zd_smem);  // [row][3][nz][TW]
+    const int lane = threadIdx.x % TW, g = threadIdx.x / TW, G = blockDim.x / TW;
+    const int kx = blockIdx.x * TW + lane, ky = blockIdx.y, ky2 = Py - ky;
+    const bool pair = ky > 0 && 2 * ky < Py;
     const bool valid = kx < Hx;
-    for (int r = g; r < 3 * nz; r += G) {
-        const int c = r / nz, k = r - c * nz;
-        st[r * 64 + lane] = valid ? S[c * s_comp + ((long)k * Py + ky) * Hxp + kx] : cx<T>{0, 0};
+    const int per_row = 3 * nz;
+    for (int r = g; r < (pair ? 2 : 1) * per_row; r += G) {
+        const int row = r / per_row, rem = r - row * per_row;
+        const int c = rem / nz, k = rem - c * nz;
+        const int y = row ? ky2 : ky;
+        st[r * TW + lane] = valid ? S[c * s_comp + ((long)k * Py + y) * Hxp + kx] : cx<T>{0, 0};
     }
     __syncthreads();
     if (!valid) return;
-    const bool upper = ky > Py / 2;
-    const int kyf = upper ? Py - ky : ky;
-    const T sy = upper ? (T)-1 : (T)1;
     const long hy = Py / 2 + 1;
     for (int t = g; t < nz; t += G) {
-        T hxr = 0, hxi = 0, hyr = 0, hyi = 0, hzr = 0, hzi = 0;
+        T a[6] = {0, 0, 0, 0, 0, 0}, b[6] = {0, 0, 0, 0, 0, 0};
         for (int sidx = 0; sidx < nz; ++sidx) {
-            const long kb = (((long)t * nz + sidx) * hy + kyf) * Hxp + kx;
+            const long kb = (((long)t * nz + sidx) * hy + ky) * Hxp + kx;
             const T kxx = K[kb], kyy = K[k_comp + kb], kzz = K[2 * k_comp + kb];
-            const T kxy = sy * K[3 * k_comp + kb];
-            const T vxz = K[4 * k_comp + kb], vyz = sy * K[5 * k_comp + kb];  // K^ = i v
-            const cx<T> Mx = st[sidx * 64 + lane], My = st[(nz + sidx) * 64 + lane],
-                        Mz = st[(2 * nz + sidx) * 64 + lane];
-            // real parts times M, plus i v times M = (-v M.im, v M.re)
-            hxr += kxx * Mx.x + kxy * My.x - vxz * Mz.y;
-            hxi += kxx * Mx.y + kxy * My.y + vxz * Mz.x;
-            hyr += kxy * Mx.x + kyy * My.x - vyz * Mz.y;
-            hyi += kxy * Mx.y + kyy * My.y + vyz * Mz.x;
-            hzr += kzz * Mz.x - vxz * Mx.y - vyz * My.y;
-            hzi += kzz * Mz.y + vxz * Mx.x + vyz * My.x;
+            const T kxy = K[3 * k_comp + kb], vxz = K[4 * k_comp + kb], vyz = K[5 * k_comp + kb];
+            // K^ M with the real xx, yy, zz, xy and i v for xz, yz:
+            // (i v) M = (-v M.im, v M.re); row Py - ky negates xy and yz
+            auto acc = [&](T* h, const cx<T>* Mrow, T sy) {
+                const cx<T> Mx = Mrow[sidx * TW], My = Mrow[(nz + sidx) * TW],
+                            Mz = Mrow[(2 * nz + sidx) * TW];
+                const T cxy = sy * kxy, cyz = sy * vyz;
+                h[0] += kxx * Mx.x + cxy * My.x - vxz * Mz.y;
+                h[1] += kxx * Mx.y + cxy * My.y + vxz * Mz.x;
+                h[2] += cxy * Mx.x + kyy * My.x - cyz * Mz.y;
+                h[3] += cxy * Mx.y + kyy * My.y + cyz * Mz.x;
+                h[4] += kzz * Mz.x - vxz * Mx.y - cyz * My.y;
+                h[5] += kzz * Mz.y + vxz * Mx.x + cyz * My.x;
+            };
+            acc(a, st + lane, (T)1);
+            if (pair) acc(b, st + per_row * TW + lane, (T)-1);
         }
         const long o = ((long)t * Py + ky) * Hxp + kx;
-        S[o] = {hxr, hxi};
-        S[s_comp + o] = {hyr, hyi};
-        S[2 * s_comp + o] = {hzr, hzi};
+        S[o] = {a[0], a[1]};
+        S[s_comp + o] = {a[2], a[3]};
+        S[2 * s_comp + o] = {a[4], a[5]};
+        if (pair) {
+            const long o2 = ((long)t * Py + ky2) * Hxp + kx;
+            S[o2] = {b[0], b[1]};
+            S[s_comp + o2] = {b[2], b[3]};
+            S[2 * s_comp + o2] = {b[4], b[5]};
+        }
     }
 }
 
 template <typename T>
 static hipError_t launch_zdense(Plan& p, cx<T>* S)
 {
+    constexpr int TW = ZdTile<T>::kTW;
     const int nz = p.n[2], Py = p.P[1];
     const int G = nz < kZdMaxLayers ? nz : kZdMaxLayers;
-    dim3 grid((unsigned)((p.Hx + 63) / 64), (unsigned)Py);
-    const size_t lds = sizeof(cx<T>) * 3 * nz * 64;
-    k_zdense<T><<<grid, 64 * G, lds, p.stream>>>(S, (const T*)p.Khat, nz, Py, p.Hx, p.Hxp,
+    dim3 grid((unsigned)((p.Hx + TW - 1) / TW), (unsigned)(Py / 2 + 1));
+    const size_t lds = sizeof(cx<T>) * 2 * 3 * nz * TW;
+    k_zdense<T><<<grid, TW * G, lds, p.stream>>>(S, (const T*)p.Khat, nz, Py, p.Hx, p.Hxp,
                                                  (long)nz * Py * p.Hxp, p.Kn);
     return hipGetLastError();
 }

@@ -121,6 +121,18 @@ def config_large(n=(512, 512, 64), seed: int = 0):
                 terms=1 | 2)
 
 
+def config_layers(n=(512, 512, 8), seed: int = 0):
+    """Thin-layer case (the non-equidistant form of Sec. 4.4): 512x512 cells
+    of 4 nm laterally, 8 layers of heights drawn from U[0.5, 4] nm (a
+    multilayer stack with thin spacers), Ms 1e6, A 1.5e-11, alpha 0.02,
+    vortex domains."""
+    d = (4e-9, 4e-9, 4e-9)
+    dz = rng(seed + 1).uniform(0.5e-9, 4e-9, n[2])
+    return dict(name="layers_%dx%dx%d" % n, n=n, d=d, dz=dz, Ms=1e6, A=1.5e-11, Ku=0.0,
+                eu=(0.0, 0.0, 1.0), alpha=0.02, H=np.zeros(3), m0=vortex_domains(n, d, 16, seed),
+                terms=1 | 2)
+
+
 SERVING_GRIDS = [(64, 64, 1), (128, 128, 2), (256, 64, 4), (256, 256, 8)]
 
 
