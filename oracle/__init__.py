@@ -25,8 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mmref.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DEMAG, EXCH, ANIS, ZEEMAN, DMI = 1, 2, 4, 8, 16
-ALL = DEMAG | EXCH | ANIS | ZEEMAN | DMI
+DEMAG, EXCH, ANIS, ZEEMAN, DMI, OERSTED = 1, 2, 4, 8, 16, 32
+ALL = DEMAG | EXCH | ANIS | ZEEMAN | DMI | OERSTED
 DMI_INTERFACE, DMI_BULK, DMI_D2D = 0, 1, 2
 MU0 = 4.0e-7 * np.pi
 GAMMA = 2.21e5
@@ -79,6 +79,11 @@ def lib():
         L.or_set_anisotropy2.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp, dp]
         L.or_set_dmi.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
         L.or_set_layers.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_oersted_entry.argtypes = [dp, C.c_long, C.c_long, C.c_long, C.c_int, dp]
+        L.or_oersted.argtypes = [C.c_void_p, dp, dp]
+        L.or_oersted.restype = C.c_int
+        L.or_set_current.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
+        L.or_set_current.restype = C.c_int
         L.or_newell_box.argtypes = [C.c_double, C.c_double, C.c_long, C.c_long, C.c_double,
                                     C.c_double, C.c_double, dp]
         L.or_layer_entry.argtypes = [C.c_double, C.c_double, dp, C.c_long, C.c_long, C.c_long,
@@ -183,6 +188,15 @@ def layer_entry(dx, dy, dz, t, s, I, J, p=20) -> np.ndarray:
     out = np.zeros(6)
     lib().or_layer_entry(float(dx), float(dy), _dp(zb), int(t), int(s), int(I), int(J), int(p),
                          _dp(out))
+    return out
+
+
+def oersted_entry(d, I, J, K, p=20) -> np.ndarray:
+    """Oersted kernel G (h_t = sum_s j_s x G(X_t - X_s)) for the cell offset
+    (I, J, K) (target minus source): the cell-averaged Biot-Savart vector
+    within Chebyshev index distance p, the singular current beyond."""
+    out = np.zeros(3)
+    lib().or_oersted_entry(_dp(_d3(d)), int(I), int(J), int(K), int(p), _dp(out))
     return out
 
 
@@ -307,6 +321,26 @@ class Oracle:
     def anisotropy(self, m):
         """First-order uniaxial anisotropy field (Sec. 4.1)."""
         return self._field("or_anisotropy", m)
+
+    def oersted(self, j):
+        """Oersted field (Sec. 4.5) of the current density j (A/m^2,
+        (3, nz, ny, nx)) at every cell, by direct summation."""
+        j = self._m(j)
+        h = np.zeros_like(j)
+        if lib().or_oersted(self._c, _dp(j), _dp(h)) != 0:
+            raise ValueError("the Oersted field needs equal layers")
+        return h
+
+    def set_current(self, j, freq=0.0):
+        """Current density for the OERSTED term: its field, times
+        sin(2 pi freq t) if freq != 0, joins the effective field on magnetic
+        cells (and the Zeeman energy).  None removes it."""
+        if j is None:
+            lib().or_set_current(self._c, None, 0.0)
+            return
+        self._j = self._m(j).copy()
+        if lib().or_set_current(self._c, self._j.ctypes.data, float(freq)) != 0:
+            raise ValueError("the Oersted field needs equal layers")
 
     def dmi(self, m):
         """DMI field by central differences with the averaged coupling D~

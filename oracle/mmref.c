@@ -39,7 +39,7 @@
 #define OR_GAMMA 2.21e5
 #define OR_PI_L 3.141592653589793238462643383279502884L
 
-enum { OR_DEMAG = 1, OR_EXCH = 2, OR_ANIS = 4, OR_ZEEMAN = 8, OR_DMI = 16 };
+enum { OR_DEMAG = 1, OR_EXCH = 2, OR_ANIS = 4, OR_ZEEMAN = 8, OR_DMI = 16, OR_OERSTED = 32 };
 
 /* ------------------------------------------------------------------------- */
 /* Newell, Williams & Dunlop (1993) cell-averaged demagnetisation tensor,     */
@@ -267,6 +267,84 @@ void or_layer_entry(double dx, double dy, const double *zb, long t, long s, long
     out[5] = pre * 3.0 * r[1] * r[2];
 }
 
+/* ------------------------------------------------------------------------- */
+/* Oersted field (Sec. 4.5): the Biot-Savart field of a current density j,    */
+/* h(x) = (1/4 pi) int j(x') x (x - x') / |x - x'|^3 dx'.  For cells of       */
+/* uniform j the cell-averaged field is h_t = sum_s j_s x G(X_t - X_s) with   */
+/* G(D) = (1/(4 pi V)) int_t int_s (x - x') / |x - x'|^3 dx' dx, the average  */
+/* over the target of the field of a uniformly "charged" source box.  Along   */
+/* its own axis G_l is a first derivative, so its stencil uses the            */
+/* antiderivative F = int f dx of Newell's f along that axis, with Newell's   */
+/* 27-point second-difference weights (Krueger et al. solve the same         */
+/* integrals analytically).  Far field: the singular current density,        */
+/* G = V D / (4 pi |D|^3).  Pinned by the point-current limit, the self term, */
+/* antisymmetry, refinement consistency and the finite straight wire          */
+/* (tests/test_oracle_oersted.py).                                            */
+/* ------------------------------------------------------------------------- */
+
+/* F(x, y, z) = int_0^x f(u, y, z) du for y, z >= 0: odd in x. */
+static long double oersted_F(long double x, long double y, long double z)
+{
+    y = fabsl(y);
+    z = fabsl(z);
+    long double x2 = x * x, y2 = y * y, z2 = z * z, r2 = y2 + z2;
+    long double R = sqrtl(x2 + y2 + z2);
+    if (R == 0.0L)
+        return 0.0L;
+    long double s = x * R * R * R / 12.0L - 5.0L / 24.0L * r2 * x * R;
+    if (r2 > 0.0L)
+        s += (y2 * z2 / 3.0L - r2 * r2 / 24.0L) * asinhl(x / sqrtl(r2));
+    if (x2 + z2 > 0.0L)
+        s += 0.5L * y * (x * z2 - x * x2 / 3.0L) * asinhl(y / sqrtl(x2 + z2));
+    if (x2 + y2 > 0.0L)
+        s += 0.5L * z * (x * y2 - x * x2 / 3.0L) * asinhl(z / sqrtl(x2 + y2));
+    if (x != 0.0L)
+        s -= 0.5L * x2 * y * z * atanl(y * z / (x * R));
+    if (z != 0.0L)
+        s -= y * z * z2 / 6.0L * atanl(x * y / (z * R));
+    if (y != 0.0L)
+        s -= y * y2 * z / 6.0L * atanl(x * z / (y * R));
+    return s;
+}
+
+/* G_l(D) for the cell offset D = (I dx, J dy, K dz) (target minus source),
+ * near field. */
+static void oersted_near(const double d[3], long oi, long oj, long ok, double out[3])
+{
+    long double D[3] = {oi * (long double)d[0], oj * (long double)d[1], ok * (long double)d[2]};
+    for (int l = 0; l < 3; l++) {
+        int u = (l + 1) % 3, v = (l + 2) % 3;
+        long double acc = 0.0L;
+        for (int e0 = -1; e0 <= 1; e0++)
+            for (int e1 = -1; e1 <= 1; e1++)
+                for (int e2 = -1; e2 <= 1; e2++) {
+                    long double w = (e0 == 0 ? 2.0L : -1.0L) * (e1 == 0 ? 2.0L : -1.0L) *
+                                    (e2 == 0 ? 2.0L : -1.0L);
+                    acc += w * oersted_F(D[l] + e0 * (long double)d[l], D[u] + e1 * (long double)d[u],
+                                         D[v] + e2 * (long double)d[v]);
+                }
+        out[l] = (double)(acc / (4.0L * OR_PI_L * d[0] * d[1] * d[2]));
+    }
+}
+
+/* Oersted kernel G(I, J, K): near field within Chebyshev index distance p
+ * (p < 0: everywhere), else the singular current density. */
+void or_oersted_entry(const double d[3], long oi, long oj, long ok, int p, double out[3])
+{
+    long cheb = labs(oi);
+    if (labs(oj) > cheb) cheb = labs(oj);
+    if (labs(ok) > cheb) cheb = labs(ok);
+    if (p < 0 || cheb <= p) {
+        oersted_near(d, oi, oj, ok, out);
+        return;
+    }
+    double D[3] = {oi * d[0], oj * d[1], ok * d[2]};
+    double r2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    double pre = d[0] * d[1] * d[2] / (4.0 * M_PI) / (r2 * sqrt(r2));
+    for (int l = 0; l < 3; l++)
+        out[l] = pre * D[l];
+}
+
 /* Demagnetisation field at selected target cells by direct summation of the
  * discrete convolution h_i = sum_j K_{i-j} Ms_j m_j (Sec. 4.4) over every
  * source cell -- no padded grid and no FFT, so it serves grids far too large
@@ -468,6 +546,10 @@ typedef struct or_ctx {
      * (nz + 1 values) and the kernel per (component, t, s, I, J) */
     double *zb;
     double *Klay;
+    /* Oersted field of the set current density (or_set_current), scaled by
+     * sin(2 pi oe_freq t) when oe_freq != 0 */
+    double *h_oe;
+    double oe_freq;
     int terms;                 /* field-term mask used by heff            */
 } or_ctx;
 
@@ -543,7 +625,7 @@ or_ctx *or_create(const long n[3], const double d[3], int p, const double *Ms, c
     c->alpha = alpha;
     c->demag_direct = demag_direct;
     c->drive_mask = calloc(c->N, 1);
-    c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN | OR_DMI;
+    c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN | OR_DMI | OR_OERSTED;
     build_kernel(c);
     return c;
 }
@@ -630,10 +712,71 @@ void or_set_layers(or_ctx *c, const double *dz)
     }
 }
 
+/* Oersted field h = sum_s j_s x G(X_t - X_s) of a current density j ([3][N],
+ * A/m^2) by direct summation over every source cell (Sec. 4.5), at every
+ * cell.  Equal cells only (returns -1 with layers). */
+int or_oersted(const or_ctx *c, const double *j, double *h)
+{
+    if (c->zb)
+        return -1;
+    long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    long ox = 2 * nx - 1, oy = 2 * ny - 1, oz = 2 * nz - 1, noff = ox * oy * oz;
+    double *G = malloc(sizeof(double) * 3 * noff);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < noff; q++) {
+        double e[3];
+        or_oersted_entry(c->d, q % ox - (nx - 1), (q / ox) % oy - (ny - 1), q / (ox * oy) - (nz - 1),
+                         c->p, e);
+        for (int l = 0; l < 3; l++)
+            G[l * noff + q] = e[l];
+    }
+#pragma omp parallel for schedule(static)
+    for (long t = 0; t < N; t++) {
+        long i = t % nx, jj = (t / nx) % ny, k = t / (nx * ny);
+        double hx = 0, hy = 0, hz = 0;
+        for (long s = 0; s < N; s++) {
+            long si = s % nx, sj = (s / nx) % ny, sk = s / (nx * ny);
+            long q = (i - si + nx - 1) + ox * ((jj - sj + ny - 1) + oy * (k - sk + nz - 1));
+            double gx = G[q], gy = G[noff + q], gz = G[2 * noff + q];
+            double jx = j[s], jy = j[N + s], jz = j[2 * N + s];
+            hx += jy * gz - jz * gy;
+            hy += jz * gx - jx * gz;
+            hz += jx * gy - jy * gx;
+        }
+        h[t] = hx;
+        h[N + t] = hy;
+        h[2 * N + t] = hz;
+    }
+    (void)oz;
+    free(G);
+    return 0;
+}
+
+/* Current density for the Oersted term (OR_OERSTED): its field is computed
+ * once and added, times sin(2 pi freq t) if freq != 0, on magnetic cells.
+ * j = NULL removes it. */
+int or_set_current(or_ctx *c, const double *j, double freq)
+{
+    free(c->h_oe);
+    c->h_oe = NULL;
+    c->oe_freq = 0.0;
+    if (!j)
+        return 0;
+    c->h_oe = malloc(sizeof(double) * 3 * c->N);
+    c->oe_freq = freq;
+    if (or_oersted(c, j, c->h_oe) != 0) {
+        free(c->h_oe);
+        c->h_oe = NULL;
+        return -1;
+    }
+    return 0;
+}
+
 void or_destroy(or_ctx *c)
 {
     if (!c)
         return;
+    free(c->h_oe);
     free(c->zb);
     free(c->Klay);
     free(c->D);
@@ -952,6 +1095,11 @@ void or_heff(const or_ctx *c, const double *m, double t, unsigned mask, double *
         for (long q = 0; q < 3 * N; q++)
             h[q] += tmp[q];
     }
+    if ((mask & OR_OERSTED) && c->h_oe) {
+        double s = c->oe_freq != 0.0 ? sin(2.0 * M_PI * c->oe_freq * t) : 1.0;
+        for (long q = 0; q < 3 * N; q++)
+            h[q] += c->Ms[q % N] != 0.0 ? s * c->h_oe[q] : 0.0;
+    }
     free(tmp);
 }
 
@@ -1001,7 +1149,8 @@ void or_energy(const or_ctx *c, const double *m, double t, double E[6])
     long N = c->N, nxy = c->n[0] * c->n[1];
     double *h = malloc(sizeof(double) * 3 * N);
     /* slots: 0 demag, 1 exchange, 2 anisotropy, 3 Zeeman, 5 DMI; 4 total */
-    unsigned masks[6] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN, 0, OR_DMI};
+    /* the Oersted field is an applied field: its energy joins the Zeeman slot */
+    unsigned masks[6] = {OR_DEMAG, OR_EXCH, OR_ANIS, OR_ZEEMAN | OR_OERSTED, 0, OR_DMI};
     double tot = 0;
     for (int e = 0; e < 6; e++) {
         if (e == 4)
@@ -1013,7 +1162,7 @@ void or_energy(const or_ctx *c, const double *m, double t, double E[6])
             continue;
         }
         if (c->terms & (int)masks[e]) {
-            or_heff(c, m, t, masks[e], h);
+            or_heff(c, m, t, masks[e] & (unsigned)c->terms, h);
             for (long q = 0; q < N; q++)
                 acc += (long double)layer_volume(c, q / nxy) * c->Ms[q] *
                        ((long double)m[q] * h[q] + (long double)m[N + q] * h[N + q] +
