@@ -66,9 +66,16 @@ typedef enum {
 
 typedef enum { MM_FP32 = 0, MM_FP64 = 1 } mm_prec;
 
-/* Field-term mask (Sec. 4).  MM_DMI only acts once mm_set_dmi gave a
- * strength. */
-enum { MM_DEMAG = 1, MM_EXCH = 2, MM_ANIS = 4, MM_ZEEMAN = 8, MM_DMI = 16, MM_ALL = 31 };
+/* Field-term mask (Sec. 4). */
+enum {
+    MM_DEMAG = 1,
+    MM_EXCH = 2,
+    MM_ANIS = 4,
+    MM_ZEEMAN = 8,
+    MM_DMI = 16,     /* acts once mm_set_dmi gave a strength        */
+    MM_OERSTED = 32, /* acts once mm_set_current gave a current     */
+    MM_ALL = 63
+};
 
 /* DMI types of Sec. 4.3 (table of DMI types), by their DMI vectors
  * (e^dmi_x, e^dmi_y, e^dmi_z): interface (C_nv) (e_y, -e_x, 0), bulk (T or O)
@@ -162,6 +169,26 @@ mm_status mm_set_exchange(mm_plan *p, const void *A_cell);
  * it with MM_DMI. */
 mm_status mm_set_dmi(mm_plan *p, int type, double D, const void *D_cell);
 
+/* Oersted field (Sec. 4.5) of a current density: h_out = sum_s j_s x G(X_t -
+ * X_s) with G the cell-averaged Biot-Savart kernel (1/(4 pi V)) int_t int_s
+ * (x - x')/|x - x'|^3 dx' dx within the near-field radius demag_p (closed
+ * form from the antiderivative of Newell's f along the component's axis, in
+ * double-double at set-up) and the singular current V D/(4 pi |D|^3) beyond
+ * (Sec. 4.5: the far field of a singular current density).  j and h_out are
+ * device buffers of 3N values of the plan's precision (A/m^2 in, A/m out),
+ * must not alias; h_out holds the field at every cell.  The first call builds
+ * and keeps the kernel spectrum and a work spectrum of 3 Px Py Pz complex
+ * values (synchronises once); later calls are asynchronous.  MM_EINVAL for
+ * thin-layer plans. */
+mm_status mm_oersted(mm_plan *p, const void *j, void *h_out);
+
+/* Current density for the MM_OERSTED term: its Oersted field is computed now
+ * (as mm_oersted) and kept; the term adds it, times sin(2 pi freq t) if freq
+ * != 0 (a current of fixed shape and sinusoidal amplitude), on magnetic
+ * cells.  Its energy is that of an applied field, counted in the Zeeman slot
+ * of mm_energy.  j NULL removes the term.  Synchronises. */
+mm_status mm_set_current(mm_plan *p, const void *j, double freq);
+
 /* Time-dependent Zeeman drive added to the external field on masked cells:
  * H(t) += mask_i * amp * sin(2 pi freq t).  mask is a device buffer of N
  * bytes (0/1) copied into the plan; NULL removes the drive. */
@@ -225,7 +252,8 @@ mm_status mm_relax(mm_plan *p, void *m, const double h_ext[3], unsigned terms, d
  * E[0] demag, E[1] exchange and E[5] DMI, each -1/2 mu0 V sum Ms m.h_t;
  * E[2] anisotropy, V times the sum of the anisotropy energy density (Sec.
  * 4.1 and 4.3: -Ku1 (e.m)^2 - Ku2 (e.m)^4 + Kc1 (cubic) + Kc2 (cubic));
- * E[3] Zeeman, -mu0 V sum Ms m.H; E[4] total of the terms in `terms`.
+ * E[3] Zeeman (with the Oersted field), -mu0 V sum Ms m.H; E[4] total of
+ * the terms in `terms`.
  * Terms left out of `terms` read 0.  Synchronises. */
 mm_status mm_energy(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
                     double E[6]);

@@ -55,7 +55,7 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->A_cell, p->D_cell, p->zw, p->lw, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
+                    p->A_cell, p->D_cell, p->zw, p->lw, p->oe_G, p->oe_S3, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -718,7 +718,7 @@ static mm_status rk4_adjoint_impl(Plan* p, const void* ckpt, const double hext[3
     s = count_region<T>(p, region, &nreg);
     if (s != MM_OK) return s;
     const double dL = nreg > 0 ? 1.0 / ((double)nsteps * nreg) : 0.0;
-    const unsigned vterms = terms & ~(unsigned)MM_ZEEMAN;
+    const unsigned vterms = terms & ~(unsigned)(MM_ZEEMAN | MM_OERSTED);
     T* y = adj_vec<T>(p, 0);
     T* ynew = adj_vec<T>(p, 1);
     T* z = adj_vec<T>(p, 7);
@@ -814,7 +814,8 @@ static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hex
         MM_HIP(eval_field<T>(*p, m, hext, terms, t, h, nullptr, p->alpha, true, nullptr), "field");
     }
     MM_HIP(zero_doubles(*p, p->gms, p->N), "clear gradient");
-    MM_HIP(field_vjp<T>(*p, m, w, h, terms & ~(unsigned)MM_ZEEMAN, p->alpha, adj_vec<T>(p, 8),
+    MM_HIP(field_vjp<T>(*p, m, w, h, terms & ~(unsigned)(MM_ZEEMAN | MM_OERSTED), p->alpha,
+                        adj_vec<T>(p, 8),
                         adj_vec<T>(p, 7), grad_m, p->gms),
            "vector-Jacobian product");
     if (grad_ms) MM_HIP(from_double<T>(*p, p->gms, grad_ms, p->N), "grad Ms");
@@ -828,8 +829,9 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
     mm_status s = ensure_rk(p);
     if (s != MM_OK) return s;
     T* h = rk_vec<T>(p, 0);
-    // reduction slots 0..3 demag, exchange, anisotropy, Zeeman; 4 DMI
-    const unsigned bits[5] = {MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_DMI};
+    // reduction slots 0..3 demag, exchange, anisotropy, Zeeman (with the
+    // Oersted field, an applied field too); 4 DMI
+    const unsigned bits[5] = {MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN | MM_OERSTED, MM_DMI};
     for (int e = 0; e < 5; ++e) {
         if (!(terms & bits[e])) {
             MM_HIP(hipMemsetAsync(p->red_out + e, 0, sizeof(double), p->stream), "clear");
@@ -841,7 +843,7 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
             MM_HIP(anis_energy<T>(*p, m, p->red_out + e), "anisotropy energy");
             continue;
         }
-        MM_HIP(eval_field<T>(*p, m, h_ext, bits[e], t, h, nullptr, p->alpha, true, nullptr),
+        MM_HIP(eval_field<T>(*p, m, h_ext, bits[e] & terms, t, h, nullptr, p->alpha, true, nullptr),
                "field");
         MM_HIP(dot_ms<T>(*p, m, h, p->red_out + e), "energy reduction");
     }
@@ -1059,6 +1061,53 @@ mm_status mm_set_dmi(mm_plan* pl, int type, double D, const void* D_cell)
         p->edmi[0][0] = -1.0;  // -e_x
         p->edmi[1][1] = 1.0;   // e_y
     }
+    return MM_OK;
+}
+
+mm_status mm_oersted(mm_plan* pl, const void* j, void* h_out)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !j || !h_out || j == h_out) {
+        set_error("invalid argument");
+        return MM_EINVAL;
+    }
+    if (p->layered) {
+        set_error("the Oersted kernel needs equal layers");
+        return MM_EINVAL;
+    }
+    hipError_t e = p->prec == MM_FP32 ? oersted_field<float>(*p, (const float*)j, (float*)h_out)
+                                      : oersted_field<double>(*p, (const double*)j, (double*)h_out);
+    if (e != hipSuccess) return hip_fail(e, "Oersted field");
+    return MM_OK;
+}
+
+mm_status mm_set_current(mm_plan* pl, const void* j, double freq)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !std::isfinite(freq)) {
+        set_error("invalid argument");
+        return MM_EINVAL;
+    }
+    if (!j) {
+        p->oe_on = false;
+        p->oe_freq = 0.0;
+        return MM_OK;
+    }
+    if (p->layered) {
+        set_error("the Oersted kernel needs equal layers");
+        return MM_EINVAL;
+    }
+    if (!p->h_oe) {
+        mm_status s = alloc(p, &p->h_oe, 3 * (size_t)p->N * elem_size(*p), "Oersted field");
+        if (s != MM_OK) return s;
+    }
+    hipError_t e = p->prec == MM_FP32 ? oersted_field<float>(*p, (const float*)j, (float*)p->h_oe)
+                                      : oersted_field<double>(*p, (const double*)j,
+                                                              (double*)p->h_oe);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "Oersted field");
+    p->oe_on = true;
+    p->oe_freq = freq;
     return MM_OK;
 }
 

@@ -92,6 +92,12 @@ struct Plan {
     void *D_cell = nullptr;   // N reals (per-cell DMI strength), or null
     void *zw = nullptr;       // layered: 4 reals per layer (z exchange down/up, 1/(2 dz_k), 0)
     double *lw = nullptr;     // layered: nz doubles, the layer heights (energy weights)
+    // Oersted field (allocated on first use)
+    void *oe_G = nullptr;     // [3][Pz/2+1][Py/2+1][Hxp] real: Im of the kernel spectrum / (Px Py Pz)
+    void *oe_S3 = nullptr;    // [3][Pz][Py][Hxp] complex work spectrum
+    void *h_oe = nullptr;     // 3N reals: field of the set current density
+    bool oe_on = false;       // Oersted term present (mm_set_current)
+    double oe_freq = 0.0;     // h_oe scaled by sin(2 pi f t) when f != 0
     unsigned char *mask = nullptr;  // N bytes drive mask, or null
     // Runge-Kutta work space (allocated on first use)
     void *rk = nullptr;       // 10 vectors of 3N
@@ -185,6 +191,11 @@ hipError_t start_norms(Plan &p, const T *y, const T *f0, const T *f1, double rto
 // Count magnetic cells (Ms > 0) into *out_dev.
 template <typename T>
 hipError_t count_magnetic(Plan &p, double *out_dev);
+// Oersted field h_out (3N) of the current density j (3N), both of the plan's
+// precision: FFT convolution with the cell-averaged Biot-Savart kernel.  The
+// kernel spectrum and the work spectrum are allocated on first use.
+template <typename T>
+hipError_t oersted_field(Plan &p, const T *j, T *h_out);
 // Numbers of negative and positive entries of v (N values) into out_dev[0..1].
 template <typename T>
 hipError_t count_signs(Plan &p, const T *v, double *out_dev);

@@ -485,6 +485,8 @@ struct LocalParams {
     double anis2;     // 4 Ku2 / mu0
     double cub1, cub2;  // 2 Kc1 / mu0, 2 Kc2 / mu0
     double ec[3][3];  // cubic principal axes
+    int with_oe;      // Oersted term present (h_oe)
+    double oe_scale;  // its time factor
     int with_dmi;     // DMI term present
     double dmi;       // 2 D / mu0, or 2 / mu0 with per-cell D (divided by Ms_i per cell)
     double edmi[3][3];  // DMI vector of axis k divided by 2 Delta_k
@@ -622,7 +624,8 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
     LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
-    const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw)
+    const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
+    const T* __restrict__ h_oe)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
     constexpr bool kMIX = EXT & EXT_MIX;
@@ -746,6 +749,12 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
                     hy += g0 * (T)P.ec[0][1] + g1 * (T)P.ec[1][1] + g2 * (T)P.ec[2][1];
                     hz += g0 * (T)P.ec[0][2] + g1 * (T)P.ec[1][2] + g2 * (T)P.ec[2][2];
                 }
+            }
+            if (P.with_oe) {
+                const T so = (T)P.oe_scale;
+                hx += so * h_oe[cell];
+                hy += so * h_oe[N + cell];
+                hz += so * h_oe[2 * N + cell];
             }
             if (P.with_zee) {
                 hx += (T)P.H[0];
@@ -965,7 +974,8 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
     k_x_c2r_local<T, M, PC, EXT><<<xcd_grid(nblocks), G::kRows * 3 * G::kT, 0, p.stream>>>(
         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
         (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
-        (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr);
+        (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
+        P.with_oe ? (const T*)p.h_oe : nullptr);
     return hipGetLastError();
 }
 
@@ -2139,6 +2149,193 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Oersted field (Sec. 4.5): h = sum_s j_s x G(X_t - X_s) as an FFT
+// convolution.  G_l is odd along l and even along the other axes, so its
+// spectrum is i g with g real, even in ky and kz except for the sign flip of
+// g_y for ky > Py/2 and of g_z for kz > Pz/2; the folded octant of g is kept.
+// ---------------------------------------------------------------------------
+__global__ void k_oe_near(double* __restrict__ near, int nI, int nJ, int nK, double dx, double dy,
+                          double dz)
+{
+    const long per = (long)nI * nJ * nK;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * per) return;
+    const int comp = (int)(q / per);
+    const long o = q % per;
+    const int I = (int)(o % nI), J = (int)((o / nI) % nJ), K = (int)(o / ((long)nI * nJ));
+    near[q] = oersted_near(comp, I, J, K, dx, dy, dz);
+}
+
+__global__ void k_oe_place(double* __restrict__ R, int comp, int nx, int ny, int nz, int Px, int Py,
+                           int Pz, const double* __restrict__ near, int nI, int nJ, int nK, int p,
+                           double dx, double dy, double dz)
+{
+    const long total = (long)Px * Py * Pz;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int pi = (int)(q % Px), pj = (int)((q / Px) % Py), pk = (int)(q / ((long)Px * Py));
+    auto off = [](int pp, int n, int P, int& o) {
+        if (pp < n) { o = pp; return true; }
+        if (pp > P - n) { o = pp - P; return true; }
+        return false;
+    };
+    int I, J, K;
+    double v = 0.0;
+    if (off(pi, nx, Px, I) && off(pj, ny, Py, J) && off(pk, nz, Pz, K)) {
+        const int aI = I < 0 ? -I : I, aJ = J < 0 ? -J : J, aK = K < 0 ? -K : K;
+        int cheb = aI > aJ ? aI : aJ;
+        cheb = cheb > aK ? cheb : aK;
+        if (p < 0 || cheb <= p) {
+            const int own = comp == 0 ? I : comp == 1 ? J : K;  // odd along its own axis
+            v = (own < 0 ? -1.0 : 1.0) * near[(((long)comp * nK + aK) * nJ + aJ) * nI + aI];
+        } else {
+            v = oersted_point(comp, I, J, K, dx, dy, dz);
+        }
+    }
+    R[q] = v;
+}
+
+template <typename T>
+__global__ void k_oe_fold(T* __restrict__ G, const cx<double>* __restrict__ C, int Hx, int Hxp,
+                          int Py, int Pz, double scale)
+{
+    const int hy = Py / 2 + 1, hz = Pz / 2 + 1;
+    const long total = (long)hz * hy * Hxp;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int kx = (int)(q % Hxp), ky = (int)((q / Hxp) % hy), kz = (int)(q / ((long)Hxp * hy));
+    G[q] = kx < Hx ? (T)(C[((long)kz * Py + ky) * Hxp + kx].y * scale) : (T)0;
+}
+
+// h^ = j^ x (i g) in place on S ([3][Pz][Py][Hxp]).
+template <typename T>
+__global__ void k_oe_product(cx<T>* __restrict__ S, const T* __restrict__ G, int Py, int Pz, int Hx,
+                             int Hxp, long s_comp, long g_comp)
+{
+    const long total = (long)Pz * Py * Hxp;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int kx = (int)(q % Hxp), ky = (int)((q / Hxp) % Py), kz = (int)(q / ((long)Hxp * Py));
+    if (kx >= Hx) return;
+    const bool uy = ky > Py / 2, uz = kz > Pz / 2;
+    const int kyf = uy ? Py - ky : ky, kzf = uz ? Pz - kz : kz;
+    const long gq = ((long)kzf * (Py / 2 + 1) + kyf) * Hxp + kx;
+    const T gx = G[gq], gy = uy ? -G[g_comp + gq] : G[g_comp + gq],
+            gz = uz ? -G[2 * g_comp + gq] : G[2 * g_comp + gq];
+    const cx<T> jx = S[q], jy = S[s_comp + q], jz = S[2 * s_comp + q];
+    // c = j x g (complex), h = i c = (-c.im, c.re)
+    const cx<T> cxv = {jy.x * gz - jz.x * gy, jy.y * gz - jz.y * gy};
+    const cx<T> cyv = {jz.x * gx - jx.x * gz, jz.y * gx - jx.y * gz};
+    const cx<T> czv = {jx.x * gy - jy.x * gx, jx.y * gy - jy.y * gx};
+    S[q] = {-cxv.y, cxv.x};
+    S[s_comp + q] = {-cyv.y, cyv.x};
+    S[2 * s_comp + q] = {-czv.y, czv.x};
+}
+
+template <typename T>
+static hipError_t oersted_setup(Plan& p)
+{
+    const int Px = p.P[0], Py = p.P[1], Pz = p.P[2];
+    const size_t es = sizeof(T);
+    const long gn = (long)(Pz / 2 + 1) * (Py / 2 + 1) * p.Hxp;
+    if (!p.oe_S3) MMX_TRY(hipMalloc(&p.oe_S3, 3 * (size_t)Pz * Py * p.Hxp * 2 * es));
+    if (p.oe_G) return hipSuccess;
+    MMX_TRY(hipMalloc(&p.oe_G, 3 * (size_t)gn * es));
+    p.bytes += 3 * (size_t)Pz * Py * p.Hxp * 2 * es + 3 * (size_t)gn * es;
+    Scratch sc;
+    const int lim = p.demag_p < 0 ? (1 << 30) : p.demag_p;
+    const int nI = std::min(p.n[0] - 1, lim) + 1, nJ = std::min(p.n[1] - 1, lim) + 1,
+              nK = std::min(p.n[2] - 1, lim) + 1;
+    const long ntab = 3L * nI * nJ * nK;
+    double *near, *R;
+    cx<double>* C;
+    cx<double>* tw64;
+    MMX_TRY(sc.get(&near, sizeof(double) * ntab));
+    k_oe_near<<<blocks_for(ntab, 64), 64, 0, p.stream>>>(near, nI, nJ, nK, p.d[0], p.d[1], p.d[2]);
+    MMX_TRY(hipGetLastError());
+    const long PN = (long)Px * Py * Pz;
+    MMX_TRY(sc.get(&R, sizeof(double) * PN));
+    MMX_TRY(sc.get(&C, sizeof(cx<double>) * (long)Pz * Py * p.Hxp));
+    MMX_TRY(sc.get(&tw64, sizeof(cx<double>) * p.Lmax));
+    k_twiddles<double><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>(tw64, p.Lmax);
+    MMX_TRY(hipGetLastError());
+    Plan q = p;
+    q.tw = tw64;
+    for (int comp = 0; comp < 3; ++comp) {
+        k_oe_place<<<blocks_for(PN, 256), 256, 0, p.stream>>>(R, comp, p.n[0], p.n[1], p.n[2], Px,
+                                                             Py, Pz, near, nI, nJ, nK, p.demag_p,
+                                                             p.d[0], p.d[1], p.d[2]);
+        MMX_TRY(hipGetLastError());
+        MMX_TRY((launch_x_r2c<double, false>(q, Px / 2, R, Px, 0, Px, nullptr, 1.0, C, p.Hxp, 0,
+                                             Py * Pz, 1)));
+        if (Py > 1)
+            MMX_TRY((launch_strided<double, -1>(q, Py, C, C, Py, Py, p.Hxp, p.Hxp, p.Hx, 1, 0, 0,
+                                                Pz, (long)Py * p.Hxp, (long)Py * p.Hxp)));
+        if (Pz > 1)
+            MMX_TRY((launch_strided<double, -1>(q, Pz, C, C, Pz, Pz, (long)Py * p.Hxp,
+                                                (long)Py * p.Hxp, p.Hx, 1, 0, 0, Py, p.Hxp,
+                                                p.Hxp)));
+        k_oe_fold<T><<<blocks_for(gn, 256), 256, 0, p.stream>>>((T*)p.oe_G + comp * gn, C, p.Hx,
+                                                                p.Hxp, Py, Pz, 1.0 / (double)PN);
+        MMX_TRY(hipGetLastError());
+    }
+    return hipStreamSynchronize(p.stream);
+}
+
+template <typename T>
+hipError_t oersted_field(Plan& p, const T* j, T* h_out)
+{
+    MMX_TRY(oersted_setup<T>(p));
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int Py = p.P[1], Pz = p.P[2];
+    const long s1c = (long)nz * ny * p.Hxp, s3c = (long)Pz * Py * p.Hxp;
+    cx<T>* S1 = (cx<T>*)p.S1;
+    cx<T>* S3 = (cx<T>*)p.oe_S3;
+    MMX_TRY((launch_x_r2c<T, false>(p, p.P[0] / 2, j, nx, p.N, nx, nullptr, (T)1, S1, p.Hxp, s1c,
+                                    ny * nz, 3)));
+    // y: S1 (ny rows per slab) -> S3 (Py rows, Pz slabs); a copy when Py = 1
+    if (Py > 1) {
+        MMX_TRY((launch_strided<T, -1>(p, Py, S1, S3, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s3c, nz,
+                                       (long)ny * p.Hxp, (long)Py * p.Hxp)));
+    } else {
+        for (int c = 0; c < 3; ++c)
+            MMX_TRY(hipMemcpyAsync(S3 + c * s3c, S1 + c * s1c, sizeof(cx<T>) * nz * p.Hxp,
+                                   hipMemcpyDeviceToDevice, p.stream));
+    }
+    // z forward in place (nz -> Pz, zero padded), product, z inverse (Pz -> nz)
+    if (Pz > 1)
+        MMX_TRY((launch_strided<T, -1>(p, Pz, S3, S3, nz, Pz, (long)Py * p.Hxp, (long)Py * p.Hxp,
+                                       p.Hx, 3, s3c, s3c, Py, p.Hxp, p.Hxp)));
+    k_oe_product<T><<<blocks_for(s3c, 256), 256, 0, p.stream>>>(
+        S3, (const T*)p.oe_G, Py, Pz, p.Hx, p.Hxp, s3c, (long)(Pz / 2 + 1) * (Py / 2 + 1) * p.Hxp);
+    MMX_TRY(hipGetLastError());
+    if (Pz > 1)
+        MMX_TRY((launch_strided<T, 1>(p, Pz, S3, S3, Pz, nz, (long)Py * p.Hxp, (long)Py * p.Hxp,
+                                      p.Hx, 3, s3c, s3c, Py, p.Hxp, p.Hxp)));
+    if (Py > 1) {
+        MMX_TRY((launch_strided<T, 1>(p, Py, S3, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s3c, s1c, nz,
+                                      (long)Py * p.Hxp, (long)ny * p.Hxp)));
+    } else {
+        for (int c = 0; c < 3; ++c)
+            MMX_TRY(hipMemcpyAsync(S1 + c * s1c, S3 + c * s3c, sizeof(cx<T>) * nz * p.Hxp,
+                                   hipMemcpyDeviceToDevice, p.stream));
+    }
+    // x inverse: the raw convolution at every cell (uniform Ms 1, no other term)
+    LocalParams P{};
+    P.nx = nx;
+    P.ny = ny;
+    P.nz = nz;
+    P.N = p.N;
+    P.s1_comp = s1c;
+    P.Hxp = p.Hxp;
+    P.with_demag = 1;
+    P.Ms = 1.0;
+    Plan q = p;
+    q.percell_A = q.percell_D = q.layered = false;
+    return launch_local<T, false, 0>(q, p.P[0] / 2, j, h_out, nullptr, P, nullptr);
+}
+
 template <typename T>
 hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
                       T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
@@ -2173,6 +2370,8 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
     P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi) ? 1 : 0;
     P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
+    P.with_oe = (terms & MM_OERSTED) && p.oe_on ? 1 : 0;
+    P.oe_scale = p.oe_freq != 0.0 ? sin(2.0 * M_PI * p.oe_freq * t) : 1.0;
     P.anis2 = 4.0 * p.Ku2 / kMu0;
     P.cub1 = 2.0 * p.Kc1 / kMu0;
     P.cub2 = 2.0 * p.Kc2 / kMu0;
@@ -2526,6 +2725,7 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
                                        double*);                                                 \
     template hipError_t count_magnetic<T>(Plan&, double*);                                       \
     template hipError_t count_signs<T>(Plan&, const T*, double*);                                \
+    template hipError_t oersted_field<T>(Plan&, const T*, T*);                                   \
     template hipError_t debug_spectrum<T>(Plan&, int, double*);                                  \
     template hipError_t field_vjp<T>(Plan&, const T*, const T*, const T*, unsigned, double, T*,  \
                                      T*, T*, double*);                                           \

@@ -253,6 +253,95 @@ __host__ __device__ inline double kernel_dipole_layer(int comp, int I, int J, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Oersted kernel (Sec. 4.5): h_t = sum_s j_s x G(X_t - X_s), G the average over
+// the target cell of the Biot-Savart vector (x - x')/(4 pi |x - x'|^3) of a
+// uniform source cell.  G_l is a first derivative along l, so its 27-point
+// stencil (Newell's weights, divided by 4 pi V) runs over Fo, the
+// antiderivative of Newell's f along l:
+//   Fo(x,y,z) = x R^3/12 - 5/24 (y^2+z^2) x R
+//             + (y^2 z^2/3 - (y^2+z^2)^2/24) asinh(x / sqrt(y^2+z^2))
+//             + y/2 (x z^2 - x^3/3) asinh(y / sqrt(x^2+z^2))
+//             + z/2 (x y^2 - x^3/3) asinh(z / sqrt(x^2+y^2))
+//             - x^2 y z/2 atan(y z/(x R)) - y z^3/6 atan(x y/(z R))
+//             - y^3 z/6 atan(x z/(y R)),
+// odd in x, even in y and z.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline dd oersted_Fo(dd x, dd y, dd z)
+{
+    // x, y, z >= 0 (the caller applies the odd parity in x)
+    dd x2 = dd_mul(x, x), y2 = dd_mul(y, y), z2 = dd_mul(z, z);
+    dd r2 = dd_add(y2, z2);
+    dd R2 = dd_add(x2, r2);
+    if (R2.hi == 0.0) return dd_from(0.0);
+    dd R = dd_sqrt(R2);
+    dd xR = dd_mul(x, R);
+    // x R^3 / 12 - 5/24 r2 x R
+    dd s = dd_sub(dd_div_d(dd_mul(xR, R2), 12.0), dd_div_d(dd_mul_d(dd_mul(r2, xR), 5.0), 24.0));
+    if (r2.hi > 0.0) {
+        dd c = dd_sub(dd_div_d(dd_mul(y2, z2), 3.0), dd_div_d(dd_mul(r2, r2), 24.0));
+        s = dd_add(s, dd_mul(c, dd_asinh_pos(dd_div(x, dd_sqrt(r2)))));
+    }
+    dd x3_3 = dd_div_d(dd_mul(x2, x), 3.0);
+    dd xz2 = dd_add(x2, z2);
+    if (xz2.hi > 0.0) {
+        dd c = dd_mul_d(dd_mul(y, dd_sub(dd_mul(x, z2), x3_3)), 0.5);
+        s = dd_add(s, dd_mul(c, dd_asinh_pos(dd_div(y, dd_sqrt(xz2)))));
+    }
+    dd xy2 = dd_add(x2, y2);
+    if (xy2.hi > 0.0) {
+        dd c = dd_mul_d(dd_mul(z, dd_sub(dd_mul(x, y2), x3_3)), 0.5);
+        s = dd_add(s, dd_mul(c, dd_asinh_pos(dd_div(z, dd_sqrt(xy2)))));
+    }
+    dd yz = dd_mul(y, z);
+    if (x.hi > 0.0)
+        s = dd_sub(s, dd_mul(dd_mul_d(dd_mul(x2, yz), 0.5), dd_atan(dd_div(yz, xR))));
+    if (z.hi > 0.0)
+        s = dd_sub(s, dd_mul(dd_div_d(dd_mul(yz, z2), 6.0), dd_atan(dd_div(dd_mul(x, y), dd_mul(z, R)))));
+    if (y.hi > 0.0)
+        s = dd_sub(s, dd_mul(dd_div_d(dd_mul(yz, y2), 6.0), dd_atan(dd_div(dd_mul(x, z), dd_mul(y, R)))));
+    return s;
+}
+
+// Near-field G_comp for the cell offset (I, J, K) (target minus source).
+__host__ __device__ inline double oersted_near(int comp, int I, int J, int K, double dx, double dy,
+                                               double dz)
+{
+    const int off[3] = {I, J, K};
+    const double d[3] = {dx, dy, dz};
+    const int l = comp, u = (comp + 1) % 3, v = (comp + 2) % 3;
+    dd acc = dd_from(0.0);
+    for (int e0 = -1; e0 <= 1; ++e0)
+        for (int e1 = -1; e1 <= 1; ++e1)
+            for (int e2 = -1; e2 <= 1; ++e2) {
+                const double w = (e0 == 0 ? 2.0 : -1.0) * (e1 == 0 ? 2.0 : -1.0) *
+                                 (e2 == 0 ? 2.0 : -1.0);
+                int a = off[l] + e0, b = off[u] + e1, c = off[v] + e2;
+                double sg = w;
+                if (a < 0) {  // Fo is odd in its first argument
+                    a = -a;
+                    sg = -sg;
+                }
+                b = b < 0 ? -b : b;
+                c = c < 0 ? -c : c;
+                dd val = oersted_Fo(two_prod((double)a, d[l]), two_prod((double)b, d[u]),
+                                    two_prod((double)c, d[v]));
+                acc = dd_add(acc, dd_mul_d(val, sg));
+            }
+    dd den = dd_mul_d(dd_mul_d(dd_mul_d(dd_mul_d(dd_pi(), 4.0), dx), dy), dz);
+    dd r = dd_div(acc, den);
+    return r.hi + r.lo;
+}
+
+// Far field: the singular current, G = V D / (4 pi |D|^3).
+__host__ __device__ inline double oersted_point(int comp, int I, int J, int K, double dx, double dy,
+                                                double dz)
+{
+    const double D[3] = {I * dx, J * dy, K * dz};
+    const double r2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+    return dx * dy * dz / (4.0 * M_PI) / (r2 * sqrt(r2)) * D[comp];
+}
+
 }  // namespace mmx
 
 // restore the compiler default for the code that follows

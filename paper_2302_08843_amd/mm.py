@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libmmx.so")
 MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ENONFINITE, MM_EDTMIN, MM_ENOTCONV, MM_EBUSY = (
     0, -1, -2, -3, -4, -5, -6, -7)
 MM_FP32, MM_FP64 = 0, 1
-MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_DMI, MM_ALL = 1, 2, 4, 8, 16, 31
+MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN, MM_DMI, MM_OERSTED, MM_ALL = 1, 2, 4, 8, 16, 32, 63
 MM_DMI_INTERFACE, MM_DMI_BULK, MM_DMI_D2D = 0, 1, 2
 
 STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4: "MM_ENONFINITE",
@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4:
 
 # Every entry point declared in include/mm.h.
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
-           "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
+           "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_oersted",
+           "mm_set_current", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
            "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error", "mm_heff_vjp",
            "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_opts_default",
@@ -121,6 +122,8 @@ def lib():
         L.mm_set_ms.argtypes = [vp, vp]
         L.mm_set_exchange.argtypes = [vp, vp]
         L.mm_set_dmi.argtypes = [vp, C.c_int, C.c_double, vp]
+        L.mm_oersted.argtypes = [vp, vp, vp]
+        L.mm_set_current.argtypes = [vp, vp, C.c_double]
         L.mm_set_drive.argtypes = [vp, dp, C.c_double, vp]
         L.mm_heff.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
         L.mm_llg_rhs.argtypes = [vp, vp, dp, C.c_uint, C.c_double, vp]
@@ -151,7 +154,8 @@ def lib():
         L.mm_rk4_adjoint.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
                                      C.c_long, vp, vp, dp]
         L.mm_last_error.restype = C.c_char_p
-        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_set_drive", "mm_heff", "mm_llg_rhs",
+        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_oersted", "mm_set_current",
+                     "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
                      "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum", "mm_heff_vjp",
                      "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_create",
@@ -229,6 +233,14 @@ def mm_set_exchange(plan, A_cell):
 
 def mm_set_dmi(plan, kind, D, D_cell):
     _check(lib().mm_set_dmi(plan, int(kind), float(D), None if D_cell is None else _ptr(D_cell)))
+
+
+def mm_oersted(plan, j, h_out):
+    _check(lib().mm_oersted(plan, _ptr(j), _ptr(h_out)))
+
+
+def mm_set_current(plan, j, freq):
+    _check(lib().mm_set_current(plan, None if j is None else _ptr(j), float(freq)))
 
 
 def mm_set_drive(plan, amp, freq, mask):
@@ -457,6 +469,23 @@ class Plan:
             return
         nx, ny, nz = self.grid
         mm_set_dmi(self.handle, kind, 0.0, self._t(D).reshape(nz, ny, nx).contiguous())
+        torch.cuda.current_stream().synchronize()
+
+    def oersted(self, j, out=None):
+        """Oersted field of the current density j (A/m^2, shape (3, nz, ny, nx))."""
+        j = self._t(j)
+        out = self.empty() if out is None else out
+        mm_oersted(self.handle, j, out)
+        return out
+
+    def set_current(self, j, freq=0.0):
+        """Current density for the MM_OERSTED term (None removes it)."""
+        import torch
+
+        if j is None:
+            mm_set_current(self.handle, None, 0.0)
+            return
+        mm_set_current(self.handle, self._t(j), freq)
         torch.cuda.current_stream().synchronize()
 
     def set_drive(self, amp, freq, mask):
