@@ -192,6 +192,45 @@ def layers(mm, W, iters):
             "equidistant_passes_us": out["equidistant"][1]}
 
 
+def oersted_bytes(grid):
+    """Algorithmic HBM bytes of one FP32 Oersted field evaluation: x forward,
+    y forward, z forward (zero padded), cross product with the kernel octant,
+    z inverse, y inverse, x inverse (current density in, field out)."""
+    nx, ny, nz = grid
+    P = [1 if n == 1 else 1 << (2 * n - 2).bit_length() for n in grid]
+    hx = P[0] // 2 + 1 if P[0] > 1 else 1
+    N = nx * ny * nz
+    s1, s2, s3 = 3 * nz * ny * hx * 8, 3 * nz * P[1] * hx * 8, 3 * P[2] * P[1] * hx * 8
+    g = 3 * (P[2] // 2 + 1) * (P[1] // 2 + 1) * hx * 4
+    return (12 * N + s1) + (s1 + s2) + (s2 + s3) + (2 * s3 + g) + (s3 + s2) + (s2 + s1) + \
+        (s1 + 24 * N)
+
+
+def oersted(mm, plan, cfg, iters):
+    """Oersted field of a current density on the benchmark grid, FP32: kernel
+    set-up once, then repeated evaluations (the cost of updating the field
+    of a time-varying current every step)."""
+    import torch
+
+    nx, ny, nz = plan.grid
+    g = np.random.Generator(np.random.PCG64(7))
+    j = plan._t(g.standard_normal((3, nz, ny, nx)) * 1e11)
+    out = plan.empty()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.oersted(j, out=out)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        plan.oersted(j, out=out)
+    torch.cuda.synchronize()
+    call = (time.perf_counter() - t0) / iters
+    b = oersted_bytes(plan.grid)
+    return {"first_call_s": setup, "call_ms": 1e3 * call, "model_bytes": b,
+            "GBs": b / call / 1e9}
+
+
 def _serve_once(mm, reqs, states, arrivals, opts):
     """Run the request server over `reqs` (start states already in HBM) with
     the given arrival offsets (s); returns completions, makespan and stats."""
@@ -316,6 +355,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-layers", dest="layers", action="store_false",
                     help="skip the thin-layer field evaluation")
+    ap.add_argument("--no-oersted", dest="oersted", action="store_false",
+                    help="skip the Oersted field evaluation")
     ap.add_argument("--layers-only", action="store_true",
                     help="only the thin-layer field evaluation (profiling its kernels alone)")
     ap.add_argument("--serve-requests", type=int, default=64,
@@ -375,6 +416,9 @@ def main():
             res["rkf45"] = dict(wall=wall_f, stats=st_f)
             print("[bench] extended stencil (per-cell A + DMI)", file=sys.stderr, flush=True)
             res["ext"] = extended_stencil(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters)
+            if args.oersted:
+                print("[bench] Oersted field", file=sys.stderr, flush=True)
+                res["oe"] = oersted(mm, plan, cfg, 10)
         del plan, m
         torch.cuda.empty_cache()
 
@@ -430,6 +474,8 @@ def main():
                              "rejected": rf["stats"]["rejected"]}
     if "ext" in res:
         out["extended_stencil_fp32"] = res["ext"]
+    if "oe" in res:
+        out["oersted_fp32"] = res["oe"]
     if args.layers:
         print("[bench] thin layers 512x512x8", file=sys.stderr, flush=True)
         out["layers_fp32"] = layers(mm, W, args.heff_iters)
