@@ -84,6 +84,12 @@ def lib():
         L.or_oersted.restype = C.c_int
         L.or_set_current.argtypes = [C.c_void_p, C.c_void_p, C.c_double]
         L.or_set_current.restype = C.c_int
+        L.or_oersted_at.argtypes = [C.POINTER(C.c_long), dp, C.c_int, dp, C.c_long,
+                                    C.POINTER(C.c_long), dp]
+        L.or_oersted_at.restype = C.c_int
+        L.or_layer_demag_at.argtypes = [C.POINTER(C.c_long), dp, dp, C.c_int, C.c_void_p,
+                                        C.c_double, dp, C.c_long, C.POINTER(C.c_long), dp]
+        L.or_layer_demag_at.restype = C.c_int
         L.or_newell_box.argtypes = [C.c_double, C.c_double, C.c_long, C.c_long, C.c_double,
                                     C.c_double, C.c_double, dp]
         L.or_layer_entry.argtypes = [C.c_double, C.c_double, dp, C.c_long, C.c_long, C.c_long,
@@ -200,6 +206,39 @@ def oersted_entry(d, I, J, K, p=20) -> np.ndarray:
     return out
 
 
+def oersted_at(n, d, j, cells, p=20) -> np.ndarray:
+    """Oersted field of the current density j ((3, nz, ny, nx)) at the given
+    linear cell indices by direct summation over every source cell: shape
+    (len(cells), 3)."""
+    nn = (C.c_long * 3)(*[int(v) for v in n])
+    j = np.ascontiguousarray(np.asarray(j, dtype=np.float64))
+    cl = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.zeros((len(cl), 3))
+    if lib().or_oersted_at(nn, _dp(_d3(d)), int(p), _dp(j), len(cl),
+                           cl.ctypes.data_as(C.POINTER(C.c_long)), _dp(out)) != 0:
+        raise ValueError("or_oersted_at needs p >= 0")
+    return out
+
+
+def layer_demag_at(n, d, dz, m, cells, Ms=1.0, p=20) -> np.ndarray:
+    """Demag field of thin layers of heights dz at the given linear cell
+    indices by direct summation: shape (len(cells), 3)."""
+    nn = (C.c_long * 3)(*[int(v) for v in n])
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+    dzl = np.ascontiguousarray(np.asarray(dz, dtype=np.float64))
+    cl = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.zeros((len(cl), 3))
+    if np.ndim(Ms) == 0:
+        ms_ptr, ms0 = None, float(Ms)
+    else:
+        msa = np.ascontiguousarray(np.asarray(Ms, dtype=np.float64))
+        ms_ptr, ms0 = msa.ctypes.data, 0.0
+    if lib().or_layer_demag_at(nn, _dp(_d3(d)), _dp(dzl), int(p), ms_ptr, ms0, _dp(m), len(cl),
+                               cl.ctypes.data_as(C.POINTER(C.c_long)), _dp(out)) != 0:
+        raise ValueError("or_layer_demag_at needs p >= 0")
+    return out
+
+
 def padded(n: int) -> int:
     """Zero-padding extent: 1 for n == 1, else next power of two >= 2n-1."""
     return int(lib().or_padded(int(n)))
@@ -233,7 +272,7 @@ class Oracle:
     """
 
     def __init__(self, n, d, Ms, A=0.0, Ku=0.0, eu=(0, 0, 1), alpha=0.5, p=20, direct=False,
-                 layers=None):
+                 layers=None, demag=True):
         self.n = tuple(int(v) for v in n)
         self.d = tuple(float(v) for v in d)
         nx, ny, nz = self.n
@@ -244,8 +283,10 @@ class Oracle:
         self.alpha = float(alpha)
         self.V = self.d[0] * self.d[1] * self.d[2]
         nn = (C.c_long * 3)(*self.n)
+        # demag=False: no demag kernel (local terms only; the demag field reads NaN)
+        mode = 2 if not demag else int(bool(direct))
         self._c = lib().or_create(nn, _dp(_d3(self.d)), int(p), _dp(self.Ms), _dp(self.A),
-                                  float(Ku), _dp(_d3(eu)), self.alpha, int(bool(direct)))
+                                  float(Ku), _dp(_d3(eu)), self.alpha, mode)
         self.Hext = np.zeros(3)
         self.terms = ALL
         self.layers = None

@@ -626,7 +626,10 @@ or_ctx *or_create(const long n[3], const double d[3], int p, const double *Ms, c
     c->demag_direct = demag_direct;
     c->drive_mask = calloc(c->N, 1);
     c->terms = OR_DEMAG | OR_EXCH | OR_ANIS | OR_ZEEMAN | OR_DMI | OR_OERSTED;
-    build_kernel(c);
+    /* demag_direct 2: no demag kernel at all (local terms only, for grids
+     * whose kernel the oracle cannot hold) */
+    if (demag_direct != 2)
+        build_kernel(c);
     return c;
 }
 
@@ -710,6 +713,106 @@ void or_set_layers(or_ctx *c, const double *dz)
         for (int a = 0; a < 6; a++)
             c->Klay[a * total + q] = e[a];
     }
+}
+
+/* Oersted field at selected target cells by direct summation over every
+ * source cell (no table of all offsets), for grids too large for or_oersted:
+ * near-field entries (Chebyshev index distance <= p) are tabulated once, the
+ * rest are the singular current.  j is [3][N]; out receives 3 values per
+ * target.  Returns -1 for p < 0. */
+int or_oersted_at(const long n[3], const double d[3], int p, const double *j, long ncell,
+                  const long *cells, double *out)
+{
+    if (p < 0)
+        return -1;
+    long nx = n[0], ny = n[1], nz = n[2], N = nx * ny * nz;
+    long rx = p < nx - 1 ? p : nx - 1, ry = p < ny - 1 ? p : ny - 1, rz = p < nz - 1 ? p : nz - 1;
+    long tx = 2 * rx + 1, ty = 2 * ry + 1, tz = 2 * rz + 1, nt = tx * ty * tz;
+    double *T = malloc(sizeof(double) * 3 * nt);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long q = 0; q < nt; q++)
+        or_oersted_entry(d, q % tx - rx, (q / tx) % ty - ry, q / (tx * ty) - rz, p, T + 3 * q);
+    for (long c = 0; c < ncell; c++) {
+        long t = cells[c];
+        long i = t % nx, jj = (t / nx) % ny, k = t / (nx * ny);
+        long double hx = 0.0L, hy = 0.0L, hz = 0.0L;
+#pragma omp parallel for reduction(+ : hx, hy, hz) schedule(static)
+        for (long src = 0; src < N; src++) {
+            long oi = i - src % nx, oj = jj - (src / nx) % ny, ok = k - src / (nx * ny);
+            double g[3];
+            if (labs(oi) <= rx && labs(oj) <= ry && labs(ok) <= rz) {
+                const double *te = T + 3 * ((oi + rx) + tx * ((oj + ry) + ty * (ok + rz)));
+                g[0] = te[0];
+                g[1] = te[1];
+                g[2] = te[2];
+            } else {
+                or_oersted_entry(d, oi, oj, ok, p, g);
+            }
+            double jx = j[src], jy = j[N + src], jz = j[2 * N + src];
+            hx += jy * g[2] - jz * g[1];
+            hy += jz * g[0] - jx * g[2];
+            hz += jx * g[1] - jy * g[0];
+        }
+        out[3 * c] = (double)hx;
+        out[3 * c + 1] = (double)hy;
+        out[3 * c + 2] = (double)hz;
+    }
+    free(T);
+    return 0;
+}
+
+/* Layered demag field at selected target cells by direct summation (layer
+ * heights dz[0..nz) stacked from 0): near-field entries (Chebyshev index
+ * distance <= p in (i, j, layer)) tabulated per layer pair, dipoles beyond.
+ * Ms per cell or NULL for Ms0.  Returns -1 for p < 0. */
+int or_layer_demag_at(const long n[3], const double d[3], const double *dz, int p,
+                      const double *Ms, double Ms0, const double *m, long ncell, const long *cells,
+                      double *out)
+{
+    if (p < 0)
+        return -1;
+    long nx = n[0], ny = n[1], nz = n[2], N = nx * ny * nz;
+    double *zb = malloc(sizeof(double) * (nz + 1));
+    zb[0] = 0.0;
+    for (long k = 0; k < nz; k++)
+        zb[k + 1] = zb[k] + dz[k];
+    long rx = p < nx - 1 ? p : nx - 1, ry = p < ny - 1 ? p : ny - 1;
+    long tx = 2 * rx + 1, ty = 2 * ry + 1, nl = tx * ty, nt = nl * nz * nz;
+    double *T = malloc(sizeof(double) * 6 * nt);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long q = 0; q < nt; q++) {
+        long l = q % nl, ts = q / nl;
+        or_layer_entry(d[0], d[1], zb, ts / nz, ts % nz, l % tx - rx, l / tx - ry, p, T + 6 * q);
+    }
+    for (long c = 0; c < ncell; c++) {
+        long t = cells[c];
+        long i = t % nx, jj = (t / nx) % ny, k = t / (nx * ny);
+        long double hx = 0.0L, hy = 0.0L, hz = 0.0L;
+#pragma omp parallel for reduction(+ : hx, hy, hz) schedule(static)
+        for (long src = 0; src < N; src++) {
+            long sk = src / (nx * ny);
+            long oi = i - src % nx, oj = jj - (src / nx) % ny;
+            double e[6];
+            if (labs(oi) <= rx && labs(oj) <= ry) {
+                const double *te = T + 6 * (((k * nz + sk) * nl) + (oi + rx) + tx * (oj + ry));
+                for (int a = 0; a < 6; a++)
+                    e[a] = te[a];
+            } else {
+                or_layer_entry(d[0], d[1], zb, k, sk, oi, oj, p, e);
+            }
+            double ms = Ms ? Ms[src] : Ms0;
+            double Mx = ms * m[src], My = ms * m[N + src], Mz = ms * m[2 * N + src];
+            hx += e[0] * Mx + e[3] * My + e[4] * Mz;
+            hy += e[3] * Mx + e[1] * My + e[5] * Mz;
+            hz += e[4] * Mx + e[5] * My + e[2] * Mz;
+        }
+        out[3 * c] = (double)hx;
+        out[3 * c + 1] = (double)hy;
+        out[3 * c + 2] = (double)hz;
+    }
+    free(T);
+    free(zb);
+    return 0;
 }
 
 /* Oersted field h = sum_s j_s x G(X_t - X_s) of a current density j ([3][N],
@@ -814,6 +917,12 @@ void or_set_Ms(or_ctx *c, const double *Ms) { memcpy(c->Ms, Ms, sizeof(double) *
 void or_demag(const or_ctx *c, const double *m, double *h)
 {
     long N = c->N, nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    if (c->demag_direct == 2 && !c->zb) {
+        /* created without a demag kernel: a loud NaN field */
+        for (long q = 0; q < 3 * N; q++)
+            h[q] = NAN;
+        return;
+    }
     if (c->zb) {
         /* layers: h_t(i, j) = sum_s sum K^{ts}(i - i', j - j') Ms m (direct) */
         long ox = 2 * nx - 1, oy = 2 * ny - 1, nl = ox * oy, total = nz * nz * nl;

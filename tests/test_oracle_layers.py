@@ -175,3 +175,21 @@ def test_equal_layers_reproduce_local_terms(orc):
     assert np.abs(o_lay.dmi(m) - o_eq.dmi(m)).max() < 1e-12 * np.abs(o_eq.dmi(m)).max()
     E1, E2 = o_eq.energy(m), o_lay.energy(m)
     assert np.abs(E1 - E2).max() < 1e-12 * np.abs(E1).max()
+
+
+def test_layer_demag_at_matches_full_sum(orc):
+    n, d = (7, 6, 4), (2e-9, 2.5e-9, 1e-9)
+    dz = [0.6e-9, 2.2e-9, 1.1e-9, 1.7e-9]
+    m, Ms = _layered_problem(n, 61)
+    for p in (1, 20):
+        full = orc.Oracle(n, d, Ms=Ms, p=p, layers=dz).demag(m).reshape(3, -1).T
+        at = orc.layer_demag_at(n, d, dz, m, np.arange(7 * 6 * 4), Ms=Ms, p=p)
+        assert np.abs(at - full).max() <= 1e-13 * np.abs(full).max()
+
+
+def test_no_demag_context_is_loud(orc):
+    o = orc.Oracle((4, 3, 2), (2e-9,) * 3, Ms=8e5, A=1e-11, demag=False)
+    m = W.random_unit_sphere((4, 3, 2), 3)
+    assert np.isnan(o.demag(m)).all()
+    ref = orc.Oracle((4, 3, 2), (2e-9,) * 3, Ms=8e5, A=1e-11).exchange(m)
+    assert np.array_equal(o.exchange(m), ref)

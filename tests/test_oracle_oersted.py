@@ -111,3 +111,15 @@ def test_oersted_term_and_energy(orc):
     assert abs(E[3] - ref) < 1e-13 * abs(ref) and E[4] == E[3]
     o.set_current(None)
     assert np.abs(o.heff(m, t)).max() == 0.0
+
+
+def test_oersted_at_matches_full_sum(orc):
+    # the sampled direct sum (near table + singular current) equals the
+    # full oracle field at every cell
+    n, d = (9, 7, 5), (2e-9, 1.5e-9, 2.5e-9)
+    j = W.rng(13).standard_normal((3, 5, 7, 9)) * 1e11
+    for p in (2, 20):
+        full = orc.Oracle(n, d, Ms=8e5, p=p).oersted(j).reshape(3, -1).T
+        cells = np.arange(9 * 7 * 5)
+        at = orc.oersted_at(n, d, j, cells, p=p)
+        assert np.abs(at - full).max() <= 1e-13 * np.abs(full).max()
