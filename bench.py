@@ -193,17 +193,17 @@ def layers(mm, W, iters):
 
 
 def oersted_bytes(grid):
-    """Algorithmic HBM bytes of one FP32 Oersted field evaluation: x forward,
-    y forward, z forward (zero padded), cross product with the kernel octant,
-    z inverse, y inverse, x inverse (current density in, field out)."""
+    """Algorithmic HBM bytes of one FP32 Oersted field evaluation: the demag
+    pass chain (x, y forward; z forward + cross product with the 3-component
+    kernel octant + z inverse; y, x inverse) reading the current density and
+    writing the field."""
     nx, ny, nz = grid
     P = [1 if n == 1 else 1 << (2 * n - 2).bit_length() for n in grid]
     hx = P[0] // 2 + 1 if P[0] > 1 else 1
     N = nx * ny * nz
-    s1, s2, s3 = 3 * nz * ny * hx * 8, 3 * nz * P[1] * hx * 8, 3 * P[2] * P[1] * hx * 8
+    s1, s2 = 3 * nz * ny * hx * 8, 3 * nz * P[1] * hx * 8
     g = 3 * (P[2] // 2 + 1) * (P[1] // 2 + 1) * hx * 4
-    return (12 * N + s1) + (s1 + s2) + (s2 + s3) + (2 * s3 + g) + (s3 + s2) + (s2 + s1) + \
-        (s1 + 24 * N)
+    return (12 * N + s1) + (s1 + s2) + (2 * s2 + g) + (s2 + s1) + (s1 + 24 * N)
 
 
 def oersted(mm, plan, cfg, iters):

@@ -55,7 +55,7 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->A_cell, p->D_cell, p->zw, p->lw, p->oe_G, p->oe_S3, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
+                    p->A_cell, p->D_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);

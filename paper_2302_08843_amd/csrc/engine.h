@@ -94,7 +94,6 @@ struct Plan {
     double *lw = nullptr;     // layered: nz doubles, the layer heights (energy weights)
     // Oersted field (allocated on first use)
     void *oe_G = nullptr;     // [3][Pz/2+1][Py/2+1][Hxp] real: Im of the kernel spectrum / (Px Py Pz)
-    void *oe_S3 = nullptr;    // [3][Pz][Py][Hxp] complex work spectrum
     void *h_oe = nullptr;     // 3N reals: field of the set current density
     bool oe_on = false;       // Oersted term present (mm_set_current)
     double oe_freq = 0.0;     // h_oe scaled by sin(2 pi f t) when f != 0
@@ -192,8 +191,9 @@ hipError_t start_norms(Plan &p, const T *y, const T *f0, const T *f1, double rto
 template <typename T>
 hipError_t count_magnetic(Plan &p, double *out_dev);
 // Oersted field h_out (3N) of the current density j (3N), both of the plan's
-// precision: FFT convolution with the cell-averaged Biot-Savart kernel.  The
-// kernel spectrum and the work spectrum are allocated on first use.
+// precision: FFT convolution with the cell-averaged Biot-Savart kernel, through
+// the demag passes with the cross product in the last-axis pass.  The kernel
+// spectrum is built and kept on first use.
 template <typename T>
 hipError_t oersted_field(Plan &p, const T *j, T *h_out);
 // Numbers of negative and positive entries of v (N values) into out_dev[0..1].

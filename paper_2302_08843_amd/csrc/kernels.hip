@@ -345,8 +345,10 @@ __device__ __forceinline__ const P& elem(const P* base, I idx)
 // components, forward transform, product with the spectral kernel, inverse
 // transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
 // Element (c, e) of the group is S[o + c*cs + e*es]; index arithmetic is done
-// in 32 bits when O32.
-template <typename T, int L, int AXIS, bool HALF, bool O32>
+// in 32 bits when O32.  PROD 0: the symmetric demag product with the six
+// folded real components; PROD 1: the Oersted product h = j x (i g) with the
+// three folded components g (imaginary spectrum, odd along its own axis).
+template <typename T, int L, int AXIS, bool HALF, bool O32, int PROD = 0>
 __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict__ Khat,
                                           int n_valid, long es_, long cs_, bool cv, int col, int g,
                                           int t, int b, cx<T>* lds, int Py, int Pz, long Kn_,
@@ -388,6 +390,19 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
             const int kyf = fy ? Py - ky : ky, kzf = fz ? Pz - kz : kz;
             const T sy = fy ? (T)-1 : (T)1, sz = fz ? (T)-1 : (T)1;
             const I kb = (I)kzf * plane + (I)kyf * (I)Hxp + (I)col;
+            if constexpr (PROD == 1) {
+                const T gx = elem<O32>(Khat, kb), gy = sy * elem<O32>(Khat, kb + Kn);
+                const T gz = sz * elem<O32>(Khat, kb + 2 * Kn);
+                const cx<T> jx = v[0][i], jy = v[1][i], jz = v[2][i];
+                // c = j x g, h = i c = (-c.im, c.re)
+                const cx<T> c0 = {jy.x * gz - jz.x * gy, jy.y * gz - jz.y * gy};
+                const cx<T> c1 = {jz.x * gx - jx.x * gz, jz.y * gx - jx.y * gz};
+                const cx<T> c2 = {jx.x * gy - jy.x * gx, jx.y * gy - jy.y * gx};
+                v[0][i] = {-c0.y, c0.x};
+                v[1][i] = {-c1.y, c1.x};
+                v[2][i] = {-c2.y, c2.x};
+                continue;
+            }
             const T kxx = elem<O32>(Khat, kb), kyy = elem<O32>(Khat, kb + Kn);
             const T kzz = elem<O32>(Khat, kb + 2 * Kn);
             const T kxy = sy * elem<O32>(Khat, kb + 3 * Kn), kxz = sz * elem<O32>(Khat, kb + 4 * Kn);
@@ -429,7 +444,7 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
 // XCD, same time), so the second read of each kernel row is an L2 hit rather
 // than a re-read after the rows have left L2.  AXIS = 1: pencils along y
 // (single layer), one group.  O32: spectra and kernel arrays below 4 GiB.
-template <typename T, int L, int AXIS, bool HALF, bool O32, bool ADJ>
+template <typename T, int L, int AXIS, bool HALF, bool O32, bool ADJ, int PROD = 0>
 __global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(
     cx<T>* S, const T* __restrict__ Khat, int n_valid, long es, long cs, long gstride, int ncols,
     int ntile, long nblocks, int Py, int Pz, long Kn, int Hxp, const cx<T>* __restrict__ tw,
@@ -458,12 +473,12 @@ __global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(
     const int b = threadIdx.x % kB, t = threadIdx.x / kB;
     const int col = tile * kB + b;
     const bool cv = col < ncols;
-    mid_group<T, L, AXIS, HALF, O32>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv, col, g,
-                                     t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    mid_group<T, L, AXIS, HALF, O32, PROD>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv,
+                                           col, g, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
     if (paired) {
         const int g2 = Py - g;
-        mid_group<T, L, AXIS, HALF, O32>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs, cv,
-                                         col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+        mid_group<T, L, AXIS, HALF, O32, PROD>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs,
+                                               cv, col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
     }
 }
 
@@ -914,7 +929,7 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
     return hipGetLastError();
 }
 
-template <typename T, int L, int AXIS>
+template <typename T, int L, int AXIS, int PROD = 0>
 static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, long cs,
                                long gstride, int G)
 {
@@ -926,17 +941,23 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
     const bool o32 = (size_t)p.S2n * 2 * sizeof(T) < (1ull << 32) &&
                      (size_t)p.Kn * 6 * sizeof(T) < (1ull << 32);
     const bool half = 2 * n_valid <= L && L > 1;
-    const bool adj = (sizeof(T) == 4 ? MMX_MID_ADJ_F32 : MMX_MID_ADJ_F64) && AXIS == 2 && G > 1;
+    // the Oersted product (PROD 1) uses the paired-in-block order only
+    const bool adj = PROD == 0 && (sizeof(T) == 4 ? MMX_MID_ADJ_F32 : MMX_MID_ADJ_F64) &&
+                     AXIS == 2 && G > 1;
     const long nb = adj ? 2 * nblocks : nblocks;
 #define MMX_KMID(H, O, AD)                                                                        \
-    k_mid<T, L, AXIS, H, O, AD><<<xcd_grid(nb), Gm::kB * Gm::kT, 0, p.stream>>>(                  \
+    k_mid<T, L, AXIS, H, O, AD, PROD><<<xcd_grid(nb), Gm::kB * Gm::kT, 0, p.stream>>>(            \
         S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntile, nb, p.P[1], p.P[2], p.Kn,     \
         p.Hxp, (const cx<T>*)p.tw, p.Lmax)
-#define MMX_KMID2(H, O)            \
-    if (adj)                       \
-        MMX_KMID(H, O, true);      \
-    else                           \
-        MMX_KMID(H, O, false);
+#define MMX_KMID2(H, O)                  \
+    if constexpr (PROD == 0) {           \
+        if (adj)                         \
+            MMX_KMID(H, O, true);        \
+        else                             \
+            MMX_KMID(H, O, false);       \
+    } else {                             \
+        MMX_KMID(H, O, false);           \
+    }
     if (half && o32) {
         MMX_KMID2(true, true)
     } else if (half) {
@@ -951,13 +972,13 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
     return hipGetLastError();
 }
 
-template <typename T, int AXIS>
+template <typename T, int AXIS, int PROD = 0>
 static hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long es, long cs,
                              long gstride, int G)
 {
     switch (L) {
 #define MMX_M(LL) \
-    case LL: return launch_mid_L<T, LL, AXIS>(p, S, n_valid, es, cs, gstride, G);
+    case LL: return launch_mid_L<T, LL, AXIS, PROD>(p, S, n_valid, es, cs, gstride, G);
         MMX_CASES(MMX_M)
 #undef MMX_M
     }
@@ -2208,41 +2229,15 @@ __global__ void k_oe_fold(T* __restrict__ G, const cx<double>* __restrict__ C, i
     G[q] = kx < Hx ? (T)(C[((long)kz * Py + ky) * Hxp + kx].y * scale) : (T)0;
 }
 
-// h^ = j^ x (i g) in place on S ([3][Pz][Py][Hxp]).
-template <typename T>
-__global__ void k_oe_product(cx<T>* __restrict__ S, const T* __restrict__ G, int Py, int Pz, int Hx,
-                             int Hxp, long s_comp, long g_comp)
-{
-    const long total = (long)Pz * Py * Hxp;
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const int kx = (int)(q % Hxp), ky = (int)((q / Hxp) % Py), kz = (int)(q / ((long)Hxp * Py));
-    if (kx >= Hx) return;
-    const bool uy = ky > Py / 2, uz = kz > Pz / 2;
-    const int kyf = uy ? Py - ky : ky, kzf = uz ? Pz - kz : kz;
-    const long gq = ((long)kzf * (Py / 2 + 1) + kyf) * Hxp + kx;
-    const T gx = G[gq], gy = uy ? -G[g_comp + gq] : G[g_comp + gq],
-            gz = uz ? -G[2 * g_comp + gq] : G[2 * g_comp + gq];
-    const cx<T> jx = S[q], jy = S[s_comp + q], jz = S[2 * s_comp + q];
-    // c = j x g (complex), h = i c = (-c.im, c.re)
-    const cx<T> cxv = {jy.x * gz - jz.x * gy, jy.y * gz - jz.y * gy};
-    const cx<T> cyv = {jz.x * gx - jx.x * gz, jz.y * gx - jx.y * gz};
-    const cx<T> czv = {jx.x * gy - jy.x * gx, jx.y * gy - jy.y * gx};
-    S[q] = {-cxv.y, cxv.x};
-    S[s_comp + q] = {-cyv.y, cyv.x};
-    S[2 * s_comp + q] = {-czv.y, czv.x};
-}
-
 template <typename T>
 static hipError_t oersted_setup(Plan& p)
 {
     const int Px = p.P[0], Py = p.P[1], Pz = p.P[2];
     const size_t es = sizeof(T);
     const long gn = (long)(Pz / 2 + 1) * (Py / 2 + 1) * p.Hxp;
-    if (!p.oe_S3) MMX_TRY(hipMalloc(&p.oe_S3, 3 * (size_t)Pz * Py * p.Hxp * 2 * es));
     if (p.oe_G) return hipSuccess;
     MMX_TRY(hipMalloc(&p.oe_G, 3 * (size_t)gn * es));
-    p.bytes += 3 * (size_t)Pz * Py * p.Hxp * 2 * es + 3 * (size_t)gn * es;
+    p.bytes += 3 * (size_t)gn * es;
     Scratch sc;
     const int lim = p.demag_p < 0 ? (1 << 30) : p.demag_p;
     const int nI = std::min(p.n[0] - 1, lim) + 1, nJ = std::min(p.n[1] - 1, lim) + 1,
@@ -2289,37 +2284,25 @@ hipError_t oersted_field(Plan& p, const T* j, T* h_out)
     MMX_TRY(oersted_setup<T>(p));
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
     const int Py = p.P[1], Pz = p.P[2];
-    const long s1c = (long)nz * ny * p.Hxp, s3c = (long)Pz * Py * p.Hxp;
+    const long s1c = (long)nz * ny * p.Hxp;
     cx<T>* S1 = (cx<T>*)p.S1;
-    cx<T>* S3 = (cx<T>*)p.oe_S3;
+    cx<T>* S2 = (cx<T>*)p.S2;
+    // the demag pass chain with the Oersted product in the last-axis pass
+    Plan q = p;
+    q.Khat = p.oe_G;
     MMX_TRY((launch_x_r2c<T, false>(p, p.P[0] / 2, j, nx, p.N, nx, nullptr, (T)1, S1, p.Hxp, s1c,
                                     ny * nz, 3)));
-    // y: S1 (ny rows per slab) -> S3 (Py rows, Pz slabs); a copy when Py = 1
-    if (Py > 1) {
-        MMX_TRY((launch_strided<T, -1>(p, Py, S1, S3, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s3c, nz,
-                                       (long)ny * p.Hxp, (long)Py * p.Hxp)));
+    if (Pz > 1) {
+        const long s2c = (long)nz * Py * p.Hxp;
+        if (Py > 1)
+            MMX_TRY((launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s2c,
+                                           nz, (long)ny * p.Hxp, (long)Py * p.Hxp)));
+        MMX_TRY((launch_mid<T, 2, 1>(q, Pz, S2, nz, (long)Py * p.Hxp, s2c, p.Hxp, Py)));
+        if (Py > 1)
+            MMX_TRY((launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c, s1c,
+                                          nz, (long)Py * p.Hxp, (long)ny * p.Hxp)));
     } else {
-        for (int c = 0; c < 3; ++c)
-            MMX_TRY(hipMemcpyAsync(S3 + c * s3c, S1 + c * s1c, sizeof(cx<T>) * nz * p.Hxp,
-                                   hipMemcpyDeviceToDevice, p.stream));
-    }
-    // z forward in place (nz -> Pz, zero padded), product, z inverse (Pz -> nz)
-    if (Pz > 1)
-        MMX_TRY((launch_strided<T, -1>(p, Pz, S3, S3, nz, Pz, (long)Py * p.Hxp, (long)Py * p.Hxp,
-                                       p.Hx, 3, s3c, s3c, Py, p.Hxp, p.Hxp)));
-    k_oe_product<T><<<blocks_for(s3c, 256), 256, 0, p.stream>>>(
-        S3, (const T*)p.oe_G, Py, Pz, p.Hx, p.Hxp, s3c, (long)(Pz / 2 + 1) * (Py / 2 + 1) * p.Hxp);
-    MMX_TRY(hipGetLastError());
-    if (Pz > 1)
-        MMX_TRY((launch_strided<T, 1>(p, Pz, S3, S3, Pz, nz, (long)Py * p.Hxp, (long)Py * p.Hxp,
-                                      p.Hx, 3, s3c, s3c, Py, p.Hxp, p.Hxp)));
-    if (Py > 1) {
-        MMX_TRY((launch_strided<T, 1>(p, Py, S3, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s3c, s1c, nz,
-                                      (long)Py * p.Hxp, (long)ny * p.Hxp)));
-    } else {
-        for (int c = 0; c < 3; ++c)
-            MMX_TRY(hipMemcpyAsync(S1 + c * s1c, S3 + c * s3c, sizeof(cx<T>) * nz * p.Hxp,
-                                   hipMemcpyDeviceToDevice, p.stream));
+        MMX_TRY((launch_mid<T, 1, 1>(q, Py, S1, ny, p.Hxp, s1c, 0, 1)));
     }
     // x inverse: the raw convolution at every cell (uniform Ms 1, no other term)
     LocalParams P{};
@@ -2331,9 +2314,9 @@ hipError_t oersted_field(Plan& p, const T* j, T* h_out)
     P.Hxp = p.Hxp;
     P.with_demag = 1;
     P.Ms = 1.0;
-    Plan q = p;
-    q.percell_A = q.percell_D = q.layered = false;
-    return launch_local<T, false, 0>(q, p.P[0] / 2, j, h_out, nullptr, P, nullptr);
+    Plan r = p;
+    r.percell_A = r.percell_D = r.layered = false;
+    return launch_local<T, false, 0>(r, p.P[0] / 2, j, h_out, nullptr, P, nullptr);
 }
 
 template <typename T>
