@@ -56,3 +56,25 @@ def test_invalid_arguments_rejected_without_device():
     assert L.mm_heff(None, None, None, 15, 0.0, None) == mm.MM_EINVAL
     assert L.mm_energy(None, None, None, 15, 0.0, None) == mm.MM_EINVAL
     L.mm_plan_destroy(None)
+
+
+def test_next_row_entry_points_reject_invalid_arguments_without_device():
+    """Per-cell exchange, DMI, the Oersted field and thin layers: invalid
+    handles, types and heights are refused before any device work."""
+    from paper_2302_08843_amd import mm
+
+    L = mm.lib()
+    assert L.mm_set_exchange(None, None) == mm.MM_EINVAL
+    assert L.mm_set_dmi(None, mm.MM_DMI_BULK, 1e-3, None) == mm.MM_EINVAL
+    assert L.mm_oersted(None, None, None) == mm.MM_EINVAL
+    assert L.mm_set_current(None, None, 0.0) == mm.MM_EINVAL
+    o = mm.mm_opts_default()
+    assert not o.dz_layers and o.ku2 == o.kc1 == o.kc2 == 0.0
+    for heights in ([1e-9, -1e-9, 1e-9], [1e-9, float("nan"), 1e-9], [1e-9] * 17):
+        arr = (C.c_double * len(heights))(*heights)
+        o.dz_layers = C.cast(arr, C.POINTER(C.c_double))
+        with pytest.raises(mm.MMError) as ei:
+            mm.mm_plan_create((4, 4, len(heights)), (1e-9,) * 3, 8e5, 1e-11, 0, 0.5, opts=o)
+        assert ei.value.status == mm.MM_EINVAL
+    assert mm.MM_ALL == (mm.MM_DEMAG | mm.MM_EXCH | mm.MM_ANIS | mm.MM_ZEEMAN | mm.MM_DMI |
+                         mm.MM_OERSTED)
