@@ -63,7 +63,7 @@ def measured_traffic(grid):
     for fn in rec["sources"]:
         with open(os.path.join(ROOT, fn), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec["source_sha256"]:
+    if h.hexdigest() != rec.get("source_sha256") or "read_bytes" not in rec:
         return None
     return rec["read_bytes"] + rec["write_bytes"]
 
