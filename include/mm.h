@@ -11,10 +11,17 @@
  *     beyond (Sec. 4.4, Eqs. convolution and dipole), the 6-neighbour
  *     exchange stencil with dm/dn = 0 (Sec. 4.2), first-order uniaxial
  *     anisotropy (Sec. 4.1) and a uniform external field;
+ *   - further terms: second-order uniaxial and cubic anisotropy, per-cell
+ *     exchange constants and DMI of the interface, bulk and D2d types
+ *     (Sec. 4.2, 4.3), the Oersted field of a current density (Sec. 4.5);
+ *   - thin layers of unequal height with the layers coupled densely per
+ *     lateral frequency (the non-equidistant case of Sec. 4.4);
  *   - the LLG equation (Sec. 3, Eq. llg) integrated by an adaptive
- *     Dormand-Prince 5(4) Runge-Kutta pair;
+ *     Dormand-Prince 5(4) or Runge-Kutta-Fehlberg 4(5) pair;
  *   - relaxation with high damping and no precession term (Sec. 3);
- *   - the linear-term energies (Sec. 4, Eqs. linear_energy(_discrete)).
+ *   - the linear-term energies (Sec. 4, Eqs. linear_energy(_discrete));
+ *   - reverse-mode gradients for inverse design (Sec. 5.2) and a request
+ *     server for many concurrent solves on one GPU.
  *
  * Units are SI: lengths in m, Ms and h in A/m, A in J/m, Ku in J/m^3, t in s.
  * gamma = 2.21e5 m/(A s) as printed with Eq. llg; mu0 = 4 pi 1e-7.
