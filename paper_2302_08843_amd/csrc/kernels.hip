@@ -1018,6 +1018,8 @@ static hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
 // Small vector kernels and deterministic reductions.
 // ---------------------------------------------------------------------------
 constexpr int kRedBlocks = 512;
+constexpr int kErrBlocks = 2048;  // error norm: 2 kErrBlocks partials <= kRedSlots
+static_assert(2 * kErrBlocks <= kRedSlots, "error-norm partials exceed the reduction buffer");
 
 __device__ inline double block_sum(double v)
 {
@@ -1186,7 +1188,7 @@ __global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
     bad = block_sum(bad);
     if (threadIdx.x == 0) {
         partials[blockIdx.x] = acc;
-        partials[kRedBlocks + blockIdx.x] = bad;
+        partials[gridDim.x + blockIdx.x] = bad;
     }
 }
 
@@ -2465,27 +2467,32 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
         vec = vec && aligned16(ks.p[j]);
     }
     const T* msc = p.percell ? (const T*)p.Ms_cell : nullptr;
+    // a streaming reduction: about 16 (vector) elements per thread, up to
+    // kErrBlocks blocks, so large grids keep 8 waves per SIMD resident and
+    // small ones launch few blocks (partials: sums in [0, nb), non-finite
+    // counts in [nb, 2 nb)); nb depends on the grid only
+    const long nv = 3 * p.N / (vec ? V16<T>::n : 1);
+    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(nv, kBlock * 16)));
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
         if (vec && p.percell)
-            k_err_norm<T, true, true><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
-                                                                           rtol, atol, p.red);
+            k_err_norm<T, true, true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
+                                                                   atol, p.red);
         else if (vec)
-            k_err_norm<T, true, false><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
-                                                                            rtol, atol, p.red);
+            k_err_norm<T, true, false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
+                                                                    atol, p.red);
         else if (p.percell)
-            k_err_norm<T, false, true><<<kRedBlocks, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N,
-                                                                            msc, rtol, atol, p.red);
+            k_err_norm<T, false, true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
+                                                                    atol, p.red);
         else
-            k_err_norm<T, false, false><<<kRedBlocks, kBlock, 0, p.stream>>>(
-                y, y1, cf, ks, p.N, msc, rtol, atol, p.red);
+            k_err_norm<T, false, false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
+                                                                     atol, p.red);
         return hipGetLastError();
     }));
     const double cnt = 3.0 * (double)p.n_magnetic;
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0,
-                                            cnt > 0 ? 1.0 / cnt : 0.0, 1);
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, cnt > 0 ? 1.0 / cnt : 0.0, 1);
     MMX_TRY(hipGetLastError());
     // out_dev[5]: number of non-finite entries of the current state y
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + kRedBlocks, kRedBlocks, out_dev, 5, 1.0, 0);
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
     return hipGetLastError();
 }
 
