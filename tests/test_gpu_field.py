@@ -240,3 +240,26 @@ def test_higher_order_anisotropy_matches_oracle(torch_cuda, mm, orc, prec):
     # the differentiation entry points refuse a field that is not linear in m
     with pytest.raises(mm.MMError):
         plan.heff_vjp(mt, mt, mm.MM_ALL)
+
+
+MAX_AXIS_GRIDS = [(512, 2, 1), (2, 512, 1), (1, 2, 512), (3, 3, 300), (512, 1, 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid", MAX_AXIS_GRIDS)
+def test_max_extent_per_axis(torch_cuda, mm, orc, prec, grid):
+    """The largest extent along each axis (512 cells, padded FFT length 1024)
+    in each pass: x (F1/I1), y (F2/I2 or the single-layer y pass), z (F3)."""
+    banner("max extent %s %s" % (grid, prec))
+    d = (2e-9, 2.5e-9, 1.5e-9)
+    m, Ms = _random_problem(grid, 33, percell=True, vacuum=True)
+    plan = mm.Plan(grid, d, Ms=1.0, A=1.2e-11, Ku=3e4, alpha=0.3, prec=prec)
+    plan.set_ms(Ms)
+    o = orc.Oracle(grid, d, Ms=Ms, A=np.where(Ms > 0, 1.2e-11, 0.0), Ku=3e4, alpha=0.3)
+    H = np.array([1e4, -2e4, 5e3])
+    o.set_field(H)
+    mt = plan._t(m)
+    for terms in (mm.MM_DEMAG, mm.MM_ALL):
+        e = rel_l2(to_np(plan.heff(mt, H, terms)), o.heff(m, 0.0, terms))
+        print("  terms %d rel-L2 %.2e" % (terms, e))
+        assert e <= TOL[prec], (terms, e)
