@@ -79,6 +79,7 @@ def lib():
         L.or_set_anisotropy2.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp, dp]
         L.or_set_dmi.argtypes = [C.c_void_p, C.c_void_p, C.c_int]
         L.or_set_layers.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_set_ku.argtypes = [C.c_void_p, C.c_void_p]
         L.or_oersted_entry.argtypes = [dp, C.c_long, C.c_long, C.c_long, C.c_int, dp]
         L.or_oersted.argtypes = [C.c_void_p, dp, dp]
         L.or_oersted.restype = C.c_int
@@ -292,6 +293,15 @@ class Oracle:
         self.layers = None
         if layers is not None:
             self.set_layers(layers)
+
+    def set_ku(self, Ku):
+        """Per-cell first-order uniaxial constant (scalar or (nz, ny, nx));
+        None restores the uniform Ku."""
+        if Ku is None:
+            lib().or_set_ku(self._c, None)
+            return
+        self.Kuc = np.ascontiguousarray(np.broadcast_to(np.asarray(Ku, np.float64), self.shape).copy())
+        lib().or_set_ku(self._c, self.Kuc.ctypes.data)
 
     def set_layers(self, dz):
         """Thin layers of heights dz[0..nz) (the non-equidistant case of

@@ -523,6 +523,7 @@ typedef struct or_ctx {
     double *Ms;      /* per cell, A/m; 0 marks a vacuum cell               */
     double *A;       /* per cell exchange constant, J/m                    */
     double Ku;       /* first-order uniaxial anisotropy constant, J/m^3    */
+    double *Kuc;     /* per-cell first-order constant, or NULL (uniform Ku) */
     double eu[3];    /* easy axis (unit)                                   */
     double Ku2;      /* second-order uniaxial constant, J/m^3              */
     double Kc1, Kc2; /* first- and second-order cubic constants, J/m^3     */
@@ -875,10 +876,24 @@ int or_set_current(or_ctx *c, const double *j, double freq)
     return 0;
 }
 
+/* Per-cell first-order uniaxial anisotropy constant (J/m^3, N values along
+ * the common easy axis); NULL restores the uniform Ku.  The material of
+ * Sec. 2 may vary per cell for every parameter. */
+void or_set_ku(or_ctx *c, const double *Ku)
+{
+    free(c->Kuc);
+    c->Kuc = NULL;
+    if (!Ku)
+        return;
+    c->Kuc = malloc(sizeof(double) * c->N);
+    memcpy(c->Kuc, Ku, sizeof(double) * c->N);
+}
+
 void or_destroy(or_ctx *c)
 {
     if (!c)
         return;
+    free(c->Kuc);
     free(c->h_oe);
     free(c->zb);
     free(c->Klay);
@@ -1063,7 +1078,8 @@ void or_anisotropy(const or_ctx *c, const double *m, double *h)
         double M[3] = {m[t], m[N + t], m[2 * N + t]};
         double em = c->eu[0] * M[0] + c->eu[1] * M[1] + c->eu[2] * M[2];
         /* uniaxial: (2 Ku1 em + 4 Ku2 em^3) e / (mu0 Ms) */
-        double pu = (2.0 * c->Ku * em + 4.0 * c->Ku2 * em * em * em) / (OR_MU0 * c->Ms[t]);
+        double ku = c->Kuc ? c->Kuc[t] : c->Ku;
+        double pu = (2.0 * ku * em + 4.0 * c->Ku2 * em * em * em) / (OR_MU0 * c->Ms[t]);
         /* cubic, in the principal axes: -2 Kc1 m_i (m_j^2 + m_k^2) - 2 Kc2 m_i m_j^2 m_k^2,
          * over mu0 Ms, mapped back along c_i */
         double p[3];
@@ -1100,7 +1116,7 @@ static double anisotropy_energy(const or_ctx *c, const double *m)
             p[i] = c->ec[i][0] * M[0] + c->ec[i][1] * M[1] + c->ec[i][2] * M[2];
         double q1 = p[0] * p[0], q2 = p[1] * p[1], q3 = p[2] * p[2];
         acc += (long double)layer_volume(c, t / (c->n[0] * c->n[1])) *
-               (-c->Ku * em * em - c->Ku2 * em * em * em * em +
+               (-(c->Kuc ? c->Kuc[t] : c->Ku) * em * em - c->Ku2 * em * em * em * em +
                 c->Kc1 * (q1 * q2 + q2 * q3 + q3 * q1) + c->Kc2 * q1 * q2 * q3);
     }
     return (double)acc;
@@ -1759,7 +1775,7 @@ void or_heff_vjp(or_ctx *c, const double *m, const double *w, unsigned mask, dou
                 continue;
             double ew = c->eu[0] * w[q] + c->eu[1] * w[N + q] + c->eu[2] * w[2 * N + q];
             double em = c->eu[0] * m[q] + c->eu[1] * m[N + q] + c->eu[2] * m[2 * N + q];
-            double pre = 2.0 * c->Ku / (OR_MU0 * c->Ms[q]);
+            double pre = 2.0 * (c->Kuc ? c->Kuc[q] : c->Ku) / (OR_MU0 * c->Ms[q]);
             for (int a = 0; a < 3; a++)
                 grad_m[a * N + q] += pre * c->eu[a] * ew;
             if (grad_ms)

@@ -214,3 +214,35 @@ def test_cubic_axes_and_covariance(orc):
     h0 = o0.anisotropy(m.reshape(3, 1, 1, 1)).ravel()
     h1 = o1.anisotropy((R @ m).reshape(3, 1, 1, 1)).ravel()
     assert np.abs(h1 - R @ h0).max() <= 1e-12 * np.abs(h0).max()
+
+
+def test_per_cell_uniaxial_constant(orc):
+    """Per-cell Ku: the field and energy are the per-cell textbook forms
+    h = 2 Ku_i/(mu0 Ms_i) e (e.m), E = -V sum Ku_i (e.m)^2; a uniform array
+    equals the scalar; the energy gradient is -mu0 V Ms h."""
+    n, d = (4, 3, 2), (2e-9, 2.5e-9, 3e-9)
+    g = W.rng(71)
+    Ms = g.uniform(4e5, 1e6, (2, 3, 4))
+    Ku = g.uniform(-2e4, 5e4, (2, 3, 4))
+    eu = np.array([2.0, 1.0, 2.0]) / 3.0
+    o = orc.Oracle(n, d, Ms=Ms, Ku=1e4, eu=eu)
+    o.set_ku(Ku)
+    o.set_field((0, 0, 0), terms=orc.ANIS)
+    m = W.random_unit_sphere(n, 72) * 0.9
+    em = np.einsum("a,a...->...", eu, m)
+    h = o.anisotropy(m)
+    assert np.allclose(h, 2 * Ku / (MU0 * Ms) * em * eu[:, None, None, None], rtol=1e-14, atol=0)
+    V = d[0] * d[1] * d[2]
+    E = o.energy(m)
+    assert abs(E[2] - (-V * (Ku * em ** 2).sum())) < 1e-13 * abs(E[2])
+    eps = 1e-6
+    grad = np.zeros_like(m)
+    for q in np.ndindex(m.shape):
+        mp_, mm_ = m.copy(), m.copy()
+        mp_[q] += eps
+        mm_[q] -= eps
+        grad[q] = (o.energy(mp_)[4] - o.energy(mm_)[4]) / (2 * eps)
+    assert np.abs(grad + MU0 * V * Ms[None] * h).max() < 1e-7 * np.abs(MU0 * V * Ms * h).max()
+    o.set_ku(np.full((2, 3, 4), 3e4))
+    ref = orc.Oracle(n, d, Ms=Ms, Ku=3e4, eu=eu).anisotropy(m)
+    assert np.array_equal(o.anisotropy(m), ref)
