@@ -163,6 +163,14 @@ mm_status mm_set_ms(mm_plan *p, const void *Ms_cell);
  * a plan that uses it with MM_EXCH. */
 mm_status mm_set_exchange(mm_plan *p, const void *A_cell);
 
+/* Set a per-cell first-order uniaxial anisotropy constant (Sec. 4.1, J/m^3,
+ * along the plan's easy axis): Ku_cell is a device buffer of N values in the
+ * plan's precision, copied into the plan (stream-ordered).  The field
+ * 2 Ku_i/(mu0 Ms_i) e (e.m) and the energy density -Ku_i (e.m)^2 use it per
+ * cell.  NULL restores the uniform Ku of mm_plan_create.  The
+ * differentiation entry points reject a plan that uses it with MM_ANIS. */
+mm_status mm_set_ku(mm_plan *p, const void *Ku_cell);
+
 /* Set the DMI term (Sec. 4.3): h_i = 2/(mu0 Ms_i) sum_{k=+-x,+-y,+-z}
  * D~_{i,k} (e^dmi_k x m_{i+e_k}) / (2 Delta_k) with e^dmi_{-k} = -e^dmi_k and
  * the DMI vectors of `type` (MM_DMI_*).  D is a uniform strength in J/m^2;

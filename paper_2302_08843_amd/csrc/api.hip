@@ -55,7 +55,7 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
-                    p->A_cell, p->D_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
+                    p->A_cell, p->D_cell, p->Ku_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -784,10 +784,12 @@ static bool nonlinear_anis(const Plan* p, unsigned terms)
     return (terms & MM_ANIS) && (p->Ku2 != 0.0 || p->Kc1 != 0.0 || p->Kc2 != 0.0);
 }
 
-// The transposed operators cover the uniform-A exchange stencil only.
+// The transposed operators cover the uniform-A exchange stencil and the
+// uniform uniaxial constant only.
 static bool stencil_extended(const Plan* p, unsigned terms)
 {
-    return ((terms & MM_EXCH) && p->percell_A) || ((terms & MM_DMI) && p->dmi);
+    return ((terms & MM_EXCH) && p->percell_A) || ((terms & MM_DMI) && p->dmi) ||
+           ((terms & MM_ANIS) && p->percell_Ku);
 }
 
 template <typename T>
@@ -799,7 +801,7 @@ static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hex
         return MM_EINVAL;
     }
     if (stencil_extended(p, terms)) {
-        set_error("per-cell exchange and DMI have no transposed operator");
+        set_error("per-cell exchange, per-cell Ku and DMI have no transposed operator");
         return MM_EINVAL;
     }
     if (p->layered) {
@@ -1020,6 +1022,23 @@ mm_status mm_set_exchange(mm_plan* pl, const void* A_cell)
     mm_status s = copy_cell_field(p, &p->A_cell, A_cell, "per-cell exchange constant");
     if (s != MM_OK) return s;
     p->percell_A = true;
+    return MM_OK;
+}
+
+mm_status mm_set_ku(mm_plan* pl, const void* Ku_cell)
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p) {
+        set_error("null plan");
+        return MM_EINVAL;
+    }
+    if (!Ku_cell) {
+        p->percell_Ku = false;
+        return MM_OK;
+    }
+    mm_status s = copy_cell_field(p, &p->Ku_cell, Ku_cell, "per-cell uniaxial constant");
+    if (s != MM_OK) return s;
+    p->percell_Ku = true;
     return MM_OK;
 }
 
@@ -1310,7 +1329,7 @@ mm_status mm_rk4_adjoint(mm_plan* pl, const void* ckpt, const double h_ext[3], u
         return MM_EINVAL;
     }
     if (p && (stencil_extended(p, terms) || p->layered)) {
-        set_error("per-cell exchange, DMI and thin layers have no adjoint");
+        set_error("per-cell exchange, per-cell Ku, DMI and thin layers have no adjoint");
         return MM_EINVAL;
     }
     if (!p || !ckpt || !region || nsteps <= 0 || !(dt > 0.0) || ckpt_every <= 0) {

@@ -66,6 +66,7 @@ struct Plan {
     int demag_p;
     bool percell;  // per-cell Ms present
     bool percell_A;  // per-cell exchange constant present (A_cell)
+    bool percell_Ku = false;  // per-cell first-order uniaxial constant present (Ku_cell)
     bool dmi;        // DMI term present
     int dmi_type;    // MM_DMI_INTERFACE / _BULK / _D2D
     double D;        // uniform DMI strength (ignored with D_cell)
@@ -89,6 +90,7 @@ struct Plan {
     void *tw = nullptr;       // Lmax complex roots exp(-2 pi i n / Lmax)
     void *Ms_cell = nullptr;  // N reals, or null
     void *A_cell = nullptr;   // N reals (per-cell exchange constant), or null
+    void *Ku_cell = nullptr;  // N reals (per-cell uniaxial constant), or null
     void *D_cell = nullptr;   // N reals (per-cell DMI strength), or null
     void *zw = nullptr;       // layered: 4 reals per layer (z exchange down/up, 1/(2 dz_k), 0)
     double *lw = nullptr;     // layered: nz doubles, the layer heights (energy weights)

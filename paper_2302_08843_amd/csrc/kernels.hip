@@ -632,8 +632,11 @@ __device__ __forceinline__ T dmi_avg(T a, T b)
 // per-cell exchange constants A_cell with the harmonic-mean coupling (Sec.
 // 4.2), P.exch then being 2 / mu0; EXT_PD takes per-cell DMI strengths D_cell
 // with the coupling of Eq. D_avg, P.dmi then being 2 / mu0; EXT_MIX adds the
-// opposite-sign case of that average (D_cell holds both signs).
-constexpr int EXT_DMI = 1, EXT_PA = 2, EXT_PD = 4, EXT_MIX = 8;
+// opposite-sign case of that average (D_cell holds both signs).  Every
+// variant but the plain one (EXT 0) reads a per-cell uniaxial constant
+// Ku_cell when given one (P.anis then 2 / mu0); EXT_PK alone is the variant
+// for a per-cell Ku without the other extensions.
+constexpr int EXT_DMI = 1, EXT_PA = 2, EXT_PD = 4, EXT_MIX = 8, EXT_PK = 16;
 
 template <typename T, int M, bool PERCELL, int EXT>
 __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
@@ -641,7 +644,7 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
     LocalParams P, double* torque, int njt, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
     const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
-    const T* __restrict__ h_oe)
+    const T* __restrict__ h_oe, const T* __restrict__ Ku_cell)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
     constexpr bool kMIX = EXT & EXT_MIX;
@@ -740,7 +743,11 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
             }
             if (P.with_anis) {
                 const T em = eux * mx + euy * my + euz * mz;
-                const T ca = anis * inv_ms * em;
+                // per-cell Ku (extended variants only): P.anis is then 2 / mu0
+                T ka = anis;
+                if constexpr (EXT != 0)
+                    if (Ku_cell) ka *= Ku_cell[cell];
+                const T ca = ka * inv_ms * em;
                 hx += ca * eux;
                 hy += ca * euy;
                 hz += ca * euz;
@@ -997,7 +1004,8 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, njt, nblocks,
         (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
         (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
-        P.with_oe ? (const T*)p.h_oe : nullptr);
+        P.with_oe ? (const T*)p.h_oe : nullptr,
+        EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr);
     return hipGetLastError();
 }
 
@@ -1324,7 +1332,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
                                                         const T* __restrict__ Ms_cell, double Ms,
                                                         long N, AnisE A, double* partials,
-                                                        const double* __restrict__ lw, long nxy)
+                                                        const double* __restrict__ lw, long nxy,
+                                                        const T* __restrict__ Ku_cell)
 {
     double acc = 0.0;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
@@ -1336,8 +1345,9 @@ __global__ __launch_bounds__(kBlock) void k_anis_energy(const T* __restrict__ m,
         double pr[3];
         for (int a = 0; a < 3; ++a) pr[a] = A.ec[a][0] * mx + A.ec[a][1] * my + A.ec[a][2] * mz;
         const double q0 = pr[0] * pr[0], q1 = pr[1] * pr[1], q2 = pr[2] * pr[2];
+        const double ku1 = Ku_cell ? (double)Ku_cell[q] : A.ku1;
         acc += (lw ? lw[q / nxy] : 1.0) *
-               (-A.ku1 * em * em - A.ku2 * em * em * em * em +
+               (-ku1 * em * em - A.ku2 * em * em * em * em +
                 A.kc1 * (q0 * q1 + q1 * q2 + q2 * q0) + A.kc2 * q0 * q1 * q2);
     }
     acc = block_sum(acc);
@@ -2346,15 +2356,16 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.with_dmi = (terms & MM_DMI) && p.dmi ? 1 : 0;
     // stencil variant (EXT_* bits); a per-cell constant moves into the
     // neighbour-pair average, leaving 2 / mu0 as the prefactor
-    const int ext = (P.with_dmi ? EXT_DMI : 0) | (P.with_exch && p.percell_A ? EXT_PA : 0) |
-                    (P.with_dmi && p.percell_D ? EXT_PD : 0) |
-                    (P.with_dmi && p.percell_D && p.dmi_mixed ? EXT_MIX : 0);
+    int ext = (P.with_dmi ? EXT_DMI : 0) | (P.with_exch && p.percell_A ? EXT_PA : 0) |
+              (P.with_dmi && p.percell_D ? EXT_PD : 0) |
+              (P.with_dmi && p.percell_D && p.dmi_mixed ? EXT_MIX : 0);
+    if (ext == 0 && (terms & MM_ANIS) && p.percell_Ku) ext = EXT_PK;
     P.dmi = 2.0 * ((ext & EXT_PD) ? 1.0 : p.D) / kMu0;
     for (int k = 0; k < 3; ++k)
         for (int a = 0; a < 3; ++a)
             P.edmi[k][a] = p.edmi[k][a] / (k == 2 && p.layered ? 1.0 : 2.0 * p.d[k]);
     P.with_anis_hi = p.Ku2 != 0.0 || p.Kc1 != 0.0 || p.Kc2 != 0.0 ? 1 : 0;
-    P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi) ? 1 : 0;
+    P.with_anis = (terms & MM_ANIS) && (p.Ku != 0.0 || P.with_anis_hi || p.percell_Ku) ? 1 : 0;
     P.with_zee = (terms & MM_ZEEMAN) ? 1 : 0;
     P.with_oe = (terms & MM_OERSTED) && p.oe_on ? 1 : 0;
     P.oe_scale = p.oe_freq != 0.0 ? sin(2.0 * M_PI * p.oe_freq * t) : 1.0;
@@ -2368,7 +2379,7 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
     P.idx2 = 1.0 / (p.d[0] * p.d[0]);
     P.idy2 = 1.0 / (p.d[1] * p.d[1]);
     P.idz2 = 1.0 / (p.d[2] * p.d[2]);
-    P.anis = 2.0 * p.Ku / kMu0;
+    P.anis = 2.0 * (p.percell_Ku ? 1.0 : p.Ku) / kMu0;
     for (int a = 0; a < 3; ++a) {
         P.eu[a] = p.eu[a];
         P.H[a] = hext ? hext[a] : 0.0;
@@ -2400,6 +2411,7 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
             MMX_X(EXT_DMI | EXT_PA | EXT_PD)
             MMX_X(EXT_DMI | EXT_PD | EXT_MIX)
             MMX_X(EXT_DMI | EXT_PA | EXT_PD | EXT_MIX)
+            MMX_X(EXT_PK)
 #undef MMX_X
         }
         return hipErrorInvalidValue;
@@ -2545,7 +2557,8 @@ hipError_t anis_energy(Plan& p, const T* m, double* out_dev)
     }
     k_anis_energy<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
         m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, p.red,
-        p.layered ? p.lw : nullptr, (long)p.n[0] * p.n[1]);
+        p.layered ? p.lw : nullptr, (long)p.n[0] * p.n[1],
+        p.percell_Ku ? (const T*)p.Ku_cell : nullptr);
     MMX_TRY(hipGetLastError());
     k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();

@@ -30,8 +30,8 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4:
 
 # Every entry point declared in include/mm.h.
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
-           "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_oersted",
-           "mm_set_current", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
+           "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi",
+           "mm_oersted", "mm_set_current", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
            "mm_debug_kernel", "mm_debug_spectrum", "mm_last_error", "mm_heff_vjp",
            "mm_llg_rhs_vjp", "mm_rk4_forward", "mm_rk4_adjoint", "mm_serve_opts_default",
@@ -121,6 +121,7 @@ def lib():
         L.mm_plan_padded.restype = None
         L.mm_set_ms.argtypes = [vp, vp]
         L.mm_set_exchange.argtypes = [vp, vp]
+        L.mm_set_ku.argtypes = [vp, vp]
         L.mm_set_dmi.argtypes = [vp, C.c_int, C.c_double, vp]
         L.mm_oersted.argtypes = [vp, vp, vp]
         L.mm_set_current.argtypes = [vp, vp, C.c_double]
@@ -154,7 +155,8 @@ def lib():
         L.mm_rk4_adjoint.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
                                      C.c_long, vp, vp, dp]
         L.mm_last_error.restype = C.c_char_p
-        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_dmi", "mm_oersted", "mm_set_current",
+        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi", "mm_oersted",
+                     "mm_set_current",
                      "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
                      "mm_profile_read", "mm_debug_kernel", "mm_debug_spectrum", "mm_heff_vjp",
@@ -229,6 +231,10 @@ def mm_set_ms(plan, Ms_cell):
 
 def mm_set_exchange(plan, A_cell):
     _check(lib().mm_set_exchange(plan, None if A_cell is None else _ptr(A_cell)))
+
+
+def mm_set_ku(plan, Ku_cell):
+    _check(lib().mm_set_ku(plan, None if Ku_cell is None else _ptr(Ku_cell)))
 
 
 def mm_set_dmi(plan, kind, D, D_cell):
@@ -457,6 +463,17 @@ class Plan:
             return
         nx, ny, nz = self.grid
         mm_set_exchange(self.handle, self._t(A_cell).reshape(nz, ny, nx).contiguous())
+        torch.cuda.current_stream().synchronize()
+
+    def set_ku(self, Ku_cell):
+        """Per-cell first-order uniaxial constant (None: the uniform Ku)."""
+        import torch
+
+        if Ku_cell is None:
+            mm_set_ku(self.handle, None)
+            return
+        nx, ny, nz = self.grid
+        mm_set_ku(self.handle, self._t(Ku_cell).reshape(nz, ny, nx).contiguous())
         torch.cuda.current_stream().synchronize()
 
     def set_dmi(self, D, kind=MM_DMI_INTERFACE):

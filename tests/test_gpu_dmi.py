@@ -158,3 +158,40 @@ def test_extended_stencil_rejected_by_differentiation(torch_cuda, mm):
     plan.heff_vjp(m, m, mm.MM_ALL)
     with pytest.raises(mm.MMError):
         plan.set_dmi(1e-3, 7)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_per_cell_ku_matches_oracle(torch_cuda, mm, orc, prec):
+    """Per-cell first-order uniaxial constant (both signs) with per-cell Ms
+    and vacuum, alone and with every other term; the density-form energy."""
+    grid = (29, 13, 4)
+    banner("per-cell Ku %s %s" % (prec, grid))
+    d = (2e-9, 2e-9, 3e-9)
+    Ms, A, g = _materials(grid, 101)
+    Ku = g.uniform(-3e4, 6e4, Ms.shape)
+    eu = np.array([0.48, 0.6, 0.64])
+    m = W.random_unit_sphere(grid, 102)
+    H = np.array([1e4, -1e4, 2e4])
+    plan = mm.Plan(grid, d, Ms=1.0, A=1.2e-11, Ku=1e4, alpha=0.2, prec=prec, ku_axis=eu,
+                   Ku2=5e3)
+    plan.set_ms(Ms)
+    plan.set_ku(Ku)
+    o = orc.Oracle(grid, d, Ms=Ms, A=np.where(Ms > 0, 1.2e-11, 0.0), Ku=1e4, eu=eu / np.linalg.norm(eu),
+                   alpha=0.2)
+    o.set_anisotropy2(Ku2=5e3)
+    o.set_ku(Ku)
+    o.set_field(H)
+    mt = plan._t(m)
+    for terms in (mm.MM_ANIS, mm.MM_ALL):
+        e = rel_l2(to_np(plan.heff(mt, H, terms)), o.heff(m, 0.0, terms))
+        print("  terms %d rel-L2 %.2e" % (terms, e))
+        assert e <= TOL[prec], (terms, e)
+    E, Er = plan.energy(mt, H, mm.MM_ALL), o.energy(m)
+    assert abs(E[2] - Er[2]) <= (1e-12 if prec == "fp64" else 2e-5) * abs(Er[2])
+    plan2 = mm.Plan(grid, d, Ms=8e5, A=1.2e-11, Ku=1e4, prec=prec, ku_axis=eu)
+    plan2.set_ku(Ku)
+    m2 = plan2._t(m)
+    with pytest.raises(mm.MMError):
+        plan2.heff_vjp(m2, m2, mm.MM_ALL)
+    plan2.set_ku(None)
+    plan2.heff_vjp(m2, m2, mm.MM_ALL)
