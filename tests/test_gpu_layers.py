@@ -140,3 +140,37 @@ def test_layered_plan_rejections(torch_cuda, mm):
         mm.Plan(grid, (2e-9,) * 3, Ms=8e5, prec="fp64", layers=[1e-9, -1e-9, 1e-9])
     with pytest.raises(mm.MMError):
         mm.Plan((8, 8, 17), (2e-9,) * 3, Ms=8e5, prec="fp64", layers=[1e-9] * 17)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_layered_per_cell_materials(torch_cuda, mm, orc, prec):
+    """Thin layers with per-cell Ms (vacuum spacer cells), per-cell A and Ku
+    and per-cell bulk DMI: the extended local pass with the layer couplings."""
+    grid = (21, 15, 5)
+    banner("layers per-cell materials %s %s" % (grid, prec))
+    nx, ny, nz = grid
+    dz = _heights(nz, 77)
+    g = W.rng(78)
+    Ms = g.uniform(4e5, 1.2e6, (nz, ny, nx))
+    Ms[2] = 0.0  # a vacuum spacer layer
+    A = np.where(Ms > 0, g.uniform(5e-12, 2e-11, Ms.shape), 0.0)
+    Ku = g.uniform(0.0, 5e4, Ms.shape)
+    D = g.uniform(1e-3, 4e-3, Ms.shape)
+    m = W.random_unit_sphere(grid, 79)
+    d = (2e-9, 2e-9, 1e-9)
+    plan = mm.Plan(grid, d, Ms=1.0, A=1e-11, Ku=1e4, prec=prec, layers=dz)
+    plan.set_ms(Ms)
+    plan.set_exchange(A)
+    plan.set_ku(Ku)
+    plan.set_dmi(D, mm.MM_DMI_BULK)
+    o = orc.Oracle(grid, d, Ms=Ms, A=A, Ku=1e4, layers=dz)
+    o.set_ku(Ku)
+    o.set_dmi(D, orc.DMI_BULK)
+    mt = plan._t(m)
+    for terms in (mm.MM_EXCH | mm.MM_DMI | mm.MM_ANIS, mm.MM_ALL):
+        e = rel_l2(to_np(plan.heff(mt, None, terms)), o.heff(m, 0.0, terms))
+        print("  terms %d rel-L2 %.2e" % (terms, e))
+        assert e <= TOL[prec], (terms, e)
+    E, Er = plan.energy(mt, None, mm.MM_ALL), o.energy(m)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    assert np.abs(E - Er).max() <= tol * np.abs(Er).max()
