@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 def pass_bytes(grid, prec):
-    """Algorithmic HBM bytes per launch of each pass (model)."""
+    """Algorithmic HBM bytes per launch of each pass (the traffic model: every
+    array a pass must read or write, once)."""
     nx, ny, nz = grid
     P = [1 if n == 1 else 1 << (2 * n - 2).bit_length() for n in grid]
     Px, Py, Pz = P
@@ -367,8 +368,8 @@ def main():
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a z-slab decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

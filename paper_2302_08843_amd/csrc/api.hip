@@ -302,7 +302,7 @@ template float* dev_state<float>(Plan*);
 template double* dev_state<double>(Plan*);
 
 // ---------------------------------------------------------------------------
-// Dormand-Prince driver.  mode_relax: alpha = 1, no precession, renormalise,
+// Dormand-Prince integrator loop.  mode_relax: alpha = 1, no precession, renormalise,
 // stop on the torque criterion.
 // ---------------------------------------------------------------------------
 template <typename T>
