@@ -314,12 +314,6 @@ struct Mid {
         cmin(64, cmax(1, (sizeof(T) == 4 ? MMX_MBLOCK : MMX_MBLOCK_F64) / kT));
 };
 
-// One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
-// components, forward transform, product with the spectral kernel, inverse
-// transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
-// One pencil group (fixed ky for AXIS = 2) of the last-axis pass: load three
-// components, forward transform, product with the spectral kernel, inverse
-// transform, store.  HALF: n_valid <= L/2 (always true with zero padding).
 // Element idx of a uniformly addressed array.  O32: idx * sizeof(P) is below
 // 4 GiB, and the access becomes a scalar base plus a 32-bit vector byte
 // offset (no 64-bit address arithmetic per access).
@@ -2039,12 +2033,6 @@ hipError_t debug_spectrum(Plan& p, int s, double* out)
 }
 
 // ---------------------------------------------------------------------------
-// Field evaluation.
-// ---------------------------------------------------------------------------
-// Demag convolution up to the x spectrum: S1 <- spectrum of K (Ms src) (or of
-// K src with use_ms = false), i.e. every pass but the last inverse x
-// transform, which the caller fuses with its local terms.
-// ---------------------------------------------------------------------------
 // Thin layers: dense coupling of the layers per lateral frequency,
 //   h^_t(kx, ky) = sum_s K^^{ts}(kx, ky) M^_s(kx, ky),
 // in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  K^ is
@@ -2132,6 +2120,12 @@ static hipError_t launch_zdense(Plan& p, cx<T>* S)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Field evaluation.
+// ---------------------------------------------------------------------------
+// Demag convolution up to the x spectrum: S1 <- spectrum of K (Ms src) (or of
+// K src with use_ms = false), i.e. every pass but the last inverse x
+// transform, which the caller fuses with its local terms.
 template <typename T>
 static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
 {
