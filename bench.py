@@ -265,6 +265,9 @@ def _serve_once(mm, reqs, states, arrivals, opts):
             i += 1
         for c in srv.poll():
             done[c["tag"]] = c
+            if len(done) % 32 == 0:
+                print("[bench] serving: %d/%d requests done" % (len(done), n), file=sys.stderr,
+                      flush=True)
     st = srv.stats()
     srv.close()
     return done, t0, st
