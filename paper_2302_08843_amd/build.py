@@ -13,7 +13,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmmx.so")
-SOURCES = ["kernels.hip", "api.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "mid_f32.hip", "mid_f64.hip", "passes_f32.hip", "passes_f64.hip",
+           "local_ext_f32.hip", "local_ext_f64.hip", "api.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,9 +28,11 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 2, out: str = LIB, defines=()) -> str:
+def build(verbose: bool = False, jobs: int = 0, out: str = LIB, defines=()) -> str:
     """Compile every source to an object and link the library (libmmx.so by
     default); always rebuilds.  `defines` are extra -D flags (tuning knobs)."""
+    if jobs <= 0:
+        jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
     tmp = tempfile.mkdtemp(prefix="mmx_build_")
     try:
         objs = []

@@ -1,0 +1,9 @@
+// local_ext_f32.hip -- the extended stencil variants of the x inverse / local
+// pass (DMI, per-cell exchange, DMI and uniaxial constants) in single precision, compiled
+// apart from the rest of the pipeline so the builds run in parallel.
+#include "passes.h"
+
+namespace mmx {
+template hipError_t launch_local_ext<float>(const Plan&, int, const float*, float*, float*, const LocalParams&,
+                                          double*, bool, int);
+}  // namespace mmx
