@@ -85,6 +85,23 @@ __device__ __forceinline__ cx<T> rot64(cx<T> v, int k)
     return {v.x * c - v.y * s, v.x * s + v.y * c};
 }
 
+// Ordering point between the LDS writes and reads of one exchange.  WAVE:
+// every thread of the transform lives in the calling wavefront, whose LDS
+// instructions execute in issue order, so only the compiler must be kept from
+// moving accesses across (wavefront-scope fences, no s_barrier); otherwise a
+// workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 constexpr int bitrev(int v, int bits)
 {
@@ -174,13 +191,14 @@ struct FFTShape {
 
 // One Stockham transform per group of kT threads.  `lds` points to this
 // transform's scratch of S::kLds complex slots, slot s at lds[s * lstride].
-// All threads of the workgroup must call run() (it contains barriers), also
-// those whose transform is masked out.  HALF_IN: the inputs x[L/2..L) are zero
+// All threads of the workgroup (WAVE: of the wavefront, which then holds the
+// whole transform) must call run(), also those whose transform is masked out.  HALF_IN: the inputs x[L/2..L) are zero
 // (the caller leaves v[kE/2..kE) zero; the first stage skips them).
 // SPLIT: the scratch holds S::kLds reals (slot s at ((T*)lds)[s * lstride])
 // and every exchange moves the real parts, then the imaginary parts -- half
 // the LDS per transform for two more barriers per exchange.
-template <typename T, int L, int E, int DIR, bool HALF_IN = false, bool SPLIT = false>
+template <typename T, int L, int E, int DIR, bool HALF_IN = false, bool SPLIT = false,
+          bool WAVE = false>
 struct WgFFT {
     using S = FFTShape<L, E>;
     static constexpr int kE = S::kE;
@@ -200,7 +218,7 @@ struct WgFFT {
         cx<T> w[kE];
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
-            __syncthreads();  // previous readers of the scratch are done
+            fft_sync<WAVE>();  // previous readers of the scratch are done
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int j = t + q * kT;
@@ -209,7 +227,7 @@ struct WgFFT {
                 for (int r = 0; r < R; ++r)
                     lr[S::lds_slot(base + r * Ns) * lstride] = half ? v[q * R + r].y : v[q * R + r].x;
             }
-            __syncthreads();
+            fft_sync<WAVE>();
 #pragma unroll
             for (int q = 0; q < NB2; ++q) {
                 const int j = t + q * kT;
@@ -236,7 +254,7 @@ struct WgFFT {
         constexpr int NB = kE / R;  // butterflies per thread
         if constexpr (s > 0 && !SPLIT) {
             // read this stage's inputs: element j + r*(L/R) for butterfly j
-            __syncthreads();
+            fft_sync<WAVE>();
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int j = t + q * kT;
@@ -265,7 +283,7 @@ struct WgFFT {
             if constexpr (SPLIT) {
                 split_exchange<s>(v, t, reinterpret_cast<T*>(lds), lstride);
             } else {
-                __syncthreads();  // previous readers of lds are done
+                fft_sync<WAVE>();  // previous readers of lds are done
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
                     const int j = t + q * kT;

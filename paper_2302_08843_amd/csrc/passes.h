@@ -69,6 +69,25 @@ namespace mmx {
 #ifndef MMX_MID_ADJ_F64
 #define MMX_MID_ADJ_F64 1
 #endif
+// z pass with wave-local transforms (k_mid_w): registers per thread
+#ifndef MMX_MIDW
+#define MMX_MIDW 1
+#endif
+#ifndef MMX_RMW_F32
+#define MMX_RMW_F32 16
+#endif
+#ifndef MMX_RMW_F64
+#define MMX_RMW_F64 8
+#endif
+#ifdef MMX_MIDW_WPE
+#define MMX_MIDW_ATTR __attribute__((amdgpu_waves_per_eu(MMX_MIDW_WPE)))
+#else
+#define MMX_MIDW_ATTR
+#endif
+// x inverse / local pass with wave-local transforms and prefetched neighbours
+#ifndef MMX_X1W
+#define MMX_X1W 1
+#endif
 #ifndef MMX_SSPLIT
 #define MMX_SSPLIT 1  // strided passes: exchange real and imaginary parts separately
 #endif
@@ -312,7 +331,8 @@ __global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_str
 // ---------------------------------------------------------------------------
 template <typename T, int L>
 struct Mid {
-    using S = FFTShape<L, Regs<T>::mid>;
+    static constexpr int kRegs = Regs<T>::mid;
+    using S = FFTShape<L, kRegs>;
     static constexpr int kE = S::kE, kT = S::kT;
     static constexpr int kB =
         cmin(64, cmax(1, (sizeof(T) == 4 ? MMX_MBLOCK : MMX_MBLOCK_F64) / kT));
@@ -325,33 +345,63 @@ struct Mid {
 // in 32 bits when O32.  PROD 0: the symmetric demag product with the six
 // folded real components; PROD 1: the Oersted product h = j x (i g) with the
 // three folded components g (imaginary spectrum, odd along its own axis).
-template <typename T, int L, int AXIS, bool HALF, bool O32, int PROD = 0>
-__device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict__ Khat,
-                                          int n_valid, long es_, long cs_, bool cv, int col, int g,
-                                          int t, int b, cx<T>* lds, int Py, int Pz, long Kn_,
-                                          int Hxp, const cx<T>* __restrict__ tw, int Lmax)
+// G: the thread shape (kE registers, kT threads per transform); the
+// transform's LDS scratch is lds[s * lstride].  WAVE: the kT threads of a
+// transform share one wavefront (exchanges without workgroup barriers).
+// The folded spectral kernel read from global memory: component c at the
+// folded indices (kyf, kzf) of column col.
+template <typename T, bool O32>
+struct KGlobal {
+    using I = typename std::conditional<O32, unsigned, long>::type;
+    const T* __restrict__ K;
+    I Kn, plane, Hxp, col;
+    __device__ __forceinline__ T operator()(int c, int kyf, int kzf) const
+    {
+        return elem<O32>(K, (I)c * Kn + (I)kzf * plane + (I)kyf * Hxp + col);
+    }
+};
+
+// KG: the kernel accessor kget(c, kyf, kzf) (c = component, kyf/kzf the
+// folded y and z indices; the sign flips are applied here).
+// Load the three components of one column of the group: v[c][r] = element
+// t + r*kT (zero beyond n_valid, in the upper half with HALF, or for !cv).
+template <typename G, typename T, bool HALF, bool O32>
+__device__ __forceinline__ void mid_load(cx<T> (&v)[3][G::kE], const cx<T>* S, long o_,
+                                         int n_valid, long es_, long cs_, bool cv, int t)
 {
     using I = typename std::conditional<O32, unsigned, long>::type;
-    using G = Mid<T, L>;
-    constexpr int kE = G::kE, kT = G::kT, kB = G::kB;
-    const I o = (I)o_, es = (I)es_, cs = (I)cs_, Kn = (I)Kn_;
-    cx<T> v[3][kE];
+    constexpr int kE = G::kE, kT = G::kT;
+    const I o = (I)o_, es = (I)es_, cs = (I)cs_;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int r = 0; r < kE; ++r) {
             const int e = t + r * kT;
             v[c][r] = (!(HALF && r >= kE / 2) && cv && e < n_valid)
-                          ? elem<O32>((const cx<T>*)S, o + (I)c * cs + (I)e * es)
+                          ? elem<O32>(S, o + (I)c * cs + (I)e * es)
                           : cx<T>{0, 0};
         }
+}
+
+// Transform, product and inverse of one column loaded by mid_load, then the
+// store of the first n_valid elements.
+template <typename G, bool WAVE, typename T, int L, int AXIS, bool HALF, bool O32, int PROD,
+          typename KG>
+__device__ __forceinline__ void mid_group(cx<T> (&v)[3][G::kE], cx<T>* S, long o_,
+                                          const KG& kget, int n_valid, long es_, long cs_,
+                                          bool cv, int g, int t, cx<T>* lds, int lstride, int Py,
+                                          int Pz, const cx<T>* __restrict__ tw, int twstride)
+{
+    using I = typename std::conditional<O32, unsigned, long>::type;
+    constexpr int kE = G::kE, kT = G::kT;
+    constexpr int kRE = G::kRegs;
+    const I o = (I)o_, es = (I)es_, cs = (I)cs_;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-        WgFFT<T, L, Regs<T>::mid, -1, HALF>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+        WgFFT<T, L, kRE, -1, HALF, false, WAVE>::run(v[c], t, lds, lstride, tw, twstride);
 
     if (cv) {
         const int hy = Py / 2, hz = Pz / 2;
-        const I plane = (I)(hy + 1) * (I)Hxp;
 #pragma unroll
         for (int i = 0; i < kE; ++i) {
             const int kk = G::S::out_index(t, i);
@@ -366,10 +416,9 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
             const bool fy = ky > hy, fz = kz > hz;
             const int kyf = fy ? Py - ky : ky, kzf = fz ? Pz - kz : kz;
             const T sy = fy ? (T)-1 : (T)1, sz = fz ? (T)-1 : (T)1;
-            const I kb = (I)kzf * plane + (I)kyf * (I)Hxp + (I)col;
             if constexpr (PROD == 1) {
-                const T gx = elem<O32>(Khat, kb), gy = sy * elem<O32>(Khat, kb + Kn);
-                const T gz = sz * elem<O32>(Khat, kb + 2 * Kn);
+                const T gx = kget(0, kyf, kzf), gy = sy * kget(1, kyf, kzf);
+                const T gz = sz * kget(2, kyf, kzf);
                 const cx<T> jx = v[0][i], jy = v[1][i], jz = v[2][i];
                 // c = j x g, h = i c = (-c.im, c.re)
                 const cx<T> c0 = {jy.x * gz - jz.x * gy, jy.y * gz - jz.y * gy};
@@ -380,10 +429,10 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
                 v[2][i] = {-c2.y, c2.x};
                 continue;
             }
-            const T kxx = elem<O32>(Khat, kb), kyy = elem<O32>(Khat, kb + Kn);
-            const T kzz = elem<O32>(Khat, kb + 2 * Kn);
-            const T kxy = sy * elem<O32>(Khat, kb + 3 * Kn), kxz = sz * elem<O32>(Khat, kb + 4 * Kn);
-            const T kyz = sy * sz * elem<O32>(Khat, kb + 5 * Kn);
+            const T kxx = kget(0, kyf, kzf), kyy = kget(1, kyf, kzf);
+            const T kzz = kget(2, kyf, kzf);
+            const T kxy = sy * kget(3, kyf, kzf), kxz = sz * kget(4, kyf, kzf);
+            const T kyz = sy * sz * kget(5, kyf, kzf);
             const cx<T> mx = v[0][i], my = v[1][i], mz = v[2][i];
             v[0][i] = {kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y};
             v[1][i] = {kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y};
@@ -403,7 +452,7 @@ __device__ __forceinline__ void mid_group(cx<T>* S, long o_, const T* __restrict
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-        WgFFT<T, L, Regs<T>::mid, 1>::run(v[c], t, lds + b, kB, tw, Lmax / L);
+        WgFFT<T, L, kRE, 1, false, false, WAVE>::run(v[c], t, lds, lstride, tw, twstride);
     if (!cv) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -450,13 +499,137 @@ __global__ __launch_bounds__((Mid<T, L>::kB * Mid<T, L>::kT)) void k_mid(
     const int b = threadIdx.x % kB, t = threadIdx.x / kB;
     const int col = tile * kB + b;
     const bool cv = col < ncols;
-    mid_group<T, L, AXIS, HALF, O32, PROD>(S, (long)g * gstride + col, Khat, n_valid, es, cs, cv,
-                                           col, g, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+    using I = typename KGlobal<T, O32>::I;
+    const KGlobal<T, O32> kg{Khat, (I)Kn, (I)((long)(Py / 2 + 1) * Hxp), (I)Hxp, (I)col};
+    {
+        cx<T> v[3][G::kE];
+        mid_load<G, T, HALF, O32>(v, S, (long)g * gstride + col, n_valid, es, cs, cv, t);
+        mid_group<G, false, T, L, AXIS, HALF, O32, PROD>(v, S, (long)g * gstride + col, kg,
+                                                         n_valid, es, cs, cv, g, t, lds + b, kB,
+                                                         Py, Pz, tw, Lmax / L);
+    }
     if (paired) {
         const int g2 = Py - g;
-        mid_group<T, L, AXIS, HALF, O32, PROD>(S, (long)g2 * gstride + col, Khat, n_valid, es, cs,
-                                               cv, col, g2, t, b, lds, Py, Pz, Kn, Hxp, tw, Lmax);
+        cx<T> v[3][G::kE];
+        mid_load<G, T, HALF, O32>(v, S, (long)g2 * gstride + col, n_valid, es, cs, cv, t);
+        mid_group<G, false, T, L, AXIS, HALF, O32, PROD>(v, S, (long)g2 * gstride + col, kg,
+                                                         n_valid, es, cs, cv, g2, t, lds + b, kB,
+                                                         Py, Pz, tw, Lmax / L);
     }
+}
+
+// Wave-local shape of the last-axis pass: kT = L/kE threads per transform,
+// all in one wavefront (lane = t * kCB + b), kCB column transforms per
+// wavefront, kW wavefronts per block.  Lengths whose transform would need
+// more than 64 threads use k_mid.
+template <typename T, int L>
+struct MidW {
+    static constexpr int kRegs = sizeof(T) == 4 ? MMX_RMW_F32 : MMX_RMW_F64;
+    using S = FFTShape<L, kRegs>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr bool kOK = kT <= 64;
+    static constexpr int kCB = kOK ? 64 / kT : 1;
+    static constexpr int kW = 2;  // AXIS = 2: the wavefronts of ky and Py - ky
+};
+
+// The block's folded kernel tile staged in LDS: component c at the folded
+// index r along the transform axis (kzf for AXIS = 2, kyf for AXIS = 1) of
+// column b of the tile, at t[(c * R + r) * CB + b].
+template <typename T, int AXIS, int R, int CB>
+struct KLds {
+    const T* t;
+    int b;
+    __device__ __forceinline__ T operator()(int c, int kyf, int kzf) const
+    {
+        return t[(c * R + (AXIS == 2 ? kzf : kyf)) * CB + b];
+    }
+};
+
+// F3 with wave-local transforms.  The block first stages what its
+// wavefronts read besides their own spectra -- the folded kernel rows of its
+// column tile(s) and the twiddles of length L -- in LDS, in the same memory
+// phase as the spectrum loads, so the transforms and the product run without
+// waiting on global memory; after that one barrier the wavefronts run on
+// their own (no further workgroup barrier).  AXIS = 2: the block holds the
+// column tile tb of the pair ky = gp (wavefront 0) and ky = Py - gp
+// (wavefront 1), which share the folded kernel rows.  AXIS = 1 (single
+// layer, one group): each wavefront its own column tile.
+template <typename T, int L, int AXIS, bool HALF, bool O32, int PROD>
+__global__ __launch_bounds__((64 * MidW<T, L>::kW)) MMX_MIDW_ATTR void k_mid_w(
+    cx<T>* S, const T* __restrict__ Khat, int n_valid, long es, long cs, long gstride, int ncols,
+    int ntb, long nblocks, int Py, int Pz, long Kn, int Hxp, const cx<T>* __restrict__ tw,
+    int Lmax)
+{
+    using G = MidW<T, L>;
+    constexpr int kCB = G::kCB, kW = G::kW;
+    constexpr int NK = PROD == 0 ? 6 : 3;        // kernel components
+    constexpr int R = L / 2 + 1;                  // folded rows along the transform axis
+    constexpr int NT = AXIS == 2 ? 1 : kW;        // column tiles per block
+    constexpr int KT = NK * R * kCB;              // kernel values per tile
+    __shared__ T kt[NT * KT];
+    __shared__ cx<T> twl[L];
+    __shared__ cx<T> lds[kW][G::S::kStages > 1 ? kCB * G::S::kLds : 1];
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;  // uniform over the block
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int tile0, g, gp = 0;
+    bool active = true;
+    if constexpr (AXIS == 2) {
+        const int tb = (int)(lb % ntb);
+        gp = (int)(lb / ntb);
+        tile0 = tb;
+        const bool mirror = wave & 1;
+        if (mirror && (gp == 0 || 2 * gp >= Py)) active = false;  // its own mirror
+        g = mirror ? Py - gp : gp;
+    } else {
+        tile0 = (int)lb * kW;
+        g = 0;
+    }
+    const int tile = AXIS == 2 ? tile0 : tile0 + wave;
+    const int b = lane % kCB, t = lane / kCB;
+    const int col = tile * kCB + b;
+    const bool cv = active && col < ncols;
+    // one memory phase: the kernel tile(s) and twiddles for LDS, then the
+    // spectrum column (every thread of the block takes part in the staging)
+    using I = typename std::conditional<O32, unsigned, long>::type;
+    const I plane = (I)(Py / 2 + 1) * (I)Hxp;
+    constexpr int NQ = (NT * KT + 64 * kW - 1) / (64 * kW);
+    constexpr int NTW = (L + 64 * kW - 1) / (64 * kW);
+    T kv[NQ];
+    cx<T> twv[NTW];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int idx = q * 64 * kW + (int)threadIdx.x;
+        const int bb = idx % kCB, r = (idx / kCB) % R, c = (idx / (kCB * R)) % NK;
+        const int cl = (tile0 + idx / KT) * kCB + bb;
+        const I off = AXIS == 2 ? (I)c * (I)Kn + (I)r * plane + (I)gp * (I)Hxp + (I)cl
+                                : (I)c * (I)Kn + (I)r * (I)Hxp + (I)cl;
+        kv[q] = idx < NT * KT && cl < ncols ? elem<O32>(Khat, off) : (T)0;
+    }
+    const int tws = Lmax / L;
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+        const int n = q * 64 * kW + (int)threadIdx.x;
+        twv[q] = n < L ? tw[n * tws] : cx<T>{0, 0};
+    }
+    cx<T> v[3][G::kE];
+    mid_load<G, T, HALF, O32>(v, S, (long)g * gstride + col, n_valid, es, cs, cv, t);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int idx = q * 64 * kW + (int)threadIdx.x;
+        if (idx < NT * KT) kt[idx] = kv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+        const int n = q * 64 * kW + (int)threadIdx.x;
+        if (n < L) twl[n] = twv[q];
+    }
+    __syncthreads();
+    if (!active || tile * kCB >= ncols) return;  // from here on, no workgroup barrier
+    const KLds<T, AXIS, R, kCB> kg{kt + (AXIS == 2 ? 0 : wave * KT), b};
+    mid_group<G, true, T, L, AXIS, HALF, O32, PROD>(v, S, (long)g * gstride + col, kg, n_valid,
+                                                    es, cs, cv, g, t, lds[wave] + b, kCB, Py, Pz,
+                                                    twl, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -796,6 +969,305 @@ __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_
     }
 }
 
+// I1, wave-local form (M >= 2).  A block of 256 threads owns kRB rows
+// (j0 .. j0 + kRB - 1) of slab k, laid out M cells apart: thread slot q holds
+// cell i = li mod M of row li / M, li = threadIdx.x + 256 q (slots with
+// i >= nx idle).  One memory phase first: the spectrum rows for the inverse
+// transforms (threads below 3 kRB kT, one transform per kT threads, all in
+// one wavefront) and, for every cell, m and its six neighbours (plus the
+// per-cell constants of the variant), all with 32-bit offsets from
+// per-component bases; then the transforms, whose real outputs go to LDS,
+// one barrier, and the local terms from registers.
+template <typename T, int M>
+struct XC2RW {
+    static constexpr int kRegs = Regs<T>::x1;
+    using S = FFTShape<(M > 0 ? M : 1), kRegs>;
+    static constexpr int kE = S::kE, kT = S::kT;
+    static constexpr bool kOK = M >= 2 && kT <= 64;     // a transform fits one wavefront
+    static constexpr int kRB = kOK ? cmin(64 / kT, 512 / M) : 1;  // rows per block (kOK)
+    static constexpr int kNT = 256;                               // threads per block
+    static constexpr int kCPT = kOK ? (kRB * M + kNT - 1) / kNT : 1;
+    static constexpr int kLogM = ilog2(M > 0 ? M : 1);
+    static_assert(!kOK || 3 * kRB * kT <= kNT, "transform threads exceed the block");
+};
+
+template <typename T, int M, bool PERCELL, int EXT>
+__global__ __launch_bounds__(256) void k_x_c2r_local_w(
+    const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
+    T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
+    LocalParams P, double* torque, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
+    const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
+    const T* __restrict__ h_oe, const T* __restrict__ Ku_cell)
+{
+    constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
+    constexpr bool kMIX = EXT & EXT_MIX;
+    using G = XC2RW<T, M>;
+    constexpr int kE = G::kE, kT = G::kT, RB = G::kRB, CPT = G::kCPT, kL = G::S::kLds;
+    constexpr int NTW = (M + G::kNT - 1) / G::kNT;
+    __shared__ cx<T> lds[3 * RB * kL];
+    __shared__ cx<T> twl[M];  // the M-point transform's twiddles
+    const long lb = xcd_logical();
+    if (lb >= nblocks) return;
+    // z fastest: the blocks of rows (j, k-1), (j, k), (j, k+1) run together
+    // on one XCD, so the z neighbours of m come from its L2
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int k = (int)((unsigned)lb % (unsigned)nz);
+    const int j0 = (int)((unsigned)lb / (unsigned)nz) * RB;
+    const int tid = threadIdx.x;
+    const unsigned N = (unsigned)P.N;
+    const unsigned sxy = (unsigned)nx * (unsigned)ny;
+
+    // ---- memory phase: spectrum rows ----
+    const bool with_demag = P.with_demag != 0;
+    const bool fthr = tid < 3 * RB * kT;
+    const int tau = tid / kT, t = tid % kT;
+    const int frl = tau / 3, fc = tau % 3;
+    const bool frow = with_demag && fthr && j0 + frl < ny;
+    cx<T> xa[kE], xb[kE];
+    {
+        const cx<T>* X =
+            S1 + (long)fc * P.s1_comp + ((long)k * ny + (frow ? j0 + frl : 0)) * P.Hxp;
+#pragma unroll
+        for (int r = 0; r < kE; ++r) {
+            const int n = t + r * kT;
+            xa[r] = frow ? X[n] : cx<T>{0, 0};
+            xb[r] = frow ? X[M - n] : cx<T>{0, 0};
+        }
+    }
+    cx<T> twv[NTW];
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+        const int n = tid + G::kNT * q;
+        twv[q] = n < M ? tw[n * (Lmax / M)] : cx<T>{0, 0};
+    }
+    // ---- memory phase: cells and neighbours ----
+    const T* mc0 = m;
+    const T* mc1 = m + N;
+    const T* mc2 = m + 2 * (size_t)N;
+    unsigned cell[CPT];
+    bool cv[CPT], has[CPT][6];
+    unsigned q6[CPT][6];
+    T mv[CPT][7][3];
+    T msv[CPT][7];
+    T Av[CPT][7], Dv[CPT][7];
+    int jj[CPT], ii[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int li = tid + G::kNT * q;
+        const int rl = li >> G::kLogM, i = li & (M - 1);
+        const int j = j0 + rl;
+        jj[q] = j;
+        ii[q] = i;
+        cv[q] = li < RB * M && i < nx && j < ny;
+        const unsigned c0 = cv[q] ? (unsigned)i + (unsigned)nx * (unsigned)j + sxy * (unsigned)k : 0u;
+        cell[q] = c0;
+        // an idle slot (cell 0 stands in) has no neighbours: its offsets
+        // must not step off the cell range
+        has[q][0] = cv[q] && i > 0;
+        has[q][1] = cv[q] && i + 1 < nx;
+        has[q][2] = cv[q] && j > 0;
+        has[q][3] = cv[q] && j + 1 < ny;
+        has[q][4] = cv[q] && k > 0;
+        has[q][5] = cv[q] && k + 1 < nz;
+        q6[q][0] = has[q][0] ? c0 - 1u : c0;
+        q6[q][1] = has[q][1] ? c0 + 1u : c0;
+        q6[q][2] = has[q][2] ? c0 - (unsigned)nx : c0;
+        q6[q][3] = has[q][3] ? c0 + (unsigned)nx : c0;
+        q6[q][4] = has[q][4] ? c0 - sxy : c0;
+        q6[q][5] = has[q][5] ? c0 + sxy : c0;
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+            const unsigned qq = d == 0 ? c0 : q6[q][d - 1];
+            mv[q][d][0] = elem<true>(mc0, qq);
+            mv[q][d][1] = elem<true>(mc1, qq);
+            mv[q][d][2] = elem<true>(mc2, qq);
+            msv[q][d] = PERCELL ? elem<true>(Ms_cell, qq) : (T)P.Ms;
+            Av[q][d] = kPA ? elem<true>(A_cell, qq) : (T)0;
+            Dv[q][d] = kPD ? elem<true>(D_cell, qq) : (T)0;
+        }
+    }
+
+    // ---- inverse x transforms (three per row, each in one wavefront) ----
+#pragma unroll
+    for (int q = 0; q < NTW; ++q) {
+        const int n = tid + G::kNT * q;
+        if (n < M) twl[n] = twv[q];
+    }
+    __syncthreads();
+    T* hd = reinterpret_cast<T*>(lds + (frl * 3 + fc) * kL);
+    if (with_demag && fthr) {
+        const int tws = Lmax / (2 * M);
+        cx<T> v[kE];
+#pragma unroll
+        for (int r = 0; r < kE; ++r) {
+            const int n = t + r * kT;
+            const cx<T> a = xa[r], bb = xb[r];
+            const cx<T> D = {a.x - bb.x, a.y + bb.y};
+            const cx<T> wD = cmulc(D, tw[n * tws]);
+            v[r] = {a.x + bb.x - wD.y, a.y - bb.y + wD.x};
+        }
+        WgFFT<T, M, G::kRegs, 1, false, false, true>::run(v, t, lds + (frl * 3 + fc) * kL, 1, twl,
+                                                          1);
+        fft_sync<true>();  // the transform's last exchange reads precede these writes
+        constexpr int Rl = G::S::kLast;
+#pragma unroll
+        for (int i = 0; i < kE; ++i) {
+            // outputs n >= M/2 are cells x >= M >= nx: never used
+            if ((i % Rl) >= Rl / 2) continue;
+            const int e = G::S::out_index(t, i);
+            hd[2 * e] = v[i].x;
+            hd[2 * e + 1] = v[i].y;
+        }
+    }
+    __syncthreads();
+
+    // ---- local terms ----
+    const T exch = (T)P.exch, anis = (T)P.anis;
+    const T ix2 = (T)P.idx2, iy2 = (T)P.idy2, iz2 = (T)P.idz2;
+    T wz_dn = iz2, wz_up = iz2, dz_s = (T)1;
+    if (zw) {
+        wz_dn = zw[4 * k];
+        wz_up = zw[4 * k + 1];
+        dz_s = zw[4 * k + 2];
+    }
+    const T eux = (T)P.eu[0], euy = (T)P.eu[1], euz = (T)P.eu[2];
+    double tmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        if (!cv[q]) continue;
+        const unsigned c0 = cell[q];
+        const int rl = jj[q] - j0, i = ii[q];
+        const T ms = msv[q][0];
+        const T mx = mv[q][0][0], my = mv[q][0][1], mz = mv[q][0][2];
+        T hx = 0, hy = 0, hz = 0;
+        if (ms != (T)0) {
+            if (with_demag) {
+                hx = reinterpret_cast<const T*>(lds + (rl * 3 + 0) * kL)[i];
+                hy = reinterpret_cast<const T*>(lds + (rl * 3 + 1) * kL)[i];
+                hz = reinterpret_cast<const T*>(lds + (rl * 3 + 2) * kL)[i];
+            }
+            const T inv_ms = (T)1 / ms;
+            if (EXT != 0 || P.with_exch) {
+                // one pass over the six neighbours serves exchange and DMI;
+                // an absent neighbour holds the cell itself with weight 0
+                T ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+                const T Ai = Av[q][0], Di = Dv[q][0];
+#pragma unroll
+                for (int nbi = 0; nbi < 6; ++nbi) {
+                    const int dir = nbi >> 1;
+                    const bool plus = nbi & 1;
+                    const T qx = mv[q][nbi + 1][0], qy = mv[q][nbi + 1][1], qz = mv[q][nbi + 1][2];
+                    const bool ok = has[q][nbi] && (!PERCELL || msv[q][nbi + 1] != (T)0);
+                    T wq = ok ? (dir == 0 ? ix2 : dir == 1 ? iy2 : plus ? wz_up : wz_dn) : (T)0;
+                    if constexpr (kPA) wq *= harmonic2(Ai, Av[q][nbi + 1]);
+                    ax += wq * (qx - mx);
+                    ay += wq * (qy - my);
+                    az += wq * (qz - mz);
+                    if constexpr (kDMI) {
+                        // D~ (e^dmi_k x m_{i+k}) / (2 Delta_k), e^dmi_{-k} = -e^dmi_k
+                        T c = ok ? (plus ? (T)1 : (T)-1) : (T)0;
+                        if (dir == 2) c *= dz_s;
+                        if constexpr (kMIX)
+                            c *= dmi_avg(Di, Dv[q][nbi + 1]);
+                        else if constexpr (kPD)
+                            c *= harmonic2(Di, Dv[q][nbi + 1]);
+                        const T ex = c * (T)P.edmi[dir][0], ey = c * (T)P.edmi[dir][1],
+                                ez = c * (T)P.edmi[dir][2];
+                        bx += ey * qz - ez * qy;
+                        by += ez * qx - ex * qz;
+                        bz += ex * qy - ey * qx;
+                    }
+                }
+                const T ce = P.with_exch ? exch * inv_ms : (T)0;
+                hx += ce * ax;
+                hy += ce * ay;
+                hz += ce * az;
+                if constexpr (kDMI) {
+                    const T cd = (T)P.dmi * inv_ms;
+                    hx += cd * bx;
+                    hy += cd * by;
+                    hz += cd * bz;
+                }
+            }
+            if (P.with_anis) {
+                const T em = eux * mx + euy * my + euz * mz;
+                // per-cell Ku (extended variants only): P.anis is then 2 / mu0
+                T ka = anis;
+                if constexpr (EXT != 0)
+                    if (Ku_cell) ka *= elem<true>(Ku_cell, c0);
+                const T ca = ka * inv_ms * em;
+                hx += ca * eux;
+                hy += ca * euy;
+                hz += ca * euz;
+                if (P.with_anis_hi) {
+                    // second-order uniaxial: 4 Ku2 (e.m)^3 e / (mu0 Ms)
+                    const T cb = (T)P.anis2 * inv_ms * em * em * em;
+                    hx += cb * eux;
+                    hy += cb * euy;
+                    hz += cb * euz;
+                    // cubic, in the principal axes c_i: -2 Kc1 m_i (m_j^2 + m_k^2)
+                    // - 2 Kc2 m_i m_j^2 m_k^2, over mu0 Ms, mapped back along c_i
+                    T pr[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        pr[a] = (T)P.ec[a][0] * mx + (T)P.ec[a][1] * my + (T)P.ec[a][2] * mz;
+                    const T s0 = pr[0] * pr[0], s1 = pr[1] * pr[1], s2 = pr[2] * pr[2];
+                    const T c1 = (T)P.cub1 * inv_ms, c2 = (T)P.cub2 * inv_ms;
+                    const T g0 = -(c1 * pr[0] * (s1 + s2) + c2 * pr[0] * s1 * s2);
+                    const T g1 = -(c1 * pr[1] * (s2 + s0) + c2 * pr[1] * s2 * s0);
+                    const T g2 = -(c1 * pr[2] * (s0 + s1) + c2 * pr[2] * s0 * s1);
+                    hx += g0 * (T)P.ec[0][0] + g1 * (T)P.ec[1][0] + g2 * (T)P.ec[2][0];
+                    hy += g0 * (T)P.ec[0][1] + g1 * (T)P.ec[1][1] + g2 * (T)P.ec[2][1];
+                    hz += g0 * (T)P.ec[0][2] + g1 * (T)P.ec[1][2] + g2 * (T)P.ec[2][2];
+                }
+            }
+            if (P.with_oe) {
+                const T so = (T)P.oe_scale;
+                hx += so * elem<true>(h_oe, c0);
+                hy += so * elem<true>(h_oe + N, c0);
+                hz += so * elem<true>(h_oe + 2 * (size_t)N, c0);
+            }
+            if (P.with_zee) {
+                hx += (T)P.H[0];
+                hy += (T)P.H[1];
+                hz += (T)P.H[2];
+                if (mask && mask[c0]) {
+                    hx += (T)P.Hd[0];
+                    hy += (T)P.Hd[1];
+                    hz += (T)P.Hd[2];
+                }
+            }
+        }
+        if (h_out) {
+            elem<true>(h_out, c0) = hx;
+            elem<true>(h_out + N, c0) = hy;
+            elem<true>(h_out + 2 * (size_t)N, c0) = hz;
+        }
+        // m x h and m x (m x h)
+        const T px = my * hz - mz * hy, py = mz * hx - mx * hz, pz = mx * hy - my * hx;
+        if (dm_out) {
+            const T qx = my * pz - mz * py, qy = mz * px - mx * pz, qz = mx * py - my * px;
+            const T gp = (T)P.gp, al = (T)P.alpha, pf = P.precess ? (T)1 : (T)0;
+            const bool mag = ms != (T)0;
+            elem<true>(dm_out, c0) = mag ? -gp * (pf * px + al * qx) : (T)0;
+            elem<true>(dm_out + N, c0) = mag ? -gp * (pf * py + al * qy) : (T)0;
+            elem<true>(dm_out + 2 * (size_t)N, c0) = mag ? -gp * (pf * pz + al * qz) : (T)0;
+        }
+        if (torque && ms != (T)0) {
+            const double tq = sqrt((double)px * px + (double)py * py + (double)pz * pz) / (double)ms;
+            tmax = tmax > tq ? tmax : tq;
+        }
+    }
+    if (torque) {
+        // wavefront max, then one atomic per wavefront
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_down(tmax, off, 64);
+            tmax = tmax > o ? tmax : o;
+        }
+        if ((threadIdx.x & 63) == 0) atomic_max_nonneg(torque, tmax);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch helpers (power-of-two lengths 1..1024).
 // ---------------------------------------------------------------------------
@@ -919,12 +1391,32 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
 {
     // AXIS = 2 pairs ky with Py - ky: groups 0 .. Py/2
     const int groups = (AXIS == 2 && G > 1) ? G / 2 + 1 : G;
-    using Gm = Mid<T, L>;
-    const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
-    const long nblocks = (long)ntile * groups;
     const bool o32 = (size_t)p.S2n * 2 * sizeof(T) < (1ull << 32) &&
                      (size_t)p.Kn * 6 * sizeof(T) < (1ull << 32);
     const bool half = 2 * n_valid <= L && L > 1;
+    if constexpr (MMX_MIDW && MidW<T, L>::kOK) {
+        using Gw = MidW<T, L>;
+        const int ntile = (p.Hx + Gw::kCB - 1) / Gw::kCB;
+        const int ntb = ntile;
+        const long nb = AXIS == 2 ? (long)ntb * groups : (ntile + Gw::kW - 1) / Gw::kW;
+#define MMX_KMIDW(H, O)                                                                           \
+    k_mid_w<T, L, AXIS, H, O, PROD><<<xcd_grid(nb), 64 * Gw::kW, 0, p.stream>>>(                  \
+        S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntb, nb, p.P[1], p.P[2], p.Kn,       \
+        p.Hxp, (const cx<T>*)p.tw, p.Lmax)
+        if (half && o32)
+            MMX_KMIDW(true, true);
+        else if (half)
+            MMX_KMIDW(true, false);
+        else if (o32)
+            MMX_KMIDW(false, true);
+        else
+            MMX_KMIDW(false, false);
+#undef MMX_KMIDW
+        return hipGetLastError();
+    } else {
+    using Gm = Mid<T, L>;
+    const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
+    const long nblocks = (long)ntile * groups;
     // the Oersted product (PROD 1) uses the paired-in-block order only
     const bool adj = PROD == 0 && (sizeof(T) == 4 ? MMX_MID_ADJ_F32 : MMX_MID_ADJ_F64) &&
                      AXIS == 2 && G > 1;
@@ -954,6 +1446,7 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
 #undef MMX_KMID2
 #undef MMX_KMID
     return hipGetLastError();
+    }
 }
 
 template <typename T, int AXIS, int PROD = 0>
@@ -973,6 +1466,18 @@ template <typename T, int M, bool PC, int EXT>
 static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
                                  double* torque)
 {
+    if constexpr (MMX_X1W && XC2RW<T, M>::kOK) {
+        using Gw = XC2RW<T, M>;
+        const int njt = (p.n[1] + Gw::kRB - 1) / Gw::kRB;
+        const long nblocks = (long)njt * p.n[2];
+        k_x_c2r_local_w<T, M, PC, EXT><<<xcd_grid(nblocks), Gw::kNT, 0, p.stream>>>(
+            (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, nblocks,
+            (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
+            (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
+            P.with_oe ? (const T*)p.h_oe : nullptr,
+            EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr);
+        return hipGetLastError();
+    }
     using G = XC2R<T, M>;
     const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
     const long nblocks = (long)njt * p.n[2];
