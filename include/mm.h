@@ -192,9 +192,11 @@ mm_status mm_set_dmi(mm_plan *p, int type, double D, const void *D_cell);
  * (Sec. 4.5: the far field of a singular current density).  j and h_out are
  * device buffers of 3N values of the plan's precision (A/m^2 in, A/m out),
  * must not alias; h_out holds the field at every cell.  The first call builds
- * and keeps the kernel spectrum and a work spectrum of 3 Px Py Pz complex
- * values (synchronises once); later calls are asynchronous.  MM_EINVAL for
- * thin-layer plans. */
+ * and keeps the kernel spectrum, the folded octant of its imaginary part
+ * (3 (Pz/2+1)(Py/2+1) Hx reals, Hx = Px/2+1 rounded up to 128 bytes), and
+ * synchronises once; the convolution runs in the plan's own spectra, so later
+ * calls allocate nothing and are asynchronous.  MM_EINVAL for thin-layer
+ * plans. */
 mm_status mm_oersted(mm_plan *p, const void *j, void *h_out);
 
 /* Current density for the MM_OERSTED term: its Oersted field is computed now

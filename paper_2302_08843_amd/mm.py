@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -90,6 +91,16 @@ class mm_step_opts(C.Structure):
 class mm_step_stats(C.Structure):
     _fields_ = [("accepted", C.c_long), ("rejected", C.c_long), ("rhs_evals", C.c_long),
                 ("t", C.c_double), ("dt", C.c_double), ("err_last", C.c_double)]
+
+
+def _destroy_plan(fn, handle):
+    # fn is the library's mm_plan_destroy, held by the finalizer itself
+    _PLANS.pop(handle, None)
+    fn(C.c_void_p(handle))
+
+
+def _destroy_server(fn, handle):
+    fn(C.c_void_p(handle))
 
 
 class MMError(RuntimeError):
@@ -188,10 +199,62 @@ def _stream_handle(stream):
     return C.c_void_p(int(stream.cuda_stream))
 
 
-def _ptr(t):
+# Plans created through this module: handle value -> (grid, dtype name, device
+# index), so that every tensor handed to the library is checked against the
+# plan it is meant for before any call (a wrong dtype, shape or device would
+# otherwise make the kernels read or write out of bounds).
+_PLANS = {}
+
+
+def _plan_info(plan):
+    info = _PLANS.get(plan.value if isinstance(plan, C.c_void_p) else plan)
+    if info is None:
+        raise ValueError("unknown plan handle")
+    return info
+
+
+def _expect(t, name, dtype, device, shape):
+    """Raise ValueError unless t is a contiguous tensor of `dtype` on CUDA
+    device `device` with exactly `shape`."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s (got %s)" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (name, tuple(shape), tuple(t.shape)))
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError("%s must be contiguous" % name)
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError("%s must live on cuda:%d (got %s)" % (name, device, t.device))
     return C.c_void_p(t.data_ptr())
+
+
+def _vec(plan, t, name):
+    """A vector field (3, nz, ny, nx) of the plan's precision."""
+    grid, dt, dev = _plan_info(plan)
+    import torch
+
+    nx, ny, nz = grid
+    return _expect(t, name, getattr(torch, dt), dev, (3, nz, ny, nx))
+
+
+def _cellf(plan, t, name, dtype=None):
+    """A scalar per-cell field (nz, ny, nx) of the plan's precision (or dtype)."""
+    grid, dt, dev = _plan_info(plan)
+    import torch
+
+    nx, ny, nz = grid
+    return _expect(t, name, dtype if dtype is not None else getattr(torch, dt), dev, (nz, ny, nx))
+
+
+def _ovec(plan, t, name):
+    return None if t is None else _vec(plan, t, name)
+
+
+def _ocellf(plan, t, name, dtype=None):
+    return None if t is None else _cellf(plan, t, name, dtype)
 
 
 # ---------------------------------------------------------------------------
@@ -210,73 +273,87 @@ def mm_plan_create(grid, cell, Ms, A, Ku, alpha, opts=None):
     d = (C.c_double * 3)(*[float(v) for v in cell])
     _check(lib().mm_plan_create(C.byref(h), g, d, float(Ms), float(A), float(Ku), float(alpha),
                                 C.byref(opts) if opts is not None else None))
+    import torch
+
+    prec = opts.prec if opts is not None else MM_FP64
+    _PLANS[h.value] = (tuple(int(v) for v in grid), "float32" if prec == MM_FP32 else "float64",
+                       torch.cuda.current_device() if torch.cuda.is_available() else -1)
     return h
 
 
 def mm_plan_destroy(plan):
+    _PLANS.pop(plan.value if isinstance(plan, C.c_void_p) else plan, None)
     lib().mm_plan_destroy(plan)
 
 
 def mm_heff(plan, m, h_ext, terms, t, h_out):
-    _check(lib().mm_heff(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(h_out)))
+    _check(lib().mm_heff(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t),
+                         _vec(plan, h_out, "h_out")))
 
 
 def mm_llg_rhs(plan, m, h_ext, terms, t, dmdt_out):
-    _check(lib().mm_llg_rhs(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(dmdt_out)))
+    _check(lib().mm_llg_rhs(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t),
+                            _vec(plan, dmdt_out, "dmdt_out")))
 
 
 def mm_set_ms(plan, Ms_cell):
-    _check(lib().mm_set_ms(plan, None if Ms_cell is None else _ptr(Ms_cell)))
+    _check(lib().mm_set_ms(plan, _ocellf(plan, Ms_cell, "Ms_cell")))
 
 
 def mm_set_exchange(plan, A_cell):
-    _check(lib().mm_set_exchange(plan, None if A_cell is None else _ptr(A_cell)))
+    _check(lib().mm_set_exchange(plan, _ocellf(plan, A_cell, "A_cell")))
 
 
 def mm_set_ku(plan, Ku_cell):
-    _check(lib().mm_set_ku(plan, None if Ku_cell is None else _ptr(Ku_cell)))
+    _check(lib().mm_set_ku(plan, _ocellf(plan, Ku_cell, "Ku_cell")))
 
 
 def mm_set_dmi(plan, kind, D, D_cell):
-    _check(lib().mm_set_dmi(plan, int(kind), float(D), None if D_cell is None else _ptr(D_cell)))
+    _check(lib().mm_set_dmi(plan, int(kind), float(D), _ocellf(plan, D_cell, "D_cell")))
 
 
 def mm_oersted(plan, j, h_out):
-    _check(lib().mm_oersted(plan, _ptr(j), _ptr(h_out)))
+    _check(lib().mm_oersted(plan, _vec(plan, j, "j"), _vec(plan, h_out, "h_out")))
 
 
 def mm_set_current(plan, j, freq):
-    _check(lib().mm_set_current(plan, None if j is None else _ptr(j), float(freq)))
+    _check(lib().mm_set_current(plan, _ovec(plan, j, "j"), float(freq)))
 
 
 def mm_set_drive(plan, amp, freq, mask):
-    _check(lib().mm_set_drive(plan, _vec3(amp), float(freq), None if mask is None else _ptr(mask)))
+    import torch
+
+    _check(lib().mm_set_drive(plan, _vec3(amp), float(freq),
+                              _ocellf(plan, mask, "mask", torch.uint8)))
 
 
 def mm_llg_step(plan, m, h_ext, terms, t, dt, opts):
+    pm = _vec(plan, m, "m")
     tt, dd = C.c_double(t), C.c_double(dt)
     st = mm_step_stats()
-    status = lib().mm_llg_step(plan, _ptr(m), _vec3(h_ext), int(terms), C.byref(tt), C.byref(dd),
+    status = lib().mm_llg_step(plan, pm, _vec3(h_ext), int(terms), C.byref(tt), C.byref(dd),
                                C.byref(opts), C.byref(st))
     return status, tt.value, dd.value, st
 
 
 def mm_relax(plan, m, h_ext, terms, tol, max_steps, rtol):
+    pm = _vec(plan, m, "m")
     st = mm_step_stats()
-    status = lib().mm_relax(plan, _ptr(m), _vec3(h_ext), int(terms), float(tol), int(max_steps),
+    status = lib().mm_relax(plan, pm, _vec3(h_ext), int(terms), float(tol), int(max_steps),
                             float(rtol), C.byref(st))
     return status, st
 
 
 def mm_energy(plan, m, h_ext, terms, t):
     E = (C.c_double * 6)()
-    _check(lib().mm_energy(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), E))
+    _check(lib().mm_energy(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t), E))
     return np.array(list(E))
 
 
 def mm_max_torque(plan, m, h_ext, terms, t):
     out = C.c_double()
-    _check(lib().mm_max_torque(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), C.byref(out)))
+    _check(lib().mm_max_torque(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t),
+                               C.byref(out)))
     return out.value
 
 
@@ -291,41 +368,72 @@ def mm_profile_read(plan):
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(MM_NPASS)}
 
 
+def _padded_f64(plan, t, name, spectrum):
+    import torch
+
+    P = mm_plan_padded(plan)
+    Px, Py, Pz = P
+    shape = ((Pz // 2 + 1, Py // 2 + 1, Px // 2 + 1 if Px > 1 else 1) if spectrum
+             else (Pz, Py, Px))
+    return _expect(t, name, torch.float64, _plan_info(plan)[2], shape)
+
+
 def mm_debug_kernel(plan, s, out):
-    _check(lib().mm_debug_kernel(plan, int(s), _ptr(out)))
+    _check(lib().mm_debug_kernel(plan, int(s), _padded_f64(plan, out, "out", False)))
 
 
 def mm_debug_spectrum(plan, s, out):
-    _check(lib().mm_debug_spectrum(plan, int(s), _ptr(out)))
+    _check(lib().mm_debug_spectrum(plan, int(s), _padded_f64(plan, out, "out", True)))
 
 
-def _optr(t):
-    return None if t is None else _ptr(t)
+def _ckpt(plan, ck, nsteps, ckpt_every, name):
+    """Checkpoints (nck, 3, nz, ny, nx), nck = ceil(nsteps / ckpt_every)."""
+    if ck is None:
+        return None
+    grid, dt, dev = _plan_info(plan)
+    import torch
+
+    nx, ny, nz = grid
+    if int(ckpt_every) <= 0:
+        raise ValueError("ckpt_every must be positive with checkpoints")
+    nck = max((int(nsteps) + int(ckpt_every) - 1) // int(ckpt_every), 1)
+    return _expect(ck, name, getattr(torch, dt), dev, (nck, 3, nz, ny, nx))
 
 
 def mm_heff_vjp(plan, m, w, terms, grad_m, grad_ms):
-    _check(lib().mm_heff_vjp(plan, _ptr(m), _ptr(w), int(terms), _ptr(grad_m), _optr(grad_ms)))
+    _check(lib().mm_heff_vjp(plan, _vec(plan, m, "m"), _vec(plan, w, "w"), int(terms),
+                             _vec(plan, grad_m, "grad_m"), _ocellf(plan, grad_ms, "grad_ms")))
 
 
 def mm_llg_rhs_vjp(plan, m, h_ext, terms, t, w, grad_m, grad_ms):
-    _check(lib().mm_llg_rhs_vjp(plan, _ptr(m), _vec3(h_ext), int(terms), float(t), _ptr(w),
-                                _ptr(grad_m), _optr(grad_ms)))
+    _check(lib().mm_llg_rhs_vjp(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t),
+                                _vec(plan, w, "w"), _vec(plan, grad_m, "grad_m"),
+                                _ocellf(plan, grad_ms, "grad_ms")))
 
 
 def mm_rk4_forward(plan, m, h_ext, terms, t0, dt, nsteps, region, ckpt_every, ckpt):
+    import torch
+
     loss = C.c_double()
-    _check(lib().mm_rk4_forward(plan, _ptr(m), _vec3(h_ext), int(terms), float(t0), float(dt),
-                                int(nsteps), _optr(region), int(ckpt_every), _optr(ckpt),
+    _check(lib().mm_rk4_forward(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t0),
+                                float(dt), int(nsteps), _ocellf(plan, region, "region", torch.uint8),
+                                int(ckpt_every), _ckpt(plan, ckpt, nsteps, ckpt_every, "ckpt"),
                                 C.byref(loss)))
     return loss.value
 
 
 def mm_rk4_adjoint(plan, ckpt, h_ext, terms, t0, dt, nsteps, region, ckpt_every, grad_ms,
                    grad_m0):
+    import torch
+
     loss = C.c_double()
-    _check(lib().mm_rk4_adjoint(plan, _ptr(ckpt), _vec3(h_ext), int(terms), float(t0), float(dt),
-                                int(nsteps), _optr(region), int(ckpt_every), _optr(grad_ms),
-                                _optr(grad_m0), C.byref(loss)))
+    if ckpt is None:
+        raise ValueError("ckpt is required")
+    _check(lib().mm_rk4_adjoint(plan, _ckpt(plan, ckpt, nsteps, ckpt_every, "ckpt"), _vec3(h_ext),
+                                int(terms), float(t0), float(dt), int(nsteps),
+                                _ocellf(plan, region, "region", torch.uint8), int(ckpt_every),
+                                _ocellf(plan, grad_ms, "grad_ms"), _ovec(plan, grad_m0, "grad_m0"),
+                                C.byref(loss)))
     return loss.value
 
 
@@ -413,12 +521,14 @@ class Plan:
         self.handle = mm_plan_create(self.grid, self.cell, Ms, A, Ku, alpha, o)
         nx, ny, nz = self.grid
         self.shape = (3, nz, ny, nx)
+        # destroyed through the ABI when collected or, at the latest, at
+        # interpreter exit (finalizers run before module teardown)
+        self._fin = weakref.finalize(self, _destroy_plan, lib().mm_plan_destroy, self.handle.value)
 
-    def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            mm_plan_destroy(h)
-            self.handle = None
+    def close(self):
+        """Release the plan's device memory now."""
+        self._fin()
+        self.handle = None
 
     def _t(self, a):
         import torch
@@ -432,14 +542,18 @@ class Plan:
 
         return torch.empty(self.shape, dtype=self.dtype, device=self.device)
 
+    def _v(self, a):
+        """A vector field as a (3, nz, ny, nx) tensor of the plan's dtype."""
+        return self._t(a).reshape(self.shape)
+
     def heff(self, m, h_ext=None, terms=MM_ALL, t=0.0, out=None):
-        m = self._t(m)
+        m = self._v(m)
         out = self.empty() if out is None else out
         mm_heff(self.handle, m, h_ext, terms, t, out)
         return out
 
     def llg_rhs(self, m, h_ext=None, terms=MM_ALL, t=0.0, out=None):
-        m = self._t(m)
+        m = self._v(m)
         out = self.empty() if out is None else out
         mm_llg_rhs(self.handle, m, h_ext, terms, t, out)
         return out
@@ -490,7 +604,7 @@ class Plan:
 
     def oersted(self, j, out=None):
         """Oersted field of the current density j (A/m^2, shape (3, nz, ny, nx))."""
-        j = self._t(j)
+        j = self._v(j)
         out = self.empty() if out is None else out
         mm_oersted(self.handle, j, out)
         return out
@@ -502,7 +616,7 @@ class Plan:
         if j is None:
             mm_set_current(self.handle, None, 0.0)
             return
-        mm_set_current(self.handle, self._t(j), freq)
+        mm_set_current(self.handle, self._v(j), freq)
         torch.cuda.current_stream().synchronize()
 
     def set_drive(self, amp, freq, mask):
@@ -511,7 +625,9 @@ class Plan:
         if mask is None:
             mm_set_drive(self.handle, None, 0.0, None)
             return
-        mk = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to(self.device).contiguous()
+        nx, ny, nz = self.grid
+        mk = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to(self.device).reshape(
+            nz, ny, nx).contiguous()
         mm_set_drive(self.handle, amp, freq, mk)
         torch.cuda.current_stream().synchronize()
 
@@ -532,10 +648,10 @@ class Plan:
         return status, _stats(st)
 
     def energy(self, m, h_ext=None, terms=MM_ALL, t=0.0):
-        return mm_energy(self.handle, self._t(m), h_ext, terms, t)
+        return mm_energy(self.handle, self._v(m), h_ext, terms, t)
 
     def max_torque(self, m, h_ext=None, terms=MM_ALL, t=0.0):
-        return mm_max_torque(self.handle, self._t(m), h_ext, terms, t)
+        return mm_max_torque(self.handle, self._v(m), h_ext, terms, t)
 
     def padded(self):
         return mm_plan_padded(self.handle)
@@ -560,7 +676,7 @@ class Plan:
 
     def heff_vjp(self, m, w, terms=MM_ALL, want_ms=True):
         """(H^T w, d(w.h)/dMs) for the linear terms in `terms`."""
-        m, w = self._t(m), self._t(w)
+        m, w = self._v(m), self._v(w)
         gm = self.empty()
         gms = self._scalar_field() if want_ms else None
         mm_heff_vjp(self.handle, m, w, terms, gm, gms)
@@ -568,7 +684,7 @@ class Plan:
 
     def llg_rhs_vjp(self, m, w, h_ext=None, terms=MM_ALL, t=0.0, want_ms=True):
         """(J^T w, d(w.f)/dMs) of the LLG right-hand side at (m, t)."""
-        m, w = self._t(m), self._t(w)
+        m, w = self._v(m), self._v(w)
         gm = self.empty()
         gms = self._scalar_field() if want_ms else None
         mm_llg_rhs_vjp(self.handle, m, h_ext, terms, t, w, gm, gms)
@@ -585,9 +701,11 @@ class Plan:
 
         if region is None:
             return None
+        nx, ny, nz = self.grid
         if isinstance(region, torch.Tensor):
-            return region.to(device=self.device, dtype=torch.uint8).contiguous()
-        return torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8)).to(self.device)
+            return region.to(device=self.device, dtype=torch.uint8).reshape(nz, ny, nx).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8)).to(
+            self.device).reshape(nz, ny, nx).contiguous()
 
     def rk4(self, m, dt, nsteps, region=None, h_ext=None, terms=MM_ALL, t0=0.0, ckpt_every=0):
         """Fixed-step RK4 (m advanced in place).  Returns (loss, checkpoints or
@@ -634,7 +752,7 @@ class RegionLoss:
 
     def __init__(self, plan, m0, dt, nsteps, region, h_ext=None, terms=MM_ALL, t0=0.0,
                  ckpt_every=50):
-        self.plan, self.m0 = plan, plan._t(m0)
+        self.plan, self.m0 = plan, plan._v(m0)
         self.dt, self.nsteps, self.region = float(dt), int(nsteps), plan._region(region)
         self.h_ext, self.terms, self.t0, self.every = h_ext, terms, float(t0), int(ckpt_every)
 
@@ -686,23 +804,21 @@ class Server:
         self.dtype = torch.float32 if o.prec == MM_FP32 else torch.float64
         self.handle = mm_serve_create(o)
         self._held = {}
-
-    def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            mm_serve_destroy(h)
-            self.handle = None
+        self._fin = weakref.finalize(self, _destroy_server, lib().mm_serve_destroy,
+                                     self.handle.value)
 
     def close(self):
-        self.__del__()
+        """Wait for the active requests and release the server now."""
+        self._fin()
+        self.handle = None
 
     def submit(self, m, grid, cell, Ms, A=0.0, Ku=0.0, ku_axis=(0, 0, 1), alpha=1.0, h_ext=None,
                terms=MM_ALL, kind=MM_SERVE_RELAX, tol=1e-5, rtol=1e-6, atol=None, t_end=0.0,
                max_steps=50000, tag=0):
         """m: contiguous (3, nz, ny, nx) device tensor of the server dtype,
         kept alive by the server until its completion is polled."""
-        if m.dtype != self.dtype or not m.is_cuda or not m.is_contiguous():
-            raise ValueError("state must be a contiguous device tensor of the server precision")
+        nx, ny, nz = (int(v) for v in grid)
+        _expect(m, "m", self.dtype, m.device.index if m.is_cuda else -2, (3, nz, ny, nx))
         r = mm_request()
         for a in range(3):
             r.grid[a] = int(grid[a])

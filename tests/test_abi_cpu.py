@@ -78,3 +78,58 @@ def test_next_row_entry_points_reject_invalid_arguments_without_device():
         assert ei.value.status == mm.MM_EINVAL
     assert mm.MM_ALL == (mm.MM_DEMAG | mm.MM_EXCH | mm.MM_ANIS | mm.MM_ZEEMAN | mm.MM_DMI |
                          mm.MM_OERSTED)
+
+
+def test_binding_rejects_bad_tensors_before_any_call(monkeypatch):
+    """Every tensor handed to the library is checked against its plan (dtype,
+    shape, contiguity, device) before the call: a mismatch raises ValueError
+    and never reaches the C ABI (which would otherwise read or write 3N values
+    of the plan's precision through the raw pointer)."""
+    import numpy as np
+    import torch
+
+    from paper_2302_08843_amd import mm
+
+    calls = []
+
+    class Spy:
+        def __getattr__(self, name):
+            def f(*a):
+                calls.append(name)
+                return mm.MM_OK
+            return f
+
+    monkeypatch.setattr(mm, "_lib", Spy())
+    fake = mm.C.c_void_p(0x1000)
+    monkeypatch.setitem(mm._PLANS, fake.value, ((5, 4, 3), "float32", 0))
+    good = torch.zeros((3, 3, 4, 5), dtype=torch.float32)  # right dtype/shape, CPU memory
+    cases = [
+        (torch.zeros((3, 3, 4, 5), dtype=torch.float64), "dtype"),
+        (torch.zeros((3, 60), dtype=torch.float32), "shape"),
+        (torch.zeros((3, 3, 4, 6), dtype=torch.float32), "shape"),
+        (torch.zeros((3, 3, 5, 4), dtype=torch.float32).transpose(2, 3), "contiguous"),
+        (good, "cuda:0"),
+        (np.zeros((3, 3, 4, 5), np.float32), "torch tensor"),
+    ]
+    for bad, word in cases:
+        # the tensor under test is the first one each call validates
+        for call in (lambda t: mm.mm_heff(fake, t, None, mm.MM_ALL, 0.0, good),
+                     lambda t: mm.mm_oersted(fake, t, good),
+                     lambda t: mm.mm_llg_step(fake, t, None, mm.MM_ALL, 0.0, 0.0,
+                                              mm.mm_step_opts()),
+                     lambda t: mm.mm_llg_rhs_vjp(fake, t, None, mm.MM_ALL, 0.0, good, good, None)):
+            with pytest.raises(ValueError) as ei:
+                call(bad)
+            assert word in str(ei.value), (word, str(ei.value))
+    # per-cell fields: (nz, ny, nx); checkpoints: (ceil(n / every), 3, nz, ny, nx)
+    with pytest.raises(ValueError, match="shape"):
+        mm.mm_set_ms(fake, torch.zeros((3, 4, 6), dtype=torch.float32))
+    with pytest.raises(ValueError, match="dtype"):
+        mm.mm_set_drive(fake, (1, 0, 0), 1e9, torch.zeros((3, 4, 5), dtype=torch.float32))
+    with pytest.raises(ValueError, match="shape"):  # 10 steps, every 4: 3 checkpoints
+        mm._ckpt(fake, torch.zeros((2, 3, 3, 4, 5), dtype=torch.float32), 10, 4, "ckpt")
+    with pytest.raises(ValueError, match="ckpt is required"):
+        mm.mm_rk4_adjoint(fake, None, None, mm.MM_ALL, 0.0, 1e-13, 10, None, 4, None, None)
+    with pytest.raises(ValueError, match="unknown plan"):
+        mm.mm_heff(mm.C.c_void_p(0x2000), good, None, mm.MM_ALL, 0.0, good)
+    assert calls == [], calls
