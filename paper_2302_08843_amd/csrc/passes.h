@@ -79,6 +79,16 @@ namespace mmx {
 #ifndef MMX_RMW_F64
 #define MMX_RMW_F64 8
 #endif
+#ifdef MMX_STRIDED_WPE
+#define MMX_STRIDED_ATTR __attribute__((amdgpu_waves_per_eu(MMX_STRIDED_WPE)))
+#else
+#define MMX_STRIDED_ATTR
+#endif
+// F1 in FP32: 96 VGPRs give 5 waves per SIMD (measured -3 % at 512x512x64)
+#ifndef MMX_XR2C_WPE_F32
+#define MMX_XR2C_WPE_F32 5
+#endif
+#define MMX_XR2C_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? MMX_XR2C_WPE_F32 : 1)))
 #ifdef MMX_MIDW_WPE
 #define MMX_MIDW_ATTR __attribute__((amdgpu_waves_per_eu(MMX_MIDW_WPE)))
 #else
@@ -170,7 +180,7 @@ struct XR2C {
 };
 
 template <typename T, int M, bool PERCELL, bool HALF>
-__global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) void k_x_r2c(
+__global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR void k_x_r2c(
     const T* __restrict__ in, long in_row, long in_comp, int n_in, const T* __restrict__ Ms_cell,
     T Ms, cx<T>* __restrict__ out, long out_row, long out_comp, int nrows, int ncomp,
     const cx<T>* __restrict__ tw, int Lmax, bool vec)
@@ -282,7 +292,7 @@ struct Strided {
 // O32: every element offset of `in` and `out` times its size is below 4 GiB
 // (32-bit index arithmetic, scalar base + vector byte offset accesses).
 template <typename T, int L, int DIR, bool HALF, bool O32>
-__global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) void k_strided(
+__global__ __launch_bounds__((Strided<T, L>::kB * Strided<T, L>::kT)) MMX_STRIDED_ATTR void k_strided(
     const cx<T>* in, cx<T>* out, int n_in, int n_out, long es_in, long es_out, int ncols,
     int ntile, int G2, long nblocks, long g1_in, long g1_out, long g2_in, long g2_out,
     const cx<T>* __restrict__ tw, int Lmax)
@@ -590,23 +600,33 @@ __global__ __launch_bounds__((64 * MidW<T, L>::kW)) MMX_MIDW_ATTR void k_mid_w(
     const int col = tile * kCB + b;
     const bool cv = active && col < ncols;
     // one memory phase: the kernel tile(s) and twiddles for LDS, then the
-    // spectrum column (every thread of the block takes part in the staging)
+    // spectrum column (every thread of the block takes part in the staging).
+    // Staging: thread (rr, bb) = (tid / kCB, tid % kCB) takes rows rr, rr + RCH,
+    // ... of every component; offsets other than its own are uniform.
     using I = typename std::conditional<O32, unsigned, long>::type;
     const I plane = (I)(Py / 2 + 1) * (I)Hxp;
-    constexpr int NQ = (NT * KT + 64 * kW - 1) / (64 * kW);
+    constexpr int RCH = 64 * kW / kCB;              // rows per staging round
+    constexpr int NCH = (R + RCH - 1) / RCH;         // rounds per component
+    constexpr int NQ = NT * NK * NCH;
     constexpr int NTW = (L + 64 * kW - 1) / (64 * kW);
+    const int rr = (int)threadIdx.x / kCB, bb = (int)threadIdx.x % kCB;
     T kv[NQ];
-    cx<T> twv[NTW];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int idx = q * 64 * kW + (int)threadIdx.x;
-        const int bb = idx % kCB, r = (idx / kCB) % R, c = (idx / (kCB * R)) % NK;
-        const int cl = (tile0 + idx / KT) * kCB + bb;
-        const I off = AXIS == 2 ? (I)c * (I)Kn + (I)r * plane + (I)gp * (I)Hxp + (I)cl
-                                : (I)c * (I)Kn + (I)r * (I)Hxp + (I)cl;
-        kv[q] = idx < NT * KT && cl < ncols ? elem<O32>(Khat, off) : (T)0;
+    for (int tl = 0; tl < NT; ++tl) {
+        const int cl = (tile0 + tl) * kCB + bb;
+        const I base = (AXIS == 2 ? (I)rr * plane + (I)gp * (I)Hxp : (I)rr * (I)Hxp) + (I)cl;
+        const I rstep = AXIS == 2 ? (I)RCH * plane : (I)RCH * (I)Hxp;
+#pragma unroll
+        for (int c = 0; c < NK; ++c)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const bool use = cl < ncols && ch * RCH + rr < R;
+                kv[(tl * NK + c) * NCH + ch] =
+                    use ? elem<O32>(Khat, base + (I)c * (I)Kn + (I)ch * rstep) : (T)0;
+            }
     }
     const int tws = Lmax / L;
+    cx<T> twv[NTW];
 #pragma unroll
     for (int q = 0; q < NTW; ++q) {
         const int n = q * 64 * kW + (int)threadIdx.x;
@@ -615,10 +635,14 @@ __global__ __launch_bounds__((64 * MidW<T, L>::kW)) MMX_MIDW_ATTR void k_mid_w(
     cx<T> v[3][G::kE];
     mid_load<G, T, HALF, O32>(v, S, (long)g * gstride + col, n_valid, es, cs, cv, t);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int idx = q * 64 * kW + (int)threadIdx.x;
-        if (idx < NT * KT) kt[idx] = kv[q];
-    }
+    for (int tl = 0; tl < NT; ++tl)
+#pragma unroll
+        for (int c = 0; c < NK; ++c)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ch * RCH + rr < R)
+                    kt[tl * KT + (c * R + ch * RCH) * kCB + (int)threadIdx.x] =
+                        kv[(tl * NK + c) * NCH + ch];
 #pragma unroll
     for (int q = 0; q < NTW; ++q) {
         const int n = q * 64 * kW + (int)threadIdx.x;
@@ -1115,8 +1139,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
             // outputs n >= M/2 are cells x >= M >= nx: never used
             if ((i % Rl) >= Rl / 2) continue;
             const int e = G::S::out_index(t, i);
-            hd[2 * e] = v[i].x;
-            hd[2 * e + 1] = v[i].y;
+            reinterpret_cast<cx<T>*>(hd)[e] = v[i];  // reals 2e, 2e + 1
         }
     }
     __syncthreads();
