@@ -33,7 +33,8 @@
  * Scalar per-cell fields (Ms) use the same cell order with one component.
  *
  * Ownership.  The plan owns every internal buffer (spectral tensor, FFT
- * spectra, Runge-Kutta stages) and frees them in mm_plan_destroy.  Caller
+ * spectra, Runge-Kutta stages) and frees them in mm_plan_destroy, unless
+ * they live in a caller workspace (mm_opts.workspace).  Caller
  * buffers are only read or written during the call (stream-ordered): they
  * must stay valid until the plan's stream has consumed the work.
  *
@@ -116,11 +117,33 @@ typedef struct {
      * (mm_heff_vjp, mm_llg_rhs_vjp, mm_rk4_adjoint and the debug entry
      * points return MM_EINVAL). */
     const double *dz_layers;
+    /* Caller-owned device workspace (e.g. a torch allocation) for the plan's
+     * persistent buffers -- spectral kernel, FFT spectra, twiddles, reduction
+     * buffers, the 10 Runge-Kutta vectors and the step controller -- laid out
+     * by the library; at least mm_plan_workspace_bytes(grid, prec) bytes,
+     * aligned to 256 bytes, equal layers only (MM_EINVAL otherwise).  NULL:
+     * the plan allocates them itself.  The workspace must outlive the plan
+     * and must not be shared by two live plans.  Set-up temporaries of
+     * mm_plan_create and buffers of optional features (per-cell fields, the
+     * Oersted kernel, the differentiation space) are still allocated by the
+     * library. */
+    void *workspace;
+    size_t workspace_bytes;
 } mm_opts;
 
 /* Fill *o with defaults: MM_FP64, axis (0,0,1), demag_p 20, stream NULL,
- * no higher-order anisotropy, equal layers. */
+ * no higher-order anisotropy, equal layers, no workspace. */
 void mm_opts_default(mm_opts *o);
+
+/* Device bytes of the workspace a plan of this grid and precision (MM_FP32
+ * or MM_FP64, equal layers) needs for mm_opts.workspace (Sec. 2: the tensors
+ * live in memory the caller provides): the folded spectral kernel
+ * 6 (Pz/2+1)(Py/2+1) Hx reals, the spectra 3 nz ny Hx and 3 nz Py Hx complex
+ * values, the twiddles, reduction buffers, 10 Runge-Kutta vectors of 3N
+ * reals and the step controller, each rounded up to 256 bytes (Hx = Px/2+1
+ * rounded up to 128 bytes of reals).  Host-only, no device access.  0 for
+ * an invalid grid or precision. */
+size_t mm_plan_workspace_bytes(const int grid[3], int prec);
 
 /* Create a plan for grid[3] = (nx, ny, nz) cells of size cell[3] = (dx, dy,
  * dz) with saturation magnetisation Ms, exchange constant A, uniaxial

@@ -45,6 +45,12 @@ void free_plan(Plan* p)
 {
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
+    if (p->ws) {
+        // carved from the caller's workspace: not ours to free
+        p->Khat = p->S1 = p->S2 = p->tw = p->rk = nullptr;
+        p->red = p->red_out = nullptr;
+        p->ctl = nullptr;
+    }
     for (auto& r : p->prof.pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -514,6 +520,22 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
             return s;                                           \
         }                                                       \
     } while (0)
+    if (o.workspace) {
+        // the caller's workspace holds every persistent buffer (checked by
+        // mm_plan_create: equal layers, large enough, 256-byte aligned)
+        const WsLayout L = ws_layout(grid, o.prec);
+        char* w = static_cast<char*>(o.workspace);
+        p->ws = true;
+        p->Khat = w + L.Khat;
+        p->S1 = w + L.S1;
+        p->S2 = L.s2_separate ? (void*)(w + L.S2) : p->S1;
+        p->tw = w + L.tw;
+        p->red = reinterpret_cast<double*>(w + L.red);
+        p->red_out = reinterpret_cast<double*>(w + L.red_out);
+        p->rk = w + L.rk;
+        p->ctl = reinterpret_cast<DevCtl*>(w + L.ctl);
+        p->bytes = L.total;
+    } else {
     if (!share) MM_ALLOC(p->Khat, 6 * (size_t)p->Kn * es, "spectral kernel");
     MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es, "spectrum S1");
     if ((p->P[2] > 1 || p->layered) && p->P[1] > 1)
@@ -523,6 +545,7 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     if (!share) MM_ALLOC(p->tw, (size_t)p->Lmax * 2 * es, "twiddles");
     MM_ALLOC(p->red, sizeof(double) * kRedSlots, "reduction partials");
     MM_ALLOC(p->red_out, sizeof(double) * 8, "reduction results");
+    }
     if (p->layered) {
         MM_ALLOC(p->zw, 4 * (size_t)grid[2] * es, "layer couplings");
         MM_ALLOC(p->lw, sizeof(double) * grid[2], "layer heights");
@@ -581,11 +604,9 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
 }
 
 
-// Device bytes a plan of this grid allocates for a device-controlled run
-// (spectra, reduction buffers, Runge-Kutta vectors, controller), plus the
-// spectral kernel and twiddles when with_tensor.  Mirrors plan_build and
-// ensure_rk.
-size_t plan_footprint(const int grid[3], int prec, bool with_tensor)
+// Layout of a plan's persistent buffers in one workspace; mirrors the
+// allocations of plan_build and ensure_rk (equal layers).
+WsLayout ws_layout(const int grid[3], int prec)
 {
     const size_t es = prec == MM_FP32 ? 4 : 8;
     int P[3];
@@ -596,16 +617,39 @@ size_t plan_footprint(const int grid[3], int prec, bool with_tensor)
     const long Hxp = (Hx + row_align - 1) / row_align * row_align;
     const long S1n = 3L * grid[2] * grid[1] * Hxp;
     const long S2n = 3L * grid[2] * P[1] * Hxp;
-    size_t b = (size_t)S1n * 2 * es;
-    if (P[2] > 1 && P[1] > 1) b += (size_t)S2n * 2 * es;
-    b += sizeof(double) * kRedSlots + sizeof(double) * 8;
-    b += 10 * 3 * (size_t)N * es + sizeof(DevCtl);
-    if (with_tensor) {
-        const long Kn = (long)(P[2] / 2 + 1) * (P[1] / 2 + 1) * Hxp;
-        const int Lmax = std::max(P[0], std::max(P[1], P[2]));
-        b += 6 * (size_t)Kn * es + (size_t)Lmax * 2 * es;
-    }
-    return b;
+    const long Kn = (long)(P[2] / 2 + 1) * (P[1] / 2 + 1) * Hxp;
+    const int Lmax = std::max(P[0], std::max(P[1], P[2]));
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    WsLayout L{};
+    size_t off = 0;
+    L.Khat = off;
+    off += up(6 * (size_t)Kn * es);
+    L.S1 = off;
+    off += up((size_t)S1n * 2 * es);
+    L.s2_separate = P[2] > 1 && P[1] > 1;
+    L.S2 = off;
+    if (L.s2_separate) off += up((size_t)S2n * 2 * es);
+    L.tw = off;
+    off += up((size_t)Lmax * 2 * es);
+    L.red = off;
+    off += up(sizeof(double) * kRedSlots);
+    L.red_out = off;
+    off += up(sizeof(double) * 8);
+    L.rk = off;
+    off += up(10 * 3 * (size_t)N * es);
+    L.ctl = off;
+    off += up(sizeof(DevCtl));
+    L.total = off;
+    return L;
+}
+
+// Device bytes a plan of this grid allocates for a device-controlled run
+// (spectra, reduction buffers, Runge-Kutta vectors, controller), plus the
+// spectral kernel and twiddles when with_tensor.
+size_t plan_footprint(const int grid[3], int prec, bool with_tensor)
+{
+    const WsLayout L = ws_layout(grid, prec);
+    return with_tensor ? L.total : L.total - (L.S1 - L.Khat) - (L.red - L.tw);
 }
 
 }  // namespace mmx
@@ -882,6 +926,8 @@ void mm_opts_default(mm_opts* o)
     o->stream = nullptr;
     o->ku2 = o->kc1 = o->kc2 = 0.0;
     o->dz_layers = nullptr;
+    o->workspace = nullptr;
+    o->workspace_bytes = 0;
     for (int a = 0; a < 3; ++a) {
         o->kc_axis1[a] = a == 0 ? 1.0 : 0.0;
         o->kc_axis2[a] = a == 1 ? 1.0 : 0.0;
@@ -947,11 +993,35 @@ mm_status mm_plan_create(mm_plan** out, const int grid[3], const double cell[3],
                 return MM_EINVAL;
             }
     }
+    if (o.workspace) {
+        const size_t need = ws_layout(grid, o.prec).total;
+        if (o.dz_layers) {
+            set_error("a caller workspace holds equal-layer plans only");
+            return MM_EINVAL;
+        }
+        if (((uintptr_t)o.workspace & 255) != 0) {
+            set_error("the workspace must be aligned to 256 bytes");
+            return MM_EINVAL;
+        }
+        if (o.workspace_bytes < need) {
+            set_error("workspace of " + std::to_string(o.workspace_bytes) + " bytes, " +
+                      std::to_string(need) + " needed (mm_plan_workspace_bytes)");
+            return MM_EINVAL;
+        }
+    }
     Plan* p = nullptr;
     mm_status s = plan_build(grid, cell, Ms, A, Ku, alpha, o, nullptr, &p);
     if (s != MM_OK) return s;
     *out = reinterpret_cast<mm_plan*>(p);
     return MM_OK;
+}
+
+size_t mm_plan_workspace_bytes(const int grid[3], int prec)
+{
+    if (!grid || (prec != MM_FP32 && prec != MM_FP64)) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 1 || grid[a] > kMaxFFT / 2) return 0;
+    return ws_layout(grid, prec).total;
 }
 
 void mm_plan_destroy(mm_plan* pl) { free_plan(reinterpret_cast<Plan*>(pl)); }

@@ -112,6 +112,7 @@ struct Plan {
     double *gms = nullptr;      // N doubles: Ms-gradient accumulator
     DevCtl *ctl = nullptr;      // device-side step controller
     SharedTensor *shared = nullptr;  // Khat and tw owned jointly with other plans
+    bool ws = false;  // Khat, S1, S2, tw, red, red_out, rk, ctl carved from a caller workspace
     size_t bytes = 0;
     Profiler prof;
 };
@@ -231,6 +232,14 @@ mm_status ensure_rk(Plan *p);
 mm_status plan_build(const int grid[3], const double cell[3], double Ms, double A, double Ku,
                      double alpha, const mm_opts &o, SharedTensor *share, Plan **out);
 size_t plan_footprint(const int grid[3], int prec, bool with_tensor);
+// Byte offsets of a plan's persistent buffers inside one workspace, each
+// aligned to 256 bytes (equal layers): spectral kernel, spectra, twiddles,
+// reduction buffers, Runge-Kutta vectors and the step controller.
+struct WsLayout {
+    size_t Khat, S1, S2, tw, red, red_out, rk, ctl, total;
+    bool s2_separate;
+};
+WsLayout ws_layout(const int grid[3], int prec);
 // Device-controlled Dormand-Prince run: dev_prepare copies m0 into the
 // state, evaluates f(y0) (and the torque for relaxation), picks the starting
 // step if init.dt <= 0, uploads the controller (synchronises); dev_step

@@ -31,6 +31,7 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4:
 
 # Every entry point declared in include/mm.h.
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
+           "mm_plan_workspace_bytes",
            "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi",
            "mm_oersted", "mm_set_current", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
@@ -79,7 +80,8 @@ class mm_opts(C.Structure):
     _fields_ = [("prec", C.c_int), ("ku_axis", C.c_double * 3), ("demag_p", C.c_int),
                 ("stream", C.c_void_p), ("ku2", C.c_double), ("kc1", C.c_double),
                 ("kc2", C.c_double), ("kc_axis1", C.c_double * 3), ("kc_axis2", C.c_double * 3),
-                ("dz_layers", C.POINTER(C.c_double))]
+                ("dz_layers", C.POINTER(C.c_double)), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
 
 
 class mm_step_opts(C.Structure):
@@ -128,6 +130,8 @@ def lib():
         L.mm_plan_destroy.restype = None
         L.mm_plan_device_bytes.argtypes = [vp]
         L.mm_plan_device_bytes.restype = C.c_size_t
+        L.mm_plan_workspace_bytes.argtypes = [ip, C.c_int]
+        L.mm_plan_workspace_bytes.restype = C.c_size_t
         L.mm_plan_padded.argtypes = [vp, ip]
         L.mm_plan_padded.restype = None
         L.mm_set_ms.argtypes = [vp, vp]
@@ -387,17 +391,23 @@ def mm_debug_spectrum(plan, s, out):
 
 
 def _ckpt(plan, ck, nsteps, ckpt_every, name):
-    """Checkpoints (nck, 3, nz, ny, nx), nck = ceil(nsteps / ckpt_every)."""
+    """Checkpoints (K, 3, nz, ny, nx) with K >= ceil(nsteps / ckpt_every), the
+    number the library reads or writes (argument errors such as a
+    non-positive step count are left to the library)."""
     if ck is None:
         return None
     grid, dt, dev = _plan_info(plan)
     import torch
 
     nx, ny, nz = grid
-    if int(ckpt_every) <= 0:
-        raise ValueError("ckpt_every must be positive with checkpoints")
-    nck = max((int(nsteps) + int(ckpt_every) - 1) // int(ckpt_every), 1)
-    return _expect(ck, name, getattr(torch, dt), dev, (nck, 3, nz, ny, nx))
+    nck = 1
+    if int(ckpt_every) > 0:
+        nck = max((int(nsteps) + int(ckpt_every) - 1) // int(ckpt_every), 1)
+    shape = (max(int(ck.shape[0]), nck) if isinstance(ck, torch.Tensor) and ck.dim() == 5 else nck,
+             3, nz, ny, nx)
+    if isinstance(ck, torch.Tensor) and ck.dim() == 5 and int(ck.shape[0]) < nck:
+        raise ValueError("%s holds %d checkpoints, %d needed" % (name, int(ck.shape[0]), nck))
+    return _expect(ck, name, getattr(torch, dt), dev, shape)
 
 
 def mm_heff_vjp(plan, m, w, terms, grad_m, grad_ms):
@@ -484,6 +494,11 @@ def mm_plan_device_bytes(plan):
     return int(lib().mm_plan_device_bytes(plan))
 
 
+def mm_plan_workspace_bytes(grid, prec):
+    g = (C.c_int * 3)(*[int(v) for v in grid])
+    return int(lib().mm_plan_workspace_bytes(g, int(prec)))
+
+
 # ---------------------------------------------------------------------------
 # Convenience object (same calls, holds the handle and the tensor dtype)
 # ---------------------------------------------------------------------------
@@ -493,7 +508,10 @@ class Plan:
 
     def __init__(self, grid, cell, Ms, A=0.0, Ku=0.0, alpha=0.5, prec="fp64", ku_axis=(0, 0, 1),
                  demag_p=20, stream=None, Ku2=0.0, Kc1=0.0, Kc2=0.0, kc_axes=((1, 0, 0), (0, 1, 0)),
-                 layers=None):
+                 layers=None, workspace=None):
+        """workspace: optional device tensor (any dtype, contiguous, at least
+        mm_plan_workspace_bytes(grid, prec) bytes) that holds the plan's
+        persistent buffers; the plan keeps a reference to it."""
         import torch
 
         self.grid = tuple(int(v) for v in grid)
@@ -518,6 +536,13 @@ class Plan:
             self.layers = np.ascontiguousarray(np.asarray(layers, dtype=np.float64))
             assert self.layers.shape == (self.grid[2],), "one height per layer"
             o.dz_layers = self.layers.ctypes.data_as(C.POINTER(C.c_double))
+        self.workspace = workspace
+        if workspace is not None:
+            if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or \
+                    not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            o.workspace = C.c_void_p(workspace.data_ptr())
+            o.workspace_bytes = workspace.numel() * workspace.element_size()
         self.handle = mm_plan_create(self.grid, self.cell, Ms, A, Ku, alpha, o)
         nx, ny, nz = self.grid
         self.shape = (3, nz, ny, nx)

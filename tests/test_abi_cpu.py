@@ -126,10 +126,54 @@ def test_binding_rejects_bad_tensors_before_any_call(monkeypatch):
         mm.mm_set_ms(fake, torch.zeros((3, 4, 6), dtype=torch.float32))
     with pytest.raises(ValueError, match="dtype"):
         mm.mm_set_drive(fake, (1, 0, 0), 1e9, torch.zeros((3, 4, 5), dtype=torch.float32))
-    with pytest.raises(ValueError, match="shape"):  # 10 steps, every 4: 3 checkpoints
+    with pytest.raises(ValueError, match="needed"):  # 10 steps, every 4: 3 checkpoints
         mm._ckpt(fake, torch.zeros((2, 3, 3, 4, 5), dtype=torch.float32), 10, 4, "ckpt")
+    with pytest.raises(ValueError, match="shape"):
+        mm._ckpt(fake, torch.zeros((3, 3, 3, 5, 4), dtype=torch.float32), 10, 4, "ckpt")
     with pytest.raises(ValueError, match="ckpt is required"):
         mm.mm_rk4_adjoint(fake, None, None, mm.MM_ALL, 0.0, 1e-13, 10, None, 4, None, None)
     with pytest.raises(ValueError, match="unknown plan"):
         mm.mm_heff(mm.C.c_void_p(0x2000), good, None, mm.MM_ALL, 0.0, good)
     assert calls == [], calls
+
+
+def _workspace_model(grid, prec):
+    """Bytes of the plan buffers written out from their definitions: padded
+    extents P = next power of two >= 2n - 1 (1 for n = 1), x bins Hx = Px/2 + 1
+    rounded up to 128 bytes of reals, the folded real kernel 6 (Pz/2+1)(Py/2+1)
+    Hx, spectra 3 nz ny Hx and (when Py, Pz > 1) 3 nz Py Hx complex, Lmax
+    twiddles, 8192 + 8 reduction doubles, 10 vectors of 3N and the 120-byte
+    controller, each rounded up to 256 bytes."""
+    def pad(n):
+        p = 1
+        while n > 1 and p < 2 * n - 1:
+            p *= 2
+        return p
+    es = 4 if prec == 0 else 8
+    nx, ny, nz = grid
+    Px, Py, Pz = pad(nx), pad(ny), pad(nz)
+    Hx = Px // 2 + 1 if Px > 1 else 1
+    al = 32 if prec == 0 else 16
+    Hx = -(-Hx // al) * al
+    up = lambda b: -(-b // 256) * 256
+    parts = [6 * (Pz // 2 + 1) * (Py // 2 + 1) * Hx * es, 3 * nz * ny * Hx * 2 * es]
+    if Py > 1 and Pz > 1:
+        parts.append(3 * nz * Py * Hx * 2 * es)
+    parts += [max(Px, Py, Pz) * 2 * es, 8 * 8192, 8 * 8, 10 * 3 * nx * ny * nz * es, 120]
+    return sum(up(b) for b in parts)
+
+
+def test_workspace_size_query():
+    """mm_plan_workspace_bytes (host only): the plan's persistent buffers for a
+    caller-owned workspace, against the layout written out independently."""
+    from paper_2302_08843_amd import mm
+
+    for grid in [(512, 512, 64), (256, 256, 16), (32, 32, 4), (64, 64, 1), (7, 1, 1), (1, 1, 1),
+                 (101, 51, 1), (3, 5, 300)]:
+        for prec in (mm.MM_FP32, mm.MM_FP64):
+            assert mm.mm_plan_workspace_bytes(grid, prec) == _workspace_model(grid, prec), (grid, prec)
+    assert mm.mm_plan_workspace_bytes((0, 4, 4), mm.MM_FP32) == 0
+    assert mm.mm_plan_workspace_bytes((513, 4, 4), mm.MM_FP32) == 0
+    assert mm.mm_plan_workspace_bytes((4, 4, 4), 7) == 0
+    # the large benchmark grid: kernel 410.5 MB + spectra 1.22 GB + RK 2.01 GB (FP32)
+    assert abs(mm.mm_plan_workspace_bytes((512, 512, 64), mm.MM_FP32) / 1e9 - 3.70) < 0.05
