@@ -298,6 +298,22 @@ mm_status mm_relax(mm_plan *p, void *m, const double h_ext[3], unsigned terms, d
 mm_status mm_energy(mm_plan *p, const void *m, const double h_ext[3], unsigned terms, double t,
                     double E[6]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * energies of mm_energy (same terms, same E[6], same kernels and reduction
+ * order, so the same values) computed without any allocation.  The field
+ * buffer (3N reals of the plan's precision) and the reduction partials and
+ * results live in one static device array of MM_NOALLOC_SCRATCH_BYTES per
+ * GPU, which each GPU the library runs on holds until the process ends; a
+ * plan needing more than that (beyond 5.58 M cells in FP32, 2.79 M in FP64)
+ * gives MM_EINVAL with the sizes in mm_last_error().  Every call on one GPU
+ * uses that GPU's array and leaves its last contents there: calls that
+ * overlap on one GPU (two host threads, or two streams in flight) race.
+ * Synchronises the plan's stream. */
+#define MM_NOALLOC_SCRATCH_BYTES (64u << 20)
+mm_status mm_energy_noalloc(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,
+                            double t, double E[6]);
+
 /* max_i |m_i x h_i| / Ms_i over magnetic cells.  Synchronises. */
 mm_status mm_max_torque(mm_plan *p, const void *m, const double h_ext[3], unsigned terms,
                         double t, double *out);

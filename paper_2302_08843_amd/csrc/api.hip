@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -868,33 +869,34 @@ static mm_status heff_vjp_impl(Plan* p, const T* m, const T* w, const double hex
     return MM_OK;
 }
 
+// The energies of `terms` at m into E[6]: the field of each term into h (3N
+// reals), its weighted dot product with m reduced through `partials`
+// (kRedSlots doubles) into out[0..4], read back through the plan's pinned
+// buffer.  Every slot of out is written (cleared by a fill kernel, not a
+// memset, so the sequence can sit in a captured graph).  Synchronises.
 template <typename T>
-static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigned terms, double t,
-                             double E[6])
+static mm_status energy_core(Plan* p, const T* m, const double h_ext[3], unsigned terms, double t,
+                             T* h, double* partials, double* out, double E[6])
 {
-    mm_status s = ensure_rk(p);
-    if (s != MM_OK) return s;
-    T* h = rk_vec<T>(p, 0);
     // reduction slots 0..3 demag, exchange, anisotropy, Zeeman (with the
     // Oersted field, an applied field too); 4 DMI
     const unsigned bits[5] = {MM_DEMAG, MM_EXCH, MM_ANIS, MM_ZEEMAN | MM_OERSTED, MM_DMI};
+    MM_HIP(zero_doubles(*p, out, 8), "clear");
     for (int e = 0; e < 5; ++e) {
-        if (!(terms & bits[e])) {
-            MM_HIP(hipMemsetAsync(p->red_out + e, 0, sizeof(double), p->stream), "clear");
-            continue;
-        }
+        if (!(terms & bits[e])) continue;
         if (bits[e] == MM_ANIS) {
             // from the energy density (the linear-term formula does not hold
             // for the higher orders)
-            MM_HIP(anis_energy<T>(*p, m, p->red_out + e), "anisotropy energy");
+            MM_HIP(anis_energy<T>(*p, m, out + e, partials), "anisotropy energy");
             continue;
         }
         MM_HIP(eval_field<T>(*p, m, h_ext, bits[e] & terms, t, h, nullptr, p->alpha, true, nullptr),
                "field");
-        MM_HIP(dot_ms<T>(*p, m, h, p->red_out + e), "energy reduction");
+        MM_HIP(dot_ms<T>(*p, m, h, out + e, partials), "energy reduction");
     }
-    s = fetch(p, 5);
-    if (s != MM_OK) return s;
+    MM_HIP(hipMemcpyAsync(p->host_out, out, sizeof(double) * 5, hipMemcpyDeviceToHost, p->stream),
+           "reading a reduction");
+    MM_HIP(hipStreamSynchronize(p->stream), "synchronising the stream");
     // thin layers: the reductions carry each layer's height
     const double V = p->d[0] * p->d[1] * (p->layered ? 1.0 : p->d[2]);
     double tot = 0.0;
@@ -907,6 +909,71 @@ static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigne
     E[5] = -0.5 * kMu0 * V * p->host_out[4];
     E[4] = tot + E[5];
     return MM_OK;
+}
+
+template <typename T>
+static mm_status energy_impl(Plan* p, const T* m, const double h_ext[3], unsigned terms, double t,
+                             double E[6])
+{
+    mm_status s = ensure_rk(p);
+    if (s != MM_OK) return s;
+    return energy_core<T>(p, m, h_ext, terms, t, rk_vec<T>(p, 0), p->red, p->red_out, E);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (mm_energy_noalloc): one static
+// device array per GPU, held until the process ends.  Host code never passes
+// the array's name to a kernel or copy; it uses the device address that
+// hipGetSymbolAddress returns, fetched once per device on the first call made
+// with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static mm_status scratch_address(void** out)
+{
+    int dev = 0;
+    MM_HIP(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the scratch table");
+        return MM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        MM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MM_OK;
+}
+
+// Scratch layout: reduction partials (kRedSlots doubles), results (8
+// doubles, padded to 256 bytes), then the field buffer of 3N reals.
+constexpr size_t kScratchPartials = 0;
+constexpr size_t kScratchOut = sizeof(double) * kRedSlots;
+constexpr size_t kScratchField = kScratchOut + 256;
+
+template <typename T>
+static mm_status energy_noalloc_impl(Plan* p, const T* m, const double h_ext[3], unsigned terms,
+                                     double t, double E[6])
+{
+    const size_t need = kScratchField + 3 * (size_t)p->N * sizeof(T);
+    if (need > (size_t)MM_NOALLOC_SCRATCH_BYTES) {
+        set_error("mm_energy_noalloc: the plan needs " + std::to_string(need) +
+                  " bytes of scratch, the maximum is " + std::to_string((size_t)MM_NOALLOC_SCRATCH_BYTES));
+        return MM_EINVAL;
+    }
+    void* base = nullptr;
+    mm_status s = scratch_address(&base);
+    if (s != MM_OK) return s;
+    char* b = static_cast<char*>(base);
+    return energy_core<T>(p, m, h_ext, terms, t, reinterpret_cast<T*>(b + kScratchField),
+                          reinterpret_cast<double*>(b + kScratchPartials),
+                          reinterpret_cast<double*>(b + kScratchOut), E);
 }
 
 }  // namespace mmx
@@ -1322,6 +1389,18 @@ mm_status mm_energy(mm_plan* pl, const void* m, const double h_ext[3], unsigned 
     }
     return p->prec == MM_FP32 ? energy_impl<float>(p, (const float*)m, h_ext, terms, t, E)
                               : energy_impl<double>(p, (const double*)m, h_ext, terms, t, E);
+}
+
+mm_status mm_energy_noalloc(mm_plan* pl, const void* m, const double h_ext[3], unsigned terms,
+                            double t, double E[6])
+{
+    Plan* p = reinterpret_cast<Plan*>(pl);
+    if (!p || !m || !E) {
+        set_error("null argument");
+        return MM_EINVAL;
+    }
+    return p->prec == MM_FP32 ? energy_noalloc_impl<float>(p, (const float*)m, h_ext, terms, t, E)
+                              : energy_noalloc_impl<double>(p, (const double*)m, h_ext, terms, t, E);
 }
 
 mm_status mm_max_torque(mm_plan* pl, const void* m, const double h_ext[3], unsigned terms,

@@ -180,11 +180,12 @@ hipError_t dp_torque(Plan &p, DevCtl *c);
 template <typename T>
 hipError_t renormalise(Plan &p, T *m);
 // anisotropy energy density (all orders) summed over magnetic cells -> *out_dev
+// (block partials in `partials`, kRedSlots doubles, or the plan's red)
 template <typename T>
-hipError_t anis_energy(Plan &p, const T *m, double *out_dev);
-// sum over cells of Ms * (a . b) in double -> *out_dev
+hipError_t anis_energy(Plan &p, const T *m, double *out_dev, double *partials = nullptr);
+// sum over cells of Ms * (a . b) in double -> *out_dev (partials as above)
 template <typename T>
-hipError_t dot_ms(Plan &p, const T *a, const T *b, double *out_dev);
+hipError_t dot_ms(Plan &p, const T *a, const T *b, double *out_dev, double *partials = nullptr);
 // Hairer-Norsett-Wanner starting-step norms: sums of (y/sc)^2, (f/sc)^2 and
 // ((f1 - f0)/sc)^2 with sc = atol + rtol |y|, into out_dev[0..2]
 template <typename T>

@@ -1544,8 +1544,9 @@ hipError_t dp_commit(Plan& p, DevCtl* c, T* y, const T* y1, T* k0, const T* k6)
 }
 
 template <typename T>
-hipError_t anis_energy(Plan& p, const T* m, double* out_dev)
+hipError_t anis_energy(Plan& p, const T* m, double* out_dev, double* partials)
 {
+    double* red = partials ? partials : p.red;
     AnisE A;
     A.ku1 = p.Ku;
     A.ku2 = p.Ku2;
@@ -1556,22 +1557,23 @@ hipError_t anis_energy(Plan& p, const T* m, double* out_dev)
         for (int b = 0; b < 3; ++b) A.ec[a][b] = p.ec[a][b];
     }
     k_anis_energy<T><<<kRedBlocks, kBlock, 0, p.stream>>>(
-        m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, p.red,
+        m, p.percell ? (const T*)p.Ms_cell : nullptr, p.Ms, p.N, A, red,
         p.layered ? p.lw : nullptr, (long)p.n[0] * p.n[1],
         p.percell_Ku ? (const T*)p.Ku_cell : nullptr);
     MMX_TRY(hipGetLastError());
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t dot_ms(Plan& p, const T* a, const T* b, double* out_dev)
+hipError_t dot_ms(Plan& p, const T* a, const T* b, double* out_dev, double* partials)
 {
+    double* red = partials ? partials : p.red;
     k_dot_ms<T><<<kRedBlocks, kBlock, 0, p.stream>>>(a, b, p.percell ? (const T*)p.Ms_cell : nullptr,
-                                                     p.Ms, p.N, p.red, p.layered ? p.lw : nullptr,
+                                                     p.Ms, p.N, red, p.layered ? p.lw : nullptr,
                                                      (long)p.n[0] * p.n[1]);
     MMX_TRY(hipGetLastError());
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, kRedBlocks, out_dev, 0, 1.0, 0);
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(red, kRedBlocks, out_dev, 0, 1.0, 0);
     return hipGetLastError();
 }
 
@@ -1723,8 +1725,8 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
                                          T* const*, int, double, double, double*, const double*); \
     template hipError_t dp_commit<T>(Plan&, DevCtl*, T*, const T*, T*, const T*);                \
     template hipError_t renormalise<T>(Plan&, T*);                                               \
-    template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*);                           \
-    template hipError_t anis_energy<T>(Plan&, const T*, double*);                                \
+    template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*, double*);                  \
+    template hipError_t anis_energy<T>(Plan&, const T*, double*, double*);                       \
     template hipError_t start_norms<T>(Plan&, const T*, const T*, const T*, double, double,      \
                                        double*);                                                 \
     template hipError_t count_magnetic<T>(Plan&, double*);                                       \

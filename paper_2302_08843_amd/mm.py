@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EHIP", -4:
 
 # Every entry point declared in include/mm.h.
 EXPORTS = ["mm_opts_default", "mm_plan_create", "mm_plan_destroy", "mm_plan_device_bytes",
-           "mm_plan_workspace_bytes",
+           "mm_plan_workspace_bytes", "mm_energy_noalloc",
            "mm_plan_padded", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi",
            "mm_oersted", "mm_set_current", "mm_set_drive", "mm_heff", "mm_llg_rhs", "mm_llg_step",
            "mm_relax", "mm_energy", "mm_max_torque", "mm_profile", "mm_profile_read",
@@ -170,7 +170,8 @@ def lib():
         L.mm_rk4_adjoint.argtypes = [vp, vp, dp, C.c_uint, C.c_double, C.c_double, C.c_long, vp,
                                      C.c_long, vp, vp, dp]
         L.mm_last_error.restype = C.c_char_p
-        for name in ("mm_plan_create", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi", "mm_oersted",
+        L.mm_energy_noalloc.argtypes = [vp, vp, dp, C.c_uint, C.c_double, dp]
+        for name in ("mm_plan_create", "mm_energy_noalloc", "mm_set_ms", "mm_set_exchange", "mm_set_ku", "mm_set_dmi", "mm_oersted",
                      "mm_set_current",
                      "mm_set_drive", "mm_heff", "mm_llg_rhs",
                      "mm_llg_step", "mm_relax", "mm_energy", "mm_max_torque", "mm_profile",
@@ -351,6 +352,13 @@ def mm_relax(plan, m, h_ext, terms, tol, max_steps, rtol):
 def mm_energy(plan, m, h_ext, terms, t):
     E = (C.c_double * 6)()
     _check(lib().mm_energy(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t), E))
+    return np.array(list(E))
+
+
+def mm_energy_noalloc(plan, m, h_ext, terms, t):
+    E = (C.c_double * 6)()
+    _check(lib().mm_energy_noalloc(plan, _vec(plan, m, "m"), _vec3(h_ext), int(terms), float(t),
+                                   E))
     return np.array(list(E))
 
 
