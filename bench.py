@@ -274,28 +274,26 @@ def _serve_once(mm, reqs, states, arrivals, opts):
 
 
 def serving(mm, W, nreq, opts):
-    """Serving measurement on the relaxation request stream (grids 64x64x1,
-    128x128x2, 256x64x4, 256x256x8; seeded material, field and smooth start
-    per request): a saturated pilot (all requests at t = 0), then Poisson
-    arrivals at 0.7 x the pilot's solves/s.  Latency = completion - scheduled
-    arrival on the host monotonic clock."""
+    """Serving on the relaxation request stream (grids 64x64x1, 128x128x2,
+    256x64x4, 256x256x8; seeded material, field and smooth start per request)
+    at the stream's parameters: torque criterion 1e-5, step cap
+    opts["max_steps"], Poisson arrivals at opts["rate"] per second (seeded).
+    Only the first `nreq` requests of the 512-request stream are served.
+    Latency = completion - scheduled arrival on the host monotonic clock;
+    p50/p99 over all requests and over the converged ones, capped requests
+    counted separately."""
     import torch
 
-    reqs = W.serving_requests(nreq, seed=0, rate=1.0)
+    reqs = W.serving_requests(512, seed=0, rate=opts["rate"])[:nreq]
     states = [torch.tensor(W.smooth_random(r["n"], 8.0, seed=r["seed"]), dtype=torch.float32,
                            device="cuda").contiguous() for r in reqs]
     torch.cuda.synchronize()
-    print("[bench] serving pilot: %d requests at t=0" % nreq, file=sys.stderr, flush=True)
-    done, t0, _ = _serve_once(mm, reqs, states, [0.0] * nreq, opts)
-    span = max(c["t_done"] for c in done.values()) - t0
-    sat = nreq / span
-    rate = 0.7 * sat
-    g = W.rng(1)
-    arrivals = list(np.cumsum(g.exponential(1.0 / rate, nreq)) - 0.0)
-    arrivals = [a - arrivals[0] for a in arrivals]
-    print("[bench] serving: Poisson arrivals at %.2f solves/s" % rate, file=sys.stderr, flush=True)
+    arrivals = [r["arrival"] - reqs[0]["arrival"] for r in reqs]
+    print("[bench] serving: %d requests, Poisson arrivals at %.2f/s, cap %d steps" %
+          (nreq, opts["rate"], opts["max_steps"]), file=sys.stderr, flush=True)
     done, t0, st = _serve_once(mm, reqs, states, arrivals, opts)
     lat = np.array([done[k]["t_done"] - (t0 + arrivals[k]) for k in range(nreq)])
+    conv = [k for k in range(nreq) if done[k]["status"] == mm.MM_OK]
     last = max(c["t_done"] for c in done.values())
     per = {}
     for cls in W.SERVING_GRIDS:
@@ -304,13 +302,19 @@ def serving(mm, W, nreq, opts):
             lc = lat[idx]
             per["%dx%dx%d" % cls] = {"n": len(idx), "p50_s": float(np.percentile(lc, 50)),
                                      "p99_s": float(np.percentile(lc, 99)),
-                                     "converged": sum(done[k]["status"] == mm.MM_OK for k in idx)}
+                                     "converged": sum(done[k]["status"] == mm.MM_OK for k in idx),
+                                     "mean_accepted": float(np.mean([done[k]["accepted"]
+                                                                     for k in idx]))}
     steps = [done[k]["accepted"] for k in range(nreq)]
+    capped = [k for k in range(nreq) if done[k]["status"] == mm.MM_ENOTCONV]
     return {
-        "requests": nreq, "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-        "solves_per_s": nreq / (last - t0), "saturated_solves_per_s": sat, "arrival_rate": rate,
-        "converged": sum(c["status"] == mm.MM_OK for c in done.values()),
-        "capped": sum(c["status"] == mm.MM_ENOTCONV for c in done.values()),
+        "requests": nreq, "stream": "first %d of the 512-request stream" % nreq,
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "converged_p50_s": float(np.percentile(lat[conv], 50)) if conv else None,
+        "converged_p99_s": float(np.percentile(lat[conv], 99)) if conv else None,
+        "solves_per_s": nreq / (last - t0), "arrival_rate": opts["rate"],
+        "converged": len(conv), "capped": len(capped),
+        "capped_final_torque": [float(done[k]["torque"]) for k in capped],
         "mean_accepted_steps": float(np.mean(steps)), "per_class": per,
         "tol": opts["tol"], "rtol": opts["rtol"], "max_steps": opts["max_steps"],
         "max_active": opts["max_active"], "steps_per_launch": opts["steps_per_launch"],
@@ -321,30 +325,156 @@ def serving(mm, W, nreq, opts):
     }
 
 
-def cpu_baseline(seconds_budget=20.0):
-    """The CPU oracle (plain FP64 C, OpenMP over FFT lines) on a bounded sample:
-    the same material and start state on a 256 x 256 x 32 grid."""
+def throughput_c2(mm, W, iters):
+    """Single-field throughput on the 256 x 256 x 16 grid (1,048,576 cells of
+    3 nm, padded 512 x 512 x 32): Ms and A drawn per run (seeds 0, 1, 2), Ku
+    5e4 along z, smooth random start; `iters` repeated field evaluations per
+    run in FP32 and FP64, median over the runs.  Every pass buffer fits the
+    256 MB Infinity Cache here, so the roofline fractions are cache-assisted."""
+    import torch
+
+    out = {}
+    for prec in ("fp32", "fp64"):
+        walls, passes = [], None
+        for seed in (0, 1, 2):
+            c = W.config_throughput(seed=seed)
+            plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], Ku=c["Ku"], alpha=0.5, prec=prec)
+            m = plan._t(c["m0"])
+            h = plan.empty()
+            for _ in range(10):
+                plan.heff(m, c["H"], c["terms"], out=h)
+            torch.cuda.synchronize()
+            plan.profile(seed == 0)
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                plan.heff(m, c["H"], c["terms"], out=h)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t0) / iters)
+            if seed == 0:
+                pr = plan.profile_read()
+                plan.profile(False)
+                pb = pass_bytes(c["n"], prec)
+                passes = {k: {"avg_us": 1e3 * v[0] / v[1], "GBs": pb[k] / (v[0] / 1e3 / v[1]) / 1e9}
+                          for k, v in pr.items() if v[1] and k in pb}
+            del plan, m, h
+        N = 256 * 256 * 16
+        wall = float(np.median(walls))
+        byt = sum(pass_bytes((256, 256, 16), prec).values())
+        out[prec] = {"cell_evals_per_s": N / wall, "ms": 1e3 * wall, "model_bytes": byt,
+                     "GBs": byt / wall / 1e9, "roofline_frac_cache_assisted": byt / wall / 1e9 /
+                     HBM_PEAK_GBS, "passes": passes, "runs": [1e3 * w for w in walls]}
+        torch.cuda.empty_cache()
+    out["fp32_over_fp64"] = out["fp32"]["cell_evals_per_s"] / out["fp64"]["cell_evals_per_s"]
+    out["iters"] = iters
+    return out
+
+
+def differentiation(mm, W):
+    """The design case (128 x 128 x 1 film, per-cell density, 500 RK4 steps of
+    0.1 ps with checkpoints every 50, time-averaged region m_z): forward and
+    discrete-adjoint wall time on the GPU in FP32 and FP64, the memory of the
+    checkpoints and the relative L2 difference of the FP32 gradient from the
+    FP64 one."""
+    import torch
+
+    c = W.config_adjoint()
+    res, grads = {}, {}
+    for prec in ("fp32", "fp64"):
+        plan = mm.Plan(c["n"], c["d"], Ms=1.0, A=c["A"], alpha=c["alpha"], prec=prec)
+        plan.set_ms(c["Ms0"] * c["rho"])
+        plan.set_drive(c["drive_amp"], c["drive_freq"], c["strip"])
+        for rep in range(2):  # the first pair allocates the work space
+            m = plan._t(c["m0"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss, ck = plan.rk4(m, c["dt"], c["steps"], c["region"], None, mm.MM_ALL, 0.0,
+                                c["checkpoint_every"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, gms, _ = plan.rk4_adjoint(ck, c["dt"], c["steps"], c["region"], None, mm.MM_ALL,
+                                         0.0, c["checkpoint_every"], want_m0=False)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        grads[prec] = gms.double().cpu().numpy() * c["Ms0"]  # dL/drho
+        res[prec] = {"forward_s": t1 - t0, "backward_s": t2 - t1, "loss": loss,
+                     "checkpoint_bytes": ck.numel() * ck.element_size()}
+        del plan
+    g32, g64 = grads["fp32"], grads["fp64"]
+    res["grad_rel_l2_fp32_vs_fp64"] = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    res["case"] = "128x128x1, 500 RK4 steps of 0.1 ps, checkpoints every 50"
+    return res
+
+
+def copy_bandwidth():
+    """Measured device-to-device copy rate (1 GiB read + 1 GiB written per
+    copy, torch copy kernel, HIP events): the attainable HBM rate beside the
+    8 TB/s nominal peak."""
+    import torch
+
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBs": 2 * (1 << 30) / t / 1e9, "bytes_per_copy": 2 * (1 << 30),
+            "frac_of_nominal": 2 * (1 << 30) / t / 1e9 / HBM_PEAK_GBS}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The CPU oracle (plain FP64 C, OpenMP over FFT lines) on the
+    single-field throughput grid (256 x 256 x 16, padded 512 x 512 x 32; Ms, A
+    of seed 0, Ku 5e4, smooth start): effective-field evaluations on all the
+    host threads, then on one."""
     import oracle
     from paper_2302_08843_amd import workloads as W
 
-    n = (256, 256, 32)
-    c = W.config_large(n=n)
-    o = oracle.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"])
+    c = W.config_throughput(seed=0)
+    o = oracle.Oracle(c["n"], c["d"], Ms=c["Ms"], A=c["A"], Ku=c["Ku"], alpha=0.5)
     o.set_field(c["H"], terms=c["terms"])
-    o.heff(c["m0"])  # first touch
-    evals, t0 = 0, time.perf_counter()
-    while True:
-        o.heff(c["m0"])
-        evals += 1
-        el = time.perf_counter() - t0
-        if el > seconds_budget / 2 or evals >= 8:
-            break
-    N = int(np.prod(n))
-    return {"value": N * evals / el, "unit": "cell-evals/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "FP64 oracle effective field (FFT demag + exchange), %d evaluations of the "
-                      "same material and vortex start on a 256x256x32 grid (padded 512x512x64); "
-                      "cells x evaluations per second" % evals}
+    N = int(np.prod(c["n"]))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    rates = {}
+    for threads, budget, cap in ((cores, 8.0, 10), (1, 10.0, 2)):
+        oracle.set_threads(threads)
+        o.heff(c["m0"])  # first touch
+        evals, t0 = 0, time.perf_counter()
+        while True:
+            o.heff(c["m0"])
+            evals += 1
+            el = time.perf_counter() - t0
+            if el > budget or evals >= cap:
+                break
+        rates[threads] = (N * evals / el, evals, oracle.num_threads())
+    oracle.set_threads(cores)
+    allc = rates[cores]
+    return {"value": allc[0], "unit": "cell-evals/s", "cores": allc[2], "kind": "oracle",
+            "sample": "FP64 oracle effective field (FFT demag + exchange + anisotropy + Zeeman) "
+                      "on the 256x256x16 throughput grid (padded 512x512x32), %d evaluations on "
+                      "%d threads; cells x evaluations per second" % (allc[1], allc[2]),
+            "one_core": {"value": rates[1][0], "evals": rates[1][1], "cores": 1},
+            "cpu_model": _cpu_model(), "host_threads": cores}
 
 
 def main():
@@ -363,9 +493,14 @@ def main():
                     help="skip the Oersted field evaluation")
     ap.add_argument("--layers-only", action="store_true",
                     help="only the thin-layer field evaluation (profiling its kernels alone)")
-    ap.add_argument("--serve-requests", type=int, default=64,
-                    help="requests of the serving sample (0: skip serving)")
-    ap.add_argument("--serve-max-steps", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=8,
+                    help="requests of the serving sample, a prefix of the stream (0: skip)")
+    ap.add_argument("--serve-max-steps", type=int, default=50000)
+    ap.add_argument("--serve-rate", type=float, default=0.2,
+                    help="Poisson arrival rate of the serving stream (requests/s)")
+    ap.add_argument("--c2-iters", type=int, default=1000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the C2 throughput, differentiation and copy measurements")
     ap.add_argument("--serve-budget-mib", type=int, default=1024)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (counter calibration)")
@@ -459,7 +594,7 @@ def main():
                    "rhs_evals": evals, "rejected": r32["stats"]["rejected"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(grid),
-                     "kernel": "k_mid<float,128,2,...> (z forward + spectral product + z inverse)",
+                     "kernel": "k_mid_w<float,128,2,...> (z forward + spectral product + z inverse)",
                      "bytes_per_launch": pb["mid"], "avg_us": mid_avg_s * 1e6},
         "passes_fp32": passes,
         "heff_only": {"fp32_cell_evals_per_s": N / r32["heff_s"], "fp32_ms": 1e3 * r32["heff_s"]},
@@ -469,7 +604,14 @@ def main():
         out["serving"] = serving(mm, W, args.serve_requests,
                                  dict(budget=args.serve_budget_mib << 20, max_active=16,
                                       steps_per_launch=8, tol=1e-5, rtol=1e-7,
-                                      max_steps=args.serve_max_steps))
+                                      max_steps=args.serve_max_steps, rate=args.serve_rate))
+    if not args.no_extras:
+        print("[bench] copy bandwidth", file=sys.stderr, flush=True)
+        out["copy_bandwidth"] = copy_bandwidth()
+        print("[bench] 256x256x16 throughput", file=sys.stderr, flush=True)
+        out["throughput_256x256x16"] = throughput_c2(mm, W, args.c2_iters)
+        print("[bench] differentiation case", file=sys.stderr, flush=True)
+        out["differentiation"] = differentiation(mm, W)
     if "rkf45" in res:
         rf = res["rkf45"]
         out["rkf45_fp32"] = {"value": rf["stats"]["rhs_evals"] * N / rf["wall"],

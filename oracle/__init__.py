@@ -114,6 +114,8 @@ def lib():
         L.or_max_torque.argtypes = [C.c_void_p, dp, C.c_double]
         L.or_max_torque.restype = C.c_double
         L.or_num_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         L.or_heff_vjp.argtypes = [C.c_void_p, dp, dp, C.c_uint, dp, dp]
         L.or_llg_jvp.argtypes = [C.c_void_p, dp, dp, C.c_double, dp]
         L.or_llg_vjp.argtypes = [C.c_void_p, dp, C.c_double, dp, dp, dp]
@@ -262,6 +264,11 @@ def dft1d(x, sign=-1) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following oracle calls (timing only)."""
+    lib().or_set_threads(int(n))
 
 
 class Oracle:

@@ -1675,6 +1675,18 @@ int or_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (timing harness only; n < 1 leaves the
+   OpenMP default).  No arithmetic depends on it. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Differentiation: transposed field operator, LLG vector-Jacobian product,   */
 /* classical RK4 with a time-averaged region loss and its discrete adjoint.  */

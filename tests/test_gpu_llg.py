@@ -45,21 +45,24 @@ def test_small_llg_fp64_200_steps(torch_cuda, mm, small_llg_oracle):
     assert st["accepted"] == 200
     assert st["accepted"] == st_ref["accepted"] and st["rejected"] == st_ref["rejected"]
     assert st["rhs_evals"] == st_ref["rhs_evals"]
-    # the embedded error estimate is a small difference of stage values, so
-    # field differences of ~1e-14 move the accepted step sizes by ~1e-9
-    assert abs(t - t_ref) <= 1e-4 * t_ref
-    # compare at equal physical time
-    m_o, t_o, _, _, status_o = o.dp45(c["m0"], rtol=c["rtol"], t_end=t)
-    assert status_o == 0
+    # This random-spin start amplifies rounding: in the oracle alone, a 1e-16
+    # relative perturbation of m0 changes m after 200 steps by ~7e-6 and t by
+    # ~2e-6 (5e-13 after 100 steps, 2e-9 after 150).  After 200 steps the
+    # bar is therefore the one for m after 200 steps; on the same path after
+    # 100 steps (before the growth) state and time agree to rounding level.
     mm_ = to_np(m)
-    # Two Dormand-Prince runs whose accepted step sizes differ by ~1e-9 (see
-    # above) agree at equal time to their truncation error, which rtol bounds
-    # per step; observed ~1e-8 here, the bar is rtol itself.
-    assert np.abs(mm_ - m_o).max() <= c["rtol"], np.abs(mm_ - m_o).max()
     assert np.abs(mm_ - m_ref).max() <= 1e-4
-    E = plan.energy(m, c["H"], c["terms"])
-    Er = o.energy(m_o)
-    assert np.allclose(E, Er, rtol=1e-7, atol=1e-30)
+    assert abs(t - t_ref) <= 1e-4 * t_ref
+    m100_ref, t100_ref, _, st100, _ = o.dp45(c["m0"], rtol=c["rtol"], max_steps=100)
+    m100 = plan._v(c["m0"])
+    _, t100, _, st100g = plan.llg_step(m100, c["H"], c["terms"], rtol=c["rtol"], max_steps=100)
+    assert st100g["rejected"] == st100["rejected"]
+    assert abs(t100 - t100_ref) <= 1e-9 * t100_ref, (t100, t100_ref)
+    dm100 = np.abs(to_np(m100) - m100_ref).max()
+    assert dm100 <= 1e-9, dm100
+    E = plan.energy(m100, c["H"], c["terms"])
+    Er = o.energy(m100_ref)
+    assert np.allclose(E, Er, rtol=1e-9, atol=1e-30), (E, Er)
 
 
 def test_small_llg_fp32_equal_time(torch_cuda, mm, orc, small_llg_oracle):
