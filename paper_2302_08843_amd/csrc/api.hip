@@ -10,6 +10,7 @@
 #include <limits>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "engine.h"
@@ -61,6 +62,7 @@ void free_plan(Plan* p)
         release_tensor(p->shared);
         p->Khat = p->tw = nullptr;
     }
+    if (p->st64) (void)hipFree(p->st64);
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
                     p->A_cell, p->D_cell, p->Ku_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
@@ -156,6 +158,10 @@ mm_status ensure_rk(Plan* p)
         mm_status s = alloc(p, &p->rk, 10 * 3 * (size_t)p->N * elem_size(*p), "Runge-Kutta buffers");
         if (s != MM_OK) return s;
     }
+    if (p->state64 && !p->st64) {
+        mm_status s = alloc(p, (void**)&p->st64, 6 * sizeof(double) * (size_t)p->N, "double state");
+        if (s != MM_OK) return s;
+    }
     if (!p->ctl) return alloc(p, (void**)&p->ctl, sizeof(DevCtl), "step controller");
     return MM_OK;
 }
@@ -227,7 +233,9 @@ static mm_status start_step(Plan* p, const T* y, T* f0, T* f1, T* ys, const doub
 // ---------------------------------------------------------------------------
 // Device-controlled Dormand-Prince steps (used by the request server): the
 // state stays in rk vector 8, the trial state in 9, stage derivatives in 0..6
-// and the stage input in 7; the controller state is p->ctl.
+// and the stage input in 7; the controller state is p->ctl.  With a double
+// state (Plan::state64) the state and trial state live in p->st64 and vector 7
+// holds the float stage input, which between steps is the rounded state.
 // ---------------------------------------------------------------------------
 template <typename T>
 mm_status dev_prepare(Plan* p, const void* m0, const double hext[3], unsigned terms,
@@ -237,18 +245,22 @@ mm_status dev_prepare(Plan* p, const void* m0, const double hext[3], unsigned te
     if (s != MM_OK) return s;
     const bool relax = init.relax != 0;
     const double alpha = relax ? 1.0 : p->alpha;
-    T* y = rk_vec<T>(p, 8);
+    const bool d64 = std::is_same<T, float>::value && p->state64;
+    // the state the fields are evaluated at: vector 8, or with a double
+    // state its float copy in vector 7
+    T* y = rk_vec<T>(p, d64 ? 7 : 8);
     T* k0 = rk_vec<T>(p, 0);
     MM_HIP(hipMemcpyAsync(y, m0, 3 * (size_t)p->N * sizeof(T), hipMemcpyDeviceToDevice, p->stream),
            "copy m");
+    if (d64) MM_HIP(convert_f32_f64(*p, (const float*)y, p->st64, 3 * p->N), "double state");
     MM_HIP(eval_field<T>(*p, y, hext, terms, init.t, nullptr, k0, alpha, !relax,
                          relax ? p->red_out + 1 : nullptr),
            "right-hand side");
     DevCtl c = init;
     c.rhs_evals = 1;
     if (!(c.dt > 0.0)) {
-        s = start_step<T>(p, y, k0, rk_vec<T>(p, 1), rk_vec<T>(p, 7), hext, terms, c.t, alpha,
-                          !relax, rtol, atol, &c.dt, &c.rhs_evals);
+        s = start_step<T>(p, y, k0, rk_vec<T>(p, 1), rk_vec<T>(p, d64 ? 9 : 7), hext, terms, c.t,
+                          alpha, !relax, rtol, atol, &c.dt, &c.rhs_evals);
         if (s != MM_OK) return s;
     }
     c.torque = std::numeric_limits<double>::infinity();
@@ -273,6 +285,33 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
     T* y1 = rk_vec<T>(p, 9);
     double* hdev = &p->ctl->h;
     MM_HIP(dp_begin(*p, p->ctl), "controller");
+    if constexpr (std::is_same<T, float>::value) {
+        if (p->state64) {
+            // double state: stage inputs formed in double, evaluated in float
+            double* yd = p->st64;
+            double* y1d = p->st64 + 3 * p->N;
+            for (int sg = 1; sg < 7; ++sg) {
+                MM_HIP(rk_combine_d(*p, ys, sg == 6 ? y1d : nullptr, yd, kA[sg], k, sg, hdev),
+                       "stage input");
+                MM_HIP(eval_field<T>(*p, ys, hext, terms, 0.0, nullptr, k[sg], alpha, !relax,
+                                     nullptr),
+                       "right-hand side");
+            }
+            double E[7];
+            for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
+            MM_HIP(rk_error_norm_d(*p, yd, y1d, E, k, 7, rtol, atol, p->red_out, hdev),
+                   "error norm");
+            MM_HIP(dp_control(*p, p->ctl), "controller");
+            MM_HIP(dp_commit_d(*p, p->ctl, yd, y1d, ys, k[0], k[6]), "commit");
+            if (renorm) {
+                MM_HIP(eval_field<T>(*p, ys, hext, terms, 0.0, nullptr, k[0], alpha, !relax,
+                                     relax ? p->red_out + 1 : nullptr),
+                       "right-hand side");
+                if (relax) MM_HIP(dp_torque(*p, p->ctl), "torque");
+            }
+            return MM_OK;
+        }
+    }
     for (int sg = 1; sg < 7; ++sg) {
         T* target = sg == 6 ? y1 : ys;
         MM_HIP(rk_combine<T>(*p, target, y, 0.0, kA[sg], k, sg, hdev), "stage input");
@@ -297,6 +336,21 @@ template <typename T>
 T* dev_state(Plan* p)
 {
     return rk_vec<T>(p, 8);
+}
+
+hipError_t dev_result(Plan* p, void* out)
+{
+    if (p->prec == MM_FP32 && p->state64)
+        return convert_f64_f32(*p, p->st64, (float*)out, 3 * p->N);
+    const size_t vb = 3 * (size_t)p->N * elem_size(*p);
+    const void* y = p->prec == MM_FP32 ? (const void*)rk_vec<float>(p, 8)
+                                       : (const void*)rk_vec<double>(p, 8);
+    return hipMemcpyAsync(out, y, vb, hipMemcpyDeviceToDevice, p->stream);
+}
+
+size_t state64_bytes(const int grid[3])
+{
+    return 6 * sizeof(double) * (size_t)grid[0] * grid[1] * grid[2];
 }
 
 template mm_status dev_prepare<float>(Plan*, const void*, const double*, unsigned, const DevCtl&,

@@ -113,6 +113,10 @@ struct Plan {
     DevCtl *ctl = nullptr;      // device-side step controller
     SharedTensor *shared = nullptr;  // Khat and tw owned jointly with other plans
     bool ws = false;  // Khat, S1, S2, tw, red, red_out, rk, ctl carved from a caller workspace
+    // FP32 plans, device-controlled runs: Runge-Kutta state in double (6N
+    // doubles: y, then the trial state y1), stages in float
+    bool state64 = false;
+    double *st64 = nullptr;
     size_t bytes = 0;
     Profiler prof;
 };
@@ -174,6 +178,20 @@ hipError_t dp_control(Plan &p, DevCtl *c);
 // k0 = k6 (first-same-as-last)
 template <typename T>
 hipError_t dp_commit(Plan &p, DevCtl *c, T *y, const T *y1, T *k0, const T *k6);
+// Double state with FP32 stages (Plan::state64): stage inputs formed in
+// double from y and rounded to float into ys (and kept in double in y1 when
+// not null); the error norm from double y, y1; the commit in double, which
+// with renormalisation leaves the rounded state in ys (the renormalised y1 on
+// acceptance, the unchanged y on rejection); conversions.
+hipError_t rk_combine_d(Plan &p, float *ys, double *y1, const double *y, const double *a,
+                        float *const *k, int nk, const double *hdev);
+hipError_t rk_error_norm_d(Plan &p, const double *y, const double *y1, const double *e,
+                           float *const *k, int nk, double rtol, double atol, double *out_dev,
+                           const double *hdev);
+hipError_t dp_commit_d(Plan &p, DevCtl *c, double *y, const double *y1, float *ys, float *k0,
+                       const float *k6);
+hipError_t convert_f32_f64(Plan &p, const float *in, double *out, long n);
+hipError_t convert_f64_f32(Plan &p, const double *in, float *out, long n);
 // c->torque = p.red_out[1] while running
 hipError_t dp_torque(Plan &p, DevCtl *c);
 // Renormalise |m| = 1 on magnetic cells, zero m on vacuum cells.
@@ -253,6 +271,11 @@ mm_status dev_step(Plan *p, const double hext[3], unsigned terms, double rtol, d
                    bool relax, bool renorm);
 template <typename T>
 T *dev_state(Plan *p);
+// Copy the device-controlled run's state (rounded to the plan's precision)
+// into out on the plan's stream.
+hipError_t dev_result(Plan *p, void *out);
+// Extra device bytes of the double state of an FP32 plan of this grid.
+size_t state64_bytes(const int grid[3]);
 
 hipError_t debug_kernel(Plan &p, int s, double *out);
 template <typename T>

@@ -1699,6 +1699,200 @@ hipError_t add_region(Plan& p, T* lam, const unsigned char* region, double val)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Double state with single-precision stages (relaxations and served requests
+// of FP32 plans, Plan::state64): the Runge-Kutta state y and trial state y1
+// are kept in double, the stage derivatives k_j are the FP32 pipeline's
+// outputs, and each stage input is formed in double and rounded once to float
+// for the field evaluation.  An FP32 state would be rounded by ~6e-8 per
+// component every step, a perturbation as large as the tolerances the
+// relaxation criterion needs, which the exchange stencil turns into torque.
+// ---------------------------------------------------------------------------
+template <int NK>
+__global__ __launch_bounds__(kBlock) void k_rk_combine_d(float* __restrict__ ys,
+                                                         double* __restrict__ y1,
+                                                         const double* __restrict__ y, Coef7 cf,
+                                                         Ptr7<float> ks, long n3)
+{
+    const double hs = cf.h ? *cf.h : 1.0;
+    double cj[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) cj[j] = cf.c[j] * hs;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n3;
+         q += (long)gridDim.x * blockDim.x) {
+        double acc = y[q];
+#pragma unroll
+        for (int j = 0; j < NK; ++j)
+            if (cf.c[j] != 0.0) acc += cj[j] * (double)ks.p[j][q];
+        if (y1) y1[q] = acc;
+        ys[q] = (float)acc;
+    }
+}
+
+// Sum over magnetic components of (e/sc)^2, e = sum_j c_j k_j, sc = atol +
+// rtol max(|y|, |y1|), with y, y1 in double; non-finite entries of y counted.
+template <bool PERCELL>
+__global__ __launch_bounds__(kBlock) void k_err_norm_d(const double* __restrict__ y,
+                                                       const double* __restrict__ y1, Coef7 cf,
+                                                       Ptr7<float> ks, long N,
+                                                       const float* __restrict__ Ms_cell,
+                                                       double rtol, double atol, double* partials)
+{
+    const double hs = cf.h ? *cf.h : 1.0;
+    double cj[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) cj[j] = cf.c[j] * hs;
+    double acc = 0.0, bad = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < 3 * N;
+         q += (long)gridDim.x * blockDim.x) {
+        const double a = y[q], b = y1[q];
+        if (!isfinite(a)) bad += 1.0;
+        if (PERCELL && Ms_cell[q % N] == 0.0f) continue;
+        double e = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            if (cf.c[j] != 0.0) e += cj[j] * (double)ks.p[j][q];
+        const double sc = atol + rtol * fmax(fabs(a), fabs(b));
+        const double r = e / sc;
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    bad = block_sum(bad);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc;
+        partials[gridDim.x + blockIdx.x] = bad;
+    }
+}
+
+// On acceptance: y = y1 (renormalised on magnetic cells, zero on vacuum, when
+// c->renorm) with its float copy ys; without renorm k0 = k6 (first-same-as-
+// last: ys already holds the rounded y1 the last stage was evaluated at).
+// With renorm the step ends by evaluating k0 at ys, so on a rejection ys is
+// reset to the rounded, unchanged y (it held the rejected trial state).
+__global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__ y,
+                              const double* __restrict__ y1, float* __restrict__ ys,
+                              float* __restrict__ k0, const float* __restrict__ k6,
+                              const float* __restrict__ Ms_cell, long N)
+{
+    const bool commit = c->commit != 0;
+    const bool renorm = c->renorm != 0;
+    if (!commit && !renorm) return;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+         q += (long)gridDim.x * blockDim.x) {
+        if (!commit) {
+            ys[q] = (float)y[q];
+            ys[N + q] = (float)y[N + q];
+            ys[2 * N + q] = (float)y[2 * N + q];
+            continue;
+        }
+        double x = y1[q], yy = y1[N + q], z = y1[2 * N + q];
+        if (renorm) {
+            if (Ms_cell && Ms_cell[q] == 0.0f) {
+                x = yy = z = 0.0;
+            } else {
+                const double inv = 1.0 / sqrt(x * x + yy * yy + z * z);
+                x *= inv;
+                yy *= inv;
+                z *= inv;
+            }
+            ys[q] = (float)x;
+            ys[N + q] = (float)yy;
+            ys[2 * N + q] = (float)z;
+        } else {
+            k0[q] = k6[q];
+            k0[N + q] = k6[N + q];
+            k0[2 * N + q] = k6[2 * N + q];
+        }
+        y[q] = x;
+        y[N + q] = yy;
+        y[2 * N + q] = z;
+    }
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, long n)
+{
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        out[q] = (B)in[q];
+}
+
+hipError_t rk_combine_d(Plan& p, float* ys, double* y1, const double* y, const double* a,
+                        float* const* k, int nk, const double* hdev)
+{
+    Coef7 cf{};
+    Ptr7<float> ks{};
+    cf.h = hdev;
+    for (int j = 0; j < nk; ++j) {
+        cf.c[j] = a[j];
+        ks.p[j] = k[j];
+    }
+    const long n3 = 3 * p.N;
+    const int blocks = (int)std::min<long>(blocks_for(n3, kBlock), 8192);
+    return timed(p, MM_PASS_RK, [&] {
+        switch (nk) {
+#define MMX_CD(NK) \
+    case NK: k_rk_combine_d<NK><<<blocks, kBlock, 0, p.stream>>>(ys, y1, y, cf, ks, n3); break;
+            MMX_CD(1) MMX_CD(2) MMX_CD(3) MMX_CD(4) MMX_CD(5) MMX_CD(6) MMX_CD(7)
+#undef MMX_CD
+        default:
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const double* e,
+                           float* const* k, int nk, double rtol, double atol, double* out_dev,
+                           const double* hdev)
+{
+    Coef7 cf{};
+    Ptr7<float> ks{};
+    cf.h = hdev;
+    for (int j = 0; j < 7; ++j) {
+        cf.c[j] = j < nk ? e[j] : 0.0;
+        ks.p[j] = j < nk ? k[j] : k[0];
+    }
+    const float* msc = p.percell ? (const float*)p.Ms_cell : nullptr;
+    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(3 * p.N, kBlock * 16)));
+    MMX_TRY(timed(p, MM_PASS_RK, [&] {
+        if (msc)
+            k_err_norm_d<true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol, p.red);
+        else
+            k_err_norm_d<false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol,
+                                                            p.red);
+        return hipGetLastError();
+    }));
+    const double cnt = 3.0 * (double)p.n_magnetic;
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, cnt > 0 ? 1.0 / cnt : 0.0, 1);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
+    return hipGetLastError();
+}
+
+hipError_t dp_commit_d(Plan& p, DevCtl* c, double* y, const double* y1, float* ys, float* k0,
+                       const float* k6)
+{
+    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    k_dp_commit_d<<<blocks, 256, 0, p.stream>>>(c, y, y1, ys, k0, k6,
+                                                p.percell ? (const float*)p.Ms_cell : nullptr, p.N);
+    return hipGetLastError();
+}
+
+hipError_t convert_f32_f64(Plan& p, const float* in, double* out, long n)
+{
+    const int blocks = (int)std::min<long>(blocks_for(n, 256), 4096);
+    k_convert<float, double><<<blocks, 256, 0, p.stream>>>(in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t convert_f64_f32(Plan& p, const double* in, float* out, long n)
+{
+    const int blocks = (int)std::min<long>(blocks_for(n, 256), 4096);
+    k_convert<double, float><<<blocks, 256, 0, p.stream>>>(in, out, n);
+    return hipGetLastError();
+}
+
 hipError_t zero_doubles(Plan& p, double* ptr, long n)
 {
     const int blocks = (int)std::min<long>(blocks_for(n, 256), 4096);

@@ -2,7 +2,8 @@
 // batching of relaxations and time integrations of different grids on one GPU.
 //
 // Every admitted request owns a plan (spectra, Runge-Kutta vectors, device
-// step controller) and a stream slot.  Its Dormand-Prince steps are decided on
+// step controller; in FP32 the Runge-Kutta state itself in double) and a
+// stream slot.  Its Dormand-Prince steps are decided on
 // the device, so a fixed sequence of steps is captured once into a HIP graph
 // and replayed until the controller reports completion; each launch is
 // followed by an 80-byte copy of the controller state to pinned host memory
@@ -69,8 +70,6 @@ struct Idle {
     Plan* plan;
     size_t bytes;
 };
-
-size_t esize(int prec) { return prec == MM_FP32 ? 4 : 8; }
 
 }  // namespace
 
@@ -213,7 +212,8 @@ bool try_admit(Server* s)
     for (auto it = s->idle.begin(); it != s->idle.end(); ++it)
         if (it->key == key) reuse = it;
     if (reuse == s->idle.end()) {
-        size_t need = plan_footprint(head.r.grid, s->o.prec, false);
+        size_t need = plan_footprint(head.r.grid, s->o.prec, false) +
+                      (s->o.prec == MM_FP32 ? state64_bytes(head.r.grid) : 0);
         if (!s->tensors.count(key)) need += tensor_bytes(head.r, s->o.prec);
         while (s->bytes + need > s->o.hbm_budget && release_one(s, &key)) {
         }
@@ -286,7 +286,9 @@ bool try_admit(Server* s)
             s->st.tensors_built++;
         }
         if (st == MM_OK) {
-            a->plan_bytes = plan_footprint(r.grid, s->o.prec, false);
+            a->plan_bytes = plan_footprint(r.grid, s->o.prec, false) +
+                            (s->o.prec == MM_FP32 ? state64_bytes(r.grid) : 0);
+            a->plan->state64 = s->o.prec == MM_FP32;
             s->bytes += a->plan_bytes;
             s->st.plans_created++;
         }
@@ -362,10 +364,7 @@ bool progress(Server* s, Active* a)
         a->head ^= 1;
         if (a->last.done) {
             // any launch still in flight is a no-op; the copy follows it
-            const size_t vb = 3 * (size_t)a->plan->N * esize(s->o.prec);
-            void* y = s->o.prec == MM_FP32 ? (void*)dev_state<float>(a->plan)
-                                           : (void*)dev_state<double>(a->plan);
-            hipError_t e2 = hipMemcpyAsync(a->q.r.m, y, vb, hipMemcpyDeviceToDevice, stream);
+            hipError_t e2 = dev_result(a->plan, a->q.r.m);
             if (e2 == hipSuccess) e2 = hipEventRecord(s->events[3 * sl + 2], stream);
             if (e2 != hipSuccess) {
                 finish(s, a->q, hip_fail(e2, "request result"), &a->last, a->t_admit);

@@ -161,6 +161,38 @@ def test_serve_alone_and_in_mix_bit_identical(torch_cuda, mm):
     assert st["tensors_built"] == 4
 
 
+def test_serve_plan_reuse_bit_identical(torch_cuda, mm):
+    """A finished request's plan is kept idle and taken over by a later request
+    of the same grid class (cell size and material rewritten, double state and
+    controller prepared afresh): with two slots and six requests of one class
+    most plans are reused, and every result is bit-identical to a run on a
+    fresh plan."""
+    banner("serve plan reuse, 6 requests of one class, 2 slots")
+    reqs = []
+    for i in range(6):
+        r = _req(70 + i, (24, 16, 1), cell=(2.0 + 0.5 * i) * 1e-9)
+        r["tag"] = i
+        reqs.append(r)
+    alone_m, alone_c = {}, {}
+    for r in reqs:
+        srv1, c, m = _run(torch_cuda, mm, [r], max_active=1)
+        assert srv1.stats()["plans_reused"] == 0
+        alone_m.update(m)
+        alone_c.update(c)
+    srv, cs, ms = _run(torch_cuda, mm, reqs, max_active=2, steps_per_launch=4)
+    st = srv.stats()
+    print("  stats", st)
+    assert st["plans_reused"] > 0
+    assert st["plans_created"] + st["plans_reused"] == len(reqs)
+    assert st["tensors_built"] == 1
+    for r in reqs:
+        k = r["tag"]
+        assert cs[k]["status"] in (mm.MM_OK, mm.MM_ENOTCONV)
+        assert np.array_equal(alone_m[k], ms[k]), k
+        for f in ("status", "accepted", "rejected", "rhs_evals", "torque"):
+            assert alone_c[k][f] == cs[k][f], (k, f)
+
+
 def test_serve_admission_by_memory_budget(torch_cuda, mm):
     banner("serve admission under a memory budget")
     reqs = _mix(8)
