@@ -4,8 +4,8 @@ Workload (default): the 512 x 512 x 64 grid of 4 nm cells (16.7 M cells,
 padded FFT 1024 x 1024 x 128), Ms 1e6 A/m, A 1.5e-11 J/m, alpha 0.02, Ku 0,
 H 0 (demag + exchange), seeded Voronoi vortex domains.  One step is one
 accepted adaptive Dormand-Prince step in FP32 (six effective-field + LLG
-right-hand-side evaluations through the FFT passes, the stage combinations,
-the error norm in FP64 and the host controller).  `value` is effective-field
+right-hand-side evaluations through the FFT passes, whose x forward pass also
+forms each stage input, the error norm in FP64 and the host controller).  `value` is effective-field
 evaluations x cells per second over the timed steps.  Inputs are resident in
 HBM before timing starts.
 
@@ -91,18 +91,45 @@ def run_steps(mm, plan, m, cfg, steps, warmup, rtol, profile=False, method=0):
     return wall, st, prof
 
 
-def heff_only(mm, plan, m, cfg, iters):
+def heff_only(mm, plan, m, cfg, iters, profile=False):
+    """Seconds per effective-field evaluation and, with profile, the per-pass
+    HIP-event times of the same evaluations."""
     import torch
 
     out = plan.empty()
     for _ in range(3):
         plan.heff(m, cfg["H"], cfg["terms"], out=out)
     torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
     t0 = time.perf_counter()
     for _ in range(iters):
         plan.heff(m, cfg["H"], cfg["terms"], out=out)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / iters
+    wall = (time.perf_counter() - t0) / iters
+    prof = plan.profile_read() if profile else None
+    if profile:
+        plan.profile(False)
+    return wall, prof
+
+
+# Dormand-Prince stage inputs: non-zero a_sj per stage s = 2..7, so the x
+# forward pass of stage s reads that many derivative vectors beside y.
+DP45_STAGE_K = (1, 2, 3, 4, 5, 5)
+
+
+def step_bytes(grid, prec):
+    """Algorithmic bytes per launch of the kernels of a Dormand-Prince step:
+    the x forward pass with the stage input formed in its load (y, the k_j of
+    non-zero a_sj and the stage input written, averaged over the six stages)
+    and the error norm (y, y1 and the six k_j of non-zero b_j - b*_j)."""
+    pb = pass_bytes(grid, prec)
+    w = 4 if prec == "fp32" else 8
+    m = 3 * grid[0] * grid[1] * grid[2] * w
+    out = dict(pb)
+    out["x_fwd_stage"] = pb["x_fwd"] + m + m * sum(DP45_STAGE_K) / len(DP45_STAGE_K)
+    out["rk"] = 8 * m
+    return out
 
 
 def extended_stencil(mm, plan, m, cfg, iters):
@@ -545,8 +572,10 @@ def main():
         print("[bench] %s %d steps in %.3f s (%d evals)" % (prec, st["accepted"], wall,
                                                             st["rhs_evals"]),
               file=sys.stderr, flush=True)
-        th = heff_only(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters)
-        res[prec] = dict(wall=wall, stats=st, prof=prof, heff_s=th, device_bytes=plan.device_bytes())
+        th, hprof = heff_only(mm, plan, plan._t(cfg["m0"]), cfg, args.heff_iters,
+                              profile=(prec == "fp32"))
+        res[prec] = dict(wall=wall, stats=st, prof=prof, heff_s=th, heff_prof=hprof,
+                         device_bytes=plan.device_bytes())
         if prec == "fp32":
             # the paper's default pair, same steps from the same start
             m = plan._t(cfg["m0"])
@@ -569,12 +598,27 @@ def main():
     mid_ms, mid_n = prof["mid"]
     mid_avg_s = mid_ms / 1e3 / mid_n
     achieved = pb["mid"] / mid_avg_s / 1e9
+    # the passes of a plain effective-field evaluation, each against its own
+    # byte model; then the kernels of the timed steps, where the x forward
+    # pass also forms the stage input
     passes = {}
+    hprof = r32["heff_prof"]
     for k in ("x_fwd", "y_fwd", "mid", "y_inv", "x_inv_local"):
+        ms, n = hprof[k]
+        if n:
+            gbs = pb[k] / (ms / 1e3 / n) / 1e9
+            passes[k] = {"avg_us": 1e3 * ms / n, "launches": n, "model_bytes": pb[k],
+                         "GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    sb = step_bytes(grid, "fp32")
+    step_k = {}
+    for k, name in (("x_fwd", "x_fwd_stage"), ("y_fwd", "y_fwd"), ("mid", "mid"),
+                    ("y_inv", "y_inv"), ("x_inv_local", "x_inv_local"), ("rk", "rk")):
         ms, n = prof[k]
         if n:
-            passes[k] = {"avg_us": 1e3 * ms / n, "launches": n, "model_bytes": pb[k],
-                         "GBs": pb[k] / (ms / 1e3 / n) / 1e9}
+            gbs = sb[name] / (ms / 1e3 / n) / 1e9
+            step_k[name] = {"avg_us": 1e3 * ms / n, "launches": n, "model_bytes": sb[name],
+                            "GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                            "ms_per_step": ms / max(1, r32["stats"]["accepted"])}
     out = {
         "metric": METRIC,
         "value": value,
@@ -597,6 +641,7 @@ def main():
                      "kernel": "k_mid_w<float,128,2,...> (z forward + spectral product + z inverse)",
                      "bytes_per_launch": pb["mid"], "avg_us": mid_avg_s * 1e6},
         "passes_fp32": passes,
+        "step_kernels_fp32": step_k,
         "heff_only": {"fp32_cell_evals_per_s": N / r32["heff_s"], "fp32_ms": 1e3 * r32["heff_s"]},
         "serving": None,
     }

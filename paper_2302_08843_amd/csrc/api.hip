@@ -172,6 +172,24 @@ static T* rk_vec(Plan* p, int i)
     return (T*)p->rk + (size_t)i * 3 * p->N;
 }
 
+// The stage input y + h sum_{j < nk} a_j k_j written to ys (h read from hdev
+// on the device when hdev is not null), coefficients as rk_combine forms them.
+template <typename T>
+static StageIn<T> stage_in(const T* y, T* const* k, const double* a, int nk, double h,
+                           const double* hdev, T* ys)
+{
+    StageIn<T> sc;
+    sc.y = y;
+    sc.ys = ys;
+    sc.nk = nk;
+    sc.h = hdev;
+    for (int j = 0; j < nk; ++j) {
+        sc.k[j] = k[j];
+        sc.c[j] = hdev ? a[j] : h * a[j];
+    }
+    return sc;
+}
+
 static mm_status fetch(Plan* p, int n)
 {
     MM_HIP(hipMemcpyAsync(p->host_out, p->red_out, sizeof(double) * n, hipMemcpyDeviceToHost,
@@ -313,9 +331,8 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
         }
     }
     for (int sg = 1; sg < 7; ++sg) {
-        T* target = sg == 6 ? y1 : ys;
-        MM_HIP(rk_combine<T>(*p, target, y, 0.0, kA[sg], k, sg, hdev), "stage input");
-        MM_HIP(eval_field<T>(*p, target, hext, terms, 0.0, nullptr, k[sg], alpha, !relax, nullptr),
+        const StageIn<T> sc = stage_in<T>(y, k, kA[sg], sg, 0.0, hdev, sg == 6 ? y1 : ys);
+        MM_HIP(eval_field_stage<T>(*p, sc, hext, terms, 0.0, k[sg], alpha, !relax, nullptr),
                "right-hand side");
     }
     double E[7];
@@ -414,9 +431,9 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
         if (*t + h > t_end) h = t_end - *t;
         for (int sg = 1; sg < S; ++sg) {
             T* target = (TB.fsal && sg == S - 1) ? y1 : ys;
-            MM_HIP(rk_combine<T>(*p, target, y, h, TB.a[sg], k, sg), "stage input");
-            MM_HIP(eval_field<T>(*p, target, hext, terms, *t + TB.c[sg] * h, nullptr, k[sg], alpha,
-                                 precess, nullptr),
+            const StageIn<T> sc = stage_in<T>(y, k, TB.a[sg], sg, h, nullptr, target);
+            MM_HIP(eval_field_stage<T>(*p, sc, hext, terms, *t + TB.c[sg] * h, k[sg], alpha,
+                                       precess, nullptr),
                    "right-hand side");
             loc.rhs_evals++;
         }

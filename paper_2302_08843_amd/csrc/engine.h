@@ -144,6 +144,26 @@ template <typename T>
 hipError_t eval_field(Plan &p, const T *m, const double hext[3], unsigned terms, double t,
                       T *h_out, T *dm_out, double alpha_eff, bool precess, double *torque);
 
+// A Runge-Kutta stage input ys = y + sum_{j < nk} c_j k_j (c_j multiplied by
+// *h when h is not null), formed by the x forward pass as it loads its rows.
+template <typename T>
+struct StageIn {
+    const T *y = nullptr;
+    const T *k[7] = {};
+    double c[7] = {};
+    const double *h = nullptr;
+    T *ys = nullptr;
+    int nk = 0;
+};
+// Right-hand side at a stage input: ys (3N, 16-byte aligned like y and the
+// k_j) is written by the x forward pass, which forms it on the fly, and the
+// local pass reads it; without the demag term, or on grids whose x extent
+// is 1, the combination runs as a kernel of its own first.  The arithmetic
+// of ys is that of rk_combine.
+template <typename T>
+hipError_t eval_field_stage(Plan &p, const StageIn<T> &sc, const double hext[3], unsigned terms,
+                            double t, T *dm_out, double alpha_eff, bool precess, double *torque);
+
 // y_out = y + h * sum_j a[j] k[j]  (nk <= 7).  hdev: if not null, h is read
 // from this device double instead (device-side step control).
 template <typename T>

@@ -1146,7 +1146,7 @@ static hipError_t launch_zdense(Plan& p, cx<T>* S)
 // K src with use_ms = false), i.e. every pass but the last inverse x
 // transform, which the caller fuses with its local terms.
 template <typename T>
-static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
+static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms, const StageIn<T>* sc = nullptr)
 {
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
     const int Py = p.P[1], Pz = p.P[2];
@@ -1158,9 +1158,9 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms)
     const T ms = use_ms ? (T)p.Ms : (T)1;
     MMX_TRY(timed(p, MM_PASS_X_FWD, [&] {
         return pc ? launch_x_r2c<T, true>(p, M, m, nx, p.N, nx, (const T*)p.Ms_cell, ms, S1, p.Hxp,
-                                          s1c, ny * nz, 3)
+                                          s1c, ny * nz, 3, sc)
                   : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, ms, S1, p.Hxp, s1c,
-                                           ny * nz, 3);
+                                           ny * nz, 3, sc);
     }));
     if (p.layered) {
         const long s2c = (long)nz * Py * p.Hxp;
@@ -1345,18 +1345,18 @@ hipError_t oersted_field(Plan& p, const T* j, T* h_out)
     return launch_local<T, false, 0>(r, p.P[0] / 2, j, h_out, nullptr, P, nullptr);
 }
 
+// sc: the x forward pass forms the stage input sc (m == sc->ys) from its
+// parts instead of reading m.
 template <typename T>
-hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
-                      T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
+static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], unsigned terms,
+                                  double t, T* h_out, T* dm_out, double alpha_eff, bool precess,
+                                  double* torque, const StageIn<T>* sc)
 {
     const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    const int Px = p.P[0], Py = p.P[1], Pz = p.P[2];
-    const int M = Px / 2;
+    const int M = p.P[0] / 2;
     const long s1c = (long)nz * ny * p.Hxp;
-    cx<T>* S1 = (cx<T>*)p.S1;
-    cx<T>* S2 = (cx<T>*)p.S2;
     const bool pc = p.percell;
-    if (terms & MM_DEMAG) MMX_TRY(demag_to_S1<T>(p, m, true));
+    if (terms & MM_DEMAG) MMX_TRY(demag_to_S1<T>(p, sc ? sc->y : m, true, sc));
     LocalParams P;
     P.nx = nx;
     P.ny = ny;
@@ -1416,6 +1416,29 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
                       : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque);
         return launch_local_ext<T>(p, M, m, h_out, dm_out, P, torque, pc, ext);
     });
+}
+
+template <typename T>
+hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
+                      T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
+{
+    return eval_field_core<T>(p, m, hext, terms, t, h_out, dm_out, alpha_eff, precess, torque,
+                              nullptr);
+}
+
+template <typename T>
+hipError_t eval_field_stage(Plan& p, const StageIn<T>& sc, const double hext[3], unsigned terms,
+                            double t, T* dm_out, double alpha_eff, bool precess, double* torque)
+{
+    if (sc.nk < 1 || sc.nk > 7 || !sc.y || !sc.ys) return hipErrorInvalidValue;
+    if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2) {
+        MMX_TRY(rk_combine<T>(p, sc.ys, sc.y, 1.0, sc.c, const_cast<T* const*>(sc.k), sc.nk,
+                              sc.h));
+        return eval_field_core<T>(p, sc.ys, hext, terms, t, nullptr, dm_out, alpha_eff, precess,
+                                  torque, nullptr);
+    }
+    return eval_field_core<T>(p, sc.ys, hext, terms, t, nullptr, dm_out, alpha_eff, precess,
+                              torque, &sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1913,6 +1936,8 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t init_twiddles<T>(Plan&);                                                 \
     template hipError_t eval_field<T>(Plan&, const T*, const double*, unsigned, double, T*, T*, \
                                       double, bool, double*);                                    \
+    template hipError_t eval_field_stage<T>(Plan&, const StageIn<T>&, const double*, unsigned,   \
+                                            double, T*, double, bool, double*);                  \
     template hipError_t rk_combine<T>(Plan&, T*, const T*, double, const double*, T* const*,     \
                                       int, const double*);                                       \
     template hipError_t rk_error_norm<T>(Plan&, const T*, const T*, double, const double*,       \

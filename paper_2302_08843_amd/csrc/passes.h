@@ -172,6 +172,20 @@ __global__ void k_twiddles(cx<T>* tw, int Lmax)
 //   X[k] = (Z[k] + conj Z[M-k])/2 - i w^k (Z[k] - conj Z[M-k])/2,
 //   w = exp(-2 pi i/(2M)).
 // ---------------------------------------------------------------------------
+// One element of a stage input (StageIn), stored to sc.ys and returned.
+template <typename T>
+__device__ __forceinline__ T stage_elem(const StageIn<T>& sc, const T (&cj)[7], long o)
+{
+    T acc = sc.y[o];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        if (sc.c[j] == 0.0) continue;
+        acc += cj[j] * sc.k[j][o];
+    }
+    sc.ys[o] = acc;
+    return acc;
+}
+
 template <typename T, int M>
 struct XR2C {
     using S = FFTShape<M, Regs<T>::x>;
@@ -179,11 +193,14 @@ struct XR2C {
     static constexpr int kRows = cmax(1, MMX_XBLOCK / kT);
 };
 
-template <typename T, int M, bool PERCELL, bool HALF>
+// COMB: the rows are those of a Runge-Kutta stage input y + sum_j c_j k_j
+// (StageIn; `in` is y), formed here in the order and precision of the
+// combination kernel and stored to sc.ys before the Ms scaling.
+template <typename T, int M, bool PERCELL, bool HALF, bool COMB>
 __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR void k_x_r2c(
     const T* __restrict__ in, long in_row, long in_comp, int n_in, const T* __restrict__ Ms_cell,
     T Ms, cx<T>* __restrict__ out, long out_row, long out_comp, int nrows, int ncomp,
-    const cx<T>* __restrict__ tw, int Lmax, bool vec)
+    const cx<T>* __restrict__ tw, int Lmax, bool vec, StageIn<T> sc)
 {
     using G = XR2C<T, M>;
     constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows;
@@ -193,8 +210,15 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
     const long row = (long)blockIdx.x * kRows + rl;
     const bool valid = row < (long)nrows * ncomp;
     const long c = valid ? row / nrows : 0, r = valid ? row % nrows : 0;
-    const T* src = in + c * in_comp + r * in_row;
+    const long base = c * in_comp + r * in_row;
+    const T* src = in + base;
     const T* msrc = PERCELL ? Ms_cell + r * in_row : nullptr;
+    T cj[7];
+    if constexpr (COMB) {
+        const double hs = sc.h ? *sc.h : 1.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) cj[j] = (T)(sc.c[j] * hs);
+    }
     cx<T> v[kE];
     if (MMX_XVEC && vec) {
         // n_in even and every row start aligned to two reals: one paired load
@@ -205,6 +229,17 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
             cx<T> ab = {0, 0};
             if (!(HALF && q >= kE / 2) && valid && 2 * n < n_in) {
                 ab = *reinterpret_cast<const cx<T>*>(src + 2 * n);
+                if constexpr (COMB) {
+                    const long o = base + 2 * n;
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        if (sc.c[j] == 0.0) continue;
+                        const cx<T> kv = *reinterpret_cast<const cx<T>*>(sc.k[j] + o);
+                        ab.x += cj[j] * kv.x;
+                        ab.y += cj[j] * kv.y;
+                    }
+                    *reinterpret_cast<cx<T>*>(sc.ys + o) = ab;
+                }
                 if (PERCELL) {
                     const cx<T> mm = *reinterpret_cast<const cx<T>*>(msrc + 2 * n);
                     ab = {ab.x * mm.x, ab.y * mm.y};
@@ -222,8 +257,13 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
             T a = 0, b = 0;
             // HALF: n_in <= M, so inputs q >= kE/2 (n >= M/2) are zero padding
             if (!(HALF && q >= kE / 2)) {
-                if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
-                if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+                if constexpr (COMB) {
+                    if (valid && i0 < n_in) a = stage_elem(sc, cj, base + i0) * (PERCELL ? msrc[i0] : Ms);
+                    if (valid && i1 < n_in) b = stage_elem(sc, cj, base + i1) * (PERCELL ? msrc[i1] : Ms);
+                } else {
+                    if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
+                    if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
+                }
             }
             v[q] = {a, b};
         }
@@ -1349,18 +1389,20 @@ hipError_t launch_strided(const Plan& p, int L, const cx<T>* in, cx<T>* out, int
 template <typename T, int M, bool PC>
 static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long in_comp, int n_in,
                                  const T* Ms_cell, T Ms, cx<T>* out, long out_row, long out_comp,
-                                 int nrows, int ncomp);
+                                 int nrows, int ncomp, const StageIn<T>* sc);
 
 template <typename T, bool PC>
 hipError_t launch_x_r2c(const Plan& p, int M, const T* in, long in_row, long in_comp,
                                int n_in, const T* Ms_cell, T Ms, cx<T>* out, long out_row,
-                               long out_comp, int nrows, int ncomp)
+                               long out_comp, int nrows, int ncomp, const StageIn<T>* sc = nullptr)
 {
+    // a stage input needs the transform kernel (M >= 2) and in == sc->y
+    if (sc && (M < 2 || in != sc->y || !sc->ys)) return hipErrorInvalidValue;
     switch (M) {
 #define MMX_X(LL)                                                                                 \
     case LL:                                                                                      \
         return launch_x_r2c_M<T, LL, PC>(p, in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, \
-                                         out_comp, nrows, ncomp);
+                                         out_comp, nrows, ncomp, sc);
         MMX_X(0) MMX_CASES(MMX_X)
 #undef MMX_X
     }
@@ -1383,7 +1425,7 @@ __global__ void k_x_copy(const T* __restrict__ in, long in_row, long in_comp, in
 template <typename T, int M, bool PC>
 static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long in_comp, int n_in,
                                  const T* Ms_cell, T Ms, cx<T>* out, long out_row, long out_comp,
-                                 int nrows, int ncomp)
+                                 int nrows, int ncomp, const StageIn<T>* sc)
 {
     const long rows = (long)nrows * ncomp;
     if constexpr (M == 0 || M == 1) {
@@ -1394,16 +1436,26 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
         using G = XR2C<T, M>;
         const long grid = (rows + G::kRows - 1) / G::kRows;
         const uintptr_t al = 2 * sizeof(T) - 1;
-        const bool vec = n_in % 2 == 0 && in_row % 2 == 0 && in_comp % 2 == 0 &&
-                         ((uintptr_t)in & al) == 0 && (!PC || ((uintptr_t)Ms_cell & al) == 0);
-        if (n_in <= M)
-            k_x_r2c<T, M, PC, true><<<grid, G::kRows * G::kT, 0, p.stream>>>(
-                in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
-                (const cx<T>*)p.tw, p.Lmax, vec);
-        else
-            k_x_r2c<T, M, PC, false><<<grid, G::kRows * G::kT, 0, p.stream>>>(
-                in, in_row, in_comp, n_in, Ms_cell, Ms, out, out_row, out_comp, nrows, ncomp,
-                (const cx<T>*)p.tw, p.Lmax, vec);
+        bool vec = n_in % 2 == 0 && in_row % 2 == 0 && in_comp % 2 == 0 &&
+                   ((uintptr_t)in & al) == 0 && (!PC || ((uintptr_t)Ms_cell & al) == 0);
+        if (sc) {
+            vec = vec && ((uintptr_t)sc->ys & al) == 0;
+            for (int j = 0; j < 7; ++j)
+                if (sc->c[j] != 0.0) vec = vec && ((uintptr_t)sc->k[j] & al) == 0;
+        }
+        const StageIn<T> none{};
+        const dim3 blk(G::kRows * G::kT);
+#define MMX_XL(HF, CB)                                                                          \
+    k_x_r2c<T, M, PC, HF, CB><<<grid, blk, 0, p.stream>>>(in, in_row, in_comp, n_in, Ms_cell, Ms, \
+                                                          out, out_row, out_comp, nrows, ncomp, \
+                                                          (const cx<T>*)p.tw, p.Lmax, vec,      \
+                                                          CB ? *sc : none)
+        if (n_in <= M) {
+            if (sc) MMX_XL(true, true); else MMX_XL(true, false);
+        } else {
+            if (sc) MMX_XL(false, true); else MMX_XL(false, false);
+        }
+#undef MMX_XL
     }
     return hipGetLastError();
 }
@@ -1563,9 +1615,11 @@ hipError_t launch_local_ext(const Plan& p, int M, const T* m, T* h, T* dm, const
                                                   int, long, long, int, int, long, long, int,   \
                                                   long, long);                                  \
     EXT_ template hipError_t launch_x_r2c<T, false>(const Plan&, int, const T*, long, long, int, \
-                                                    const T*, T, cx<T>*, long, long, int, int); \
+                                                    const T*, T, cx<T>*, long, long, int, int,  \
+                                                    const StageIn<T>*);                         \
     EXT_ template hipError_t launch_x_r2c<T, true>(const Plan&, int, const T*, long, long, int,  \
-                                                   const T*, T, cx<T>*, long, long, int, int);  \
+                                                   const T*, T, cx<T>*, long, long, int, int,   \
+                                                   const StageIn<T>*);                          \
     EXT_ template hipError_t launch_local<T, false, 0>(const Plan&, int, const T*, T*, T*,      \
                                                        const LocalParams&, double*);            \
     EXT_ template hipError_t launch_local<T, true, 0>(const Plan&, int, const T*, T*, T*,       \
