@@ -173,14 +173,15 @@ def extended_stencil(mm, plan, m, cfg, iters):
 
 def zdense_bytes(grid, prec):
     """Algorithmic HBM bytes per launch of the dense layer-coupling pass: the
-    kernel spectra 6 nz^2 (Py/2+1) Hx reals, the y-transformed spectrum
-    3 nz Py Hx complex read and written."""
+    kernel spectra of the nz (nz + 1) / 2 unordered layer pairs, 6 (Py/2+1) Hx
+    reals each, and the y-transformed spectrum 3 nz Py Hx complex read and
+    written."""
     nx, ny, nz = grid
     Px = 1 if nx == 1 else 1 << (2 * nx - 2).bit_length()
     Py = 1 if ny == 1 else 1 << (2 * ny - 2).bit_length()
     hx = Px // 2 + 1 if Px > 1 else 1
     w = 4 if prec == "fp32" else 8
-    return 6 * nz * nz * (Py // 2 + 1) * hx * w + 2 * 3 * nz * Py * hx * 2 * w
+    return 6 * nz * (nz + 1) // 2 * (Py // 2 + 1) * hx * w + 2 * 3 * nz * Py * hx * 2 * w
 
 
 def layers(mm, W, iters):

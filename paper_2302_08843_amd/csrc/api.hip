@@ -533,7 +533,8 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
     p->Hxp = (p->Hx + row_align - 1) / row_align * row_align;
     p->S1n = 3L * grid[2] * grid[1] * p->Hxp;
     p->S2n = 3L * grid[2] * p->P[1] * p->Hxp;
-    p->Kn = p->layered ? (long)grid[2] * grid[2] * (p->P[1] / 2 + 1) * p->Hxp
+    // layered: one kernel per unordered layer pair, nz (nz + 1) / 2 of them
+    p->Kn = p->layered ? (long)grid[2] * (grid[2] + 1) / 2 * (p->P[1] / 2 + 1) * p->Hxp
                        : (long)(p->P[2] / 2 + 1) * (p->P[1] / 2 + 1) * p->Hxp;
     p->Lmax = std::max(p->P[0], std::max(p->P[1], p->P[2]));
     p->prec = o.prec;

@@ -937,6 +937,22 @@ __global__ void k_fold_layer(T* __restrict__ Khat, const cx<double>* __restrict_
     Khat[q] = kx < Hx ? (T)((imag ? c.y : c.x) * scale) : (T)0;
 }
 
+// Thin layers: mean layer height, the unit of the weights w_t = c_t / c_ref
+// of the stored layer-pair kernels.
+static double layer_ref(const Plan& p) { return (p.zb.back() - p.zb.front()) / p.n[2]; }
+
+// Packed index of the unordered layer pair a <= b (row-major upper triangle).
+__host__ __device__ inline long layer_pair(int a, int b, int nz)
+{
+    return (long)a * nz - (long)a * (a - 1) / 2 + (b - a);
+}
+
+// The layer-pair kernels satisfy reciprocity, V_t N^{ts}(r) = V_s N^{st}(-r)
+// (the target average of the field of a uniform source cell, N even in r; it
+// holds term by term for the near field and for the dipole far field), so in
+// the lateral spectrum W^{ts} = w_t K^^{ts} is Hermitian in (t, s): the real
+// xx, yy, zz, xy parts are symmetric and the imaginary xz, yz parts
+// antisymmetric.  Only W^{ts} with t <= s is built and stored.
 template <typename T>
 static hipError_t build_tensor_layers(Plan& p)
 {
@@ -965,9 +981,11 @@ static hipError_t build_tensor_layers(Plan& p)
     Plan q = p;
     q.tw = tw64;
     const long hyx = (long)(Py / 2 + 1) * p.Hxp;
+    const double cref = layer_ref(p);
     for (int comp = 0; comp < 6; ++comp)
         for (int t = 0; t < nz; ++t)
-            for (int s = 0; s < nz; ++s) {
+            for (int s = t; s < nz; ++s) {
+                const double wt = (p.zb[t + 1] - p.zb[t]) / cref;
                 k_place_layer<<<blocks_for(PN, 256), 256, 0, p.stream>>>(
                     R, comp, t, s, nx, ny, nz, Px, Py, near, nI, nJ, zb, p.demag_p, p.d[0], p.d[1]);
                 MMX_TRY(hipGetLastError());
@@ -977,8 +995,8 @@ static hipError_t build_tensor_layers(Plan& p)
                     MMX_TRY((launch_strided<double, -1>(q, Py, C, C, Py, Py, p.Hxp, p.Hxp, p.Hx, 1,
                                                         0, 0, 1, 0, 0)));
                 k_fold_layer<T><<<blocks_for(hyx, 256), 256, 0, p.stream>>>(
-                    (T*)p.Khat + comp * p.Kn + ((long)t * nz + s) * hyx, C, p.Hx, p.Hxp, Py,
-                    comp >= 4 ? 1 : 0, 1.0 / (double)PN);
+                    (T*)p.Khat + comp * p.Kn + layer_pair(t, s, nz) * hyx, C, p.Hx, p.Hxp, Py,
+                    comp >= 4 ? 1 : 0, wt / (double)PN);
                 MMX_TRY(hipGetLastError());
             }
     return hipStreamSynchronize(p.stream);
@@ -1053,14 +1071,17 @@ hipError_t debug_spectrum(Plan& p, int s, double* out)
 
 // ---------------------------------------------------------------------------
 // Thin layers: dense coupling of the layers per lateral frequency,
-//   h^_t(kx, ky) = sum_s K^^{ts}(kx, ky) M^_s(kx, ky),
-// in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  K^ is
-// [6][nz][nz][Py/2+1][Hxp]: xx, yy, zz, xy real, xz, yz imaginary (stored as
-// their imaginary part); row Py - ky uses row ky with the y-odd components
-// (xy, yz) negated.  A block holds TW consecutive kx of the row pair (ky,
-// Py - ky), so every kernel row is read once for both: the spectra of all
-// layers of both rows are staged in LDS, then thread (kx, g) accumulates
-// targets t = g, g + G, ... .
+//   h^_t(kx, ky) = sum_s K^^{ts}(kx, ky) M^_s(kx, ky)
+//               = (1 / w_t) sum_s W^{ts}(kx, ky) M^_s(kx, ky),
+// in place on the y-transformed spectrum S ([3][nz][Py][Hxp]).  W is stored
+// for the layer pairs t <= s only, [6][nz (nz + 1) / 2][Py/2+1][Hxp]: xx, yy,
+// zz, xy real, xz, yz imaginary (stored as their imaginary part); a pair
+// t > s reads (s, t) with xz, yz negated.  Row Py - ky uses row ky with the
+// y-odd components (xy, yz) negated.  A block holds TW consecutive kx of the
+// row pair (ky, Py - ky), so every kernel row is read once for both: the
+// spectra of all layers of both rows are staged in LDS, then thread (kx, g)
+// accumulates targets t = g, g + G, ...; the two targets of a pair run in
+// one block, so the second read of a kernel row is a cache hit.
 // ---------------------------------------------------------------------------
 constexpr int kZdMaxLayers = 16;
 
@@ -1072,7 +1093,7 @@ struct ZdTile {
 template <typename T>
 __global__ __launch_bounds__(ZdTile<T>::kTW * kZdMaxLayers) void k_zdense(
     cx<T>* __restrict__ S, const T* __restrict__ K, int nz, int Py, int Hx, int Hxp, long s_comp,
-    long k_comp)
+    long k_comp, const double* __restrict__ lw, double cref)
 {
     constexpr int TW = ZdTile<T>::kTW;
     extern __shared__ unsigned char zd_smem[];
@@ -1094,9 +1115,13 @@ __global__ __launch_bounds__(ZdTile<T>::kTW * kZdMaxLayers) void k_zdense(
     for (int t = g; t < nz; t += G) {
         T a[6] = {0, 0, 0, 0, 0, 0}, b[6] = {0, 0, 0, 0, 0, 0};
         for (int sidx = 0; sidx < nz; ++sidx) {
-            const long kb = (((long)t * nz + sidx) * hy + ky) * Hxp + kx;
+            const bool lower = t > sidx;
+            const long kb =
+                (layer_pair(lower ? sidx : t, lower ? t : sidx, nz) * hy + ky) * Hxp + kx;
             const T kxx = K[kb], kyy = K[k_comp + kb], kzz = K[2 * k_comp + kb];
-            const T kxy = K[3 * k_comp + kb], vxz = K[4 * k_comp + kb], vyz = K[5 * k_comp + kb];
+            const T kxy = K[3 * k_comp + kb];
+            const T vxz = lower ? -K[4 * k_comp + kb] : K[4 * k_comp + kb];
+            const T vyz = lower ? -K[5 * k_comp + kb] : K[5 * k_comp + kb];
             // K^ M with the real xx, yy, zz, xy and i v for xz, yz:
             // (i v) M = (-v M.im, v M.re); row Py - ky negates xy and yz
             auto acc = [&](T* h, const cx<T>* Mrow, T sy) {
@@ -1112,6 +1137,12 @@ __global__ __launch_bounds__(ZdTile<T>::kTW * kZdMaxLayers) void k_zdense(
             };
             acc(a, st + lane, (T)1);
             if (pair) acc(b, st + per_row * TW + lane, (T)-1);
+        }
+        const T iw = (T)(cref / lw[t]);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            a[e] *= iw;
+            b[e] *= iw;
         }
         const long o = ((long)t * Py + ky) * Hxp + kx;
         S[o] = {a[0], a[1]};
@@ -1135,7 +1166,8 @@ static hipError_t launch_zdense(Plan& p, cx<T>* S)
     dim3 grid((unsigned)((p.Hx + TW - 1) / TW), (unsigned)(Py / 2 + 1));
     const size_t lds = sizeof(cx<T>) * 2 * 3 * nz * TW;
     k_zdense<T><<<grid, TW * G, lds, p.stream>>>(S, (const T*)p.Khat, nz, Py, p.Hx, p.Hxp,
-                                                 (long)nz * Py * p.Hxp, p.Kn);
+                                                 (long)nz * Py * p.Hxp, p.Kn, p.lw,
+                                                 layer_ref(p));
     return hipGetLastError();
 }
 
