@@ -372,18 +372,23 @@ mm_status mm_rk4_adjoint(mm_plan *p, const void *ckpt, const double h_ext[3], un
  * Relaxations (Sec. 3: alpha = 1, no precession, renormalised steps, until
  * max_i |m_i x h_i| / Ms_i < tol) and time integrations (Eq. llg with the
  * request's alpha up to t_end) on grids of different sizes, run concurrently
- * on one GPU.  Each admitted request gets a plan (spectra, Runge-Kutta
- * vectors and a device-side step controller) and one of max_active streams;
- * its Dormand-Prince steps are decided on the device (the same accept/reject
- * and step-size rules as mm_llg_step) and replayed from a HIP graph of
- * steps_per_launch steps, so no step waits for the host.  Requests are
- * admitted first come first served as slots and device memory (hbm_budget)
- * free up; graphs of different requests overlap on the device.  Plans of one
- * grid class (grid, precision, near-field order and cell proportions) share
- * one resident spectral kernel (the demag tensor depends on the cell shape,
- * not its size); finished plans stay resident for reuse by later requests of
- * the same grid and are released, least recently used first, when memory is
- * needed.  A request's arithmetic does not depend on what else runs, so its
+ * on one GPU.  Requests of one grid class (grid, precision, near-field order
+ * and cell proportions), kind, terms and tolerances share launches: a group
+ * of up to `batch` of them (at most 2^17 cells together, within hbm_budget;
+ * one where the x extent is 1) lives in one batch plan (spectra, Runge-Kutta
+ * vectors -- in FP32 with the state in double -- and a device-side step
+ * controller per request) on one of max_active streams, and every kernel of a
+ * step covers all its requests.  The steps are decided on the device per
+ * request (the same accept/reject and step-size rules as mm_llg_step) and
+ * replayed from one HIP graph of steps_per_launch steps per group, so no step
+ * waits for the host.  A request that finishes frees its slot for the next
+ * request of the same group, which joins the running batch; other requests
+ * start new groups first come first served as streams and device memory
+ * (hbm_budget) free up, and groups overlap on the device.  Groups of one class
+ * share one resident spectral kernel (the demag tensor depends on the cell
+ * shape, not its size); finished groups stay resident for reuse and are
+ * released, least recently used first, when memory is needed.  A request's
+ * arithmetic does not depend on what else runs or which slot it takes, so its
  * result is bit-identical alone and in a mix.  Fields must be static (no
  * drive); the material is uniform per request.  The server is not
  * thread-safe: one host thread submits and polls. */
@@ -391,12 +396,13 @@ typedef struct mm_server mm_server;
 
 typedef struct {
     size_t hbm_budget;     /* device bytes the server may hold; 0: 80 % of free memory */
-    int max_active;        /* requests on the device at once (streams), 1..64 */
+    int max_active;        /* groups on the device at once (streams), 1..64 */
     int steps_per_launch;  /* device-controlled steps per graph launch, 1..64 */
     mm_prec prec;          /* arithmetic of every request */
     int demag_p;           /* near-field order as in mm_opts */
+    int batch;             /* requests per group (shared launches), 1..64 */
 } mm_serve_opts;
-void mm_serve_opts_default(mm_serve_opts *o); /* 0, 16, 8, MM_FP32, 20 */
+void mm_serve_opts_default(mm_serve_opts *o); /* 0, 16, 8, MM_FP32, 20, 8 */
 
 enum { MM_SERVE_RELAX = 0, MM_SERVE_INTEGRATE = 1 };
 
@@ -431,7 +437,10 @@ typedef struct {
     long submitted, admitted, completed, queued, active;
     long waited_memory, waited_slot; /* requests that waited at the head of the queue */
     size_t bytes_in_use, bytes_peak, budget;
-    long tensors_built, plans_created, plans_reused, graph_launches;
+    long tensors_built;
+    long plans_created, plans_reused; /* admissions that built a group plan / used one */
+    long graph_launches;
+    long max_batch;                   /* most requests that shared one group at once */
 } mm_serve_stats;
 
 /* MM_EINVAL for options out of range; MM_ENOMEM/MM_EHIP on allocation. */

@@ -21,7 +21,7 @@ static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 
-static int padded_extent(int n)
+int padded_extent(int n)
 {
     if (n <= 1) return 1;
     int p = 1;
@@ -63,6 +63,9 @@ void free_plan(Plan* p)
         p->Khat = p->tw = nullptr;
     }
     if (p->st64) (void)hipFree(p->st64);
+    if (p->Pb) (void)hipFree(p->Pb);
+    if (p->Ms_b) (void)hipFree(p->Ms_b);
+    if (p->Pb_host) (void)hipHostFree(p->Pb_host);
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
                     p->A_cell, p->D_cell, p->Ku_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
                     p->gms, p->ctl};
@@ -154,22 +157,30 @@ static Tableau tableau(int method)
 
 mm_status ensure_rk(Plan* p)
 {
+    // a batch plan holds every request's vectors and controller
+    const size_t nb = (size_t)p->batch;
     if (!p->rk) {
-        mm_status s = alloc(p, &p->rk, 10 * 3 * (size_t)p->N * elem_size(*p), "Runge-Kutta buffers");
+        mm_status s = alloc(p, &p->rk, 10 * 3 * (size_t)p->N * nb * elem_size(*p),
+                            "Runge-Kutta buffers");
         if (s != MM_OK) return s;
     }
     if (p->state64 && !p->st64) {
-        mm_status s = alloc(p, (void**)&p->st64, 6 * sizeof(double) * (size_t)p->N, "double state");
+        mm_status s = alloc(p, (void**)&p->st64, 6 * sizeof(double) * (size_t)p->N * nb,
+                            "double state");
         if (s != MM_OK) return s;
     }
-    if (!p->ctl) return alloc(p, (void**)&p->ctl, sizeof(DevCtl), "step controller");
+    if (!p->ctl) return alloc(p, (void**)&p->ctl, sizeof(DevCtl) * nb, "step controller");
     return MM_OK;
 }
+
+// Elements between consecutive Runge-Kutta vectors (and between y and y1 of
+// the double state): 3N, or the whole batch's 3N per vector.
+static long vec_stride(const Plan* p) { return p->vstride ? p->vstride : 3 * p->N; }
 
 template <typename T>
 static T* rk_vec(Plan* p, int i)
 {
-    return (T*)p->rk + (size_t)i * 3 * p->N;
+    return (T*)p->rk + (size_t)i * vec_stride(p);
 }
 
 // The stage input y + h sum_{j < nk} a_j k_j written to ys (h read from hdev
@@ -307,7 +318,7 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
         if (p->state64) {
             // double state: stage inputs formed in double, evaluated in float
             double* yd = p->st64;
-            double* y1d = p->st64 + 3 * p->N;
+            double* y1d = p->st64 + vec_stride(p);
             for (int sg = 1; sg < 7; ++sg) {
                 MM_HIP(rk_combine_d(*p, ys, sg == 6 ? y1d : nullptr, yd, kA[sg], k, sg, hdev),
                        "stage input");
@@ -505,9 +516,13 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
 // spectral kernel and twiddles of another plan of the same grid class are
 // reused (reference counted) instead of built.
 mm_status plan_build(const int grid[3], const double cell[3], double Ms, double A, double Ku,
-                     double alpha, const mm_opts& o, SharedTensor* share, Plan** out)
+                     double alpha, const mm_opts& o, SharedTensor* share, Plan** out, int batch)
 {
     *out = nullptr;
+    if (batch < 1 || batch > 64 || (batch > 1 && (o.workspace || o.dz_layers))) {
+        set_error("a batch plan holds 1 to 64 equal-layer requests and no caller workspace");
+        return MM_EINVAL;
+    }
     const double nrm = std::sqrt(o.ku_axis[0] * o.ku_axis[0] + o.ku_axis[1] * o.ku_axis[1] +
                                  o.ku_axis[2] * o.ku_axis[2]);
     Plan* p = new Plan();
@@ -609,15 +624,29 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
         p->ctl = reinterpret_cast<DevCtl*>(w + L.ctl);
         p->bytes = L.total;
     } else {
+    // a batch plan: spectra, reductions and controllers for every request
+    const size_t nb = (size_t)batch;
+    p->batch = batch;
+    p->vstride = batch > 1 ? 3 * p->N * batch : 0;
     if (!share) MM_ALLOC(p->Khat, 6 * (size_t)p->Kn * es, "spectral kernel");
-    MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es, "spectrum S1");
+    MM_ALLOC(p->S1, (size_t)p->S1n * 2 * es * nb, "spectrum S1");
     if ((p->P[2] > 1 || p->layered) && p->P[1] > 1)
-        MM_ALLOC(p->S2, (size_t)p->S2n * 2 * es, "spectrum S2");
+        MM_ALLOC(p->S2, (size_t)p->S2n * 2 * es * nb, "spectrum S2");
     else
         p->S2 = p->S1;
     if (!share) MM_ALLOC(p->tw, (size_t)p->Lmax * 2 * es, "twiddles");
-    MM_ALLOC(p->red, sizeof(double) * kRedSlots, "reduction partials");
-    MM_ALLOC(p->red_out, sizeof(double) * 8, "reduction results");
+    MM_ALLOC(p->red, sizeof(double) * kRedSlots * nb, "reduction partials");
+    MM_ALLOC(p->red_out, sizeof(double) * 8 * nb, "reduction results");
+    if (batch > 1) {
+        MM_ALLOC(p->Pb, (batch_slot_bytes() - sizeof(double)) * nb, "per-request constants");
+        MM_ALLOC(p->Ms_b, es * nb, "per-request Ms");
+        hipError_t eh = hipHostMalloc(&p->Pb_host, batch_slot_bytes() * nb, hipHostMallocDefault);
+        if (eh != hipSuccess) {
+            p->Pb_host = nullptr;
+            free_plan(p);
+            return hip_fail(eh, "per-request constants staging");
+        }
+    }
     }
     if (p->layered) {
         MM_ALLOC(p->zw, 4 * (size_t)grid[2] * es, "layer couplings");
@@ -723,6 +752,38 @@ size_t plan_footprint(const int grid[3], int prec, bool with_tensor)
 {
     const WsLayout L = ws_layout(grid, prec);
     return with_tensor ? L.total : L.total - (L.S1 - L.Khat) - (L.red - L.tw);
+}
+
+size_t batch_footprint(const int grid[3], int prec, int batch, bool state64)
+{
+    // per request: the spectra, reductions, Runge-Kutta space and controller
+    // of a plan without kernel, the double state, its constants; rounding
+    // to 256 bytes per buffer is counted once per request (an upper bound)
+    const size_t es = prec == MM_FP32 ? 4 : 8;
+    const size_t per = plan_footprint(grid, prec, false) + (state64 ? state64_bytes(grid) : 0) +
+                       (batch > 1 ? batch_slot_bytes() + es : 0);
+    return per * (size_t)batch;
+}
+
+Plan batch_view(const Plan& g, int b)
+{
+    Plan v = g;
+    const size_t es = elem_size(g);
+    const long n3 = 3 * g.N;
+    v.batch = 1;
+    v.Pb = v.Ms_b = v.Pb_host = nullptr;
+    v.shared = nullptr;
+    v.ws = true;  // owns nothing
+    v.S1 = static_cast<char*>(g.S1) + (size_t)b * g.S1n * 2 * es;
+    v.S2 = g.S2 == g.S1 ? v.S1 : static_cast<char*>(g.S2) + (size_t)b * g.S2n * 2 * es;
+    v.red = g.red + (size_t)b * kRedSlots;
+    v.red_out = g.red_out + (size_t)b * 8;
+    v.rk = g.rk ? static_cast<char*>(g.rk) + (size_t)b * n3 * es : nullptr;
+    v.vstride = n3 * g.batch;
+    v.st64 = g.st64 ? g.st64 + (size_t)b * n3 : nullptr;
+    v.ctl = g.ctl ? g.ctl + b : nullptr;
+    v.prof = Profiler{};
+    return v;
 }
 
 }  // namespace mmx

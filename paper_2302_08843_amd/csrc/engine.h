@@ -117,6 +117,18 @@ struct Plan {
     // doubles: y, then the trial state y1), stages in float
     bool state64 = false;
     double *st64 = nullptr;
+    // A batch of requests of one grid (request server): S1, S2, the
+    // Runge-Kutta vectors and st64 hold `batch` requests each, request b
+    // after b - 1 (vector v of request b at v * vstride + b * 3N); ctl, the
+    // reduction slots (8 doubles per request in red_out) likewise.  Pb: one
+    // LocalParams per request (device), Ms_b: one Ms per request (device, in
+    // the plan's precision).  vstride: elements between Runge-Kutta vectors
+    // (0: 3N; a view of one request of a batch keeps the batch's stride).
+    int batch = 1;
+    long vstride = 0;
+    void *Pb = nullptr;
+    void *Ms_b = nullptr;
+    void *Pb_host = nullptr;  // pinned staging of Pb and Ms_b, one entry per request
     size_t bytes = 0;
     Profiler prof;
 };
@@ -269,7 +281,30 @@ void free_plan(Plan *p);
 void release_tensor(SharedTensor *t);
 mm_status ensure_rk(Plan *p);
 mm_status plan_build(const int grid[3], const double cell[3], double Ms, double A, double Ku,
-                     double alpha, const mm_opts &o, SharedTensor *share, Plan **out);
+                     double alpha, const mm_opts &o, SharedTensor *share, Plan **out,
+                     int batch = 1);
+// Device bytes of a batch plan of `batch` requests of this grid for the
+// request server (no spectral kernel), with the double state when state64.
+size_t batch_footprint(const int grid[3], int prec, int batch, bool state64);
+// Request b of a batch plan as a plan of its own (views into the batch's
+// buffers; never freed, owns nothing).
+Plan batch_view(const Plan &g, int b);
+// Slot b of a batch plan takes the constants of request view v (material,
+// cell, field h_ext, terms, alpha_eff / precession): staged in pinned memory
+// and copied on g's stream.  Uniform material and the plain stencil only.
+hipError_t batch_set_slot(Plan &g, int b, const Plan &v, const double hext[3], unsigned terms,
+                          double alpha_eff, bool precess);
+// Bytes of one request's constants in a batch plan (Pb entry + Ms entry).
+size_t batch_slot_bytes();
+// Every slot of a batch plan empty: the plan's geometry with no material
+// (zero field and right-hand side), Ms 0; on g's stream from its staging.
+hipError_t batch_init_slots(Plan &g);
+// Zero-padded FFT extent along an axis of n cells: 1 for n = 1, else the
+// smallest power of two >= 2n - 1.
+int padded_extent(int n);
+// Whether requests of this grid can share launches (the batched kernels
+// cover its transform lengths: x extent at least 2).
+bool batch_supported(const int grid[3], int prec);
 size_t plan_footprint(const int grid[3], int prec, bool with_tensor);
 // Byte offsets of a plan's persistent buffers inside one workspace, each
 // aligned to 256 bytes (equal layers): spectral kernel, spectra, twiddles,

@@ -21,6 +21,8 @@
 // product, y inverse).  The 1/(Px Py Pz) of the inverse transform is folded
 // into the resident spectral kernel.  No MFMA: FFTs and stencils are not dense
 // contractions; everything here is VALU + LDS, bounded by HBM traffic.
+#include <cstring>
+
 #include "passes.h"
 
 namespace mmx {
@@ -70,6 +72,29 @@ __global__ void k_final_sum(const double* __restrict__ partials, int n, double* 
     }
 }
 
+// Batched k_final_sum: block b sums partials[b pstride .. b pstride + n) in
+// the same order into out[b ostride + slot].
+__global__ void k_final_sum_b(const double* __restrict__ partials, int n, long pstride,
+                              double* out, long ostride, int slot, double scale, int do_sqrt)
+{
+    partials += (long)blockIdx.x * pstride;
+    out += (long)blockIdx.x * ostride;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) {
+        v *= scale;
+        out[slot] = do_sqrt ? sqrt(v) : v;
+    }
+}
+
+// p[i * stride] = v for i < n.
+__global__ void k_fill_strided(double* p, int n, long stride, double v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[(long)i * stride] = v;
+}
+
 __global__ void k_fill(double* p, int n, double v)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,11 +103,15 @@ __global__ void k_fill(double* p, int n, double v)
 
 // Coefficients of a stage combination.  h: if not null, every coefficient is
 // multiplied by *h (the step size held on the device by the device-side
-// controller); the host-driven path folds h into c and leaves h null.
+// controller); the host-driven path folds h into c and leaves h null.  In a
+// batch (blockIdx.y = request) request b's step size is h[b * hstride].
 struct Coef7 {
     double c[7];
     const double* h;
+    long hstride;
 };
+static_assert(sizeof(DevCtl) % sizeof(double) == 0, "controller records are whole doubles");
+constexpr long kCtlStride = sizeof(DevCtl) / sizeof(double);
 
 template <typename T>
 struct Ptr7 {
@@ -133,7 +162,13 @@ __global__ __launch_bounds__(kBlock) void k_rk_combine(T* __restrict__ y_out,
                                                        Ptr7<T> ks, long n3)
 {
     constexpr int W = VEC ? V16<T>::n : 1;
-    const double hs = cf.h ? *cf.h : 1.0;
+    // request blockIdx.y of a batch: its vectors follow those of the previous one
+    const long bo = (long)blockIdx.y * n3;
+    y_out += bo;
+    y += bo;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) ks.p[j] += bo;
+    const double hs = cf.h ? cf.h[blockIdx.y * cf.hstride] : 1.0;
     T cj[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) cj[j] = (T)(cf.c[j] * hs);
@@ -163,7 +198,15 @@ __global__ __launch_bounds__(kBlock) void k_err_norm(const T* __restrict__ y,
                                                      double rtol, double atol, double* partials)
 {
     constexpr int W = VEC ? V16<T>::n : 1;
-    const double hs = cf.h ? *cf.h : 1.0;
+    // request blockIdx.y of a batch (uniform material, no Ms_cell): its
+    // vectors and its 2 gridDim.x partials follow those of the previous one
+    const long bo = (long)blockIdx.y * 3 * N;
+    y += bo;
+    y1 += bo;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) ks.p[j] += bo;
+    partials += (long)blockIdx.y * 2 * gridDim.x;
+    const double hs = cf.h ? cf.h[blockIdx.y * cf.hstride] : 1.0;
     double cj[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) cj[j] = cf.c[j] * hs;
@@ -237,8 +280,11 @@ __global__ void k_renorm(T* __restrict__ m, const T* __restrict__ Ms_cell, long 
 // clipped to t_end keeps the proposal), a non-finite trial error is a
 // rejection with factor 0.2 unless the state itself is non-finite.
 // ---------------------------------------------------------------------------
-__global__ void k_dp_begin(DevCtl* c)
+__global__ void k_dp_begin(DevCtl* c, int nbatch)
 {
+    // one thread per request of a batch
+    if ((int)threadIdx.x >= nbatch) return;
+    c += threadIdx.x;
     if (c->done) return;
     if (c->relax && c->torque < c->torque_tol) {
         c->done = 1;
@@ -259,8 +305,12 @@ __global__ void k_dp_begin(DevCtl* c)
     c->h = h;
 }
 
-__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red)
+__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
 {
+    // one thread per request of a batch, its reductions rstride doubles apart
+    if ((int)threadIdx.x >= nbatch) return;
+    c += threadIdx.x;
+    red += (long)threadIdx.x * rstride;
     c->commit = 0;
     if (c->done) return;
     c->rhs_evals += 6;
@@ -295,8 +345,11 @@ __global__ void k_dp_control(DevCtl* c, const double* __restrict__ red)
     }
 }
 
-__global__ void k_dp_torque(DevCtl* c, const double* __restrict__ red)
+__global__ void k_dp_torque(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
 {
+    if ((int)threadIdx.x >= nbatch) return;
+    c += threadIdx.x;
+    red += (long)threadIdx.x * rstride;
     if (!c->done) c->torque = red[1];
 }
 
@@ -307,6 +360,13 @@ __global__ void k_dp_commit(const DevCtl* __restrict__ c, T* __restrict__ y,
                             const T* __restrict__ y1, T* __restrict__ k0,
                             const T* __restrict__ k6, const T* __restrict__ Ms_cell, long N)
 {
+    // request blockIdx.y of a batch: its controller and vectors
+    const long bo = (long)blockIdx.y * 3 * N;
+    c += blockIdx.y;
+    y += bo;
+    y1 += bo;
+    k0 += bo;
+    k6 += bo;
     if (!c->commit) return;
     const bool renorm = c->renorm != 0;
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
@@ -979,6 +1039,8 @@ static hipError_t build_tensor_layers(Plan& p)
     k_twiddles<double><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>(tw64, p.Lmax);
     MMX_TRY(hipGetLastError());
     Plan q = p;
+    q.batch = 1;  // set-up and single-request helpers never run batched
+    q.Ms_b = q.Pb = nullptr;
     q.tw = tw64;
     const long hyx = (long)(Py / 2 + 1) * p.Hxp;
     const double cref = layer_ref(p);
@@ -1023,6 +1085,8 @@ hipError_t build_tensor(Plan& p)
     // the FFT launchers read the twiddles from the plan: point them at the
     // double table while the kernel is transformed
     Plan q = p;
+    q.batch = 1;  // set-up and single-request helpers never run batched
+    q.Ms_b = q.Pb = nullptr;
     q.tw = tw64;
     for (int s = 0; s < 6; ++s) {
         k_place<<<blocks_for(PN, 256), 256, 0, p.stream>>>(R, s, p.n[0], p.n[1], p.n[2], Px, Py, Pz,
@@ -1188,13 +1252,18 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms, const StageIn<T>
     cx<T>* S2 = (cx<T>*)p.S2;
     const bool pc = p.percell && use_ms;
     const T ms = use_ms ? (T)p.Ms : (T)1;
+    // a batch of requests: 3 components each, one after the other; the
+    // x forward pass scales by each request's Ms (p.Ms_b)
+    const int nc = 3 * p.batch;
+    if (p.Pb && (pc || !use_ms || sc || !p.Ms_b || M < 2)) return hipErrorInvalidValue;
     MMX_TRY(timed(p, MM_PASS_X_FWD, [&] {
         return pc ? launch_x_r2c<T, true>(p, M, m, nx, p.N, nx, (const T*)p.Ms_cell, ms, S1, p.Hxp,
                                           s1c, ny * nz, 3, sc)
                   : launch_x_r2c<T, false>(p, M, m, nx, p.N, nx, nullptr, ms, S1, p.Hxp, s1c,
-                                           ny * nz, 3, sc);
+                                           ny * nz, nc, sc);
     }));
     if (p.layered) {
+        if (p.Pb) return hipErrorInvalidValue;
         const long s2c = (long)nz * Py * p.Hxp;
         if (Py > 1)
             MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
@@ -1211,7 +1280,7 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms, const StageIn<T>
         const long s2c = (long)nz * Py * p.Hxp;
         if (Py > 1)
             MMX_TRY(timed(p, MM_PASS_Y_FWD, [&] {
-                return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, 3, s1c, s2c,
+                return launch_strided<T, -1>(p, Py, S1, S2, ny, Py, p.Hxp, p.Hxp, p.Hx, nc, s1c, s2c,
                                              nz, (long)ny * p.Hxp, (long)Py * p.Hxp);
             }));
         MMX_TRY(timed(p, MM_PASS_MID, [&] {
@@ -1219,7 +1288,7 @@ static hipError_t demag_to_S1(Plan& p, const T* m, bool use_ms, const StageIn<T>
         }));
         if (Py > 1)
             MMX_TRY(timed(p, MM_PASS_Y_INV, [&] {
-                return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, 3, s2c, s1c,
+                return launch_strided<T, 1>(p, Py, S2, S1, Py, ny, p.Hxp, p.Hxp, p.Hx, nc, s2c, s1c,
                                             nz, (long)Py * p.Hxp, (long)ny * p.Hxp);
             }));
     } else {
@@ -1314,6 +1383,8 @@ static hipError_t oersted_setup(Plan& p)
     k_twiddles<double><<<blocks_for(p.Lmax, 256), 256, 0, p.stream>>>(tw64, p.Lmax);
     MMX_TRY(hipGetLastError());
     Plan q = p;
+    q.batch = 1;  // set-up and single-request helpers never run batched
+    q.Ms_b = q.Pb = nullptr;
     q.tw = tw64;
     for (int comp = 0; comp < 3; ++comp) {
         k_oe_place<<<blocks_for(PN, 256), 256, 0, p.stream>>>(R, comp, p.n[0], p.n[1], p.n[2], Px,
@@ -1347,6 +1418,8 @@ hipError_t oersted_field(Plan& p, const T* j, T* h_out)
     cx<T>* S2 = (cx<T>*)p.S2;
     // the demag pass chain with the Oersted product in the last-axis pass
     Plan q = p;
+    q.batch = 1;  // set-up and single-request helpers never run batched
+    q.Ms_b = q.Pb = nullptr;
     q.Khat = p.oe_G;
     MMX_TRY((launch_x_r2c<T, false>(p, p.P[0] / 2, j, nx, p.N, nx, nullptr, (T)1, S1, p.Hxp, s1c,
                                     ny * nz, 3)));
@@ -1377,24 +1450,18 @@ hipError_t oersted_field(Plan& p, const T* j, T* h_out)
     return launch_local<T, false, 0>(r, p.P[0] / 2, j, h_out, nullptr, P, nullptr);
 }
 
-// sc: the x forward pass forms the stage input sc (m == sc->ys) from its
-// parts instead of reading m.
-template <typename T>
-static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], unsigned terms,
-                                  double t, T* h_out, T* dm_out, double alpha_eff, bool precess,
-                                  double* torque, const StageIn<T>* sc)
+// The constants of the local pass for plan p at time t (field h_ext, terms,
+// alpha_eff and precession of the LLG right-hand side); *ext_out: the
+// stencil variant (EXT_* bits) the plan's material needs.
+static LocalParams make_local_params(const Plan& p, const double hext[3], unsigned terms, double t,
+                                     double alpha_eff, bool precess, int* ext_out)
 {
-    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
-    const int M = p.P[0] / 2;
-    const long s1c = (long)nz * ny * p.Hxp;
-    const bool pc = p.percell;
-    if (terms & MM_DEMAG) MMX_TRY(demag_to_S1<T>(p, sc ? sc->y : m, true, sc));
-    LocalParams P;
-    P.nx = nx;
-    P.ny = ny;
-    P.nz = nz;
+    LocalParams P{};
+    P.nx = p.n[0];
+    P.ny = p.n[1];
+    P.nz = p.n[2];
     P.N = p.N;
-    P.s1_comp = s1c;
+    P.s1_comp = (long)p.n[2] * p.n[1] * p.Hxp;
     P.Hxp = p.Hxp;
     P.with_demag = (terms & MM_DEMAG) ? 1 : 0;
     P.with_exch = (terms & MM_EXCH) && (p.A != 0.0 || p.percell_A) ? 1 : 0;
@@ -1437,8 +1504,114 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
     P.gp = kGamma / (1.0 + alpha_eff * alpha_eff);
     P.alpha = alpha_eff;
     P.precess = precess ? 1 : 0;
+    *ext_out = ext;
+    return P;
+}
+
+size_t batch_slot_bytes() { return sizeof(LocalParams) + sizeof(double); }
+
+hipError_t batch_init_slots(Plan& g)
+{
+    if (g.batch <= 1 || !g.Pb || !g.Ms_b || !g.Pb_host) return hipErrorInvalidValue;
+    // the plan's geometry, no material: an empty slot's field and right-hand
+    // side are zero
+    int ext = 0;
+    LocalParams P = make_local_params(g, nullptr, 0u, 0.0, 1.0, false, &ext);
+    P.Ms = 0.0;
+    char* stage = static_cast<char*>(g.Pb_host);
+    LocalParams* hp = reinterpret_cast<LocalParams*>(stage);
+    for (int b = 0; b < g.batch; ++b) hp[b] = P;
+    double* hm = reinterpret_cast<double*>(stage + sizeof(LocalParams) * g.batch);
+    std::memset(hm, 0, sizeof(double) * g.batch);
+    hipError_t e = hipMemcpyAsync(g.Pb, hp, sizeof(LocalParams) * g.batch, hipMemcpyHostToDevice,
+                                  g.stream);
+    if (e != hipSuccess) return e;
+    const size_t es = g.prec == MM_FP32 ? sizeof(float) : sizeof(double);
+    return hipMemcpyAsync(g.Ms_b, hm, es * g.batch, hipMemcpyHostToDevice, g.stream);
+}
+
+// Batches run the wave-local z pass and local pass only.
+template <typename T>
+static bool batch_kernels_ok(int L, int M)
+{
+    bool mid = false, loc = false;
+    switch (L) {
+#define MMX_B(LL) \
+    case LL: mid = MMX_MIDW && MidW<T, LL>::kOK; break;
+        MMX_CASES(MMX_B)
+#undef MMX_B
+    }
+    switch (M) {
+#define MMX_B(LL) \
+    case LL: loc = MMX_X1W && XC2RW<T, LL>::kOK; break;
+        MMX_CASES(MMX_B)
+#undef MMX_B
+    }
+    return mid && loc;
+}
+
+bool batch_supported(const int grid[3], int prec)
+{
+    int P[3];
+    for (int a = 0; a < 3; ++a) P[a] = padded_extent(grid[a]);
+    const int M = P[0] / 2, L = P[2] > 1 ? P[2] : P[1];
+    if (M < 2) return false;
+    return prec == MM_FP32 ? batch_kernels_ok<float>(L, M) : batch_kernels_ok<double>(L, M);
+}
+
+hipError_t batch_set_slot(Plan& g, int b, const Plan& v, const double hext[3], unsigned terms,
+                          double alpha_eff, bool precess)
+{
+    if (g.batch <= 1 || b < 0 || b >= g.batch || !g.Pb || !g.Ms_b || !g.Pb_host)
+        return hipErrorInvalidValue;
+    int ext = 0;
+    const LocalParams P = make_local_params(v, hext, terms, 0.0, alpha_eff, precess, &ext);
+    if (ext != 0 || v.percell) return hipErrorInvalidValue;
+    // staging entry b: its LocalParams, then (after all of them) its Ms
+    char* stage = static_cast<char*>(g.Pb_host);
+    LocalParams* hp = reinterpret_cast<LocalParams*>(stage) + b;
+    double* hm = reinterpret_cast<double*>(stage + sizeof(LocalParams) * g.batch) + b;
+    *hp = P;
+    size_t ms_bytes;
+    if (g.prec == MM_FP32) {
+        const float f = (float)v.Ms;
+        std::memcpy(hm, &f, sizeof f);
+        ms_bytes = sizeof f;
+    } else {
+        *hm = v.Ms;
+        ms_bytes = sizeof(double);
+    }
+    hipError_t e = hipMemcpyAsync(static_cast<LocalParams*>(g.Pb) + b, hp, sizeof(LocalParams),
+                                  hipMemcpyHostToDevice, g.stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(static_cast<char*>(g.Ms_b) + (size_t)b * ms_bytes, hm, ms_bytes,
+                          hipMemcpyHostToDevice, g.stream);
+}
+
+// sc: the x forward pass forms the stage input sc (m == sc->ys) from its
+// parts instead of reading m.
+template <typename T>
+static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], unsigned terms,
+                                  double t, T* h_out, T* dm_out, double alpha_eff, bool precess,
+                                  double* torque, const StageIn<T>* sc)
+{
+    const int M = p.P[0] / 2;
+    const bool pc = p.percell;
+    // a batch plan (p.Pb; p.batch of its requests per launch): uniform
+    // material and the plain stencil only, at most 64 requests
+    if (p.Pb && (pc || p.percell_A || p.percell_D || p.percell_Ku || p.dmi || p.layered ||
+                 p.batch > 64 || !p.Ms_b))
+        return hipErrorInvalidValue;
+    if (!p.Pb && p.batch != 1) return hipErrorInvalidValue;
+    if (terms & MM_DEMAG) MMX_TRY(demag_to_S1<T>(p, sc ? sc->y : m, true, sc));
+    int ext = 0;
+    const LocalParams P = make_local_params(p, hext, terms, t, alpha_eff, precess, &ext);
     if (torque) {
-        k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
+        // a batch keeps one maximum per request, 8 doubles apart
+        if (p.Pb)
+            k_fill_strided<<<1, 64, 0, p.stream>>>(torque, p.batch, 8, 0.0);
+        else
+            k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
         MMX_TRY(hipGetLastError());
     }
     // DMI and the coupling averages only in the variants that need them
@@ -1463,7 +1636,9 @@ hipError_t eval_field_stage(Plan& p, const StageIn<T>& sc, const double hext[3],
                             double t, T* dm_out, double alpha_eff, bool precess, double* torque)
 {
     if (sc.nk < 1 || sc.nk > 7 || !sc.y || !sc.ys) return hipErrorInvalidValue;
-    if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2) {
+    // a batch forms its stage inputs in the combination kernel (one step
+    // size per request)
+    if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2 || p.Pb) {
         MMX_TRY(rk_combine<T>(p, sc.ys, sc.y, 1.0, sc.c, const_cast<T* const*>(sc.k), sc.nk,
                               sc.h));
         return eval_field_core<T>(p, sc.ys, hext, terms, t, nullptr, dm_out, alpha_eff, precess,
@@ -1478,17 +1653,38 @@ hipError_t eval_field_stage(Plan& p, const StageIn<T>& sc, const double hext[3],
 // ---------------------------------------------------------------------------
 static bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
 
+// The error norm's final sums from its nb (sum, non-finite count) partial
+// pairs: out_dev[0] = RMS over the magnetic components, out_dev[5] = number
+// of non-finite entries of the current state; per request of a batch (its
+// partials 2 nb apart, its results 8 doubles apart).
+static hipError_t err_final_sums(Plan& p, int nb, double* out_dev)
+{
+    const double cnt = 3.0 * (double)p.n_magnetic;
+    const double sc = cnt > 0 ? 1.0 / cnt : 0.0;
+    if (p.batch > 1) {
+        k_final_sum_b<<<p.batch, kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, 0, sc, 1);
+        MMX_TRY(hipGetLastError());
+        k_final_sum_b<<<p.batch, kBlock, 0, p.stream>>>(p.red + nb, nb, 2L * nb, out_dev, 8, 5, 1.0,
+                                                        0);
+        return hipGetLastError();
+    }
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, sc, 1);
+    MMX_TRY(hipGetLastError());
+    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
+    return hipGetLastError();
+}
+
 template <typename T, int NK>
 static hipError_t launch_combine(Plan& p, T* y_out, const T* y, const Coef7& cf, const Ptr7<T>& ks,
                                  bool vec)
 {
     const long n3 = 3 * p.N;
     const long work = vec ? n3 / V16<T>::n : n3;
-    const int blocks = (int)std::min<long>(blocks_for(work, 256), 8192);
+    const dim3 grid((unsigned)std::min<long>(blocks_for(work, 256), 8192), (unsigned)p.batch);
     if (vec)
-        k_rk_combine<T, NK, true><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
+        k_rk_combine<T, NK, true><<<grid, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
     else
-        k_rk_combine<T, NK, false><<<blocks, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
+        k_rk_combine<T, NK, false><<<grid, 256, 0, p.stream>>>(y_out, y, cf, ks, n3);
     return hipGetLastError();
 }
 
@@ -1499,6 +1695,7 @@ hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, 
     Coef7 cf{};
     Ptr7<T> ks{};
     cf.h = hdev;
+    cf.hstride = hdev && p.batch > 1 ? kCtlStride : 0;
     bool vec = (p.N % V16<T>::n) == 0 && aligned16(y_out) && aligned16(y);
     for (int j = 0; j < nk; ++j) {
         cf.c[j] = hdev ? a[j] : h * a[j];
@@ -1526,6 +1723,7 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
     Coef7 cf{};
     Ptr7<T> ks{};
     cf.h = hdev;
+    cf.hstride = hdev && p.batch > 1 ? kCtlStride : 0;
     bool vec = (p.N % V16<T>::n) == 0 && aligned16(y) && aligned16(y1) &&
                (!p.percell || aligned16(p.Ms_cell));
     for (int j = 0; j < 7; ++j) {
@@ -1540,27 +1738,24 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
     // counts in [nb, 2 nb)); nb depends on the grid only
     const long nv = 3 * p.N / (vec ? V16<T>::n : 1);
     const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(nv, kBlock * 16)));
+    if (p.batch > 1 && p.percell) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb, (unsigned)p.batch);
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
         if (vec && p.percell)
-            k_err_norm<T, true, true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
-                                                                   atol, p.red);
-        else if (vec)
-            k_err_norm<T, true, false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
-                                                                    atol, p.red);
-        else if (p.percell)
-            k_err_norm<T, false, true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
-                                                                    atol, p.red);
-        else
-            k_err_norm<T, false, false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
+            k_err_norm<T, true, true><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol,
                                                                      atol, p.red);
+        else if (vec)
+            k_err_norm<T, true, false><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
+                                                                      rtol, atol, p.red);
+        else if (p.percell)
+            k_err_norm<T, false, true><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
+                                                                      rtol, atol, p.red);
+        else
+            k_err_norm<T, false, false><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc,
+                                                                       rtol, atol, p.red);
         return hipGetLastError();
     }));
-    const double cnt = 3.0 * (double)p.n_magnetic;
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, cnt > 0 ? 1.0 / cnt : 0.0, 1);
-    MMX_TRY(hipGetLastError());
-    // out_dev[5]: number of non-finite entries of the current state y
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
-    return hipGetLastError();
+    return err_final_sums(p, nb, out_dev);
 }
 
 template <typename T>
@@ -1571,30 +1766,33 @@ hipError_t renormalise(Plan& p, T* m)
     return hipGetLastError();
 }
 
+// One controller thread per request (a batch's controllers are adjacent, its
+// reduction results 8 doubles apart).
 hipError_t dp_begin(Plan& p, DevCtl* c)
 {
-    k_dp_begin<<<1, 1, 0, p.stream>>>(c);
+    k_dp_begin<<<1, p.batch, 0, p.stream>>>(c, p.batch);
     return hipGetLastError();
 }
 
 hipError_t dp_control(Plan& p, DevCtl* c)
 {
-    k_dp_control<<<1, 1, 0, p.stream>>>(c, p.red_out);
+    k_dp_control<<<1, p.batch, 0, p.stream>>>(c, p.red_out, p.batch, 8);
     return hipGetLastError();
 }
 
 hipError_t dp_torque(Plan& p, DevCtl* c)
 {
-    k_dp_torque<<<1, 1, 0, p.stream>>>(c, p.red_out);
+    k_dp_torque<<<1, p.batch, 0, p.stream>>>(c, p.red_out, p.batch, 8);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t dp_commit(Plan& p, DevCtl* c, T* y, const T* y1, T* k0, const T* k6)
 {
-    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
-    k_dp_commit<T><<<blocks, 256, 0, p.stream>>>(c, y, y1, k0, k6,
-                                                 p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
+    if (p.batch > 1 && p.percell) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)std::min<long>(blocks_for(p.N, 256), 4096), (unsigned)p.batch);
+    k_dp_commit<T><<<grid, 256, 0, p.stream>>>(c, y, y1, k0, k6,
+                                               p.percell ? (const T*)p.Ms_cell : nullptr, p.N);
     return hipGetLastError();
 }
 
@@ -1769,7 +1967,14 @@ __global__ __launch_bounds__(kBlock) void k_rk_combine_d(float* __restrict__ ys,
                                                          const double* __restrict__ y, Coef7 cf,
                                                          Ptr7<float> ks, long n3)
 {
-    const double hs = cf.h ? *cf.h : 1.0;
+    // request blockIdx.y of a batch
+    const long bo = (long)blockIdx.y * n3;
+    ys += bo;
+    if (y1) y1 += bo;
+    y += bo;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) ks.p[j] += bo;
+    const double hs = cf.h ? cf.h[blockIdx.y * cf.hstride] : 1.0;
     double cj[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) cj[j] = cf.c[j] * hs;
@@ -1793,7 +1998,14 @@ __global__ __launch_bounds__(kBlock) void k_err_norm_d(const double* __restrict_
                                                        const float* __restrict__ Ms_cell,
                                                        double rtol, double atol, double* partials)
 {
-    const double hs = cf.h ? *cf.h : 1.0;
+    // request blockIdx.y of a batch (uniform material)
+    const long bo = (long)blockIdx.y * 3 * N;
+    y += bo;
+    y1 += bo;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) ks.p[j] += bo;
+    partials += (long)blockIdx.y * 2 * gridDim.x;
+    const double hs = cf.h ? cf.h[blockIdx.y * cf.hstride] : 1.0;
     double cj[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) cj[j] = cf.c[j] * hs;
@@ -1829,6 +2041,14 @@ __global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__
                               float* __restrict__ k0, const float* __restrict__ k6,
                               const float* __restrict__ Ms_cell, long N)
 {
+    // request blockIdx.y of a batch
+    const long bo = (long)blockIdx.y * 3 * N;
+    c += blockIdx.y;
+    y += bo;
+    y1 += bo;
+    ys += bo;
+    k0 += bo;
+    k6 += bo;
     const bool commit = c->commit != 0;
     const bool renorm = c->renorm != 0;
     if (!commit && !renorm) return;
@@ -1878,12 +2098,13 @@ hipError_t rk_combine_d(Plan& p, float* ys, double* y1, const double* y, const d
     Coef7 cf{};
     Ptr7<float> ks{};
     cf.h = hdev;
+    cf.hstride = hdev && p.batch > 1 ? kCtlStride : 0;
     for (int j = 0; j < nk; ++j) {
         cf.c[j] = a[j];
         ks.p[j] = k[j];
     }
     const long n3 = 3 * p.N;
-    const int blocks = (int)std::min<long>(blocks_for(n3, kBlock), 8192);
+    const dim3 blocks((unsigned)std::min<long>(blocks_for(n3, kBlock), 8192), (unsigned)p.batch);
     return timed(p, MM_PASS_RK, [&] {
         switch (nk) {
 #define MMX_CD(NK) \
@@ -1904,31 +2125,32 @@ hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const dou
     Coef7 cf{};
     Ptr7<float> ks{};
     cf.h = hdev;
+    cf.hstride = hdev && p.batch > 1 ? kCtlStride : 0;
     for (int j = 0; j < 7; ++j) {
         cf.c[j] = j < nk ? e[j] : 0.0;
         ks.p[j] = j < nk ? k[j] : k[0];
     }
     const float* msc = p.percell ? (const float*)p.Ms_cell : nullptr;
+    if (p.batch > 1 && msc) return hipErrorInvalidValue;
     const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(3 * p.N, kBlock * 16)));
+    const dim3 grid((unsigned)nb, (unsigned)p.batch);
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
         if (msc)
-            k_err_norm_d<true><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol, p.red);
+            k_err_norm_d<true><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol,
+                                                              p.red);
         else
-            k_err_norm_d<false><<<nb, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol,
-                                                            p.red);
+            k_err_norm_d<false><<<grid, kBlock, 0, p.stream>>>(y, y1, cf, ks, p.N, msc, rtol, atol,
+                                                               p.red);
         return hipGetLastError();
     }));
-    const double cnt = 3.0 * (double)p.n_magnetic;
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, cnt > 0 ? 1.0 / cnt : 0.0, 1);
-    MMX_TRY(hipGetLastError());
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
-    return hipGetLastError();
+    return err_final_sums(p, nb, out_dev);
 }
 
 hipError_t dp_commit_d(Plan& p, DevCtl* c, double* y, const double* y1, float* ys, float* k0,
                        const float* k6)
 {
-    const int blocks = (int)std::min<long>(blocks_for(p.N, 256), 4096);
+    if (p.batch > 1 && p.percell) return hipErrorInvalidValue;
+    const dim3 blocks((unsigned)std::min<long>(blocks_for(p.N, 256), 4096), (unsigned)p.batch);
     k_dp_commit_d<<<blocks, 256, 0, p.stream>>>(c, y, y1, ys, k0, k6,
                                                 p.percell ? (const float*)p.Ms_cell : nullptr, p.N);
     return hipGetLastError();

@@ -195,12 +195,14 @@ struct XR2C {
 
 // COMB: the rows are those of a Runge-Kutta stage input y + sum_j c_j k_j
 // (StageIn; `in` is y), formed here in the order and precision of the
-// combination kernel and stored to sc.ys before the Ms scaling.
+// combination kernel and stored to sc.ys before the Ms scaling.  Ms_b (a
+// batch of requests, components 3b..3b+2 of request b): uniform Ms per
+// request, Ms_b[c / 3] in place of Ms.
 template <typename T, int M, bool PERCELL, bool HALF, bool COMB>
 __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR void k_x_r2c(
     const T* __restrict__ in, long in_row, long in_comp, int n_in, const T* __restrict__ Ms_cell,
     T Ms, cx<T>* __restrict__ out, long out_row, long out_comp, int nrows, int ncomp,
-    const cx<T>* __restrict__ tw, int Lmax, bool vec, StageIn<T> sc)
+    const cx<T>* __restrict__ tw, int Lmax, bool vec, StageIn<T> sc, const T* __restrict__ Ms_b)
 {
     using G = XR2C<T, M>;
     constexpr int kE = G::kE, kT = G::kT, kRows = G::kRows;
@@ -213,6 +215,7 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
     const long base = c * in_comp + r * in_row;
     const T* src = in + base;
     const T* msrc = PERCELL ? Ms_cell + r * in_row : nullptr;
+    if (!PERCELL && Ms_b) Ms = Ms_b[(int)c / 3];
     T cj[7];
     if constexpr (COMB) {
         const double hs = sc.h ? *sc.h : 1.0;
@@ -603,12 +606,14 @@ struct KLds {
 // their own (no further workgroup barrier).  AXIS = 2: the block holds the
 // column tile tb of the pair ky = gp (wavefront 0) and ky = Py - gp
 // (wavefront 1), which share the folded kernel rows.  AXIS = 1 (single
-// layer, one group): each wavefront its own column tile.
+// layer, one group): each wavefront its own column tile.  A batch of nbatch
+// requests (spectra bstride complex values apart, one kernel) takes nbatch
+// times the blocks, request-major.
 template <typename T, int L, int AXIS, bool HALF, bool O32, int PROD>
 __global__ __launch_bounds__((64 * MidW<T, L>::kW)) MMX_MIDW_ATTR void k_mid_w(
     cx<T>* S, const T* __restrict__ Khat, int n_valid, long es, long cs, long gstride, int ncols,
     int ntb, long nblocks, int Py, int Pz, long Kn, int Hxp, const cx<T>* __restrict__ tw,
-    int Lmax)
+    int Lmax, int nbatch, long bstride)
 {
     using G = MidW<T, L>;
     constexpr int kCB = G::kCB, kW = G::kW;
@@ -619,8 +624,15 @@ __global__ __launch_bounds__((64 * MidW<T, L>::kW)) MMX_MIDW_ATTR void k_mid_w(
     __shared__ T kt[NT * KT];
     __shared__ cx<T> twl[L];
     __shared__ cx<T> lds[kW][G::S::kStages > 1 ? kCB * G::S::kLds : 1];
-    const long lb = xcd_logical();
-    if (lb >= nblocks) return;  // uniform over the block
+    long lb = xcd_logical();
+    if (nbatch > 1) {
+        if (lb >= nblocks * nbatch) return;
+        const long bi = lb / nblocks;
+        lb -= bi * nblocks;
+        S += bi * bstride;
+    } else if (lb >= nblocks) {
+        return;  // uniform over the block
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int tile0, g, gp = 0;
     bool active = true;
@@ -1055,13 +1067,19 @@ struct XC2RW {
     static_assert(!kOK || 3 * kRB * kT <= kNT, "transform threads exceed the block");
 };
 
-template <typename T, int M, bool PERCELL, int EXT>
+// BATCH: nbatch requests of one grid, request-major blocks; request b's
+// spectrum, state and outputs follow those of b - 1 (3 components each), its
+// material and field constants are Pb[b] and its torque maximum goes to
+// torque[b * tstride].  Every address comes from the launch's own geometry
+// (Pk: nx, ny, nz, N, s1_comp, Hxp), never from a request's entry.
+template <typename T, int M, bool PERCELL, int EXT, bool BATCH>
 __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
-    LocalParams P, double* torque, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
+    LocalParams Pk, double* torque, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
     const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
-    const T* __restrict__ h_oe, const T* __restrict__ Ku_cell)
+    const T* __restrict__ h_oe, const T* __restrict__ Ku_cell,
+    const LocalParams* __restrict__ Pb, int nbatch, long tstride)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
     constexpr bool kMIX = EXT & EXT_MIX;
@@ -1070,15 +1088,29 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     constexpr int NTW = (M + G::kNT - 1) / G::kNT;
     __shared__ cx<T> lds[3 * RB * kL];
     __shared__ cx<T> twl[M];  // the M-point transform's twiddles
-    const long lb = xcd_logical();
-    if (lb >= nblocks) return;
+    long lb = xcd_logical();
+    int bi = 0;
+    if constexpr (BATCH) {
+        if (lb >= nblocks * nbatch) return;
+        bi = (int)(lb / nblocks);
+        lb -= (long)bi * nblocks;
+        const long n3 = 3 * Pk.N;
+        S1 += (long)bi * 3 * Pk.s1_comp;
+        m += (long)bi * n3;
+        if (h_out) h_out += (long)bi * n3;
+        if (dm_out) dm_out += (long)bi * n3;
+        if (torque) torque += (long)bi * tstride;
+    } else {
+        if (lb >= nblocks) return;
+    }
+    const LocalParams& P = BATCH ? Pb[bi] : Pk;
     // z fastest: the blocks of rows (j, k-1), (j, k), (j, k+1) run together
     // on one XCD, so the z neighbours of m come from its L2
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int nx = Pk.nx, ny = Pk.ny, nz = Pk.nz;
     const int k = (int)((unsigned)lb % (unsigned)nz);
     const int j0 = (int)((unsigned)lb / (unsigned)nz) * RB;
     const int tid = threadIdx.x;
-    const unsigned N = (unsigned)P.N;
+    const unsigned N = (unsigned)Pk.N;
     const unsigned sxy = (unsigned)nx * (unsigned)ny;
 
     // ---- memory phase: spectrum rows ----
@@ -1090,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     cx<T> xa[kE], xb[kE];
     {
         const cx<T>* X =
-            S1 + (long)fc * P.s1_comp + ((long)k * ny + (frow ? j0 + frl : 0)) * P.Hxp;
+            S1 + (long)fc * Pk.s1_comp + ((long)k * ny + (frow ? j0 + frl : 0)) * Pk.Hxp;
 #pragma unroll
         for (int r = 0; r < kE; ++r) {
             const int n = t + r * kT;
@@ -1284,7 +1316,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
                     hz += g0 * (T)P.ec[0][2] + g1 * (T)P.ec[1][2] + g2 * (T)P.ec[2][2];
                 }
             }
-            if (P.with_oe) {
+            if (P.with_oe && h_oe) {
                 const T so = (T)P.oe_scale;
                 hx += so * elem<true>(h_oe, c0);
                 hy += so * elem<true>(h_oe + N, c0);
@@ -1449,7 +1481,8 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
     k_x_r2c<T, M, PC, HF, CB><<<grid, blk, 0, p.stream>>>(in, in_row, in_comp, n_in, Ms_cell, Ms, \
                                                           out, out_row, out_comp, nrows, ncomp, \
                                                           (const cx<T>*)p.tw, p.Lmax, vec,      \
-                                                          CB ? *sc : none)
+                                                          CB ? *sc : none,                      \
+                                                          PC ? nullptr : (const T*)p.Ms_b)
         if (n_in <= M) {
             if (sc) MMX_XL(true, true); else MMX_XL(true, false);
         } else {
@@ -1474,10 +1507,12 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
         const int ntile = (p.Hx + Gw::kCB - 1) / Gw::kCB;
         const int ntb = ntile;
         const long nb = AXIS == 2 ? (long)ntb * groups : (ntile + Gw::kW - 1) / Gw::kW;
+        // a batch: the requests' spectra follow each other, 3 components apart
+        const int nbatch = p.batch > 1 ? p.batch : 1;
 #define MMX_KMIDW(H, O)                                                                           \
-    k_mid_w<T, L, AXIS, H, O, PROD><<<xcd_grid(nb), 64 * Gw::kW, 0, p.stream>>>(                  \
+    k_mid_w<T, L, AXIS, H, O, PROD><<<xcd_grid(nb * nbatch), 64 * Gw::kW, 0, p.stream>>>(         \
         S, (const T*)p.Khat, n_valid, es, cs, gstride, p.Hx, ntb, nb, p.P[1], p.P[2], p.Kn,       \
-        p.Hxp, (const cx<T>*)p.tw, p.Lmax)
+        p.Hxp, (const cx<T>*)p.tw, p.Lmax, nbatch, 3 * cs)
         if (half && o32)
             MMX_KMIDW(true, true);
         else if (half)
@@ -1489,6 +1524,7 @@ static hipError_t launch_mid_L(const Plan& p, cx<T>* S, int n_valid, long es, lo
 #undef MMX_KMIDW
         return hipGetLastError();
     } else {
+    if (p.batch > 1) return hipErrorInvalidValue;  // batches need the wave-local kernel
     using Gm = Mid<T, L>;
     const int ntile = (p.Hx + Gm::kB - 1) / Gm::kB;
     const long nblocks = (long)ntile * groups;
@@ -1545,14 +1581,29 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
         using Gw = XC2RW<T, M>;
         const int njt = (p.n[1] + Gw::kRB - 1) / Gw::kRB;
         const long nblocks = (long)njt * p.n[2];
-        k_x_c2r_local_w<T, M, PC, EXT><<<xcd_grid(nblocks), Gw::kNT, 0, p.stream>>>(
+        if (p.Pb) {
+            // a batch plan: uniform material per request, constants from
+            // p.Pb, p.batch requests per launch, torque maxima 8 doubles apart
+            if constexpr (!PC && EXT == 0) {
+                if (p.layered || p.batch < 1) return hipErrorInvalidValue;
+                k_x_c2r_local_w<T, M, false, 0, true>
+                    <<<xcd_grid(nblocks * p.batch), Gw::kNT, 0, p.stream>>>(
+                        (const cx<T>*)p.S1, m, h, dm, nullptr, nullptr, P, torque, nblocks,
+                        (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        (const LocalParams*)p.Pb, p.batch, 8);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
+        k_x_c2r_local_w<T, M, PC, EXT, false><<<xcd_grid(nblocks), Gw::kNT, 0, p.stream>>>(
             (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque, nblocks,
             (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
             (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
             P.with_oe ? (const T*)p.h_oe : nullptr,
-            EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr);
+            EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr, nullptr, 1, 0);
         return hipGetLastError();
     }
+    if (p.Pb) return hipErrorInvalidValue;  // batches need the wave-local kernel
     using G = XC2R<T, M>;
     const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
     const long nblocks = (long)njt * p.n[2];

@@ -49,7 +49,7 @@ MM_NPASS = len(PASS_NAMES)
 
 class mm_serve_opts(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int), ("steps_per_launch", C.c_int),
-                ("prec", C.c_int), ("demag_p", C.c_int)]
+                ("prec", C.c_int), ("demag_p", C.c_int), ("batch", C.c_int)]
 
 
 class mm_request(C.Structure):
@@ -73,7 +73,7 @@ class mm_serve_stats(C.Structure):
                                         "waited_memory", "waited_slot")] + \
                [(n, C.c_size_t) for n in ("bytes_in_use", "bytes_peak", "budget")] + \
                [(n, C.c_long) for n in ("tensors_built", "plans_created", "plans_reused",
-                                        "graph_launches")]
+                                        "graph_launches", "max_batch")]
 
 
 class mm_opts(C.Structure):
@@ -824,13 +824,15 @@ class Server:
     device-resident start states, poll for completions.  Results are written
     into each request's state tensor in place."""
 
-    def __init__(self, budget=0, max_active=16, steps_per_launch=8, prec="fp32", demag_p=20):
+    def __init__(self, budget=0, max_active=16, steps_per_launch=8, prec="fp32", demag_p=20,
+                 batch=8):
         import torch
 
         o = mm_serve_opts_default()
         o.hbm_budget = int(budget)
         o.max_active = int(max_active)
         o.steps_per_launch = int(steps_per_launch)
+        o.batch = int(batch)
         o.prec = MM_FP32 if prec in ("fp32", MM_FP32, "f32") else MM_FP64
         o.demag_p = int(demag_p)
         self.prec = o.prec

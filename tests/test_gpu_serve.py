@@ -157,8 +157,10 @@ def test_serve_alone_and_in_mix_bit_identical(torch_cuda, mm):
         assert np.array_equal(alone_m[k], mix_m[k]), k
         for f in ("status", "accepted", "rejected", "rhs_evals", "torque"):
             assert alone_c[k][f] == mix_c[k][f], (k, f)
-    # four grid classes, five cell sizes each: one resident kernel per class
+    # four grid classes, five cell sizes each: one resident kernel per class;
+    # the requests of a class share launches
     assert st["tensors_built"] == 4
+    assert st["max_batch"] >= 2
 
 
 def test_serve_plan_reuse_bit_identical(torch_cuda, mm):
@@ -193,11 +195,54 @@ def test_serve_plan_reuse_bit_identical(torch_cuda, mm):
             assert alone_c[k][f] == cs[k][f], (k, f)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_serve_shared_launches_bit_identical(torch_cuda, mm, prec):
+    """Requests of one group run in shared launches (batch plan, request index
+    in every kernel's grid, one graph for the group), joining and leaving the
+    batch as slots free up: six requests through four slots give results
+    bit-identical to a server that runs every request on a plan of its own
+    (batch = 1, the single-request kernels)."""
+    banner("serve shared launches vs single-request plans, %s" % prec)
+    dt = torch_cuda.float32 if prec == "fp32" else torch_cuda.float64
+    reqs = []
+    for i in range(6):
+        r = _req(90 + i, (20, 12, 2), cell=(2.0 + 0.4 * i) * 1e-9)
+        r["tag"] = i
+        reqs.append(r)
+    res = {}
+    for batch in (1, 4):
+        srv = mm.Server(max_active=2, steps_per_launch=4, prec=prec, batch=batch)
+        ms = {}
+        for r in reqs:
+            m = torch_cuda.tensor(r["m0"], dtype=dt, device="cuda").contiguous()
+            ms[r["tag"]] = m
+            srv.submit(m, r["grid"], r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=r["H"], tol=1e-4,
+                       rtol=1e-7, max_steps=600, tag=r["tag"])
+        comps = _drain(srv, len(reqs))
+        st = srv.stats()
+        print("  batch %d stats %s" % (batch, st))
+        res[batch] = (comps, {k: to_np(v) for k, v in ms.items()}, st)
+    for r in reqs:
+        k = r["tag"]
+        c1, c4 = res[1][0][k], res[4][0][k]
+        assert c4["status"] in (mm.MM_OK, mm.MM_ENOTCONV)
+        assert np.array_equal(res[1][1][k], res[4][1][k]), k
+        for f in ("status", "accepted", "rejected", "rhs_evals", "torque"):
+            assert c1[f] == c4[f], (k, f)
+    # four requests shared one group's launches; the other two started a
+    # second group on the second stream; fewer graph launches in all
+    assert res[1][2]["max_batch"] == 1
+    assert res[4][2]["max_batch"] == 4
+    assert res[4][2]["plans_created"] <= 2
+    assert res[4][2]["plans_created"] + res[4][2]["plans_reused"] == len(reqs)
+    assert res[4][2]["graph_launches"] < res[1][2]["graph_launches"]
+
+
 def test_serve_admission_by_memory_budget(torch_cuda, mm):
     banner("serve admission under a memory budget")
     reqs = _mix(8)
-    # room for the four resident kernels (about 0.23 MB) and two or three
-    # plans (0.11 - 0.36 MB each) at a time
+    # room for the four resident kernels (about 0.23 MB) and a few plans
+    # (0.11 - 0.36 MB per request) at a time; groups shrink to fit
     budget = 800 * 1024
     srv, comps, _ = _run(torch_cuda, mm, reqs, max_active=8, budget=budget)
     st = srv.stats()
