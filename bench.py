@@ -266,7 +266,8 @@ def _serve_once(mm, reqs, states, arrivals, opts):
     import torch
 
     srv = mm.Server(budget=opts["budget"], max_active=opts["max_active"],
-                    steps_per_launch=opts["steps_per_launch"], prec="fp32")
+                    steps_per_launch=opts["steps_per_launch"], prec="fp32",
+                    batch=opts.get("batch", 8))
     # resident kernels and plans for every grid class before the clock starts
     seen = set()
     for r in reqs:
@@ -349,8 +350,58 @@ def serving(mm, W, nreq, opts):
         "hbm_budget_bytes": st["budget"], "hbm_peak_bytes": st["bytes_peak"],
         "waited_memory": st["waited_memory"], "waited_slot": st["waited_slot"],
         "graph_launches": st["graph_launches"], "plans_created": st["plans_created"],
-        "plans_reused": st["plans_reused"],
+        "plans_reused": st["plans_reused"], "batch": opts.get("batch", 8),
+        "max_batch": st["max_batch"],
     }
+
+
+def serving_shared_launches(mm, W, count=32, grids=((64, 64, 1), (128, 128, 2))):
+    """Shared launches on small requests: `count` relaxations of one small
+    grid class (seeded material, field and smooth start; tol 1e-5, rtol 1e-7,
+    cap 2,000 steps) submitted at once, served with groups of up to 8 requests
+    per launch and with one request per plan; makespan and request-steps
+    (accepted + rejected) per second.  The trajectories are identical."""
+    import torch
+
+    out = {}
+    for grid in grids:
+        g = W.rng(7)
+        reqs = []
+        for i in range(count):
+            d = g.standard_normal(3)
+            d /= np.linalg.norm(d)
+            reqs.append(dict(cell=float(g.uniform(2e-9, 5e-9)), Ms=float(g.uniform(4e5, 1.4e6)),
+                             A=float(g.uniform(5e-12, 2e-11)), Ku=float(g.uniform(0.0, 5e4)),
+                             H=W.mT(float(g.uniform(0.0, 50.0))) * d,
+                             m0=W.smooth_random(grid, 8.0, seed=1000 + i)))
+        row = {}
+        for batch in (8, 1):
+            states = [torch.tensor(r["m0"], dtype=torch.float32, device="cuda").contiguous()
+                      for r in reqs]
+            torch.cuda.synchronize()
+            srv = mm.Server(budget=8 << 30, max_active=16, steps_per_launch=8, prec="fp32",
+                            batch=batch)
+            t0 = srv.clock()
+            for i, r in enumerate(reqs):
+                c = r["cell"]
+                srv.submit(states[i], grid, (c, c, c), r["Ms"], r["A"], r["Ku"], h_ext=r["H"],
+                           tol=1e-5, rtol=1e-7, max_steps=2000, tag=i)
+            done = {}
+            while len(done) < count:
+                for c in srv.poll():
+                    done[c["tag"]] = c
+                time.sleep(0.0005)
+            T = max(c["t_done"] for c in done.values()) - t0
+            steps = sum(c["accepted"] + c["rejected"] for c in done.values())
+            st = srv.stats()
+            row["batch%d" % batch] = {"makespan_s": T, "request_steps_per_s": steps / T,
+                                      "graph_launches": st["graph_launches"],
+                                      "max_batch": st["max_batch"], "request_steps": steps}
+            srv.close()
+        row["speedup"] = row["batch8"]["request_steps_per_s"] / row["batch1"]["request_steps_per_s"]
+        out["%dx%dx%d" % grid] = row
+    out["requests"] = count
+    return out
 
 
 def throughput_c2(mm, W, iters):
@@ -658,6 +709,8 @@ def main():
         out["throughput_256x256x16"] = throughput_c2(mm, W, args.c2_iters)
         print("[bench] differentiation case", file=sys.stderr, flush=True)
         out["differentiation"] = differentiation(mm, W)
+        print("[bench] serving: shared launches on small requests", file=sys.stderr, flush=True)
+        out["serving_shared_launches"] = serving_shared_launches(mm, W)
     if "rkf45" in res:
         rf = res["rkf45"]
         out["rkf45_fp32"] = {"value": rf["stats"]["rhs_evals"] * N / rf["wall"],
