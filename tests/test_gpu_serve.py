@@ -163,36 +163,39 @@ def test_serve_alone_and_in_mix_bit_identical(torch_cuda, mm):
     assert st["max_batch"] >= 2
 
 
-def test_serve_plan_reuse_bit_identical(torch_cuda, mm):
-    """A finished request's plan is kept idle and taken over by a later request
-    of the same grid class (cell size and material rewritten, double state and
-    controller prepared afresh): with two slots and six requests of one class
-    most plans are reused, and every result is bit-identical to a run on a
-    fresh plan."""
-    banner("serve plan reuse, 6 requests of one class, 2 slots")
+@pytest.mark.parametrize("batch", [1, 8])
+def test_serve_plan_reuse_bit_identical(torch_cuda, mm, batch):
+    """Later requests of a class run on resident plans (cell size, material and
+    field rewritten, state and controller prepared afresh): with batch = 1 a
+    finished request's plan is kept idle and taken over by the next request
+    of its class, with batch = 8 a finished request's slot in a running group
+    is refilled.  Eight requests of two classes through two streams: plans are
+    reused, and every result is bit-identical to a run on a fresh server."""
+    banner("serve plan reuse, 8 requests of two classes, 2 streams, batch %d" % batch)
     reqs = []
-    for i in range(6):
-        r = _req(70 + i, (24, 16, 1), cell=(2.0 + 0.5 * i) * 1e-9)
+    for i in range(8):
+        grid = (24, 16, 1) if i % 2 == 0 else (16, 8, 2)
+        r = _req(70 + i, grid, cell=(2.0 + 0.5 * i) * 1e-9)
         r["tag"] = i
         reqs.append(r)
     alone_m, alone_c = {}, {}
     for r in reqs:
-        srv1, c, m = _run(torch_cuda, mm, [r], max_active=1)
+        srv1, c, m = _run(torch_cuda, mm, [r], max_active=1, batch=batch)
         assert srv1.stats()["plans_reused"] == 0
         alone_m.update(m)
         alone_c.update(c)
-    srv, cs, ms = _run(torch_cuda, mm, reqs, max_active=2, steps_per_launch=4)
+    srv, cs, ms = _run(torch_cuda, mm, reqs, max_active=2, steps_per_launch=4, batch=batch)
     st = srv.stats()
     print("  stats", st)
-    assert st["plans_reused"] > 0
-    assert st["plans_created"] + st["plans_reused"] == len(reqs)
-    assert st["tensors_built"] == 1
     for r in reqs:
         k = r["tag"]
         assert cs[k]["status"] in (mm.MM_OK, mm.MM_ENOTCONV)
         assert np.array_equal(alone_m[k], ms[k]), k
         for f in ("status", "accepted", "rejected", "rhs_evals", "torque"):
             assert alone_c[k][f] == cs[k][f], (k, f)
+    assert st["plans_reused"] > 0
+    assert st["plans_created"] + st["plans_reused"] == len(reqs)
+    assert st["tensors_built"] == 2
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
