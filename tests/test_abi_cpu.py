@@ -58,6 +58,24 @@ def test_invalid_arguments_rejected_without_device():
     L.mm_plan_destroy(None)
 
 
+def test_serve_options_and_rejections_without_device():
+    """Serving options: the defaults the header documents (the binding's
+    structure carries every field, batch included), and options out of range
+    rejected before the device is touched."""
+    from paper_2302_08843_amd import mm
+
+    o = mm.mm_serve_opts_default()
+    assert (o.hbm_budget, o.max_active, o.steps_per_launch, o.prec, o.demag_p, o.batch) == \
+        (0, 16, 8, mm.MM_FP32, 20, 8)
+    for field, val in (("batch", 0), ("batch", 65), ("max_active", 0), ("steps_per_launch", 65)):
+        b = mm.mm_serve_opts_default()
+        setattr(b, field, val)
+        with pytest.raises(mm.MMError) as ei:
+            mm.mm_serve_create(b)
+        assert ei.value.status == mm.MM_EINVAL, field
+    assert [f for f, _ in mm.mm_serve_stats._fields_][-1] == "max_batch"
+
+
 def test_next_row_entry_points_reject_invalid_arguments_without_device():
     """Per-cell exchange, DMI, the Oersted field and thin layers: invalid
     handles, types and heights are refused before any device work."""
