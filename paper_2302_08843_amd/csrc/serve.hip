@@ -339,6 +339,10 @@ int cover(const Group* g)
 
 mm_status launch(Server* s, Group* g)
 {
+    if (g->graphs.empty()) {
+        set_error("a group without captured steps was launched");
+        return MM_EINVAL;
+    }
     hipStream_t stream = s->streams[g->sl];
     const int idx = (g->head + g->inflight) & 1;
     const int need = std::max(1, cover(g));
