@@ -119,15 +119,20 @@ DP45_STAGE_K = (1, 2, 3, 4, 5, 5)
 
 
 def step_bytes(grid, prec):
-    """Algorithmic bytes per launch of the kernels of a Dormand-Prince step:
-    the x forward pass with the stage input formed in its load (y, the k_j of
-    non-zero a_sj and the stage input written, averaged over the six stages)
-    and the error norm (y, y1 and the six k_j of non-zero b_j - b*_j)."""
+    """Algorithmic bytes per launch of the kernels of a Dormand-Prince step,
+    averaged over its six stages: the x forward pass with the stage input
+    formed in its load (y, the k_j of non-zero a_sj, the stage input written;
+    the last stage also writes the partial error), the x inverse + local pass
+    (the last stage also reads the partial error and y for the error norm),
+    and the error norm as a kernel of its own where it runs (y, y1 and the
+    six k_j of non-zero b_j - b*_j)."""
     pb = pass_bytes(grid, prec)
     w = 4 if prec == "fp32" else 8
     m = 3 * grid[0] * grid[1] * grid[2] * w
+    ns = len(DP45_STAGE_K)
     out = dict(pb)
-    out["x_fwd_stage"] = pb["x_fwd"] + m + m * sum(DP45_STAGE_K) / len(DP45_STAGE_K)
+    out["x_fwd_stage"] = pb["x_fwd"] + m + m * sum(DP45_STAGE_K) / ns + m / ns
+    out["x_inv_local"] = pb["x_inv_local"] + 2 * m / ns
     out["rk"] = 8 * m
     return out
 

@@ -119,7 +119,8 @@ typedef struct {
     const double *dz_layers;
     /* Caller-owned device workspace (e.g. a torch allocation) for the plan's
      * persistent buffers -- spectral kernel, FFT spectra, twiddles, reduction
-     * buffers, the 10 Runge-Kutta vectors and the step controller -- laid out
+     * buffers, the 10 Runge-Kutta vectors, the step controller and the error
+     * norm's block partials -- laid out
      * by the library; at least mm_plan_workspace_bytes(grid, prec) bytes,
      * aligned to 256 bytes, equal layers only (MM_EINVAL otherwise).  NULL:
      * the plan allocates them itself.  The workspace must outlive the plan
@@ -140,7 +141,8 @@ void mm_opts_default(mm_opts *o);
  * live in memory the caller provides): the folded spectral kernel
  * 6 (Pz/2+1)(Py/2+1) Hx reals, the spectra 3 nz ny Hx and 3 nz Py Hx complex
  * values, the twiddles, reduction buffers, 10 Runge-Kutta vectors of 3N
- * reals and the step controller, each rounded up to 256 bytes (Hx = Px/2+1
+ * reals, the step controller and 2 ny nz doubles of error-norm partials,
+ * each rounded up to 256 bytes (Hx = Px/2+1
  * rounded up to 128 bytes of reals).  Host-only, no device access.  0 for
  * an invalid grid or precision. */
 size_t mm_plan_workspace_bytes(const int grid[3], int prec);

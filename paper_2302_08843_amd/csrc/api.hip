@@ -52,6 +52,7 @@ void free_plan(Plan* p)
         p->Khat = p->S1 = p->S2 = p->tw = p->rk = nullptr;
         p->red = p->red_out = nullptr;
         p->ctl = nullptr;
+        p->epart = nullptr;
     }
     for (auto& r : p->prof.pending) {
         (void)hipEventDestroy(r.a);
@@ -68,7 +69,7 @@ void free_plan(Plan* p)
     if (p->Pb_host) (void)hipHostFree(p->Pb_host);
     void* bufs[] = {p->Khat, p->S1, p->S2 == p->S1 ? nullptr : p->S2, p->tw, p->Ms_cell,
                     p->A_cell, p->D_cell, p->Ku_cell, p->zw, p->lw, p->oe_G, p->h_oe, p->mask, p->rk, p->red, p->red_out, p->adj, p->seg,
-                    p->gms, p->ctl};
+                    p->gms, p->ctl, p->epart};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->host_out) (void)hipHostFree(p->host_out);
@@ -171,6 +172,17 @@ mm_status ensure_rk(Plan* p)
     }
     if (!p->ctl) return alloc(p, (void**)&p->ctl, sizeof(DevCtl) * nb, "step controller");
     return MM_OK;
+}
+
+// Error-norm partials of the last stage's local pass (one pair per block, at
+// most one block per x row), for host-controlled steps (part of a caller
+// workspace, else allocated on first use).
+static bool ensure_epart(Plan* p)
+{
+    if (p->epart) return true;
+    if (p->ws || p->Pb) return false;
+    return alloc(p, (void**)&p->epart, 2 * sizeof(double) * (size_t)p->n[1] * p->n[2],
+                 "error-norm partials") == MM_OK;
 }
 
 // Elements between consecutive Runge-Kutta vectors (and between y and y1 of
@@ -428,6 +440,9 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
     bool last_rejected = false;
     double torque = std::numeric_limits<double>::infinity();
     bool torque_known = false;
+    // Dormand-Prince (first-same-as-last, 7 stages): the error norm is
+    // accumulated by the last stage's passes where the plan allows it
+    const bool fuse_err = TB.fsal && S == 7 && ensure_epart(p) && err_fusable(*p, terms);
     while (loc.accepted < max_steps && *t < t_end) {
         if (relax) {
             if (!torque_known) {
@@ -442,14 +457,33 @@ static mm_status dp45(Plan* p, void* m_user, const double hext[3], unsigned term
         if (*t + h > t_end) h = t_end - *t;
         for (int sg = 1; sg < S; ++sg) {
             T* target = (TB.fsal && sg == S - 1) ? y1 : ys;
-            const StageIn<T> sc = stage_in<T>(y, k, TB.a[sg], sg, h, nullptr, target);
-            MM_HIP(eval_field_stage<T>(*p, sc, hext, terms, *t + TB.c[sg] * h, k[sg], alpha,
-                                       precess, nullptr),
-                   "right-hand side");
+            StageIn<T> sc = stage_in<T>(y, k, TB.a[sg], sg, h, nullptr, target);
+            if (fuse_err && sg == S - 1) {
+                // the last stage's x forward pass also forms the partial error
+                // of the first six derivatives (into the free stage-input
+                // vector) and its local pass adds the seventh and reduces
+                sc.ep = ys;
+                for (int j = 0; j < sg; ++j) sc.e[j] = h * TB.e[j];
+                ErrIn<T> ei;
+                ei.y = y;
+                ei.e6 = h * TB.e[sg];
+                ei.rtol = rtol;
+                ei.atol = atol;
+                ei.out_dev = p->red_out;
+                MM_HIP(eval_field_stage<T>(*p, sc, hext, terms, *t + TB.c[sg] * h, k[sg], alpha,
+                                           precess, nullptr, &ei),
+                       "right-hand side and error norm");
+            } else {
+                MM_HIP(eval_field_stage<T>(*p, sc, hext, terms, *t + TB.c[sg] * h, k[sg], alpha,
+                                           precess, nullptr),
+                       "right-hand side");
+            }
             loc.rhs_evals++;
         }
         if (!TB.fsal) MM_HIP(rk_combine<T>(*p, y1, y, h, TB.b, k, S), "solution");
-        MM_HIP(rk_error_norm<T>(*p, y, y1, h, TB.e, k, S, rtol, atol, p->red_out), "error norm");
+        if (!fuse_err)
+            MM_HIP(rk_error_norm<T>(*p, y, y1, h, TB.e, k, S, rtol, atol, p->red_out),
+                   "error norm");
         s = fetch(p, 6);
         if (s != MM_OK) break;
         double err = p->host_out[0];
@@ -622,6 +656,7 @@ mm_status plan_build(const int grid[3], const double cell[3], double Ms, double 
         p->red_out = reinterpret_cast<double*>(w + L.red_out);
         p->rk = w + L.rk;
         p->ctl = reinterpret_cast<DevCtl*>(w + L.ctl);
+        p->epart = reinterpret_cast<double*>(w + L.epart);
         p->bytes = L.total;
     } else {
     // a batch plan: spectra, reductions and controllers for every request
@@ -741,6 +776,8 @@ WsLayout ws_layout(const int grid[3], int prec)
     off += up(10 * 3 * (size_t)N * es);
     L.ctl = off;
     off += up(sizeof(DevCtl));
+    L.epart = off;
+    off += up(2 * sizeof(double) * (size_t)grid[1] * grid[2]);
     L.total = off;
     return L;
 }

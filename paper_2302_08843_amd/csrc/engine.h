@@ -124,6 +124,7 @@ struct Plan {
     // LocalParams per request (device), Ms_b: one Ms per request (device, in
     // the plan's precision).  vstride: elements between Runge-Kutta vectors
     // (0: 3N; a view of one request of a batch keeps the batch's stride).
+    double *epart = nullptr;  // error-norm partials of the local pass, 2 ny nz doubles
     int batch = 1;
     long vstride = 0;
     void *Pb = nullptr;
@@ -166,6 +167,23 @@ struct StageIn {
     const double *h = nullptr;
     T *ys = nullptr;
     int nk = 0;
+    // optional: the partial error sum_{j < nk} e_j k_j (e_j multiplied by *h
+    // like c_j), formed in double from the same loads and stored to ep
+    T *ep = nullptr;
+    double e[7] = {};
+};
+
+// The Dormand-Prince error norm accumulated by the local pass of the last
+// stage: per component e = ep + e6 k6 (ep from the x forward pass, k6 the
+// right-hand side just computed), sc = atol + rtol max(|y|, |y1|) with y1 the
+// stage input; out_dev[0] = RMS of e / sc over magnetic components,
+// out_dev[5] = number of non-finite entries of y.
+template <typename T>
+struct ErrIn {
+    const T *y = nullptr;
+    double e6 = 0.0;
+    double rtol = 0.0, atol = 0.0;
+    double *out_dev = nullptr;
 };
 // Right-hand side at a stage input: ys (3N, 16-byte aligned like y and the
 // k_j) is written by the x forward pass, which forms it on the fly, and the
@@ -174,7 +192,12 @@ struct StageIn {
 // of ys is that of rk_combine.
 template <typename T>
 hipError_t eval_field_stage(Plan &p, const StageIn<T> &sc, const double hext[3], unsigned terms,
-                            double t, T *dm_out, double alpha_eff, bool precess, double *torque);
+                            double t, T *dm_out, double alpha_eff, bool precess, double *torque,
+                            const ErrIn<T> *err = nullptr);
+// Whether eval_field_stage can accumulate the error norm (ErrIn, sc.ep set)
+// for this plan and terms: the demag chain runs, the plain stencil, one
+// request, the wave-local local pass, the partials buffer in place.
+bool err_fusable(const Plan &p, unsigned terms);
 
 // y_out = y + h * sum_j a[j] k[j]  (nk <= 7).  hdev: if not null, h is read
 // from this device double instead (device-side step control).
@@ -310,7 +333,7 @@ size_t plan_footprint(const int grid[3], int prec, bool with_tensor);
 // aligned to 256 bytes (equal layers): spectral kernel, spectra, twiddles,
 // reduction buffers, Runge-Kutta vectors and the step controller.
 struct WsLayout {
-    size_t Khat, S1, S2, tw, red, red_out, rk, ctl, total;
+    size_t Khat, S1, S2, tw, red, red_out, rk, ctl, epart, total;
     bool s2_separate;
 };
 WsLayout ws_layout(const int grid[3], int prec);

@@ -1550,6 +1550,29 @@ static bool batch_kernels_ok(int L, int M)
     return mid && loc;
 }
 
+template <typename T>
+static bool local_wave_ok(int M)
+{
+    switch (M) {
+#define MMX_B(LL) \
+    case LL: return MMX_X1W && XC2RW<T, LL>::kOK;
+        MMX_CASES(MMX_B)
+#undef MMX_B
+    }
+    return false;
+}
+
+bool err_fusable(const Plan& p, unsigned terms)
+{
+    if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2 || p.Pb || !p.epart || p.batch != 1)
+        return false;
+    int ext = 0;
+    (void)make_local_params(p, nullptr, terms, 0.0, 1.0, true, &ext);
+    if (ext != 0) return false;
+    const int M = p.P[0] / 2;
+    return p.prec == MM_FP32 ? local_wave_ok<float>(M) : local_wave_ok<double>(M);
+}
+
 bool batch_supported(const int grid[3], int prec)
 {
     int P[3];
@@ -1589,11 +1612,13 @@ hipError_t batch_set_slot(Plan& g, int b, const Plan& v, const double hext[3], u
 }
 
 // sc: the x forward pass forms the stage input sc (m == sc->ys) from its
-// parts instead of reading m.
+// parts instead of reading m.  err (with sc->ep): the local pass also
+// accumulates the error norm into err->out_dev.
 template <typename T>
 static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], unsigned terms,
                                   double t, T* h_out, T* dm_out, double alpha_eff, bool precess,
-                                  double* torque, const StageIn<T>* sc)
+                                  double* torque, const StageIn<T>* sc,
+                                  const ErrIn<T>* err = nullptr)
 {
     const int M = p.P[0] / 2;
     const bool pc = p.percell;
@@ -1614,6 +1639,23 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
             k_fill<<<1, 64, 0, p.stream>>>(torque, 1, 0.0);
         MMX_TRY(hipGetLastError());
     }
+    if (err) {
+        // the error norm accumulated by the local pass: block partials, then
+        // the final sums as in rk_error_norm
+        if (ext != 0 || !sc || !sc->ep || !p.epart) return hipErrorInvalidValue;
+        const LocalErr<T> le{sc->ep, err->y, err->e6, err->rtol, err->atol, p.epart};
+        long nb = 0;
+        MMX_TRY(timed(p, MM_PASS_X_INV_LOCAL, [&] {
+            return pc ? launch_local<T, true, 0>(p, M, m, h_out, dm_out, P, torque, &le, &nb)
+                      : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque, &le, &nb);
+        }));
+        const double cnt = 3.0 * (double)p.n_magnetic;
+        k_final_sum<<<1, kBlock, 0, p.stream>>>(p.epart, (int)nb, err->out_dev, 0,
+                                                cnt > 0 ? 1.0 / cnt : 0.0, 1);
+        MMX_TRY(hipGetLastError());
+        k_final_sum<<<1, kBlock, 0, p.stream>>>(p.epart + nb, (int)nb, err->out_dev, 5, 1.0, 0);
+        return hipGetLastError();
+    }
     // DMI and the coupling averages only in the variants that need them
     return timed(p, MM_PASS_X_INV_LOCAL, [&] {
         if (ext == 0)
@@ -1633,9 +1675,15 @@ hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms,
 
 template <typename T>
 hipError_t eval_field_stage(Plan& p, const StageIn<T>& sc, const double hext[3], unsigned terms,
-                            double t, T* dm_out, double alpha_eff, bool precess, double* torque)
+                            double t, T* dm_out, double alpha_eff, bool precess, double* torque,
+                            const ErrIn<T>* err)
 {
     if (sc.nk < 1 || sc.nk > 7 || !sc.y || !sc.ys) return hipErrorInvalidValue;
+    if (err || sc.ep) {
+        if (!(err && sc.ep) || !err_fusable(p, terms)) return hipErrorInvalidValue;
+        return eval_field_core<T>(p, sc.ys, hext, terms, t, nullptr, dm_out, alpha_eff, precess,
+                                  torque, &sc, err);
+    }
     // a batch forms its stage inputs in the combination kernel (one step
     // size per request)
     if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2 || p.Pb) {
@@ -2191,7 +2239,8 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t eval_field<T>(Plan&, const T*, const double*, unsigned, double, T*, T*, \
                                       double, bool, double*);                                    \
     template hipError_t eval_field_stage<T>(Plan&, const StageIn<T>&, const double*, unsigned,   \
-                                            double, T*, double, bool, double*);                  \
+                                            double, T*, double, bool, double*,                   \
+                                            const ErrIn<T>*);                                    \
     template hipError_t rk_combine<T>(Plan&, T*, const T*, double, const double*, T* const*,     \
                                       int, const double*);                                       \
     template hipError_t rk_error_norm<T>(Plan&, const T*, const T*, double, const double*,       \

@@ -172,17 +172,24 @@ __global__ void k_twiddles(cx<T>* tw, int Lmax)
 //   X[k] = (Z[k] + conj Z[M-k])/2 - i w^k (Z[k] - conj Z[M-k])/2,
 //   w = exp(-2 pi i/(2M)).
 // ---------------------------------------------------------------------------
-// One element of a stage input (StageIn), stored to sc.ys and returned.
+// One element of a stage input (StageIn), stored to sc.ys and returned; with
+// sc.ep also the partial error sum_j e_j k_j (double, from the same loads).
 template <typename T>
-__device__ __forceinline__ T stage_elem(const StageIn<T>& sc, const T (&cj)[7], long o)
+__device__ __forceinline__ T stage_elem(const StageIn<T>& sc, const T (&cj)[7],
+                                        const double (&ej)[7], long o)
 {
     T acc = sc.y[o];
+    double e = 0.0;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        if (sc.c[j] == 0.0) continue;
-        acc += cj[j] * sc.k[j][o];
+        const bool uc = sc.c[j] != 0.0, ue = sc.ep && sc.e[j] != 0.0;
+        if (!uc && !ue) continue;
+        const T kv = sc.k[j][o];
+        if (uc) acc += cj[j] * kv;
+        if (ue) e += ej[j] * (double)kv;
     }
     sc.ys[o] = acc;
+    if (sc.ep) sc.ep[o] = (T)e;
     return acc;
 }
 
@@ -217,10 +224,14 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
     const T* msrc = PERCELL ? Ms_cell + r * in_row : nullptr;
     if (!PERCELL && Ms_b) Ms = Ms_b[(int)c / 3];
     T cj[7];
+    double ej[7];
     if constexpr (COMB) {
         const double hs = sc.h ? *sc.h : 1.0;
 #pragma unroll
-        for (int j = 0; j < 7; ++j) cj[j] = (T)(sc.c[j] * hs);
+        for (int j = 0; j < 7; ++j) {
+            cj[j] = (T)(sc.c[j] * hs);
+            ej[j] = sc.e[j] * hs;
+        }
     }
     cx<T> v[kE];
     if (MMX_XVEC && vec) {
@@ -234,14 +245,23 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
                 ab = *reinterpret_cast<const cx<T>*>(src + 2 * n);
                 if constexpr (COMB) {
                     const long o = base + 2 * n;
+                    double e0 = 0.0, e1 = 0.0;
 #pragma unroll
                     for (int j = 0; j < 7; ++j) {
-                        if (sc.c[j] == 0.0) continue;
+                        const bool uc = sc.c[j] != 0.0, ue = sc.ep && sc.e[j] != 0.0;
+                        if (!uc && !ue) continue;
                         const cx<T> kv = *reinterpret_cast<const cx<T>*>(sc.k[j] + o);
-                        ab.x += cj[j] * kv.x;
-                        ab.y += cj[j] * kv.y;
+                        if (uc) {
+                            ab.x += cj[j] * kv.x;
+                            ab.y += cj[j] * kv.y;
+                        }
+                        if (ue) {
+                            e0 += ej[j] * (double)kv.x;
+                            e1 += ej[j] * (double)kv.y;
+                        }
                     }
                     *reinterpret_cast<cx<T>*>(sc.ys + o) = ab;
+                    if (sc.ep) *reinterpret_cast<cx<T>*>(sc.ep + o) = cx<T>{(T)e0, (T)e1};
                 }
                 if (PERCELL) {
                     const cx<T> mm = *reinterpret_cast<const cx<T>*>(msrc + 2 * n);
@@ -261,8 +281,8 @@ __global__ __launch_bounds__((XR2C<T, M>::kRows * XR2C<T, M>::kT)) MMX_XR2C_ATTR
             // HALF: n_in <= M, so inputs q >= kE/2 (n >= M/2) are zero padding
             if (!(HALF && q >= kE / 2)) {
                 if constexpr (COMB) {
-                    if (valid && i0 < n_in) a = stage_elem(sc, cj, base + i0) * (PERCELL ? msrc[i0] : Ms);
-                    if (valid && i1 < n_in) b = stage_elem(sc, cj, base + i1) * (PERCELL ? msrc[i1] : Ms);
+                    if (valid && i0 < n_in) a = stage_elem(sc, cj, ej, base + i0) * (PERCELL ? msrc[i0] : Ms);
+                    if (valid && i1 < n_in) b = stage_elem(sc, cj, ej, base + i1) * (PERCELL ? msrc[i1] : Ms);
                 } else {
                     if (valid && i0 < n_in) a = src[i0] * (PERCELL ? msrc[i0] : Ms);
                     if (valid && i1 < n_in) b = src[i1] * (PERCELL ? msrc[i1] : Ms);
@@ -1067,19 +1087,31 @@ struct XC2RW {
     static_assert(!kOK || 3 * kRB * kT <= kNT, "transform threads exceed the block");
 };
 
+// The error-norm accumulation of the last Dormand-Prince stage (ERR): the
+// partial error ep from the x forward pass, the state y, the coefficient e6
+// of the derivative computed here, the tolerances, and the block partials
+// (sums in part[0, nblocks), non-finite counts in part[nblocks, 2 nblocks)).
+template <typename T>
+struct LocalErr {
+    const T* ep;
+    const T* y;
+    double e6, rtol, atol;
+    double* part;
+};
+
 // BATCH: nbatch requests of one grid, request-major blocks; request b's
 // spectrum, state and outputs follow those of b - 1 (3 components each), its
 // material and field constants are Pb[b] and its torque maximum goes to
 // torque[b * tstride].  Every address comes from the launch's own geometry
 // (Pk: nx, ny, nz, N, s1_comp, Hxp), never from a request's entry.
-template <typename T, int M, bool PERCELL, int EXT, bool BATCH>
+template <typename T, int M, bool PERCELL, int EXT, bool BATCH, bool ERR = false>
 __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     const cx<T>* __restrict__ S1, const T* __restrict__ m, T* __restrict__ h_out,
     T* __restrict__ dm_out, const T* __restrict__ Ms_cell, const unsigned char* __restrict__ mask,
     LocalParams Pk, double* torque, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
     const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
     const T* __restrict__ h_oe, const T* __restrict__ Ku_cell,
-    const LocalParams* __restrict__ Pb, int nbatch, long tstride)
+    const LocalParams* __restrict__ Pb, int nbatch, long tstride, LocalErr<T> E)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
     constexpr bool kMIX = EXT & EXT_MIX;
@@ -1227,6 +1259,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     }
     const T eux = (T)P.eu[0], euy = (T)P.eu[1], euz = (T)P.eu[2];
     double tmax = 0.0;
+    double eacc = 0.0, ebad = 0.0;  // ERR
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
         if (!cv[q]) continue;
@@ -1344,9 +1377,28 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
             const T qx = my * pz - mz * py, qy = mz * px - mx * pz, qz = mx * py - my * px;
             const T gp = (T)P.gp, al = (T)P.alpha, pf = P.precess ? (T)1 : (T)0;
             const bool mag = ms != (T)0;
-            elem<true>(dm_out, c0) = mag ? -gp * (pf * px + al * qx) : (T)0;
-            elem<true>(dm_out + N, c0) = mag ? -gp * (pf * py + al * qy) : (T)0;
-            elem<true>(dm_out + 2 * (size_t)N, c0) = mag ? -gp * (pf * pz + al * qz) : (T)0;
+            const T d[3] = {mag ? -gp * (pf * px + al * qx) : (T)0,
+                            mag ? -gp * (pf * py + al * qy) : (T)0,
+                            mag ? -gp * (pf * pz + al * qz) : (T)0};
+            elem<true>(dm_out, c0) = d[0];
+            elem<true>(dm_out + N, c0) = d[1];
+            elem<true>(dm_out + 2 * (size_t)N, c0) = d[2];
+            if constexpr (ERR) {
+                // e = ep + e6 k6 per component, scaled by atol + rtol max(|y|, |y1|)
+                const T y1c[3] = {mx, my, mz};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double yv = (double)elem<true>(E.y + (size_t)c * N, c0);
+                    if (!isfinite(yv)) ebad += 1.0;
+                    if (PERCELL && !mag) continue;
+                    const double e =
+                        (double)elem<true>(E.ep + (size_t)c * N, c0) + E.e6 * (double)d[c];
+                    const double ya = fabs(yv), yb = fabs((double)y1c[c]);
+                    const double scl = E.atol + E.rtol * (ya > yb ? ya : yb);
+                    const double r = e / scl;
+                    eacc += r * r;
+                }
+            }
         }
         if (torque && ms != (T)0) {
             const double tq = sqrt((double)px * px + (double)py * py + (double)pz * pz) / (double)ms;
@@ -1360,6 +1412,29 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
             tmax = tmax > o ? tmax : o;
         }
         if ((threadIdx.x & 63) == 0) atomic_max_nonneg(torque, tmax);
+    }
+    if constexpr (ERR) {
+        // block partials in a fixed order: a wavefront tree, then the
+        // wavefronts in order
+        __shared__ double esum[2][G::kNT / 64];
+        for (int off = 32; off > 0; off >>= 1) {
+            eacc += __shfl_down(eacc, off, 64);
+            ebad += __shfl_down(ebad, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            esum[0][threadIdx.x >> 6] = eacc;
+            esum[1][threadIdx.x >> 6] = ebad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < G::kNT / 64; ++w) {
+                s0 += esum[0][w];
+                s1 += esum[1][w];
+            }
+            E.part[lb] = s0;
+            E.part[nblocks + lb] = s1;
+        }
     }
 }
 
@@ -1471,9 +1546,10 @@ static hipError_t launch_x_r2c_M(const Plan& p, const T* in, long in_row, long i
         bool vec = n_in % 2 == 0 && in_row % 2 == 0 && in_comp % 2 == 0 &&
                    ((uintptr_t)in & al) == 0 && (!PC || ((uintptr_t)Ms_cell & al) == 0);
         if (sc) {
-            vec = vec && ((uintptr_t)sc->ys & al) == 0;
+            vec = vec && ((uintptr_t)sc->ys & al) == 0 && ((uintptr_t)sc->ep & al) == 0;
             for (int j = 0; j < 7; ++j)
-                if (sc->c[j] != 0.0) vec = vec && ((uintptr_t)sc->k[j] & al) == 0;
+                if (sc->c[j] != 0.0 || (sc->ep && sc->e[j] != 0.0))
+                    vec = vec && ((uintptr_t)sc->k[j] & al) == 0;
         }
         const StageIn<T> none{};
         const dim3 blk(G::kRows * G::kT);
@@ -1573,14 +1649,31 @@ hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long es, long
     return hipErrorInvalidValue;
 }
 
+// err: also accumulate the error norm's block partials (plain stencil, one
+// request, wave-local kernel); *nb_out: the number of blocks (partial pairs).
 template <typename T, int M, bool PC, int EXT>
 static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
-                                 double* torque)
+                                 double* torque, const LocalErr<T>* err, long* nb_out)
 {
     if constexpr (MMX_X1W && XC2RW<T, M>::kOK) {
         using Gw = XC2RW<T, M>;
         const int njt = (p.n[1] + Gw::kRB - 1) / Gw::kRB;
         const long nblocks = (long)njt * p.n[2];
+        if (nb_out) *nb_out = nblocks;
+        if (err) {
+            if constexpr (EXT == 0) {
+                if (p.Pb || !dm || !err->part || nblocks > (long)p.n[1] * p.n[2])
+                    return hipErrorInvalidValue;
+                k_x_c2r_local_w<T, M, PC, 0, false, true>
+                    <<<xcd_grid(nblocks), Gw::kNT, 0, p.stream>>>(
+                        (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque,
+                        nblocks, (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr,
+                        p.layered ? (const T*)p.zw : nullptr, P.with_oe ? (const T*)p.h_oe : nullptr,
+                        nullptr, nullptr, 1, 0, *err);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
         if (p.Pb) {
             // a batch plan: uniform material per request, constants from
             // p.Pb, p.batch requests per launch, torque maxima 8 doubles apart
@@ -1590,7 +1683,7 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
                     <<<xcd_grid(nblocks * p.batch), Gw::kNT, 0, p.stream>>>(
                         (const cx<T>*)p.S1, m, h, dm, nullptr, nullptr, P, torque, nblocks,
                         (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr, nullptr, nullptr, nullptr,
-                        (const LocalParams*)p.Pb, p.batch, 8);
+                        (const LocalParams*)p.Pb, p.batch, 8, LocalErr<T>{});
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
@@ -1600,10 +1693,13 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
             (const cx<T>*)p.tw, p.Lmax, (EXT & EXT_PA) ? (const T*)p.A_cell : nullptr,
             (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
             P.with_oe ? (const T*)p.h_oe : nullptr,
-            EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr, nullptr, 1, 0);
+            EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr, nullptr, 1, 0,
+            LocalErr<T>{});
         return hipGetLastError();
     }
-    if (p.Pb) return hipErrorInvalidValue;  // batches need the wave-local kernel
+    // batches and the error accumulation need the wave-local kernel
+    if (p.Pb || err) return hipErrorInvalidValue;
+    if (nb_out) *nb_out = 0;
     using G = XC2R<T, M>;
     const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
     const long nblocks = (long)njt * p.n[2];
@@ -1618,11 +1714,12 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
 
 template <typename T, bool PC, int EXT>
 hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
-                               const LocalParams& P, double* torque)
+                               const LocalParams& P, double* torque,
+                               const LocalErr<T>* err = nullptr, long* nb_out = nullptr)
 {
     switch (M) {
 #define MMX_L(LL) \
-    case LL: return launch_local_M<T, LL, PC, EXT>(p, m, h, dm, P, torque);
+    case LL: return launch_local_M<T, LL, PC, EXT>(p, m, h, dm, P, torque, err, nb_out);
         MMX_L(0) MMX_CASES(MMX_L)
 #undef MMX_L
     }
@@ -1672,9 +1769,11 @@ hipError_t launch_local_ext(const Plan& p, int M, const T* m, T* h, T* dm, const
                                                    const T*, T, cx<T>*, long, long, int, int,   \
                                                    const StageIn<T>*);                          \
     EXT_ template hipError_t launch_local<T, false, 0>(const Plan&, int, const T*, T*, T*,      \
-                                                       const LocalParams&, double*);            \
+                                                       const LocalParams&, double*,             \
+                                                       const LocalErr<T>*, long*);              \
     EXT_ template hipError_t launch_local<T, true, 0>(const Plan&, int, const T*, T*, T*,       \
-                                                      const LocalParams&, double*);
+                                                      const LocalParams&, double*,              \
+                                                      const LocalErr<T>*, long*);
 #define MMX_MID_INST(EXT_, T)                                                                    \
     EXT_ template hipError_t launch_mid<T, 2, 0>(const Plan&, int, cx<T>*, int, long, long,     \
                                                  long, int);                                    \

@@ -160,8 +160,9 @@ def _workspace_model(grid, prec):
     extents P = next power of two >= 2n - 1 (1 for n = 1), x bins Hx = Px/2 + 1
     rounded up to 128 bytes of reals, the folded real kernel 6 (Pz/2+1)(Py/2+1)
     Hx, spectra 3 nz ny Hx and (when Py, Pz > 1) 3 nz Py Hx complex, Lmax
-    twiddles, 8192 + 8 reduction doubles, 10 vectors of 3N and the 120-byte
-    controller, each rounded up to 256 bytes."""
+    twiddles, 8192 + 8 reduction doubles, 10 vectors of 3N, the 120-byte
+    controller and 2 ny nz doubles of error-norm partials, each rounded up to
+    256 bytes."""
     def pad(n):
         p = 1
         while n > 1 and p < 2 * n - 1:
@@ -177,7 +178,8 @@ def _workspace_model(grid, prec):
     parts = [6 * (Pz // 2 + 1) * (Py // 2 + 1) * Hx * es, 3 * nz * ny * Hx * 2 * es]
     if Py > 1 and Pz > 1:
         parts.append(3 * nz * Py * Hx * 2 * es)
-    parts += [max(Px, Py, Pz) * 2 * es, 8 * 8192, 8 * 8, 10 * 3 * nx * ny * nz * es, 120]
+    parts += [max(Px, Py, Pz) * 2 * es, 8 * 8192, 8 * 8, 10 * 3 * nx * ny * nz * es, 120,
+              2 * 8 * ny * nz]
     return sum(up(b) for b in parts)
 
 
