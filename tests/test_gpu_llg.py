@@ -65,6 +65,46 @@ def test_small_llg_fp64_200_steps(torch_cuda, mm, small_llg_oracle):
     assert np.allclose(E, Er, rtol=1e-9, atol=1e-30), (E, Er)
 
 
+def test_llg_percell_ms_vacuum_fp64(torch_cuda, mm, orc):
+    """Adaptive Dormand-Prince steps on a plan with per-cell Ms and vacuum
+    cells (uniform A, Ku, Zeeman): the error norm accumulated by the last
+    stage's passes skips vacuum components and counts non-finite ones like
+    the separate norm.  Against the oracle: the same step path (counts equal,
+    m to rounding level), and at equal time."""
+    grid = (17, 12, 3)
+    banner("llg per-cell Ms with vacuum fp64 %s" % (grid,))
+    g = W.rng(401)
+    Ms = g.uniform(6e5, 1.1e6, (grid[2], grid[1], grid[0]))
+    Ms[g.uniform(size=Ms.shape) < 0.12] = 0.0
+    d = (3e-9, 3e-9, 2e-9)
+    A, Ku, alpha = 1.3e-11, 3e4, 0.3
+    H = W.mT(25.0) * np.array([0.3, -0.4, 0.866])
+    m0 = W.smooth_random(grid, 3.0, seed=402)
+    plan = mm.Plan(grid, d, Ms=1.0, A=A, Ku=Ku, alpha=alpha, prec="fp64")
+    plan.set_ms(Ms)
+    o = orc.Oracle(grid, d, Ms=Ms, A=np.where(Ms > 0, A, 0.0), Ku=Ku, alpha=alpha)
+    o.set_field(H)
+    m_ref, t_ref, _, st_ref, _ = o.dp45(m0, rtol=1e-8, max_steps=60)
+    m = plan._t(m0)
+    _, t, _, st = plan.llg_step(m, H, mm.MM_ALL, rtol=1e-8, max_steps=60)
+    dm = np.abs(to_np(m) - m_ref).max()
+    print("  60 steps: rejected %d/%d (gpu/oracle), |dm| %.2e, dt rel %.2e" %
+          (st["rejected"], st_ref["rejected"], dm, abs(t - t_ref) / t_ref))
+    assert st["accepted"] == 60 and st["rejected"] == st_ref["rejected"]
+    assert st["rhs_evals"] == st_ref["rhs_evals"]
+    assert abs(t - t_ref) <= 1e-9 * t_ref
+    assert dm <= 1e-9
+    # equal time, longer run
+    t_end = 3e-11
+    ref, tt, _, _, _ = o.dp45(m0, rtol=1e-8, t_end=t_end)
+    m2 = plan._t(m0)
+    status, t2, _, _ = plan.llg_step(m2, H, mm.MM_ALL, rtol=1e-8, t_end=t_end)
+    assert status == mm.MM_OK and t2 == t_end
+    e = rel_l2(to_np(m2), ref)
+    print("  to t = %.1e s: rel-L2 vs oracle %.2e" % (t_end, e))
+    assert e <= 1e-7
+
+
 def test_small_llg_fp32_equal_time(torch_cuda, mm, orc, small_llg_oracle):
     c, o, m_ref, t_ref, st_ref = small_llg_oracle
     banner("llg 32x32x4 fp32 200 steps")
