@@ -249,3 +249,48 @@ def test_rkf45_matches_oracle(torch_cuda, mm, orc, prec):
     print("  %d steps, %d rejected, %d evals, |m - oracle| %.2e" % (st["accepted"], st["rejected"],
                                                                    st["rhs_evals"], d))
     assert d <= bar
+
+
+def test_full_size_steps_properties(torch_cuda, mm):
+    """The benchmark's adaptive steps at their own size and launch
+    configuration (512 x 512 x 64, vortex start, rtol 1e-6: stage inputs
+    formed in the x forward pass, the error norm in the last stage's passes),
+    checked by properties that hold at any size.  Two runs from the same
+    start are bit-identical (every reduction has a fixed order); without
+    renormalisation the RMS of |m| - 1 stays within K (atol + rtol) after K
+    steps (each accepted step's error estimate is at most atol + rtol per
+    component in RMS, and |m| is conserved by the equation, Sec. 3); FP32 at
+    the FP64 run's end time agrees with FP64 within 1e-4."""
+    c = W.config_large()
+    rtol, K = 1e-6, 5
+    banner("full-size steps %s, %d steps" % (c["n"], K))
+    res = {}
+    t_end = None
+    for prec in ("fp64", "fp32"):
+        plan = mm.Plan(c["n"], c["d"], Ms=c["Ms"], A=c["A"], alpha=c["alpha"], prec=prec)
+        runs = []
+        for _ in range(2):
+            m = plan._t(c["m0"])
+            if t_end is None or prec == "fp64":
+                _, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, max_steps=K)
+            else:
+                _, t, dt, st = plan.llg_step(m, c["H"], c["terms"], rtol=rtol, t_end=t_end)
+            runs.append((to_np(m), t, dt, st))
+        del plan
+        (m1, t1, dt1, st1), (m2, t2, dt2, st2) = runs
+        assert np.array_equal(m1, m2) and t1 == t2 and dt1 == dt2 and st1 == st2, prec
+        if prec == "fp64":
+            t_end = t1
+            assert st1["accepted"] == K
+        else:
+            assert t1 == t_end
+        nrm = np.sqrt((m1 * m1).sum(axis=0))
+        drift = float(np.sqrt(np.mean((nrm - 1.0) ** 2)))
+        print("  %s: %d accepted, %d rejected, t %.3e s, last error norm %.3f, RMS(|m| - 1) %.2e"
+              % (prec, st1["accepted"], st1["rejected"], t1, st1["err_last"], drift))
+        assert 0.0 < st1["err_last"] <= 1.0
+        assert drift <= st1["accepted"] * 2 * rtol, (prec, drift)
+        res[prec] = m1
+    d = float(np.abs(res["fp32"] - res["fp64"]).max())
+    print("  |m32 - m64| at t %.3e s: %.2e" % (t_end, d))
+    assert d <= 1e-4
