@@ -525,9 +525,10 @@ bool try_admit(Server* s)
     if (s->queue.empty()) return false;
     Req& head = s->queue.front();
     const GroupKey key = group_of(head.r, s->o);
-    // a free slot in a running group of the key
+    // a free slot in a running group of the key (not one that failed and
+    // waits for the next poll to be removed: it has no plan)
     for (Group* g : s->groups) {
-        if (!(g->key == key)) continue;
+        if (!(g->key == key) || !g->plan) continue;
         for (int b = 0; b < g->B; ++b)
             if (!g->slots[b].busy) {
                 if (s->o.prec == MM_FP32)
