@@ -72,19 +72,26 @@ __global__ void k_final_sum(const double* __restrict__ partials, int n, double* 
     }
 }
 
-// Batched k_final_sum: block b sums partials[b pstride .. b pstride + n) in
-// the same order into out[b ostride + slot].
-__global__ void k_final_sum_b(const double* __restrict__ partials, int n, long pstride,
-                              double* out, long ostride, int slot, double scale, int do_sqrt)
+// The error norm's two final sums in one launch: block b (a request of a
+// batch) sums partials[b pstride .. + n) (squared scaled errors) into
+// out[b ostride] as sqrt(scale * sum) and partials[b pstride + n .. + n)
+// (non-finite counts) into out[b ostride + 5], each in the order of
+// k_final_sum.
+__global__ void k_err_sums(const double* __restrict__ partials, int n, long pstride, double* out,
+                           long ostride, double scale)
 {
     partials += (long)blockIdx.x * pstride;
     out += (long)blockIdx.x * ostride;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    double v = 0.0, w = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        v += partials[i];
+        w += partials[n + i];
+    }
     v = block_sum(v);
+    w = block_sum(w);
     if (threadIdx.x == 0) {
-        v *= scale;
-        out[slot] = do_sqrt ? sqrt(v) : v;
+        out[0] = sqrt(v * scale);
+        out[5] = w;
     }
 }
 
@@ -1650,10 +1657,8 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
                       : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque, &le, &nb);
         }));
         const double cnt = 3.0 * (double)p.n_magnetic;
-        k_final_sum<<<1, kBlock, 0, p.stream>>>(p.epart, (int)nb, err->out_dev, 0,
-                                                cnt > 0 ? 1.0 / cnt : 0.0, 1);
-        MMX_TRY(hipGetLastError());
-        k_final_sum<<<1, kBlock, 0, p.stream>>>(p.epart + nb, (int)nb, err->out_dev, 5, 1.0, 0);
+        k_err_sums<<<1, kBlock, 0, p.stream>>>(p.epart, (int)nb, 2 * nb, err->out_dev, 8,
+                                               cnt > 0 ? 1.0 / cnt : 0.0);
         return hipGetLastError();
     }
     // DMI and the coupling averages only in the variants that need them
@@ -1709,16 +1714,7 @@ static hipError_t err_final_sums(Plan& p, int nb, double* out_dev)
 {
     const double cnt = 3.0 * (double)p.n_magnetic;
     const double sc = cnt > 0 ? 1.0 / cnt : 0.0;
-    if (p.batch > 1) {
-        k_final_sum_b<<<p.batch, kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, 0, sc, 1);
-        MMX_TRY(hipGetLastError());
-        k_final_sum_b<<<p.batch, kBlock, 0, p.stream>>>(p.red + nb, nb, 2L * nb, out_dev, 8, 5, 1.0,
-                                                        0);
-        return hipGetLastError();
-    }
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red, nb, out_dev, 0, sc, 1);
-    MMX_TRY(hipGetLastError());
-    k_final_sum<<<1, kBlock, 0, p.stream>>>(p.red + nb, nb, out_dev, 5, 1.0, 0);
+    k_err_sums<<<std::max(1, p.batch), kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, sc);
     return hipGetLastError();
 }
 
@@ -1780,12 +1776,12 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
         vec = vec && aligned16(ks.p[j]);
     }
     const T* msc = p.percell ? (const T*)p.Ms_cell : nullptr;
-    // a streaming reduction: about 16 (vector) elements per thread, up to
+    // a streaming reduction: about 4 (vector) elements per thread, up to
     // kErrBlocks blocks, so large grids keep 8 waves per SIMD resident and
-    // small ones launch few blocks (partials: sums in [0, nb), non-finite
-    // counts in [nb, 2 nb)); nb depends on the grid only
+    // mid-sized ones (the served grids) still fill the chip (partials: sums
+    // in [0, nb), non-finite counts in [nb, 2 nb)); nb depends on the grid only
     const long nv = 3 * p.N / (vec ? V16<T>::n : 1);
-    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(nv, kBlock * 16)));
+    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(nv, kBlock * 4)));
     if (p.batch > 1 && p.percell) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb, (unsigned)p.batch);
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
@@ -2180,7 +2176,7 @@ hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const dou
     }
     const float* msc = p.percell ? (const float*)p.Ms_cell : nullptr;
     if (p.batch > 1 && msc) return hipErrorInvalidValue;
-    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(3 * p.N, kBlock * 16)));
+    const int nb = (int)std::max<long>(1, std::min<long>(kErrBlocks, blocks_for(3 * p.N, kBlock * 4)));
     const dim3 grid((unsigned)nb, (unsigned)p.batch);
     MMX_TRY(timed(p, MM_PASS_RK, [&] {
         if (msc)
