@@ -340,16 +340,15 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
             }
             double E[7];
             for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
-            MM_HIP(rk_error_norm_d(*p, yd, y1d, E, k, 7, rtol, atol, p->red_out, hdev),
-                   "error norm");
-            MM_HIP(dp_control(*p, p->ctl), "controller");
+            MM_HIP(rk_error_norm_d(*p, yd, y1d, E, k, 7, rtol, atol, p->red_out, hdev, p->ctl),
+                   "error norm and controller");
             MM_HIP(dp_commit_d(*p, p->ctl, yd, y1d, ys, k[0], k[6]), "commit");
-            if (renorm) {
+            // the closing evaluation leaves the torque for the next step's
+            // begin
+            if (renorm)
                 MM_HIP(eval_field<T>(*p, ys, hext, terms, 0.0, nullptr, k[0], alpha, !relax,
                                      relax ? p->red_out + 1 : nullptr),
                        "right-hand side");
-                if (relax) MM_HIP(dp_torque(*p, p->ctl), "torque");
-            }
             return MM_OK;
         }
     }
@@ -360,15 +359,14 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
     }
     double E[7];
     for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
-    MM_HIP(rk_error_norm<T>(*p, y, y1, 0.0, E, k, 7, rtol, atol, p->red_out, hdev), "error norm");
-    MM_HIP(dp_control(*p, p->ctl), "controller");
+    MM_HIP(rk_error_norm<T>(*p, y, y1, 0.0, E, k, 7, rtol, atol, p->red_out, hdev, p->ctl),
+           "error norm and controller");
     MM_HIP(dp_commit<T>(*p, p->ctl, y, y1, k[0], k[6]), "commit");
-    if (renorm) {
+    // the closing evaluation leaves the torque for the next step's begin
+    if (renorm)
         MM_HIP(eval_field<T>(*p, y, hext, terms, 0.0, nullptr, k[0], alpha, !relax,
                              relax ? p->red_out + 1 : nullptr),
                "right-hand side");
-        if (relax) MM_HIP(dp_torque(*p, p->ctl), "torque");
-    }
     return MM_OK;
 }
 

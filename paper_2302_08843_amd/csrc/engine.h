@@ -206,11 +206,12 @@ hipError_t rk_combine(Plan &p, T *y_out, const T *y, double h, const double *a, 
                       int nk, const double *hdev = nullptr);
 // RMS error norm of e = h sum_j e[j] k[j] scaled by atol + rtol max(|y|,|y1|)
 // over magnetic components into out_dev[0]; the number of non-finite entries
-// of y into out_dev[5].
+// of y into out_dev[5].  ctl (device-controlled steps): the same launch then
+// takes the accept / reject decision of dp_control on out_dev.
 template <typename T>
 hipError_t rk_error_norm(Plan &p, const T *y, const T *y1, double h, const double *e,
                          T *const *k, int nk, double rtol, double atol, double *out_dev,
-                         const double *hdev = nullptr);
+                         const double *hdev = nullptr, DevCtl *ctl = nullptr);
 
 // Device-side Dormand-Prince controller state (one per plan in device
 // memory).  Every decision the host-driven loop takes from a synchronised
@@ -223,8 +224,10 @@ struct DevCtl {
     int result;    // mm_status of a finished run
     int last_rejected, commit, relax, renorm;
 };
-// start of a step: finish on the torque criterion / step cap / t_end, else
-// set the trial step h = min(dt, t_end - t)
+// start of a step: a relaxation takes its torque from p.red_out[1] (left
+// there by the previous step's closing evaluation, or dp_torque at the
+// start); finish on the torque criterion / step cap / t_end, else set the
+// trial step h = min(dt, t_end - t)
 hipError_t dp_begin(Plan &p, DevCtl *c);
 // accept / reject from the error norm in p.red_out[0] (non-finite count in
 // p.red_out[5]) and the new step size
@@ -242,7 +245,7 @@ hipError_t rk_combine_d(Plan &p, float *ys, double *y1, const double *y, const d
                         float *const *k, int nk, const double *hdev);
 hipError_t rk_error_norm_d(Plan &p, const double *y, const double *y1, const double *e,
                            float *const *k, int nk, double rtol, double atol, double *out_dev,
-                           const double *hdev);
+                           const double *hdev, DevCtl *ctl = nullptr);
 hipError_t dp_commit_d(Plan &p, DevCtl *c, double *y, const double *y1, float *ys, float *k0,
                        const float *k6);
 hipError_t convert_f32_f64(Plan &p, const float *in, double *out, long n);

@@ -72,13 +72,15 @@ __global__ void k_final_sum(const double* __restrict__ partials, int n, double* 
     }
 }
 
+__device__ void dp_control_one(DevCtl* c, const double* red);
+
 // The error norm's two final sums in one launch: block b (a request of a
 // batch) sums partials[b pstride .. + n) (squared scaled errors) into
 // out[b ostride] as sqrt(scale * sum) and partials[b pstride + n .. + n)
 // (non-finite counts) into out[b ostride + 5], each in the order of
-// k_final_sum.
+// k_final_sum; with ctl, then runs the step controller ctl[b] on them.
 __global__ void k_err_sums(const double* __restrict__ partials, int n, long pstride, double* out,
-                           long ostride, double scale)
+                           long ostride, double scale, DevCtl* ctl)
 {
     partials += (long)blockIdx.x * pstride;
     out += (long)blockIdx.x * ostride;
@@ -92,6 +94,8 @@ __global__ void k_err_sums(const double* __restrict__ partials, int n, long pstr
     if (threadIdx.x == 0) {
         out[0] = sqrt(v * scale);
         out[5] = w;
+        // the step controller of request b (ctl: device-controlled steps)
+        if (ctl) dp_control_one(ctl + blockIdx.x, out);
     }
 }
 
@@ -287,12 +291,15 @@ __global__ void k_renorm(T* __restrict__ m, const T* __restrict__ Ms_cell, long 
 // clipped to t_end keeps the proposal), a non-finite trial error is a
 // rejection with factor 0.2 unless the state itself is non-finite.
 // ---------------------------------------------------------------------------
-__global__ void k_dp_begin(DevCtl* c, int nbatch)
+__global__ void k_dp_begin(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
 {
-    // one thread per request of a batch
+    // one thread per request of a batch, its reductions rstride doubles apart
     if ((int)threadIdx.x >= nbatch) return;
     c += threadIdx.x;
     if (c->done) return;
+    // a relaxation's torque at its current state: the maximum the previous
+    // step's closing evaluation (or the start) left in red[1]
+    if (c->relax) c->torque = red[(long)threadIdx.x * rstride + 1];
     if (c->relax && c->torque < c->torque_tol) {
         c->done = 1;
         c->result = MM_OK;
@@ -312,12 +319,10 @@ __global__ void k_dp_begin(DevCtl* c, int nbatch)
     c->h = h;
 }
 
-__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
+// Accept or reject one request's step from its error norm red[0] (red[5]:
+// non-finite entries of the state) and choose the next step size.
+__device__ void dp_control_one(DevCtl* c, const double* red)
 {
-    // one thread per request of a batch, its reductions rstride doubles apart
-    if ((int)threadIdx.x >= nbatch) return;
-    c += threadIdx.x;
-    red += (long)threadIdx.x * rstride;
     c->commit = 0;
     if (c->done) return;
     c->rhs_evals += 6;
@@ -350,6 +355,13 @@ __global__ void k_dp_control(DevCtl* c, const double* __restrict__ red, int nbat
         c->done = 1;
         c->result = MM_EDTMIN;
     }
+}
+
+__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
+{
+    // one thread per request of a batch, its reductions rstride doubles apart
+    if ((int)threadIdx.x >= nbatch) return;
+    dp_control_one(c + threadIdx.x, red + (long)threadIdx.x * rstride);
 }
 
 __global__ void k_dp_torque(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
@@ -1658,7 +1670,7 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
         }));
         const double cnt = 3.0 * (double)p.n_magnetic;
         k_err_sums<<<1, kBlock, 0, p.stream>>>(p.epart, (int)nb, 2 * nb, err->out_dev, 8,
-                                               cnt > 0 ? 1.0 / cnt : 0.0);
+                                               cnt > 0 ? 1.0 / cnt : 0.0, nullptr);
         return hipGetLastError();
     }
     // DMI and the coupling averages only in the variants that need them
@@ -1710,11 +1722,12 @@ static bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
 // pairs: out_dev[0] = RMS over the magnetic components, out_dev[5] = number
 // of non-finite entries of the current state; per request of a batch (its
 // partials 2 nb apart, its results 8 doubles apart).
-static hipError_t err_final_sums(Plan& p, int nb, double* out_dev)
+static hipError_t err_final_sums(Plan& p, int nb, double* out_dev, DevCtl* ctl = nullptr)
 {
     const double cnt = 3.0 * (double)p.n_magnetic;
     const double sc = cnt > 0 ? 1.0 / cnt : 0.0;
-    k_err_sums<<<std::max(1, p.batch), kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, sc);
+    k_err_sums<<<std::max(1, p.batch), kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, sc,
+                                                              ctl);
     return hipGetLastError();
 }
 
@@ -1762,7 +1775,8 @@ hipError_t rk_combine(Plan& p, T* y_out, const T* y, double h, const double* a, 
 
 template <typename T>
 hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const double* e, T* const* k,
-                         int nk, double rtol, double atol, double* out_dev, const double* hdev)
+                         int nk, double rtol, double atol, double* out_dev, const double* hdev,
+                         DevCtl* ctl)
 {
     Coef7 cf{};
     Ptr7<T> ks{};
@@ -1799,7 +1813,7 @@ hipError_t rk_error_norm(Plan& p, const T* y, const T* y1, double h, const doubl
                                                                        rtol, atol, p.red);
         return hipGetLastError();
     }));
-    return err_final_sums(p, nb, out_dev);
+    return err_final_sums(p, nb, out_dev, ctl);
 }
 
 template <typename T>
@@ -1814,7 +1828,7 @@ hipError_t renormalise(Plan& p, T* m)
 // reduction results 8 doubles apart).
 hipError_t dp_begin(Plan& p, DevCtl* c)
 {
-    k_dp_begin<<<1, p.batch, 0, p.stream>>>(c, p.batch);
+    k_dp_begin<<<1, p.batch, 0, p.stream>>>(c, p.red_out, p.batch, 8);
     return hipGetLastError();
 }
 
@@ -2164,7 +2178,7 @@ hipError_t rk_combine_d(Plan& p, float* ys, double* y1, const double* y, const d
 
 hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const double* e,
                            float* const* k, int nk, double rtol, double atol, double* out_dev,
-                           const double* hdev)
+                           const double* hdev, DevCtl* ctl)
 {
     Coef7 cf{};
     Ptr7<float> ks{};
@@ -2187,7 +2201,7 @@ hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const dou
                                                                p.red);
         return hipGetLastError();
     }));
-    return err_final_sums(p, nb, out_dev);
+    return err_final_sums(p, nb, out_dev, ctl);
 }
 
 hipError_t dp_commit_d(Plan& p, DevCtl* c, double* y, const double* y1, float* ys, float* k0,
@@ -2240,7 +2254,8 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t rk_combine<T>(Plan&, T*, const T*, double, const double*, T* const*,     \
                                       int, const double*);                                       \
     template hipError_t rk_error_norm<T>(Plan&, const T*, const T*, double, const double*,       \
-                                         T* const*, int, double, double, double*, const double*); \
+                                         T* const*, int, double, double, double*, const double*,  \
+                                         DevCtl*);                                                \
     template hipError_t dp_commit<T>(Plan&, DevCtl*, T*, const T*, T*, const T*);                \
     template hipError_t renormalise<T>(Plan&, T*);                                               \
     template hipError_t dot_ms<T>(Plan&, const T*, const T*, double*, double*);                  \
