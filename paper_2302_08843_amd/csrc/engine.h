@@ -207,7 +207,7 @@ hipError_t rk_combine(Plan &p, T *y_out, const T *y, double h, const double *a, 
 // RMS error norm of e = h sum_j e[j] k[j] scaled by atol + rtol max(|y|,|y1|)
 // over magnetic components into out_dev[0]; the number of non-finite entries
 // of y into out_dev[5].  ctl (device-controlled steps): the same launch then
-// takes the accept / reject decision of dp_control on out_dev.
+// takes the step's accept / reject decision and next step size on out_dev.
 template <typename T>
 hipError_t rk_error_norm(Plan &p, const T *y, const T *y1, double h, const double *e,
                          T *const *k, int nk, double rtol, double atol, double *out_dev,
@@ -229,9 +229,8 @@ struct DevCtl {
 // start); finish on the torque criterion / step cap / t_end, else set the
 // trial step h = min(dt, t_end - t)
 hipError_t dp_begin(Plan &p, DevCtl *c);
-// accept / reject from the error norm in p.red_out[0] (non-finite count in
-// p.red_out[5]) and the new step size
-hipError_t dp_control(Plan &p, DevCtl *c);
+// (accept / reject and the new step size: in the error norm's final launch,
+// rk_error_norm / rk_error_norm_d with ctl)
 // on acceptance: y = y1 (renormalised if c->renorm) and, without renorm,
 // k0 = k6 (first-same-as-last)
 template <typename T>

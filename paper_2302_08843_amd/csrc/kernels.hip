@@ -357,13 +357,6 @@ __device__ void dp_control_one(DevCtl* c, const double* red)
     }
 }
 
-__global__ void k_dp_control(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
-{
-    // one thread per request of a batch, its reductions rstride doubles apart
-    if ((int)threadIdx.x >= nbatch) return;
-    dp_control_one(c + threadIdx.x, red + (long)threadIdx.x * rstride);
-}
-
 __global__ void k_dp_torque(DevCtl* c, const double* __restrict__ red, int nbatch, int rstride)
 {
     if ((int)threadIdx.x >= nbatch) return;
@@ -1829,12 +1822,6 @@ hipError_t renormalise(Plan& p, T* m)
 hipError_t dp_begin(Plan& p, DevCtl* c)
 {
     k_dp_begin<<<1, p.batch, 0, p.stream>>>(c, p.red_out, p.batch, 8);
-    return hipGetLastError();
-}
-
-hipError_t dp_control(Plan& p, DevCtl* c)
-{
-    k_dp_control<<<1, p.batch, 0, p.stream>>>(c, p.red_out, p.batch, 8);
     return hipGetLastError();
 }
 
