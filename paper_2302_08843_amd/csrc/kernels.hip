@@ -1714,7 +1714,8 @@ static bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
 // The error norm's final sums from its nb (sum, non-finite count) partial
 // pairs: out_dev[0] = RMS over the magnetic components, out_dev[5] = number
 // of non-finite entries of the current state; per request of a batch (its
-// partials 2 nb apart, its results 8 doubles apart).
+// partials 2 nb apart, its results 8 doubles apart); with ctl, the same
+// launch then takes each request's step decision.
 static hipError_t err_final_sums(Plan& p, int nb, double* out_dev, DevCtl* ctl = nullptr)
 {
     const double cnt = 3.0 * (double)p.n_magnetic;
