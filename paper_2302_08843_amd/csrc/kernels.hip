@@ -77,21 +77,38 @@ __device__ void dp_control_one(DevCtl* c, const double* red);
 // The error norm's two final sums in one launch: block b (a request of a
 // batch) sums partials[b pstride .. + n) (squared scaled errors) into
 // out[b ostride] as sqrt(scale * sum) and partials[b pstride + n .. + n)
-// (non-finite counts) into out[b ostride + 5], each in the order of
-// k_final_sum; with ctl, then runs the step controller ctl[b] on them.
-__global__ void k_err_sums(const double* __restrict__ partials, int n, long pstride, double* out,
-                           long ostride, double scale, DevCtl* ctl)
+// (non-finite counts) into out[b ostride + 5], each in a fixed order (a
+// strided sum per thread, a wavefront tree, the wavefronts in order); with
+// ctl, then runs the step controller ctl[b] on them.
+constexpr int kSumBlock = 1024;  // threads of k_err_sums (up to 32768 partial pairs)
+
+__global__ __launch_bounds__(kSumBlock) void k_err_sums(const double* __restrict__ partials, int n,
+                                                        long pstride, double* out, long ostride,
+                                                        double scale, DevCtl* ctl)
 {
+    __shared__ double ws[2][kSumBlock / 64];
     partials += (long)blockIdx.x * pstride;
     out += (long)blockIdx.x * ostride;
     double v = 0.0, w = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += kSumBlock) {
         v += partials[i];
         w += partials[n + i];
     }
-    v = block_sum(v);
-    w = block_sum(w);
+    for (int off = 32; off > 0; off >>= 1) {
+        v += __shfl_down(v, off, 64);
+        w += __shfl_down(w, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        ws[0][threadIdx.x / 64] = v;
+        ws[1][threadIdx.x / 64] = w;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        v = w = 0.0;
+        for (int i = 0; i < kSumBlock / 64; ++i) {
+            v += ws[0][i];
+            w += ws[1][i];
+        }
         out[0] = sqrt(v * scale);
         out[5] = w;
         // the step controller of request b (ctl: device-controlled steps)
@@ -1662,8 +1679,8 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
                       : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque, &le, &nb);
         }));
         const double cnt = 3.0 * (double)p.n_magnetic;
-        k_err_sums<<<1, kBlock, 0, p.stream>>>(p.epart, (int)nb, 2 * nb, err->out_dev, 8,
-                                               cnt > 0 ? 1.0 / cnt : 0.0, nullptr);
+        k_err_sums<<<1, kSumBlock, 0, p.stream>>>(p.epart, (int)nb, 2 * nb, err->out_dev, 8,
+                                                  cnt > 0 ? 1.0 / cnt : 0.0, nullptr);
         return hipGetLastError();
     }
     // DMI and the coupling averages only in the variants that need them
@@ -1720,8 +1737,8 @@ static hipError_t err_final_sums(Plan& p, int nb, double* out_dev, DevCtl* ctl =
 {
     const double cnt = 3.0 * (double)p.n_magnetic;
     const double sc = cnt > 0 ? 1.0 / cnt : 0.0;
-    k_err_sums<<<std::max(1, p.batch), kBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8, sc,
-                                                              ctl);
+    k_err_sums<<<std::max(1, p.batch), kSumBlock, 0, p.stream>>>(p.red, nb, 2L * nb, out_dev, 8,
+                                                                 sc, ctl);
     return hipGetLastError();
 }
 
