@@ -116,6 +116,39 @@ def test_serve_integrate_matches_oracle(torch_cuda, mm, orc):
     assert e <= 1e-7
 
 
+def test_serve_batched_integrations_match_oracle(torch_cuda, mm, orc):
+    """Four time integrations of one grid class -- cell edges 2 to 3.5 nm (the
+    class's one spectral kernel, rescaled), each with its own material, field
+    and damping -- share one batch plan and every launch; each final state
+    against the oracle's FP64 integration of that request alone."""
+    grid = (16, 12, 2)
+    banner("serve batched integrations fp64 vs oracle %s" % (grid,))
+    t_end = 3e-11
+    srv = mm.Server(max_active=2, steps_per_launch=5, prec="fp64", batch=4)
+    reqs, ms = [], {}
+    for i in range(4):
+        r = _req(70 + i, grid, cell=(2.0 + 0.5 * i) * 1e-9)
+        r["alpha"] = 0.05 + 0.05 * i
+        reqs.append(r)
+        ms[i] = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float64, device="cuda").contiguous()
+        srv.submit(ms[i], grid, r["cell"], r["Ms"], r["A"], r["Ku"], alpha=r["alpha"],
+                   h_ext=r["H"], kind=mm.MM_SERVE_INTEGRATE, rtol=1e-8, t_end=t_end, tag=i)
+    comps = _drain(srv, 4)
+    st = srv.stats()
+    srv.close()
+    assert st["max_batch"] == 4 and st["plans_created"] == 1, st
+    for i, r in enumerate(reqs):
+        c = comps[i]
+        assert c["status"] == mm.MM_OK and c["t"] == t_end, c
+        o = orc.Oracle(grid, r["cell"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], alpha=r["alpha"])
+        o.set_field(r["H"])
+        ref = o.dp45(r["m0"], rtol=1e-8, t_end=t_end)[0]
+        e = rel_l2(to_np(ms[i]), ref)
+        print("  request %d (cell %.1f nm, alpha %.2f): accepted %d rejected %d rel-L2 vs oracle %.2e"
+              % (i, r["cell"][0] * 1e9, r["alpha"], c["accepted"], c["rejected"], e))
+        assert e <= 1e-7
+
+
 def _mix(n):
     grids = [(16, 16, 1), (24, 8, 2), (32, 32, 1), (20, 12, 3)]
     reqs = []
