@@ -116,23 +116,27 @@ def test_serve_integrate_matches_oracle(torch_cuda, mm, orc):
     assert e <= 1e-7
 
 
-def test_serve_batched_integrations_match_oracle(torch_cuda, mm, orc):
+@pytest.mark.parametrize("prec,rtol,bar", [("fp64", 1e-8, 1e-7), ("fp32", 1e-6, 1e-4)])
+def test_serve_batched_integrations_match_oracle(torch_cuda, mm, orc, prec, rtol, bar):
     """Four time integrations of one grid class -- cell edges 2 to 3.5 nm (the
     class's one spectral kernel, rescaled), each with its own material, field
     and damping -- share one batch plan and every launch; each final state
-    against the oracle's FP64 integration of that request alone."""
+    against the oracle's FP64 integration of that request alone (rtol 1e-8).
+    Bars: FP64 10 rtol; FP32 (its own step sequence at rtol 1e-6, FP32
+    fields) 1e-4, the FP32-against-FP64 trajectory bar."""
     grid = (16, 12, 2)
-    banner("serve batched integrations fp64 vs oracle %s" % (grid,))
+    banner("serve batched integrations %s vs oracle %s" % (prec, grid))
     t_end = 3e-11
-    srv = mm.Server(max_active=2, steps_per_launch=5, prec="fp64", batch=4)
+    dt = torch_cuda.float64 if prec == "fp64" else torch_cuda.float32
+    srv = mm.Server(max_active=2, steps_per_launch=5, prec=prec, batch=4)
     reqs, ms = [], {}
     for i in range(4):
         r = _req(70 + i, grid, cell=(2.0 + 0.5 * i) * 1e-9)
         r["alpha"] = 0.05 + 0.05 * i
         reqs.append(r)
-        ms[i] = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float64, device="cuda").contiguous()
+        ms[i] = torch_cuda.tensor(r["m0"], dtype=dt, device="cuda").contiguous()
         srv.submit(ms[i], grid, r["cell"], r["Ms"], r["A"], r["Ku"], alpha=r["alpha"],
-                   h_ext=r["H"], kind=mm.MM_SERVE_INTEGRATE, rtol=1e-8, t_end=t_end, tag=i)
+                   h_ext=r["H"], kind=mm.MM_SERVE_INTEGRATE, rtol=rtol, t_end=t_end, tag=i)
     comps = _drain(srv, 4)
     st = srv.stats()
     srv.close()
@@ -146,7 +150,7 @@ def test_serve_batched_integrations_match_oracle(torch_cuda, mm, orc):
         e = rel_l2(to_np(ms[i]), ref)
         print("  request %d (cell %.1f nm, alpha %.2f): accepted %d rejected %d rel-L2 vs oracle %.2e"
               % (i, r["cell"][0] * 1e9, r["alpha"], c["accepted"], c["rejected"], e))
-        assert e <= 1e-7
+        assert e <= bar
 
 
 def _mix(n):
