@@ -153,6 +153,44 @@ def test_serve_batched_integrations_match_oracle(torch_cuda, mm, orc, prec, rtol
         assert e <= bar
 
 
+def test_serve_batched_relaxations_match_oracle(torch_cuda, mm, orc):
+    """Four FP64 relaxations of one grid class (cell edges 2 to 3.5 nm, own
+    material and field) in one batch plan, each to its own torque criterion:
+    every final state against the oracle's relaxation of that request alone,
+    and its torque measured by the oracle."""
+    grid = (12, 10, 2)
+    banner("serve batched relaxations fp64 vs oracle %s" % (grid,))
+    tol = 1e-6
+    srv = mm.Server(max_active=2, steps_per_launch=4, prec="fp64", batch=4)
+    reqs, ms = [], {}
+    for i in range(4):
+        r = _req(80 + i, grid, cell=(2.0 + 0.5 * i) * 1e-9)
+        reqs.append(r)
+        ms[i] = torch_cuda.tensor(r["m0"], dtype=torch_cuda.float64, device="cuda").contiguous()
+        srv.submit(ms[i], grid, r["cell"], r["Ms"], r["A"], r["Ku"], h_ext=r["H"], tol=tol,
+                   rtol=1e-8, tag=i)
+    comps = _drain(srv, 4)
+    st = srv.stats()
+    srv.close()
+    assert st["max_batch"] == 4 and st["plans_created"] == 1, st
+    for i, r in enumerate(reqs):
+        c = comps[i]
+        assert c["status"] == mm.MM_OK and c["torque"] < tol, c
+        o = orc.Oracle(grid, r["cell"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], alpha=1.0)
+        o.set_field(r["H"])
+        ref, st_o, status_o = o.relax(r["m0"], tol=tol, rtol=1e-8)
+        got = to_np(ms[i])
+        e = rel_l2(got, ref)
+        print("  request %d (cell %.1f nm): accepted %d (oracle %d) torque %.2e rel-L2 vs oracle %.2e"
+              % (i, r["cell"][0] * 1e9, c["accepted"], st_o["accepted"], c["torque"], e))
+        assert status_o == 0
+        # the same step path as the oracle: the states agree to rounding
+        # accumulated over the steps; otherwise to the relaxation tolerance
+        same = c["accepted"] == st_o["accepted"] and c["rejected"] == st_o["rejected"]
+        assert e <= (1e-9 if same else 1e-4)
+        assert o.max_torque(got) < 2 * tol
+
+
 def _mix(n):
     grids = [(16, 16, 1), (24, 8, 2), (32, 32, 1), (20, 12, 3)]
     reqs = []
