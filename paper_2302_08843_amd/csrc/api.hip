@@ -275,8 +275,9 @@ static mm_status start_step(Plan* p, const T* y, T* f0, T* f1, T* ys, const doub
 // Device-controlled Dormand-Prince steps (used by the request server): the
 // state stays in rk vector 8, the trial state in 9, stage derivatives in 0..6
 // and the stage input in 7; the controller state is p->ctl.  With a double
-// state (Plan::state64) the state and trial state live in p->st64 and vector 7
-// holds the float stage input, which between steps is the rounded state.
+// state (Plan::state64) the state and trial state live in p->st64, vector 7
+// holds the float stage input, which between steps is the rounded state, and
+// vector 8 its rounding residual.
 // ---------------------------------------------------------------------------
 template <typename T>
 mm_status dev_prepare(Plan* p, const void* m0, const double hext[3], unsigned terms,
@@ -328,26 +329,30 @@ mm_status dev_step(Plan* p, const double hext[3], unsigned terms, double rtol, d
     MM_HIP(dp_begin(*p, p->ctl), "controller");
     if constexpr (std::is_same<T, float>::value) {
         if (p->state64) {
-            // double state: stage inputs formed in double, evaluated in float
+            // double state: stage inputs formed in double and evaluated in
+            // float, the rounding residual (vector 8, free with a double
+            // state) carried into the exchange differences
             double* yd = p->st64;
             double* y1d = p->st64 + vec_stride(p);
+            T* ys_lo = y;
             for (int sg = 1; sg < 7; ++sg) {
-                MM_HIP(rk_combine_d(*p, ys, sg == 6 ? y1d : nullptr, yd, kA[sg], k, sg, hdev),
+                MM_HIP(rk_combine_d(*p, ys, sg == 6 ? y1d : nullptr, yd, kA[sg], k, sg, hdev,
+                                    ys_lo),
                        "stage input");
                 MM_HIP(eval_field<T>(*p, ys, hext, terms, 0.0, nullptr, k[sg], alpha, !relax,
-                                     nullptr),
+                                     nullptr, ys_lo),
                        "right-hand side");
             }
             double E[7];
             for (int j = 0; j < 7; ++j) E[j] = kB5[j] - kB4[j];
             MM_HIP(rk_error_norm_d(*p, yd, y1d, E, k, 7, rtol, atol, p->red_out, hdev, p->ctl),
                    "error norm and controller");
-            MM_HIP(dp_commit_d(*p, p->ctl, yd, y1d, ys, k[0], k[6]), "commit");
+            MM_HIP(dp_commit_d(*p, p->ctl, yd, y1d, ys, k[0], k[6], ys_lo), "commit");
             // the closing evaluation leaves the torque for the next step's
             // begin
             if (renorm)
                 MM_HIP(eval_field<T>(*p, ys, hext, terms, 0.0, nullptr, k[0], alpha, !relax,
-                                     relax ? p->red_out + 1 : nullptr),
+                                     relax ? p->red_out + 1 : nullptr, ys_lo),
                        "right-hand side");
             return MM_OK;
         }

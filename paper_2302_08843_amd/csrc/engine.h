@@ -153,9 +153,13 @@ hipError_t init_twiddles(Plan &p);
 //   dm_out   : LLG right-hand side (may be null), with alpha_eff and precess
 //   torque   : if non-null, per-block maxima of |m x h|/Ms into p.red and the
 //              final maximum into *torque (device double)
+//   m_lo     : if non-null (FP32, plain stencil), the state is m + m_lo, the
+//              float rounding residual of a double state, and the exchange
+//              differences take it into account
 template <typename T>
 hipError_t eval_field(Plan &p, const T *m, const double hext[3], unsigned terms, double t,
-                      T *h_out, T *dm_out, double alpha_eff, bool precess, double *torque);
+                      T *h_out, T *dm_out, double alpha_eff, bool precess, double *torque,
+                      const T *m_lo = nullptr);
 
 // A Runge-Kutta stage input ys = y + sum_{j < nk} c_j k_j (c_j multiplied by
 // *h when h is not null), formed by the x forward pass as it loads its rows.
@@ -237,16 +241,17 @@ template <typename T>
 hipError_t dp_commit(Plan &p, DevCtl *c, T *y, const T *y1, T *k0, const T *k6);
 // Double state with FP32 stages (Plan::state64): stage inputs formed in
 // double from y and rounded to float into ys (and kept in double in y1 when
-// not null); the error norm from double y, y1; the commit in double, which
-// with renormalisation leaves the rounded state in ys (the renormalised y1 on
-// acceptance, the unchanged y on rejection); conversions.
+// not null; with ys_lo, the rounding residual float(v - ys) too); the error
+// norm from double y, y1; the commit in double, which with renormalisation
+// leaves the rounded state in ys (and its residual in ys_lo) -- the
+// renormalised y1 on acceptance, the unchanged y on rejection; conversions.
 hipError_t rk_combine_d(Plan &p, float *ys, double *y1, const double *y, const double *a,
-                        float *const *k, int nk, const double *hdev);
+                        float *const *k, int nk, const double *hdev, float *ys_lo = nullptr);
 hipError_t rk_error_norm_d(Plan &p, const double *y, const double *y1, const double *e,
                            float *const *k, int nk, double rtol, double atol, double *out_dev,
                            const double *hdev, DevCtl *ctl = nullptr);
 hipError_t dp_commit_d(Plan &p, DevCtl *c, double *y, const double *y1, float *ys, float *k0,
-                       const float *k6);
+                       const float *k6, float *ys_lo = nullptr);
 hipError_t convert_f32_f64(Plan &p, const float *in, double *out, long n);
 hipError_t convert_f64_f32(Plan &p, const double *in, float *out, long n);
 // c->torque = p.red_out[1] while running

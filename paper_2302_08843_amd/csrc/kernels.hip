@@ -1647,7 +1647,7 @@ template <typename T>
 static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], unsigned terms,
                                   double t, T* h_out, T* dm_out, double alpha_eff, bool precess,
                                   double* torque, const StageIn<T>* sc,
-                                  const ErrIn<T>* err = nullptr)
+                                  const ErrIn<T>* err = nullptr, const T* m_lo = nullptr)
 {
     const int M = p.P[0] / 2;
     const bool pc = p.percell;
@@ -1683,21 +1683,27 @@ static hipError_t eval_field_core(Plan& p, const T* m, const double hext[3], uns
                                                   cnt > 0 ? 1.0 / cnt : 0.0, nullptr);
         return hipGetLastError();
     }
-    // DMI and the coupling averages only in the variants that need them
+    // DMI and the coupling averages only in the variants that need them.
+    // The split state needs the wave-local pass; elsewhere the float part
+    // alone is used
+    if (m_lo && (ext != 0 || pc || sc)) return hipErrorInvalidValue;
+    if (m_lo && !(std::is_same<T, float>::value && local_wave_ok<T>(M))) m_lo = nullptr;
     return timed(p, MM_PASS_X_INV_LOCAL, [&] {
         if (ext == 0)
             return pc ? launch_local<T, true, 0>(p, M, m, h_out, dm_out, P, torque)
-                      : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque);
+                      : launch_local<T, false, 0>(p, M, m, h_out, dm_out, P, torque, nullptr,
+                                                  nullptr, m_lo);
         return launch_local_ext<T>(p, M, m, h_out, dm_out, P, torque, pc, ext);
     });
 }
 
 template <typename T>
 hipError_t eval_field(Plan& p, const T* m, const double hext[3], unsigned terms, double t,
-                      T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque)
+                      T* h_out, T* dm_out, double alpha_eff, bool precess, double* torque,
+                      const T* m_lo)
 {
     return eval_field_core<T>(p, m, hext, terms, t, h_out, dm_out, alpha_eff, precess, torque,
-                              nullptr);
+                              nullptr, nullptr, m_lo);
 }
 
 template <typename T>
@@ -2028,12 +2034,14 @@ template <int NK>
 __global__ __launch_bounds__(kBlock) void k_rk_combine_d(float* __restrict__ ys,
                                                          double* __restrict__ y1,
                                                          const double* __restrict__ y, Coef7 cf,
-                                                         Ptr7<float> ks, long n3)
+                                                         Ptr7<float> ks, long n3,
+                                                         float* __restrict__ ys_lo)
 {
     // request blockIdx.y of a batch
     const long bo = (long)blockIdx.y * n3;
     ys += bo;
     if (y1) y1 += bo;
+    if (ys_lo) ys_lo += bo;
     y += bo;
 #pragma unroll
     for (int j = 0; j < NK; ++j) ks.p[j] += bo;
@@ -2048,7 +2056,9 @@ __global__ __launch_bounds__(kBlock) void k_rk_combine_d(float* __restrict__ ys,
         for (int j = 0; j < NK; ++j)
             if (cf.c[j] != 0.0) acc += cj[j] * (double)ks.p[j][q];
         if (y1) y1[q] = acc;
-        ys[q] = (float)acc;
+        const float hi = (float)acc;
+        ys[q] = hi;
+        if (ys_lo) ys_lo[q] = (float)(acc - (double)hi);
     }
 }
 
@@ -2102,7 +2112,7 @@ __global__ __launch_bounds__(kBlock) void k_err_norm_d(const double* __restrict_
 __global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__ y,
                               const double* __restrict__ y1, float* __restrict__ ys,
                               float* __restrict__ k0, const float* __restrict__ k6,
-                              const float* __restrict__ Ms_cell, long N)
+                              const float* __restrict__ Ms_cell, long N, float* __restrict__ ys_lo)
 {
     // request blockIdx.y of a batch
     const long bo = (long)blockIdx.y * 3 * N;
@@ -2110,6 +2120,7 @@ __global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__
     y += bo;
     y1 += bo;
     ys += bo;
+    if (ys_lo) ys_lo += bo;
     k0 += bo;
     k6 += bo;
     const bool commit = c->commit != 0;
@@ -2118,9 +2129,13 @@ __global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__
     for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
          q += (long)gridDim.x * blockDim.x) {
         if (!commit) {
-            ys[q] = (float)y[q];
-            ys[N + q] = (float)y[N + q];
-            ys[2 * N + q] = (float)y[2 * N + q];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double v = y[a * N + q];
+                const float hi = (float)v;
+                ys[a * N + q] = hi;
+                if (ys_lo) ys_lo[a * N + q] = (float)(v - (double)hi);
+            }
             continue;
         }
         double x = y1[q], yy = y1[N + q], z = y1[2 * N + q];
@@ -2133,9 +2148,15 @@ __global__ void k_dp_commit_d(const DevCtl* __restrict__ c, double* __restrict__
                 yy *= inv;
                 z *= inv;
             }
-            ys[q] = (float)x;
-            ys[N + q] = (float)yy;
-            ys[2 * N + q] = (float)z;
+            const float hx = (float)x, hy = (float)yy, hz = (float)z;
+            ys[q] = hx;
+            ys[N + q] = hy;
+            ys[2 * N + q] = hz;
+            if (ys_lo) {
+                ys_lo[q] = (float)(x - (double)hx);
+                ys_lo[N + q] = (float)(yy - (double)hy);
+                ys_lo[2 * N + q] = (float)(z - (double)hz);
+            }
         } else {
             k0[q] = k6[q];
             k0[N + q] = k6[N + q];
@@ -2156,7 +2177,7 @@ __global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, long n)
 }
 
 hipError_t rk_combine_d(Plan& p, float* ys, double* y1, const double* y, const double* a,
-                        float* const* k, int nk, const double* hdev)
+                        float* const* k, int nk, const double* hdev, float* ys_lo)
 {
     Coef7 cf{};
     Ptr7<float> ks{};
@@ -2171,7 +2192,9 @@ hipError_t rk_combine_d(Plan& p, float* ys, double* y1, const double* y, const d
     return timed(p, MM_PASS_RK, [&] {
         switch (nk) {
 #define MMX_CD(NK) \
-    case NK: k_rk_combine_d<NK><<<blocks, kBlock, 0, p.stream>>>(ys, y1, y, cf, ks, n3); break;
+    case NK:                                                                                 \
+        k_rk_combine_d<NK><<<blocks, kBlock, 0, p.stream>>>(ys, y1, y, cf, ks, n3, ys_lo);     \
+        break;
             MMX_CD(1) MMX_CD(2) MMX_CD(3) MMX_CD(4) MMX_CD(5) MMX_CD(6) MMX_CD(7)
 #undef MMX_CD
         default:
@@ -2210,12 +2233,13 @@ hipError_t rk_error_norm_d(Plan& p, const double* y, const double* y1, const dou
 }
 
 hipError_t dp_commit_d(Plan& p, DevCtl* c, double* y, const double* y1, float* ys, float* k0,
-                       const float* k6)
+                       const float* k6, float* ys_lo)
 {
     if (p.batch > 1 && p.percell) return hipErrorInvalidValue;
     const dim3 blocks((unsigned)std::min<long>(blocks_for(p.N, 256), 4096), (unsigned)p.batch);
     k_dp_commit_d<<<blocks, 256, 0, p.stream>>>(c, y, y1, ys, k0, k6,
-                                                p.percell ? (const float*)p.Ms_cell : nullptr, p.N);
+                                                p.percell ? (const float*)p.Ms_cell : nullptr, p.N,
+                                                ys_lo);
     return hipGetLastError();
 }
 
@@ -2252,7 +2276,7 @@ hipError_t from_double(Plan& p, const double* in, T* out, long n)
     template hipError_t build_tensor<T>(Plan&);                                                  \
     template hipError_t init_twiddles<T>(Plan&);                                                 \
     template hipError_t eval_field<T>(Plan&, const T*, const double*, unsigned, double, T*, T*, \
-                                      double, bool, double*);                                    \
+                                      double, bool, double*, const T*);                          \
     template hipError_t eval_field_stage<T>(Plan&, const StageIn<T>&, const double*, unsigned,   \
                                             double, T*, double, bool, double*,                   \
                                             const ErrIn<T>*);                                    \

@@ -882,6 +882,10 @@ __device__ __forceinline__ T dmi_avg(T a, T b)
 // Ku_cell when given one (P.anis then 2 / mu0); EXT_PK alone is the variant
 // for a per-cell Ku without the other extensions.
 constexpr int EXT_DMI = 1, EXT_PA = 2, EXT_PD = 4, EXT_MIX = 8, EXT_PK = 16;
+// EXT_LO (wave-local local pass, FP32, plain stencil): the state is given as
+// m + m_lo (two floats, the rounding residual of a double state), and the
+// exchange differences are taken as (m_j - m_i) + (m_lo_j - m_lo_i)
+constexpr int EXT_LO = 32;
 
 template <typename T, int M, bool PERCELL, int EXT>
 __global__ __launch_bounds__((XC2R<T, M>::kRows * 3 * XC2R<T, M>::kT)) void k_x_c2r_local(
@@ -1111,10 +1115,11 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     LocalParams Pk, double* torque, long nblocks, const cx<T>* __restrict__ tw, int Lmax,
     const T* __restrict__ A_cell, const T* __restrict__ D_cell, const T* __restrict__ zw,
     const T* __restrict__ h_oe, const T* __restrict__ Ku_cell,
-    const LocalParams* __restrict__ Pb, int nbatch, long tstride, LocalErr<T> E)
+    const LocalParams* __restrict__ Pb, int nbatch, long tstride, LocalErr<T> E,
+    const T* __restrict__ m_lo)
 {
     constexpr bool kDMI = EXT & EXT_DMI, kPA = EXT & EXT_PA, kPD = EXT & EXT_PD;
-    constexpr bool kMIX = EXT & EXT_MIX;
+    constexpr bool kMIX = EXT & EXT_MIX, kLO = EXT & EXT_LO;
     using G = XC2RW<T, M>;
     constexpr int kE = G::kE, kT = G::kT, RB = G::kRB, CPT = G::kCPT, kL = G::S::kLds;
     constexpr int NTW = (M + G::kNT - 1) / G::kNT;
@@ -1129,6 +1134,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
         const long n3 = 3 * Pk.N;
         S1 += (long)bi * 3 * Pk.s1_comp;
         m += (long)bi * n3;
+        if constexpr (kLO) m_lo += (long)bi * n3;
         if (h_out) h_out += (long)bi * n3;
         if (dm_out) dm_out += (long)bi * n3;
         if (torque) torque += (long)bi * tstride;
@@ -1176,6 +1182,7 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
     bool cv[CPT], has[CPT][6];
     unsigned q6[CPT][6];
     T mv[CPT][7][3];
+    T mlo[kLO ? CPT : 1][kLO ? 7 : 1][3];
     T msv[CPT][7];
     T Av[CPT][7], Dv[CPT][7];
     int jj[CPT], ii[CPT];
@@ -1212,6 +1219,11 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
             msv[q][d] = PERCELL ? elem<true>(Ms_cell, qq) : (T)P.Ms;
             Av[q][d] = kPA ? elem<true>(A_cell, qq) : (T)0;
             Dv[q][d] = kPD ? elem<true>(D_cell, qq) : (T)0;
+            if constexpr (kLO) {
+                mlo[q][d][0] = elem<true>(m_lo, qq);
+                mlo[q][d][1] = elem<true>(m_lo + N, qq);
+                mlo[q][d][2] = elem<true>(m_lo + 2 * (size_t)N, qq);
+            }
         }
     }
 
@@ -1288,9 +1300,18 @@ __global__ __launch_bounds__(256) void k_x_c2r_local_w(
                     const bool ok = has[q][nbi] && (!PERCELL || msv[q][nbi + 1] != (T)0);
                     T wq = ok ? (dir == 0 ? ix2 : dir == 1 ? iy2 : plus ? wz_up : wz_dn) : (T)0;
                     if constexpr (kPA) wq *= harmonic2(Ai, Av[q][nbi + 1]);
-                    ax += wq * (qx - mx);
-                    ay += wq * (qy - my);
-                    az += wq * (qz - mz);
+                    if constexpr (kLO) {
+                        // differences of the split state: the float parts
+                        // subtract exactly for neighbouring directions, the
+                        // residuals carry the rest of the double state
+                        ax += wq * ((qx - mx) + (mlo[q][nbi + 1][0] - mlo[q][0][0]));
+                        ay += wq * ((qy - my) + (mlo[q][nbi + 1][1] - mlo[q][0][1]));
+                        az += wq * ((qz - mz) + (mlo[q][nbi + 1][2] - mlo[q][0][2]));
+                    } else {
+                        ax += wq * (qx - mx);
+                        ay += wq * (qy - my);
+                        az += wq * (qz - mz);
+                    }
                     if constexpr (kDMI) {
                         // D~ (e^dmi_k x m_{i+k}) / (2 Delta_k), e^dmi_{-k} = -e^dmi_k
                         T c = ok ? (plus ? (T)1 : (T)-1) : (T)0;
@@ -1653,13 +1674,37 @@ hipError_t launch_mid(const Plan& p, int L, cx<T>* S, int n_valid, long es, long
 // request, wave-local kernel); *nb_out: the number of blocks (partial pairs).
 template <typename T, int M, bool PC, int EXT>
 static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const LocalParams& P,
-                                 double* torque, const LocalErr<T>* err, long* nb_out)
+                                 double* torque, const LocalErr<T>* err, long* nb_out,
+                                 const T* m_lo)
 {
     if constexpr (MMX_X1W && XC2RW<T, M>::kOK) {
         using Gw = XC2RW<T, M>;
         const int njt = (p.n[1] + Gw::kRB - 1) / Gw::kRB;
         const long nblocks = (long)njt * p.n[2];
         if (nb_out) *nb_out = nblocks;
+        if (m_lo) {
+            // the split state (FP32 fields of a double state): plain stencil,
+            // one material per request
+            if constexpr (std::is_same<T, float>::value && !PC && EXT == 0) {
+                if (err || p.layered) return hipErrorInvalidValue;
+                if (p.Pb) {
+                    k_x_c2r_local_w<T, M, false, EXT_LO, true>
+                        <<<xcd_grid(nblocks * p.batch), Gw::kNT, 0, p.stream>>>(
+                            (const cx<T>*)p.S1, m, h, dm, nullptr, nullptr, P, torque, nblocks,
+                            (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, (const LocalParams*)p.Pb, p.batch, 8, LocalErr<T>{}, m_lo);
+                } else {
+                    k_x_c2r_local_w<T, M, false, EXT_LO, false>
+                        <<<xcd_grid(nblocks), Gw::kNT, 0, p.stream>>>(
+                            (const cx<T>*)p.S1, m, h, dm, nullptr, p.mask, P, torque, nblocks,
+                            (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr, nullptr,
+                            P.with_oe ? (const T*)p.h_oe : nullptr, nullptr, nullptr, 1, 0,
+                            LocalErr<T>{}, m_lo);
+                }
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
         if (err) {
             if constexpr (EXT == 0) {
                 if (p.Pb || !dm || !err->part || nblocks > (long)p.n[1] * p.n[2])
@@ -1669,7 +1714,7 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
                         (const cx<T>*)p.S1, m, h, dm, (const T*)p.Ms_cell, p.mask, P, torque,
                         nblocks, (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr,
                         p.layered ? (const T*)p.zw : nullptr, P.with_oe ? (const T*)p.h_oe : nullptr,
-                        nullptr, nullptr, 1, 0, *err);
+                        nullptr, nullptr, 1, 0, *err, nullptr);
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
@@ -1683,7 +1728,7 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
                     <<<xcd_grid(nblocks * p.batch), Gw::kNT, 0, p.stream>>>(
                         (const cx<T>*)p.S1, m, h, dm, nullptr, nullptr, P, torque, nblocks,
                         (const cx<T>*)p.tw, p.Lmax, nullptr, nullptr, nullptr, nullptr, nullptr,
-                        (const LocalParams*)p.Pb, p.batch, 8, LocalErr<T>{});
+                        (const LocalParams*)p.Pb, p.batch, 8, LocalErr<T>{}, nullptr);
                 return hipGetLastError();
             }
             return hipErrorInvalidValue;
@@ -1694,11 +1739,12 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
             (EXT & EXT_PD) ? (const T*)p.D_cell : nullptr, p.layered ? (const T*)p.zw : nullptr,
             P.with_oe ? (const T*)p.h_oe : nullptr,
             EXT != 0 && p.percell_Ku ? (const T*)p.Ku_cell : nullptr, nullptr, 1, 0,
-            LocalErr<T>{});
+            LocalErr<T>{}, nullptr);
         return hipGetLastError();
     }
-    // batches and the error accumulation need the wave-local kernel
-    if (p.Pb || err) return hipErrorInvalidValue;
+    // batches, the error accumulation and the split state need the
+    // wave-local kernel
+    if (p.Pb || err || m_lo) return hipErrorInvalidValue;
     if (nb_out) *nb_out = 0;
     using G = XC2R<T, M>;
     const int njt = (p.n[1] + G::kRows - 1) / G::kRows;
@@ -1715,11 +1761,12 @@ static hipError_t launch_local_M(const Plan& p, const T* m, T* h, T* dm, const L
 template <typename T, bool PC, int EXT>
 hipError_t launch_local(const Plan& p, int M, const T* m, T* h, T* dm,
                                const LocalParams& P, double* torque,
-                               const LocalErr<T>* err = nullptr, long* nb_out = nullptr)
+                               const LocalErr<T>* err = nullptr, long* nb_out = nullptr,
+                               const T* m_lo = nullptr)
 {
     switch (M) {
 #define MMX_L(LL) \
-    case LL: return launch_local_M<T, LL, PC, EXT>(p, m, h, dm, P, torque, err, nb_out);
+    case LL: return launch_local_M<T, LL, PC, EXT>(p, m, h, dm, P, torque, err, nb_out, m_lo);
         MMX_L(0) MMX_CASES(MMX_L)
 #undef MMX_L
     }
@@ -1770,10 +1817,10 @@ hipError_t launch_local_ext(const Plan& p, int M, const T* m, T* h, T* dm, const
                                                    const StageIn<T>*);                          \
     EXT_ template hipError_t launch_local<T, false, 0>(const Plan&, int, const T*, T*, T*,      \
                                                        const LocalParams&, double*,             \
-                                                       const LocalErr<T>*, long*);              \
+                                                       const LocalErr<T>*, long*, const T*);    \
     EXT_ template hipError_t launch_local<T, true, 0>(const Plan&, int, const T*, T*, T*,       \
                                                       const LocalParams&, double*,              \
-                                                      const LocalErr<T>*, long*);
+                                                      const LocalErr<T>*, long*, const T*);
 #define MMX_MID_INST(EXT_, T)                                                                    \
     EXT_ template hipError_t launch_mid<T, 2, 0>(const Plan&, int, cx<T>*, int, long, long,     \
                                                  long, int);                                    \
