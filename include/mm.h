@@ -378,7 +378,8 @@ mm_status mm_rk4_adjoint(mm_plan *p, const void *ckpt, const double h_ext[3], un
  * and cell proportions), kind, terms and tolerances share launches: a group
  * of up to `batch` of them (at most 2^17 cells together, within hbm_budget;
  * one where the x extent is 1) lives in one batch plan (spectra, Runge-Kutta
- * vectors -- in FP32 with the state in double -- and a device-side step
+ * vectors -- in FP32 with the state in double, the float stage input's
+ * rounding residual taken into the exchange differences -- and a device-side step
  * controller per request) on one of max_active streams, and every kernel of a
  * step covers all its requests.  The steps are decided on the device per
  * request (the same accept/reject and step-size rules as mm_llg_step) and

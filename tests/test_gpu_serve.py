@@ -191,6 +191,29 @@ def test_serve_batched_relaxations_match_oracle(torch_cuda, mm, orc):
         assert o.max_torque(got) < 2 * tol
 
 
+def test_serve_fp32_relaxation_converges_like_fp64(torch_cuda, mm):
+    """Request 6 of the serving stream (128x128x2, 3 nm cells, tol 1e-5, rtol
+    1e-7), whose FP32 torque levelled off at 1.5e-5 while the exchange
+    stencil took the float-rounded state: with the split state the FP32
+    server reaches the criterion within 2 % of the FP64 server's step count."""
+    r = W.serving_requests(512, seed=0, rate=0.2)[6]
+    banner("serve fp32 relaxation vs fp64 steps %s" % (r["n"],))
+    steps = {}
+    for prec, dt in (("fp64", torch_cuda.float64), ("fp32", torch_cuda.float32)):
+        m = torch_cuda.tensor(W.smooth_random(r["n"], 8.0, seed=r["seed"]), dtype=dt,
+                              device="cuda").contiguous()
+        srv = mm.Server(max_active=2, steps_per_launch=8, prec=prec)
+        srv.submit(m, r["n"], r["d"], r["Ms"], r["A"], r["Ku"], ku_axis=r["eu"], h_ext=r["H"],
+                   tol=1e-5, rtol=1e-7, max_steps=20000, tag=0)
+        c = _drain(srv, 1)[0]
+        srv.close()
+        print("  %s: status %d accepted %d rejected %d torque %.3g"
+              % (prec, c["status"], c["accepted"], c["rejected"], c["torque"]))
+        assert c["status"] == mm.MM_OK and c["torque"] < 1e-5, c
+        steps[prec] = c["accepted"]
+    assert abs(steps["fp32"] - steps["fp64"]) <= 0.02 * steps["fp64"], steps
+
+
 def _mix(n):
     grids = [(16, 16, 1), (24, 8, 2), (32, 32, 1), (20, 12, 3)]
     reqs = []
