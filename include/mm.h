@@ -286,7 +286,13 @@ mm_status mm_llg_step(mm_plan *p, void *m, const double h_ext[3], unsigned terms
 /* Relaxation (Sec. 3): integrate dm/dt = -gamma/2 m x (m x h) (alpha = 1, no
  * precession term) with renormalised Dormand-Prince steps at tolerance rtol
  * until max_i |m_i x h_i| / Ms_i < tol.  Returns MM_ENOTCONV with the last
- * accepted state in m if max_steps steps do not reach the criterion. */
+ * accepted state in m if max_steps steps do not reach the criterion.  An
+ * FP32 plan with uniform Ms, the plain stencil, equal layers and static
+ * fields keeps the state in double (6N doubles allocated on first use) and
+ * takes the exchange differences of the float stage input plus its rounding
+ * residual, with the step decisions on the device (the host reads the
+ * controller every 16 steps); other FP32 plans keep a float state, whose
+ * rounding noise can hold the torque near 1e-5. */
 mm_status mm_relax(mm_plan *p, void *m, const double h_ext[3], unsigned terms, double tol,
                    long max_steps, double rtol, mm_step_stats *st);
 

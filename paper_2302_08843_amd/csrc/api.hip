@@ -1531,6 +1531,61 @@ mm_status mm_llg_step(mm_plan* pl, void* m, const double h_ext[3], unsigned term
                               dt_min, o->renorm != 0, false, 0.0, st, o->method);
 }
 
+// FP32 relaxation with a double state: the device-controlled steps of the
+// request server on this plan (the state and trial state in double, stage
+// inputs rounded once to float with their residual in the exchange
+// differences).  With a float state the rounding noise, amplified by the
+// stiffest exchange modes at the step size the controller settles on, holds
+// the torque of some relaxations near 1e-5.  The host polls the controller
+// every 16 steps; steps after completion change nothing.
+static mm_status relax_split(Plan* p, void* m, const double h_ext[3], unsigned terms, double tol,
+                             long max_steps, double rtol, mm_step_stats* st)
+{
+    const bool was = p->state64;
+    p->state64 = true;
+    mm_status s = ensure_rk(p);
+    DevCtl c{};
+    if (s == MM_OK) {
+        c.t = 0.0;
+        c.dt = -1.0;
+        c.t_end = std::numeric_limits<double>::infinity();
+        c.dt_min = 1e-20;
+        c.torque_tol = tol;
+        c.max_steps = max_steps;
+        c.relax = 1;
+        c.renorm = 1;
+        s = dev_prepare<float>(p, m, h_ext, terms, c, rtol, rtol);
+    }
+    while (s == MM_OK) {
+        for (int i = 0; i < 16 && s == MM_OK; ++i)
+            s = dev_step<float>(p, h_ext, terms, rtol, rtol, true, true);
+        if (s != MM_OK) break;
+        hipError_t e = hipMemcpyAsync(&c, p->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) s = hip_fail(e, "reading the step controller");
+        if (s == MM_OK && c.done) break;
+    }
+    if (s == MM_OK) {
+        hipError_t e = dev_result(p, m);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) s = hip_fail(e, "copying the result");
+    }
+    p->state64 = was;
+    if (s != MM_OK) return s;
+    if (st) {
+        st->accepted = c.accepted;
+        st->rejected = c.rejected;
+        st->rhs_evals = c.rhs_evals;
+        st->t = c.t;
+        st->dt = c.dt;
+        st->err_last = c.err_last;
+    }
+    if (c.result == MM_ENOTCONV) set_error("relaxation did not reach the torque criterion");
+    if (c.result == MM_EDTMIN) set_error("step size fell below dt_min");
+    if (c.result == MM_ENONFINITE) set_error("non-finite magnetisation");
+    return (mm_status)c.result;
+}
+
 mm_status mm_relax(mm_plan* pl, void* m, const double h_ext[3], unsigned terms, double tol,
                    long max_steps, double rtol, mm_step_stats* st)
 {
@@ -1545,6 +1600,7 @@ mm_status mm_relax(mm_plan* pl, void* m, const double h_ext[3], unsigned terms, 
     }
     double t = 0.0, dt = -1.0;
     const double inf = std::numeric_limits<double>::infinity();
+    if (split_state_ok(*p, terms)) return relax_split(p, m, h_ext, terms, tol, max_steps, rtol, st);
     return p->prec == MM_FP32
                ? dp45<float>(p, m, h_ext, terms, &t, &dt, rtol, rtol, inf, max_steps, 1e-20, true,
                              true, tol, st)

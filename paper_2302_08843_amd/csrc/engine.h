@@ -202,6 +202,10 @@ hipError_t eval_field_stage(Plan &p, const StageIn<T> &sc, const double hext[3],
 // for this plan and terms: the demag chain runs, the plain stencil, one
 // request, the wave-local local pass, the partials buffer in place.
 bool err_fusable(const Plan &p, unsigned terms);
+// whether device-controlled steps with a double state and the split-state
+// exchange can run on this plan and terms: FP32, one request, uniform Ms,
+// plain stencil, equal layers, static fields
+bool split_state_ok(const Plan &p, unsigned terms);
 
 // y_out = y + h * sum_j a[j] k[j]  (nk <= 7).  hdev: if not null, h is read
 // from this device double instead (device-side step control).

@@ -1591,6 +1591,17 @@ static bool local_wave_ok(int M)
     return false;
 }
 
+bool split_state_ok(const Plan& p, unsigned terms)
+{
+    if (p.prec != MM_FP32 || p.Pb || p.batch != 1 || p.percell || p.layered) return false;
+    // static fields: no drive, no oscillating current
+    if (p.drive && p.mask) return false;
+    if ((terms & MM_OERSTED) && p.oe_on && p.oe_freq != 0.0) return false;
+    int ext = 0;
+    (void)make_local_params(p, nullptr, terms, 0.0, 1.0, false, &ext);
+    return ext == 0 && local_wave_ok<float>(p.P[0] / 2);
+}
+
 bool err_fusable(const Plan& p, unsigned terms)
 {
     if (!(terms & MM_DEMAG) || p.P[0] / 2 < 2 || p.Pb || !p.epart || p.batch != 1)

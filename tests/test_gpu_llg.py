@@ -294,3 +294,31 @@ def test_full_size_steps_properties(torch_cuda, mm):
     d = float(np.abs(res["fp32"] - res["fp64"]).max())
     print("  |m32 - m64| at t %.3e s: %.2e" % (t_end, d))
     assert d <= 1e-4
+
+
+def test_relax_fp32_converges_like_fp64(torch_cuda, mm):
+    """mm_relax on an FP32 plan (double state, exchange differences of the
+    split float state) reaches tol 1e-5 on request 6 of the serving stream
+    (128x128x2, 3 nm cells, rtol 1e-7) within 2 % of the FP64 plan's step
+    count; with a float state its torque levelled off at 1.4e-5."""
+    r = W.serving_requests(512, seed=0, rate=0.2)[6]
+    banner("relax fp32 vs fp64 steps %s" % (r["n"],))
+    steps = {}
+    for prec in ("fp64", "fp32"):
+        plan = mm.Plan(r["n"], r["d"], Ms=r["Ms"], A=r["A"], Ku=r["Ku"], ku_axis=r["eu"],
+                       alpha=1.0, prec=prec)
+        m = plan._t(W.smooth_random(r["n"], 8.0, seed=r["seed"]))
+        status, st = plan.relax(m, r["H"], mm.MM_ALL, tol=1e-5, max_steps=20000, rtol=1e-7)
+        tq = plan.max_torque(m, r["H"])
+        print("  %s: status %d accepted %d rejected %d torque of the returned state %.3g"
+              % (prec, status, st["accepted"], st["rejected"], tq))
+        assert status == mm.MM_OK
+        # the FP32 result is the double state rounded to float: a rounding of
+        # at most 2^-24 per component moves the torque by up to about
+        # 12 (2A / (mu0 Ms dx^2)) 2^-24 sqrt(3) / Ms (2.4e-6 here)
+        w = 2 * r["A"] / (4e-7 * np.pi * r["Ms"] * r["d"][0] ** 2)
+        floor = 0.0 if prec == "fp64" else 12 * w * 2.0 ** -24 * 3 ** 0.5 / r["Ms"]
+        assert tq < 1e-5 + floor
+        steps[prec] = st["accepted"]
+        plan.close()
+    assert abs(steps["fp32"] - steps["fp64"]) <= 0.02 * steps["fp64"], steps
