@@ -438,7 +438,8 @@ typedef struct {
     int status;        /* MM_OK, MM_ENOTCONV (relaxation hit max_steps), MM_EDTMIN,
                           MM_ENONFINITE, MM_ENOMEM (larger than the budget), MM_EHIP */
     long accepted, rejected, rhs_evals;
-    double t, torque;  /* final time; final torque (relaxations) */
+    double t, torque;  /* final time; final torque (relaxations; FP32: of the double
+                          state, before the result is rounded to float) */
     double t_submit, t_admit, t_done; /* mm_serve_clock() seconds */
 } mm_completion;
 
